@@ -1,0 +1,220 @@
+/*
+ * fusedir.h -- C ABI of libfusedir.so: fusion-patch multi-view direction
+ * optimisation on AMD Instinct MI355X (gfx950).
+ *
+ * For every 3D hair point the library projects the point and candidate
+ * tangents into calibrated views, samples each view's orientation and
+ * confidence maps over a P x P patch and returns the direction with the best
+ * patch-fused, confidence-weighted bidirectional agreement (EfficientMonoHair,
+ * Sec. 3.1: top-K confident views, Eq. (4); reprojected candidate offset,
+ * Eq. (8); bidirectional similarity, confidence weighting and patch maximum,
+ * Eqs. (9)-(11); best candidate, Eq. (12)).  Candidates are a hemisphere
+ * Fibonacci lattice followed by a pattern-search refinement; a learned form
+ * starts from a network proposal instead and falls back to the full search.
+ *
+ * Conventions shared by every entry point
+ *   - Camera (fd_camera, 64 bytes): fx, fy, cx, cy, R (row-major,
+ *     world->camera), t;  X_c = R p + t, OpenCV axes (x right, y down,
+ *     z forward), pixel u = (fx X/Z + cx, fy Y/Z + cy), texel (i, j) centred
+ *     on pixel coordinate (i, j).
+ *   - Maps: V x H x W row-major, orientation theta in [0, pi] radians
+ *     measured from image +x towards +y, confidence C in [0, 1] (0 = no
+ *     measurement); element type FD_F32 (float) or FD_F16 (IEEE binary16).
+ *   - Directions: unit float3, sign-canonical (z > 0, else y > 0, else
+ *     x >= 0).  Cost J in [0, 1] = 1 - mean over the selected views of the
+ *     patch-max confidence-weighted |cos| agreement; a point with no eligible
+ *     view gets direction (0, 0, 0) and cost +inf.  This is not an error.
+ *   - Pointers named "device" are HIP device pointers owned by the caller;
+ *     the library never frees them.  All computation is enqueued on
+ *     params->stream (a hipStream_t; NULL = the default stream) and the call
+ *     returns after enqueueing: inputs must stay valid and outputs untouched
+ *     until the stream has passed the call.
+ *   - Return codes: FD_OK, or an error code with a message from
+ *     fd_last_error() (thread-local).  On an error detected on the host
+ *     nothing is enqueued and outputs are untouched.  No C++ exception
+ *     crosses this interface.
+ */
+#ifndef FUSEDIR_H
+#define FUSEDIR_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  FD_OK = 0,
+  FD_E_INVAL = 1,        /* bad argument: null pointer, size out of range ... */
+  FD_E_UNSUPPORTED = 2,  /* device is not gfx950 */
+  FD_E_HIP = 3,          /* HIP runtime or launch error */
+  FD_E_NOMEM = 4         /* context workspace smaller than the request */
+};
+
+enum { FD_F32 = 0, FD_F16 = 1 };
+enum { FD_MODE_PLAIN = 0, FD_MODE_LEARNED = 1 };
+/* Source of the learned form's starting direction.  Only FD_PROPOSAL_MLP
+ * uses the network; the others replace it for testing (GIVEN reads
+ * params->proposal_dirs, NAN makes every proposal invalid). */
+enum { FD_PROPOSAL_MLP = 0, FD_PROPOSAL_GIVEN = 1, FD_PROPOSAL_NAN = 2 };
+
+#define FD_MAX_TOPK 8
+#define FD_MAX_PATCH 7
+#define FD_MAX_VIEWS 65535
+#define FD_MAX_CANDIDATES 4096
+#define FD_MAX_REFINE 32
+#define FD_FEATURE_SLOTS 16
+#define FD_FEATURE_DIM 112 /* 16 slots x 7 */
+
+typedef struct fd_camera {
+  float fx, fy, cx, cy;
+  float R[9];
+  float t[3];
+} fd_camera;
+
+typedef struct fd_context fd_context;
+typedef struct fd_mlp fd_mlp;
+
+/* Host struct, read during the call only.  Fill it with fd_params_init. */
+typedef struct fd_params {
+  int32_t width, height;   /* map size W, H (>= 1, <= 32768) */
+  int32_t map_dtype;       /* FD_F32 or FD_F16 */
+  int32_t patch;           /* P: odd, 1..FD_MAX_PATCH (Eqs. 9-11) */
+  int32_t n_candidates;    /* hemisphere lattice size, 1..FD_MAX_CANDIDATES */
+  int32_t refine_iters;    /* pattern-search iterations, 0..FD_MAX_REFINE */
+  float refine_step0;      /* first stencil angle (rad); <= 0: 0.5 sqrt(2 pi / n_candidates) */
+  int32_t top_k;           /* K of Eq. (4), 1..FD_MAX_TOPK */
+  float z_near;            /* a view is eligible only if camera-space Z > z_near */
+  int32_t mode;            /* FD_MODE_PLAIN or FD_MODE_LEARNED */
+  const fd_mlp* mlp;       /* network for FD_MODE_LEARNED with FD_PROPOSAL_MLP */
+  int32_t learned_iters;   /* refinement iterations after the proposal */
+  float learned_step0;     /* their first stencil angle (rad) */
+  float fallback_cost;     /* tau: refined cost above tau -> full search */
+  int32_t proposal;        /* FD_PROPOSAL_* */
+  const float* proposal_dirs; /* device N x 3, for FD_PROPOSAL_GIVEN */
+  float head_centre[3];    /* world point the frontal-view ranking is relative to */
+  void* stream;            /* hipStream_t */
+  fd_context* ctx;         /* workspace; NULL = a per-device default that grows */
+} fd_params;
+
+/* Defaults: K = 5 (Sec. 3.1.2, Eq. 4), P = 5 (Sec. 4), 128 candidates,
+ * 8 refinement iterations, z_near = 1e-3, plain mode, FD_F16 maps,
+ * learned_iters = 2. */
+void fd_params_init(fd_params* params);
+
+/* ---- context: library-owned workspace ------------------------------------
+ * create: allocates the small fixed buffers on the current device.
+ * reserve: grows the per-point buffers to max_points points (and the scene
+ * table to max_scenes); it is the only call after create that allocates.
+ * A context is bound to the device current at create and must be used from
+ * one stream at a time.  destroy: frees everything (synchronises the
+ * device). */
+int fd_context_create(fd_context** out);
+int fd_context_reserve(fd_context* ctx, int64_t max_points, int32_t max_views,
+                       int32_t max_scenes);
+void fd_context_destroy(fd_context* ctx);
+
+/* ---- main entry point -----------------------------------------------------
+ * points      device, n_points x 3 float (metres, world frame)
+ * n_points    >= 0 (0: nothing is enqueued)
+ * cams        device, n_views fd_camera
+ * n_views     1..FD_MAX_VIEWS
+ * orient_maps device, n_views x H x W of params->map_dtype (theta)
+ * conf_maps   device, same shape and type (C)
+ * params      host, see fd_params
+ * dirs        device, n_points x 3 float, written
+ * costs       device, n_points float, written
+ * Plain mode: tiling of the points by a spatial key, Eq. (4) view selection,
+ * patch sampling, lattice argmin of J, pattern-search refinement.  Learned
+ * mode: proposal (network or test hook), refinement from it, and the plain
+ * search for every point whose refined cost exceeds params->fallback_cost.
+ * The learned form needs a context (params->ctx or the default one). */
+int fd_fuse_directions(const float* points, int64_t n_points,
+                       const fd_camera* cams, int32_t n_views,
+                       const void* orient_maps, const void* conf_maps,
+                       const fd_params* params, float* dirs, float* costs);
+
+/* Number of points of the last learned call on this context that took the
+ * full search (reads a device counter; synchronises params->stream). */
+int fd_last_fallback_count(fd_context* ctx, void* stream, int64_t* out);
+
+/* ---- many scenes in one launch --------------------------------------------
+ * Every scene has its own points, cameras, maps (own W x H and view count)
+ * and outputs; all use params' search settings and map dtype.  The scenes
+ * array is host memory holding device pointers.  Results equal those of
+ * fd_fuse_directions on each scene alone, bit for bit. */
+typedef struct fd_scene {
+  const float* points;
+  int64_t n_points;
+  const fd_camera* cams;
+  int32_t n_views;
+  int32_t width, height;
+  const void* orient_maps;
+  const void* conf_maps;
+  float* dirs;
+  float* costs;
+  float head_centre[3];
+} fd_scene;
+
+int fd_fuse_directions_batched(const fd_scene* scenes, int32_t n_scenes,
+                               const fd_params* params, fd_context* ctx);
+
+/* ---- learned proposal: 112 -> 256 -> 256 -> 256 -> 3 MLP ------------------
+ * GELU (tanh form) after the three hidden layers, output normalised.
+ * Weights: float master copy (Adam state beside it) and a bfloat16 copy the
+ * matrix-core kernels read; activations bfloat16, accumulation float.
+ * Flat parameter order (161283 floats): W1[112][256], b1[256], W2[256][256],
+ * b2, W3[256][256], b3, W4[256][3], b4[3] with y = x W + b. */
+#define FD_MLP_N_PARAMS 161283
+
+typedef struct fd_adam {
+  float lr, beta1, beta2, eps;
+} fd_adam;
+
+int fd_mlp_create(fd_mlp** out, uint64_t seed);
+int fd_mlp_set_params(fd_mlp* mlp, const float* host_params);
+int fd_mlp_get_params(const fd_mlp* mlp, float* host_params);
+int fd_mlp_set_calibration(fd_mlp* mlp, float learned_step0, float fallback_cost);
+int fd_mlp_get_calibration(const fd_mlp* mlp, float* learned_step0, float* fallback_cost);
+/* Checkpoint: header, float master weights, Adam moments, step count,
+ * calibration.  Little-endian binary file. */
+int fd_mlp_save(const fd_mlp* mlp, const char* path);
+int fd_mlp_load(fd_mlp* mlp, const char* path);
+/* feats: device batch x 112 bfloat16 (raw 16-bit); out: device batch x 3
+ * float unit directions. */
+int fd_mlp_forward(const fd_mlp* mlp, const void* feats, int64_t batch,
+                   float* out, void* stream);
+/* Loss and gradient of the mean axial loss 1 - (y . t)^2 over a batch
+ * (batch <= 65536): grad device FD_MLP_N_PARAMS floats, loss device float. */
+int fd_mlp_loss_grad(fd_mlp* mlp, const void* feats, const float* targets,
+                     int32_t batch, float* grad, float* loss, void* stream);
+/* One Adam step on the loss of the batch; loss (device float) may be NULL. */
+int fd_mlp_train_step(fd_mlp* mlp, const void* feats, const float* targets,
+                      int32_t batch, const fd_adam* opt, float* loss,
+                      void* stream);
+void fd_mlp_destroy(fd_mlp* mlp);
+
+/* Proposal-network input of every point: the FD_FEATURE_SLOTS most frontal
+ * eligible views (largest cosine between the point->camera direction and
+ * p - params->head_centre), each (m_x, m_y, C, v_x, v_y, v_z, valid): the
+ * bilinear confidence-weighted doubled-angle vector, the bilinear
+ * confidence, the unit point->camera direction, 1.  feats: device
+ * n_points x 112 bfloat16. */
+int fd_features(const float* points, int64_t n_points, const fd_camera* cams,
+                int32_t n_views, const void* orient_maps,
+                const void* conf_maps, const fd_params* params, void* feats);
+
+/* ---- tuning ---------------------------------------------------------------
+ * Times the batched launch for each tile shape on the sample scenes and
+ * stores the fastest per shape class in the context (and, if cache_path is
+ * not NULL, in that JSON file, which later contexts read).  Offline: it
+ * synchronises and is not meant for timed regions. */
+int fd_autotune(fd_context* ctx, const fd_scene* sample, int32_t n_scenes,
+                const fd_params* params, const char* cache_path);
+
+const char* fd_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -65,6 +65,7 @@ def lib():
             "fdo_sample": (None, [P, P, i32, i32, i32, dbl, dbl, P]),
             "fdo_objective": (dbl, [P, P, P, i32, P, P, pp]),
             "fdo_objective_many": (i32, [P, P, i64, P, i32, P, P, pp, P, i32]),
+            "fdo_objective_each": (i32, [P, P, i64, P, i32, P, P, pp, P, i32]),
             "fdo_lattice": (None, [i32, P]),
             "fdo_onb": (None, [P, P, P]),
             "fdo_fuse_directions": (i32, [P, i64, P, i32, P, P, pp, P, P, i32]),
@@ -149,6 +150,15 @@ class Oracle:
         dirs = _c(dirs, np.float64).reshape(-1, 3)
         out = np.empty(len(dirs), np.float64)
         lib().fdo_objective_many(_ptr(p), _ptr(dirs), len(dirs), _ptr(self.cams), self.V,
+                                 _ptr(self.theta), _ptr(self.conf), ctypes.byref(self.prm),
+                                 _ptr(out), int(n_threads))
+        return out
+
+    def objective_each(self, points, dirs, n_threads=0):
+        pts = _c(points, np.float32).reshape(-1, 3)
+        d = _c(dirs, np.float64).reshape(-1, 3)
+        out = np.empty(len(pts), np.float64)
+        lib().fdo_objective_each(_ptr(pts), _ptr(d), len(pts), _ptr(self.cams), self.V,
                                  _ptr(self.theta), _ptr(self.conf), ctypes.byref(self.prm),
                                  _ptr(out), int(n_threads))
         return out

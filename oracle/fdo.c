@@ -294,6 +294,28 @@ int fdo_objective_many(const float* p, const double* dirs, int64_t m,
   return 0;
 }
 
+int fdo_objective_each(const float* points, const double* dirs, int64_t n,
+                       const float* cams, int32_t n_views,
+                       const void* theta_maps, const void* conf_maps,
+                       const fdo_params* prm, double* J_out, int32_t n_threads) {
+#ifdef _OPENMP
+  if (n_threads > 0) omp_set_num_threads(n_threads);
+#pragma omp parallel
+#endif
+  {
+    point_state* st = (point_state*)malloc(sizeof(point_state));
+#ifdef _OPENMP
+#pragma omp for schedule(dynamic, 64)
+#endif
+    for (int64_t i = 0; i < n; ++i) {
+      point_setup(points + 3 * i, cams, n_views, theta_maps, conf_maps, prm, st);
+      J_out[i] = objective(st, dirs + 3 * i);
+    }
+    free(st);
+  }
+  return 0;
+}
+
 /* ------------------------------------------------------------------------ */
 /* candidate search                                                          */
 

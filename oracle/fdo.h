@@ -78,6 +78,12 @@ int fdo_objective_many(const float* p, const double* dirs, int64_t m,
                        const void* theta_maps, const void* conf_maps,
                        const fdo_params* prm, double* J_out, int32_t n_threads);
 
+/* J of point i for its own direction dirs[i] (N x 3), i = 0..n-1. */
+int fdo_objective_each(const float* points, const double* dirs, int64_t n,
+                       const float* cams, int32_t n_views,
+                       const void* theta_maps, const void* conf_maps,
+                       const fdo_params* prm, double* J_out, int32_t n_threads);
+
 /* Hemisphere Fibonacci lattice of n unit directions (n x 3). */
 void fdo_lattice(int32_t n, double* dirs);
 

@@ -1,0 +1,322 @@
+// fd_api.hip -- host side of libfusedir.so: argument checks, workspace,
+// launch sequences.  See include/fusedir.h for the contract.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+
+#include "../../include/fusedir.h"
+#include "fd_api_internal.hpp"
+#include "fd_kernels.hpp"
+
+using namespace fd;
+
+// ---- errors -------------------------------------------------------------------
+
+static thread_local std::string g_err;
+
+int fd::set_error(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+int fd::hip_error(hipError_t e, const char* what) {
+  return set_error(FD_E_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+extern "C" const char* fd_last_error(void) { return g_err.c_str(); }
+
+// ---- device check ---------------------------------------------------------------
+
+int fd::check_device(int* dev_out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_error(e, "hipGetDevice");
+  static std::mutex mu;
+  static std::map<int, int> ok;  // device -> 1 gfx950, 0 other
+  std::lock_guard<std::mutex> lk(mu);
+  auto it = ok.find(dev);
+  if (it == ok.end()) {
+    hipDeviceProp_t prop;
+    e = hipGetDeviceProperties(&prop, dev);
+    if (e != hipSuccess) return hip_error(e, "hipGetDeviceProperties");
+    ok[dev] = std::strncmp(prop.gcnArchName, "gfx950", 6) == 0 ? 1 : 0;
+    it = ok.find(dev);
+  }
+  if (!it->second)
+    return set_error(FD_E_UNSUPPORTED, "device %d is not gfx950 (MI355X)", dev);
+  if (dev_out) *dev_out = dev;
+  return FD_OK;
+}
+
+// ---- context ---------------------------------------------------------------------
+
+template <typename T>
+static int grow(T** p, size_t* cap, size_t need, const char* what) {
+  if (*cap >= need && *p) return FD_OK;
+  if (*p) {
+    hipError_t e = hipFree(*p);
+    if (e != hipSuccess) return hip_error(e, what);
+    *p = nullptr;
+    *cap = 0;
+  }
+  size_t n = need > 0 ? need : 1;
+  hipError_t e = hipMalloc((void**)p, n * sizeof(T));
+  if (e != hipSuccess) return set_error(FD_E_HIP, "hipMalloc %s (%zu bytes): %s", what,
+                                        n * sizeof(T), hipGetErrorString(e));
+  *cap = n;
+  return FD_OK;
+}
+
+int fd::context_reserve_points(fd_context* c, int64_t n) {
+  int r;
+  size_t need = (size_t)(n > 0 ? n : 1);
+  if ((r = grow(&c->key, &c->cap_key, need, "tile keys"))) return r;
+  if ((r = grow(&c->perm, &c->cap_perm, need, "permutation"))) return r;
+  if ((r = grow(&c->views, &c->cap_views, need * FD_TOPK_SLOTS, "views"))) return r;
+  if ((r = grow(&c->kcount, &c->cap_kcount, need, "view counts"))) return r;
+  if ((r = grow(&c->fb_list, &c->cap_fb, need, "fallback list"))) return r;
+  if ((r = grow(&c->prop, &c->cap_prop, need * 3, "proposals"))) return r;
+  if ((r = grow(&c->feats, &c->cap_feats, need * FD_FEATURE_DIM, "features"))) return r;
+  c->max_points = std::max<int64_t>(c->max_points, n);
+  return FD_OK;
+}
+
+extern "C" int fd_context_create(fd_context** out) {
+  if (!out) return set_error(FD_E_INVAL, "fd_context_create: out is NULL");
+  int dev, r;
+  if ((r = check_device(&dev))) return r;
+  fd_context* c = new (std::nothrow) fd_context();
+  if (!c) return set_error(FD_E_NOMEM, "fd_context_create: host allocation failed");
+  c->device = dev;
+  size_t cap = 0;
+  if ((r = grow(&c->bbox, &cap, 6, "bbox")) ||
+      (r = grow(&c->counts, &(cap = 0), (size_t)tile_cells(), "cell counts")) ||
+      (r = grow(&c->cursor, &(cap = 0), (size_t)tile_cells(), "cell cursor")) ||
+      (r = grow(&c->lattice, &(cap = 0), (size_t)3 * FD_MAX_CANDIDATES, "lattice")) ||
+      (r = grow(&c->fb_count, &(cap = 0), (size_t)4, "fallback counter"))) {
+    fd_context_destroy(c);
+    return r;
+  }
+  if ((r = context_reserve_points(c, 1))) {
+    fd_context_destroy(c);
+    return r;
+  }
+  *out = c;
+  return FD_OK;
+}
+
+extern "C" int fd_context_reserve(fd_context* c, int64_t max_points, int32_t max_views,
+                                  int32_t max_scenes) {
+  if (!c) return set_error(FD_E_INVAL, "fd_context_reserve: ctx is NULL");
+  if (max_points < 0 || max_views < 0 || max_scenes < 0)
+    return set_error(FD_E_INVAL, "fd_context_reserve: negative size");
+  int r;
+  if ((r = context_reserve_points(c, max_points))) return r;
+  if ((r = context_reserve_scenes(c, max_scenes, max_points))) return r;
+  return FD_OK;
+}
+
+extern "C" void fd_context_destroy(fd_context* c) {
+  if (!c) return;
+  (void)hipDeviceSynchronize();
+  void* bufs[] = {c->bbox, c->counts, c->cursor, c->lattice, c->fb_count, c->key,
+                  c->perm, c->views, c->kcount, c->fb_list, c->prop, c->feats,
+                  c->scene_tab, c->tile_tab, c->tile_queue, c->batch_key, c->batch_perm};
+  for (void* p : bufs)
+    if (p) (void)hipFree(p);
+  if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
+  if (c->graph) (void)hipGraphDestroy(c->graph);
+  delete c;
+}
+
+// Per-device default context, grown on demand (so calls through it may
+// allocate; pass params->ctx for allocation-free calls).
+fd_context* fd::default_context(int dev, int64_t n, int* err) {
+  static std::mutex mu;
+  static std::map<int, fd_context*> ctxs;
+  std::lock_guard<std::mutex> lk(mu);
+  fd_context*& c = ctxs[dev];
+  if (!c) {
+    if ((*err = fd_context_create(&c))) {
+      c = nullptr;
+      return nullptr;
+    }
+  }
+  if (c->max_points < n) {
+    if ((*err = context_reserve_points(c, n))) return nullptr;
+  }
+  *err = FD_OK;
+  return c;
+}
+
+// ---- params ------------------------------------------------------------------------
+
+extern "C" void fd_params_init(fd_params* p) {
+  if (!p) return;
+  std::memset(p, 0, sizeof *p);
+  p->width = p->height = 0;
+  p->map_dtype = FD_F16;
+  p->patch = 5;
+  p->n_candidates = 128;
+  p->refine_iters = 8;
+  p->refine_step0 = 0.0f;
+  p->top_k = 5;
+  p->z_near = 1e-3f;
+  p->mode = FD_MODE_PLAIN;
+  p->mlp = nullptr;
+  p->learned_iters = 2;
+  p->learned_step0 = 0.0f;
+  p->fallback_cost = INFINITY;
+  p->proposal = FD_PROPOSAL_MLP;
+  p->proposal_dirs = nullptr;
+  p->stream = nullptr;
+  p->ctx = nullptr;
+}
+
+int fd::check_search_params(const fd_params* p, const char* fn) {
+  if (!p) return set_error(FD_E_INVAL, "%s: params is NULL", fn);
+  if (p->map_dtype != FD_F32 && p->map_dtype != FD_F16)
+    return set_error(FD_E_INVAL, "%s: unknown map_dtype %d", fn, p->map_dtype);
+  if (p->patch < 1 || p->patch > FD_MAX_PATCH || (p->patch & 1) == 0)
+    return set_error(FD_E_INVAL, "%s: patch must be odd in [1, %d], got %d", fn, FD_MAX_PATCH,
+                     p->patch);
+  if (p->n_candidates < 1 || p->n_candidates > FD_MAX_CANDIDATES)
+    return set_error(FD_E_INVAL, "%s: n_candidates must be in [1, %d], got %d", fn,
+                     FD_MAX_CANDIDATES, p->n_candidates);
+  if (p->refine_iters < 0 || p->refine_iters > FD_MAX_REFINE)
+    return set_error(FD_E_INVAL, "%s: refine_iters must be in [0, %d], got %d", fn,
+                     FD_MAX_REFINE, p->refine_iters);
+  if (p->top_k < 1 || p->top_k > FD_MAX_TOPK)
+    return set_error(FD_E_INVAL, "%s: top_k must be in [1, %d], got %d", fn, FD_MAX_TOPK,
+                     p->top_k);
+  if (!(p->z_near >= 0.0f) || !std::isfinite(p->z_near))
+    return set_error(FD_E_INVAL, "%s: z_near must be finite and >= 0", fn);
+  if (p->mode != FD_MODE_PLAIN && p->mode != FD_MODE_LEARNED)
+    return set_error(FD_E_INVAL, "%s: unknown mode %d", fn, p->mode);
+  if (p->mode == FD_MODE_LEARNED) {
+    if (p->learned_iters < 0 || p->learned_iters > FD_MAX_REFINE)
+      return set_error(FD_E_INVAL, "%s: learned_iters must be in [0, %d]", fn, FD_MAX_REFINE);
+    if (p->proposal == FD_PROPOSAL_MLP && !p->mlp)
+      return set_error(FD_E_INVAL, "%s: learned mode with the network proposal needs mlp", fn);
+    if (p->proposal == FD_PROPOSAL_GIVEN && !p->proposal_dirs)
+      return set_error(FD_E_INVAL, "%s: FD_PROPOSAL_GIVEN needs proposal_dirs", fn);
+    if (p->proposal < FD_PROPOSAL_MLP || p->proposal > FD_PROPOSAL_NAN)
+      return set_error(FD_E_INVAL, "%s: unknown proposal %d", fn, p->proposal);
+  }
+  return FD_OK;
+}
+
+float fd::default_step0(int n_candidates) {
+  return (float)(0.5 * std::sqrt(2.0 * 3.14159265358979323846 / (double)n_candidates));
+}
+
+int fd::ensure_lattice(fd_context* c, int n, hipStream_t st) {
+  if (c->lattice_n == n) return FD_OK;
+  hipError_t e = launch_lattice(c->lattice, n, st);
+  if (e != hipSuccess) return hip_error(e, "lattice kernel");
+  c->lattice_n = n;
+  return FD_OK;
+}
+
+// ---- single scene ---------------------------------------------------------------------
+
+extern "C" int fd_fuse_directions(const float* points, int64_t n_points, const fd_camera* cams,
+                                  int32_t n_views, const void* orient_maps,
+                                  const void* conf_maps, const fd_params* params, float* dirs,
+                                  float* costs) {
+  const char* fn = "fd_fuse_directions";
+  int r;
+  if ((r = check_search_params(params, fn))) return r;
+  if (n_points < 0) return set_error(FD_E_INVAL, "%s: n_points < 0", fn);
+  if (n_points > (int64_t)UINT32_MAX)
+    return set_error(FD_E_INVAL, "%s: n_points exceeds 2^32 - 1", fn);
+  if (n_views < 1 || n_views > FD_MAX_VIEWS)
+    return set_error(FD_E_INVAL, "%s: n_views must be in [1, %d], got %d", fn, FD_MAX_VIEWS,
+                     n_views);
+  if (params->width < 1 || params->height < 1 || params->width > 32768 ||
+      params->height > 32768)
+    return set_error(FD_E_INVAL, "%s: map size %d x %d out of range", fn, params->width,
+                     params->height);
+  if (params->top_k > n_views)
+    return set_error(FD_E_INVAL, "%s: top_k (%d) > n_views (%d)", fn, params->top_k, n_views);
+  if (n_points > 0 && (!points || !cams || !orient_maps || !conf_maps || !dirs || !costs))
+    return set_error(FD_E_INVAL, "%s: null pointer argument", fn);
+  if ((r = check_device(nullptr))) return r;
+  if (n_points == 0) return FD_OK;
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  fd_context* c = params->ctx;
+  if (c) {
+    if (c->device != dev)
+      return set_error(FD_E_INVAL, "%s: context belongs to device %d, current is %d", fn,
+                       c->device, dev);
+    if (c->max_points < n_points)
+      return set_error(FD_E_NOMEM, "%s: context reserved for %lld points, call has %lld", fn,
+                       (long long)c->max_points, (long long)n_points);
+  } else {
+    c = default_context(dev, n_points, &r);
+    if (!c) return r;
+  }
+  SceneArgs sa;
+  sa.points = points;
+  sa.n = n_points;
+  sa.cams = (const float*)cams;
+  sa.V = n_views;
+  sa.W = params->width;
+  sa.H = params->height;
+  sa.theta = orient_maps;
+  sa.conf = conf_maps;
+  sa.dirs = dirs;
+  sa.costs = costs;
+  for (int k = 0; k < 3; ++k) sa.hc[k] = params->head_centre[k];
+  return run_scene(c, sa, params, (hipStream_t)params->stream);
+}
+
+int fd::run_scene(fd_context* c, const SceneArgs& a, const fd_params* p, hipStream_t st) {
+  int r;
+  if ((r = ensure_lattice(c, p->n_candidates, st))) return r;
+  TileWork tw{c->bbox, c->key, c->counts, c->cursor, c->perm};
+  hipError_t e = launch_tiling(a.points, a.n, tw, st);
+  if (e != hipSuccess) return hip_error(e, "tiling kernels");
+  SceneDev s;
+  s.pts = a.points;
+  s.cams = a.cams;
+  s.theta = a.theta;
+  s.conf = a.conf;
+  s.dirs = a.dirs;
+  s.costs = a.costs;
+  s.perm = c->perm;
+  s.views = c->views;
+  s.kcount = c->kcount;
+  s.n = a.n;
+  s.V = a.V;
+  s.W = a.W;
+  s.H = a.H;
+  for (int k = 0; k < 3; ++k) s.hc[k] = a.hc[k];
+  SearchDev q;
+  q.lattice = c->lattice;
+  q.n_candidates = p->n_candidates;
+  q.refine_iters = p->refine_iters;
+  q.step0 = p->refine_step0 > 0.0f ? p->refine_step0 : default_step0(p->n_candidates);
+  q.K = p->top_k;
+  q.z_near = p->z_near;
+  if ((e = launch_topk(s, q, p->map_dtype, st)) != hipSuccess)
+    return hip_error(e, "view selection kernel");
+  if (p->mode == FD_MODE_PLAIN) {
+    if ((e = launch_fuse(s, q, p->map_dtype, p->patch, nullptr, nullptr, st)) != hipSuccess)
+      return hip_error(e, "fusion kernel");
+    return FD_OK;
+  }
+  return run_learned(c, s, q, p, st);
+}

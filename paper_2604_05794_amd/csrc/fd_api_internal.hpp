@@ -1,0 +1,83 @@
+// fd_api_internal.hpp -- host-side state shared by the API sources.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <algorithm>
+
+#include "../../include/fusedir.h"
+#include "fd_kernels.hpp"
+
+struct fd_context {
+  int device = 0;
+  int64_t max_points = 0;
+  // fixed buffers
+  int* bbox = nullptr;
+  uint32_t* counts = nullptr;
+  uint32_t* cursor = nullptr;
+  float* lattice = nullptr;
+  int lattice_n = -1;
+  uint32_t* fb_count = nullptr;
+  // per-point buffers
+  uint32_t* key = nullptr;
+  size_t cap_key = 0;
+  uint32_t* perm = nullptr;
+  size_t cap_perm = 0;
+  uint16_t* views = nullptr;
+  size_t cap_views = 0;
+  uint8_t* kcount = nullptr;
+  size_t cap_kcount = 0;
+  uint32_t* fb_list = nullptr;
+  size_t cap_fb = 0;
+  float* prop = nullptr;
+  size_t cap_prop = 0;
+  uint16_t* feats = nullptr;
+  size_t cap_feats = 0;
+  // batched launch
+  int32_t max_scenes = 0;
+  void* scene_tab = nullptr;
+  size_t cap_scene_tab = 0;
+  void* tile_tab = nullptr;
+  size_t cap_tile_tab = 0;
+  uint32_t* tile_queue = nullptr;
+  size_t cap_tile_queue = 0;
+  uint32_t* batch_key = nullptr;
+  size_t cap_batch_key = 0;
+  uint32_t* batch_perm = nullptr;
+  size_t cap_batch_perm = 0;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t graph_exec = nullptr;
+  uint64_t graph_sig = 0;
+  // tuned tile shapes: waves per workgroup for the batched kernel
+  int tuned_wpb = 0;
+};
+
+namespace fd {
+
+struct SceneArgs {
+  const float* points;
+  int64_t n;
+  const float* cams;
+  int V, W, H;
+  const void* theta;
+  const void* conf;
+  float* dirs;
+  float* costs;
+  float hc[3];
+};
+
+int set_error(int code, const char* fmt, ...);
+int hip_error(hipError_t e, const char* what);
+int check_device(int* dev_out);
+int check_search_params(const fd_params* p, const char* fn);
+float default_step0(int n_candidates);
+int context_reserve_points(fd_context* c, int64_t n);
+int context_reserve_scenes(fd_context* c, int32_t n_scenes, int64_t total_points);
+fd_context* default_context(int dev, int64_t n, int* err);
+int ensure_lattice(fd_context* c, int n, hipStream_t st);
+int run_scene(fd_context* c, const SceneArgs& a, const fd_params* p, hipStream_t st);
+int run_learned(fd_context* c, const SceneDev& s, const SearchDev& q, const fd_params* p,
+                hipStream_t st);
+
+}  // namespace fd

@@ -1,0 +1,88 @@
+// fd_device.hpp -- device helpers shared by the gfx950 kernels of libfusedir.
+//
+// Camera records are 16 floats: fx, fy, cx, cy, R[9] (row-major), t[3].
+// Maps are V x H x W of float or binary16.
+#pragma once
+
+#include <hip/hip_fp16.h>
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace fd {
+
+constexpr int kWave = 64;
+
+// Texel of one map as float; outside the image reads 0 (zero border).
+template <typename T>
+__device__ __forceinline__ float tex_load(const T* __restrict__ m, int W, int H,
+                                          int x, int y);
+
+template <>
+__device__ __forceinline__ float tex_load<float>(const float* __restrict__ m,
+                                                 int W, int H, int x, int y) {
+  if ((unsigned)x >= (unsigned)W || (unsigned)y >= (unsigned)H) return 0.0f;
+  return m[(size_t)y * W + x];
+}
+
+template <>
+__device__ __forceinline__ float tex_load<__half>(const __half* __restrict__ m,
+                                                  int W, int H, int x, int y) {
+  if ((unsigned)x >= (unsigned)W || (unsigned)y >= (unsigned)H) return 0.0f;
+  return __half2float(m[(size_t)y * W + x]);
+}
+
+// Projection and eligibility, in binary32 with the fixed operation order
+// every implementation of the method shares (view selection is a discrete
+// decision and must come out the same everywhere):
+//   X = fma(R0, px, fma(R1, py, fma(R2, pz, t0)))  (likewise Y, Z)
+//   front: Z > z_near;  u = fma(fx, X / Z, cx), v = fma(fy, Y / Z, cy)
+//   inside: 0 <= u <= W-1 and 0 <= v <= H-1
+// Division is IEEE (the library is built without fast-math).
+struct Proj {
+  float X, Y, Z, u, v;
+};
+
+__device__ __forceinline__ bool project32(const float* __restrict__ cam,
+                                          float px, float py, float pz, int W,
+                                          int H, float z_near, Proj& o) {
+  const float* R = cam + 4;
+  const float* t = cam + 13;
+  o.X = __builtin_fmaf(R[0], px, __builtin_fmaf(R[1], py, __builtin_fmaf(R[2], pz, t[0])));
+  o.Y = __builtin_fmaf(R[3], px, __builtin_fmaf(R[4], py, __builtin_fmaf(R[5], pz, t[1])));
+  o.Z = __builtin_fmaf(R[6], px, __builtin_fmaf(R[7], py, __builtin_fmaf(R[8], pz, t[2])));
+  if (!(o.Z > z_near)) return false;
+  o.u = __builtin_fmaf(cam[0], o.X / o.Z, cam[2]);
+  o.v = __builtin_fmaf(cam[1], o.Y / o.Z, cam[3]);
+  return o.u >= 0.0f && o.u <= (float)(W - 1) && o.v >= 0.0f &&
+         o.v <= (float)(H - 1);
+}
+
+// Bilinear confidence at the projection, same fixed order:
+//   x0 = floor(u), fx = u - x0, gx = 1 - fx (likewise y)
+//   w00 = gx*gy, w10 = fx*gy, w01 = gx*fy, w11 = fx*fy
+//   C = fma(w11, C11, fma(w01, C01, fma(w10, C10, w00*C00)))
+template <typename T>
+__device__ __forceinline__ float centre_conf32(const T* __restrict__ cm, int W,
+                                               int H, float u, float v) {
+  float x0 = floorf(u), y0 = floorf(v);
+  float fx = u - x0, fy = v - y0;
+  float gx = 1.0f - fx, gy = 1.0f - fy;
+  int ix = (int)x0, iy = (int)y0;
+  float c00 = tex_load<T>(cm, W, H, ix, iy);
+  float c10 = tex_load<T>(cm, W, H, ix + 1, iy);
+  float c01 = tex_load<T>(cm, W, H, ix, iy + 1);
+  float c11 = tex_load<T>(cm, W, H, ix + 1, iy + 1);
+  float w00 = gx * gy, w10 = fx * gy, w01 = gx * fy, w11 = fx * fy;
+  return __builtin_fmaf(w11, c11, __builtin_fmaf(w01, c01, __builtin_fmaf(w10, c10, w00 * c00)));
+}
+
+// Lanes of a wave are split into groups of `k` consecutive lanes; returns the
+// sum of v over the caller's group, added in lane order (slot 0 first) so
+// every lane of the group gets the same bits.
+__device__ __forceinline__ float group_sum(float v, int group_base, int k) {
+  float s = __shfl(v, group_base, kWave);
+  for (int j = 1; j < k; ++j) s += __shfl(v, group_base + j, kWave);
+  return s;
+}
+
+}  // namespace fd

@@ -1,0 +1,372 @@
+// fd_fuse.hip -- direction fusion kernels for gfx950.
+//
+// EfficientMonoHair, Sec. 3.1.  Per point: the K most confident eligible
+// views (Eq. 4), a P x P patch of bilinear doubled-angle samples around the
+// projection in each of them, and the objective
+//   J(d) = 1 - (1/K_eff) sum_v max_p C_p |cos(phi_v(d) - theta_p)|
+// (Eqs. 8-11: phi_v(d) is the image angle of the tangent d, the maximum runs
+// over the patch, the views are averaged), minimised over a hemisphere
+// Fibonacci lattice (Eq. 12) and refined by a six-direction pattern search.
+//
+// Mapping onto the hardware.  A wavefront fuses floor(64 / K) points; the K
+// lanes of a point each own one selected view and keep that view's patch in
+// registers as quadratic-form coefficients
+//   (a, b, c) = C^2/2 * (1, cos 2theta, sin 2theta),
+// so that for an image direction r with n2 = |r|^2,
+//   C^2 cos^2(phi - theta) = a + b (rx^2 - ry^2)/n2 + c (2 rx ry)/n2,
+// and the patch maximum costs two FMAs and half a max3 per sample.  The view
+// sum of a candidate is a fixed-order shuffle sum over the point's K lanes,
+// so all K lanes hold bit-identical J and take the same argmin decisions
+// without any synchronisation.  Candidates are wave-uniform (scalar loads).
+#include <hip/hip_fp16.h>
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+#include "fd_device.hpp"
+#include "fd_kernels.hpp"
+
+namespace fd {
+
+constexpr float kInvPi = 0.318309886183790671538f;
+
+// ---- candidate lattice ------------------------------------------------------
+// Hemisphere Fibonacci lattice (Gonzalez 2010): z_k = 1 - (k + 1/2)/n,
+// psi_k = k pi (3 - sqrt 5); evaluated in double, stored as float.
+__global__ void k_lattice(float* __restrict__ out, int n) {
+  int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  const double golden = 3.14159265358979323846 * (3.0 - sqrt(5.0));
+  double z = 1.0 - ((double)k + 0.5) / (double)n;
+  double rho = sqrt(fmax(0.0, 1.0 - z * z));
+  double psi = golden * (double)k;
+  out[3 * k] = (float)(rho * cos(psi));
+  out[3 * k + 1] = (float)(rho * sin(psi));
+  out[3 * k + 2] = (float)z;
+}
+
+hipError_t launch_lattice(float* lattice, int n, hipStream_t st) {
+  hipLaunchKernelGGL(k_lattice, dim3((n + 255) / 256), dim3(256), 0, st, lattice, n);
+  return hipGetLastError();
+}
+
+// ---- Eq. (4): top-K views by centre confidence ------------------------------
+// One lane per point (processing order).  Stable insertion into a register
+// list of 8: a view enters ahead of a listed one only if strictly more
+// confident, so equal confidences keep the lower view index first.
+template <typename T>
+__global__ __launch_bounds__(256) void k_topk(SceneDev s, SearchDev q) {
+  int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= s.n) return;
+  const uint32_t i = s.perm[j];
+  const float px = s.pts[3 * (size_t)i], py = s.pts[3 * (size_t)i + 1],
+              pz = s.pts[3 * (size_t)i + 2];
+  float sc[FD_TOPK_SLOTS];
+  int id[FD_TOPK_SLOTS];
+#pragma unroll
+  for (int k = 0; k < FD_TOPK_SLOTS; ++k) {
+    sc[k] = -1.0f;
+    id[k] = 0;
+  }
+  const T* conf = (const T*)s.conf;
+  const size_t plane = (size_t)s.W * s.H;
+  for (int v = 0; v < s.V; ++v) {
+    Proj pr;
+    if (!project32(s.cams + 16 * v, px, py, pz, s.W, s.H, q.z_near, pr)) continue;
+    float c = centre_conf32<T>(conf + plane * v, s.W, s.H, pr.u, pr.v);
+    if (!(c > 0.0f)) continue;
+    float cs = c;
+    int cv = v;
+    bool ins = false;
+#pragma unroll
+    for (int k = 0; k < FD_TOPK_SLOTS; ++k) {
+      bool take = ins || (cs > sc[k]);
+      float ts = sc[k];
+      int tv = id[k];
+      sc[k] = take ? cs : ts;
+      id[k] = take ? cv : tv;
+      cs = take ? ts : cs;
+      cv = take ? tv : cv;
+      ins = take;
+    }
+  }
+  int keff = 0;
+#pragma unroll
+  for (int k = 0; k < FD_TOPK_SLOTS; ++k) {
+    if (k < q.K && sc[k] > 0.0f) keff = k + 1;
+    s.views[FD_TOPK_SLOTS * j + k] = (uint16_t)id[k];
+  }
+  s.kcount[j] = (uint8_t)keff;
+}
+
+hipError_t launch_topk(const SceneDev& s, const SearchDev& q, int dtype, hipStream_t st) {
+  if (s.n <= 0) return hipSuccess;
+  dim3 grid((unsigned)((s.n + 255) / 256));
+  if (dtype == 1)
+    hipLaunchKernelGGL(k_topk<__half>, grid, dim3(256), 0, st, s, q);
+  else
+    hipLaunchKernelGGL(k_topk<float>, grid, dim3(256), 0, st, s, q);
+  return hipGetLastError();
+}
+
+// ---- per-lane view state ------------------------------------------------------
+
+template <int P>
+struct ViewPatch {
+  static constexpr int P2 = P * P;
+  float a[P2], b[P2], c[P2];  // quadratic-form coefficients per patch sample
+  float M[6];                  // image direction r = M d (rows of the projection Jacobian)
+};
+
+// Build the lane's view state: Jacobian rows and the P x P patch of Sec. 3.1.3
+// centred on the projection (offsets (a, b) in {-h..h}^2 pixels from the
+// sub-pixel centre, each a bilinear sample of the doubled-angle vector
+// weighted by bilinear weight times confidence, zero outside the image).
+template <typename T, int P>
+__device__ __forceinline__ void build_patch(const SceneDev& s, const SearchDev& q, int view,
+                                            bool active, float px, float py, float pz,
+                                            ViewPatch<P>& vp) {
+  constexpr int P2 = P * P, HP = (P - 1) / 2;
+#pragma unroll
+  for (int k = 0; k < P2; ++k) vp.a[k] = vp.b[k] = vp.c[k] = 0.0f;
+#pragma unroll
+  for (int k = 0; k < 6; ++k) vp.M[k] = 0.0f;
+  if (!active) return;
+  const float* cam = s.cams + 16 * view;
+  Proj pr;
+  project32(cam, px, py, pz, s.W, s.H, q.z_near, pr);
+  // r = J_pi d up to the positive factor 1/Z^2:
+  //   r_x = fx (Z (R0 . d) - X (R2 . d)),  r_y = fy (Z (R1 . d) - Y (R2 . d))
+  const float* R = cam + 4;
+  vp.M[0] = cam[0] * (pr.Z * R[0] - pr.X * R[6]);
+  vp.M[1] = cam[0] * (pr.Z * R[1] - pr.X * R[7]);
+  vp.M[2] = cam[0] * (pr.Z * R[2] - pr.X * R[8]);
+  vp.M[3] = cam[1] * (pr.Z * R[3] - pr.Y * R[6]);
+  vp.M[4] = cam[1] * (pr.Z * R[4] - pr.Y * R[7]);
+  vp.M[5] = cam[1] * (pr.Z * R[5] - pr.Y * R[8]);
+
+  const size_t plane = (size_t)s.W * s.H;
+  const T* th = (const T*)s.theta + plane * view;
+  const T* cf = (const T*)s.conf + plane * view;
+  const float x0 = floorf(pr.u), y0 = floorf(pr.v);
+  const float fx = pr.u - x0, fy = pr.v - y0;
+  const float gx = 1.0f - fx, gy = 1.0f - fy;
+  const float w00 = gx * gy, w10 = fx * gy, w01 = gx * fy, w11 = fx * fy;
+  const int ix = (int)x0 - HP, iy = (int)y0 - HP;
+  // texel rows of the (P+1)^2 footprint: C, C cos 2theta, C sin 2theta
+  float rc[2][P + 1], rx[2][P + 1], ry[2][P + 1];
+  auto load_row = [&](int slot, int y) {
+#pragma unroll
+    for (int a = 0; a <= P; ++a) {
+      float t = tex_load<T>(th, s.W, s.H, ix + a, y);
+      float c = tex_load<T>(cf, s.W, s.H, ix + a, y);
+      float turns = t * kInvPi;  // 2 theta in revolutions
+      rc[slot][a] = c;
+      rx[slot][a] = c * __builtin_amdgcn_cosf(turns);
+      ry[slot][a] = c * __builtin_amdgcn_sinf(turns);
+    }
+  };
+  load_row(0, iy);
+#pragma unroll
+  for (int b = 0; b < P; ++b) {
+    const int r0 = b & 1, r1 = (b + 1) & 1;
+    load_row(r1, iy + b + 1);
+#pragma unroll
+    for (int a = 0; a < P; ++a) {
+      float cb = w00 * rc[r0][a] + w10 * rc[r0][a + 1] + w01 * rc[r1][a] + w11 * rc[r1][a + 1];
+      float mx = w00 * rx[r0][a] + w10 * rx[r0][a + 1] + w01 * rx[r1][a] + w11 * rx[r1][a + 1];
+      float my = w00 * ry[r0][a] + w10 * ry[r0][a + 1] + w01 * ry[r1][a] + w11 * ry[r1][a + 1];
+      float n2 = mx * mx + my * my;
+      float al = 0.5f * cb * cb;
+      float inv = n2 > 0.0f ? __builtin_amdgcn_rsqf(n2) : 0.0f;
+      const int k = b * P + a;
+      vp.a[k] = n2 > 0.0f ? al : 0.0f;
+      vp.b[k] = al * mx * inv;
+      vp.c[k] = al * my * inv;
+    }
+  }
+}
+
+// max_p C_p |cos(phi(d) - theta_p)| for this lane's view (0 if the tangent
+// projects to a point or the lane has no view).
+template <int P>
+__device__ __forceinline__ float eval_view(const ViewPatch<P>& vp, float dx, float dy,
+                                           float dz) {
+  constexpr int P2 = P * P;
+  float rx = __builtin_fmaf(vp.M[0], dx, __builtin_fmaf(vp.M[1], dy, vp.M[2] * dz));
+  float ry = __builtin_fmaf(vp.M[3], dx, __builtin_fmaf(vp.M[4], dy, vp.M[5] * dz));
+  float xx = rx * rx, yy = ry * ry;
+  float n2 = xx + yy;
+  float inv = n2 > 0.0f ? __builtin_amdgcn_rcpf(n2) : 0.0f;
+  float c2 = (xx - yy) * inv;
+  float s2 = 2.0f * rx * ry * inv;
+  float m = 0.0f;
+#pragma unroll
+  for (int k = 0; k + 1 < P2; k += 2) {
+    float q0 = __builtin_fmaf(vp.b[k], c2, __builtin_fmaf(vp.c[k], s2, vp.a[k]));
+    float q1 = __builtin_fmaf(vp.b[k + 1], c2, __builtin_fmaf(vp.c[k + 1], s2, vp.a[k + 1]));
+    m = __builtin_fmaxf(m, __builtin_fmaxf(q0, q1));
+  }
+  if (P2 & 1) {
+    float q0 = __builtin_fmaf(vp.b[P2 - 1], c2, __builtin_fmaf(vp.c[P2 - 1], s2, vp.a[P2 - 1]));
+    m = __builtin_fmaxf(m, q0);
+  }
+  return n2 > 0.0f ? __builtin_amdgcn_sqrtf(m) : 0.0f;
+}
+
+struct Group {
+  int K, G, g, slot, base;
+  bool lane_ok;
+};
+
+__device__ __forceinline__ Group make_group(int K) {
+  Group gr;
+  const int lane = threadIdx.x & (kWave - 1);
+  gr.K = K;
+  gr.G = kWave / K;
+  gr.g = lane / K;
+  gr.slot = lane - gr.g * K;
+  gr.lane_ok = gr.g < gr.G;
+  gr.base = (gr.lane_ok ? gr.g : gr.G - 1) * K;
+  return gr;
+}
+
+// Pattern search (six directions at angle alpha around d in the basis of
+// Duff et al. 2017, best strictly-better one taken, alpha halves).
+template <int P>
+__device__ __forceinline__ void refine(const ViewPatch<P>& vp, const Group& gr, float kinv,
+                                       int iters, float alpha, float& dx, float& dy, float& dz,
+                                       float& Jd) {
+  const float cj[6] = {1.0f, 0.5f, -0.5f, -1.0f, -0.5f, 0.5f};
+  const float sj[6] = {0.0f, 0.86602540378443865f, 0.86602540378443865f, 0.0f,
+                       -0.86602540378443865f, -0.86602540378443865f};
+  for (int t = 0; t < iters; ++t) {
+    const float sg = copysignf(1.0f, dz);
+    const float aa = -1.0f / (sg + dz);
+    const float bb = dx * dy * aa;
+    const float e1x = 1.0f + sg * dx * dx * aa, e1y = sg * bb, e1z = -sg * dx;
+    const float e2x = bb, e2y = sg + dy * dy * aa, e2z = -dy;
+    const float ca = cosf(alpha), sa = sinf(alpha);
+    float bJ = INFINITY, bx = dx, by = dy, bz = dz;
+#pragma unroll
+    for (int j = 0; j < 6; ++j) {
+      float ux = ca * dx + sa * (cj[j] * e1x + sj[j] * e2x);
+      float uy = ca * dy + sa * (cj[j] * e1y + sj[j] * e2y);
+      float uz = ca * dz + sa * (cj[j] * e1z + sj[j] * e2z);
+      float il = 1.0f / sqrtf(ux * ux + uy * uy + uz * uz);
+      ux *= il;
+      uy *= il;
+      uz *= il;
+      float L = eval_view<P>(vp, ux, uy, uz);
+      float J = 1.0f - group_sum(L, gr.base, gr.K) * kinv;
+      if (J < bJ) {
+        bJ = J;
+        bx = ux;
+        by = uy;
+        bz = uz;
+      }
+    }
+    if (bJ < Jd) {
+      Jd = bJ;
+      dx = bx;
+      dy = by;
+      dz = bz;
+    }
+    alpha *= 0.5f;
+  }
+}
+
+__device__ __forceinline__ void write_result(const SceneDev& s, uint32_t i, float dx, float dy,
+                                             float dz, float J) {
+  const bool flip = dz != 0.0f ? dz < 0.0f : (dy != 0.0f ? dy < 0.0f : dx < 0.0f);
+  const float sgn = flip ? -1.0f : 1.0f;
+  s.dirs[3 * (size_t)i] = sgn * dx;
+  s.dirs[3 * (size_t)i + 1] = sgn * dy;
+  s.dirs[3 * (size_t)i + 2] = sgn * dz;
+  s.costs[i] = J;
+}
+
+// Wave index with blocks of one XCD covering a contiguous range of tiles:
+// the dispatcher deals workgroups to the 8 XCDs round-robin, so remap
+// blockIdx so that neighbouring (spatially sorted) tiles share an L2.
+__device__ __forceinline__ int64_t xcd_tile(int64_t nblocks) {
+  const int64_t b = blockIdx.x;
+  const int64_t per = nblocks / 8, rem = nblocks % 8;
+  const int64_t xcd = b % 8, k = b / 8;
+  // XCD x owns logical blocks [start(x), start(x) + per + (x < rem))
+  const int64_t start = xcd * per + (xcd < rem ? xcd : rem);
+  return start + k;
+}
+
+// ---- plain search: lattice argmin + refinement ---------------------------------
+// `list` (optional): processing-order indices to fuse, *list_count of them
+// (read on the device; the grid is sized for the worst case).
+template <typename T, int P>
+__global__ __launch_bounds__(256) void k_fuse(SceneDev s, SearchDev q, const uint32_t* list,
+                                              const uint32_t* list_count) {
+  const Group gr = make_group(q.K);
+  const int64_t blk = xcd_tile(gridDim.x);
+  const int64_t wave = blk * (blockDim.x / kWave) + (threadIdx.x / kWave);
+  const int64_t t = wave * gr.G + gr.g;
+  const int64_t limit = list ? (int64_t)*list_count : s.n;
+  if (wave * gr.G >= limit) return;  // whole wave idle (uniform exit)
+  const bool pt_ok = gr.lane_ok && t < limit;
+  const int64_t j = pt_ok ? (list ? (int64_t)list[t] : t) : 0;
+  const uint32_t i = pt_ok ? s.perm[j] : 0u;
+  const int keff = pt_ok ? (int)s.kcount[j] : 0;
+  const bool slot_ok = pt_ok && gr.slot < keff;
+  const int view = slot_ok ? (int)s.views[FD_TOPK_SLOTS * j + gr.slot] : 0;
+  const float px = s.pts[3 * (size_t)i], py = s.pts[3 * (size_t)i + 1],
+              pz = s.pts[3 * (size_t)i + 2];
+  ViewPatch<P> vp;
+  build_patch<T, P>(s, q, view, slot_ok, px, py, pz, vp);
+  const float kinv = keff > 0 ? 1.0f / (float)keff : 0.0f;
+
+  float Jb = INFINITY;
+  int kb = 0;
+  for (int k = 0; k < q.n_candidates; ++k) {
+    const float dx = q.lattice[3 * k], dy = q.lattice[3 * k + 1], dz = q.lattice[3 * k + 2];
+    float L = eval_view<P>(vp, dx, dy, dz);
+    float J = 1.0f - group_sum(L, gr.base, gr.K) * kinv;
+    if (J < Jb) {
+      Jb = J;
+      kb = k;
+    }
+  }
+  float dx = q.lattice[3 * kb], dy = q.lattice[3 * kb + 1], dz = q.lattice[3 * kb + 2];
+  refine<P>(vp, gr, kinv, q.refine_iters, q.step0, dx, dy, dz, Jb);
+  if (pt_ok && gr.slot == 0) {
+    if (keff == 0)
+      write_result(s, i, 0.0f, 0.0f, 0.0f, INFINITY);
+    else
+      write_result(s, i, dx, dy, dz, Jb);
+  }
+}
+
+template <typename T>
+static hipError_t launch_fuse_t(const SceneDev& s, const SearchDev& q, int patch,
+                                const uint32_t* list, const uint32_t* list_count,
+                                hipStream_t st) {
+  const int G = kWave / q.K;
+  const int64_t pts_per_block = 4 * (int64_t)G;
+  const int64_t nb = (s.n + pts_per_block - 1) / pts_per_block;
+  if (nb <= 0) return hipSuccess;
+  dim3 grid((unsigned)nb), block(256);
+  switch (patch) {
+    case 1: hipLaunchKernelGGL((k_fuse<T, 1>), grid, block, 0, st, s, q, list, list_count); break;
+    case 3: hipLaunchKernelGGL((k_fuse<T, 3>), grid, block, 0, st, s, q, list, list_count); break;
+    case 5: hipLaunchKernelGGL((k_fuse<T, 5>), grid, block, 0, st, s, q, list, list_count); break;
+    case 7: hipLaunchKernelGGL((k_fuse<T, 7>), grid, block, 0, st, s, q, list, list_count); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_fuse(const SceneDev& s, const SearchDev& q, int dtype, int patch,
+                       const uint32_t* list, const uint32_t* list_count, hipStream_t st) {
+  if (s.n <= 0) return hipSuccess;
+  return dtype == 1 ? launch_fuse_t<__half>(s, q, patch, list, list_count, st)
+                    : launch_fuse_t<float>(s, q, patch, list, list_count, st);
+}
+
+}  // namespace fd

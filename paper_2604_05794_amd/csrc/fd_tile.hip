@@ -1,0 +1,178 @@
+// fd_tile.hip -- spatial tiling of the points (gfx950).
+//
+// Points are grouped by a Morton-ordered cell of a 64^3 grid over their
+// bounding box, so that the points one wavefront fuses together project to
+// neighbouring pixels and their patch gathers share cache lines.  Cell order
+// is a counting sort (histogram, exclusive scan, scatter).  The order of
+// points inside one cell depends on atomic timing; nothing downstream
+// depends on it, because every point is fused independently of the others.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "fd_kernels.hpp"
+
+namespace fd {
+
+constexpr int kCellBits = 6;  // per axis
+constexpr int kCells = 1 << (3 * kCellBits);
+
+__device__ __forceinline__ int float_to_ordered(float f) {
+  int i = __float_as_int(f);
+  return i >= 0 ? i : i ^ 0x7fffffff;
+}
+__device__ __forceinline__ float ordered_to_float(int i) {
+  return __int_as_float(i >= 0 ? i : i ^ 0x7fffffff);
+}
+
+__global__ void k_fill_u32(uint32_t* __restrict__ p, int64_t n, uint32_t v) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (; i < n; i += stride) p[i] = v;
+}
+
+// bbox[0..2] = ordered min, bbox[3..5] = ordered max (pre-filled by the host
+// path with INT_MAX / INT_MIN through k_fill_u32).
+__global__ __launch_bounds__(256) void k_bbox(const float* __restrict__ pts,
+                                              int64_t n, int* __restrict__ bbox) {
+  int mn[3] = {INT32_MAX, INT32_MAX, INT32_MAX};
+  int mx[3] = {INT32_MIN, INT32_MIN, INT32_MIN};
+  int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+    for (int a = 0; a < 3; ++a) {
+      float f = pts[3 * i + a];
+      if (f == f) {  // skip NaN
+        int o = float_to_ordered(f);
+        mn[a] = min(mn[a], o);
+        mx[a] = max(mx[a], o);
+      }
+    }
+  }
+  for (int a = 0; a < 3; ++a) {
+    for (int off = 32; off > 0; off >>= 1) {
+      mn[a] = min(mn[a], __shfl_xor(mn[a], off, 64));
+      mx[a] = max(mx[a], __shfl_xor(mx[a], off, 64));
+    }
+  }
+  if ((threadIdx.x & 63) == 0) {
+    for (int a = 0; a < 3; ++a) {
+      atomicMin(&bbox[a], mn[a]);
+      atomicMax(&bbox[3 + a], mx[a]);
+    }
+  }
+}
+
+__device__ __forceinline__ uint32_t spread3(uint32_t x) {
+  // 6-bit x -> bits at positions 0, 3, 6, ...
+  uint32_t r = 0;
+  for (int b = 0; b < kCellBits; ++b) r |= ((x >> b) & 1u) << (3 * b);
+  return r;
+}
+
+__global__ __launch_bounds__(256) void k_cell_count(const float* __restrict__ pts,
+                                                    int64_t n, const int* __restrict__ bbox,
+                                                    uint32_t* __restrict__ key,
+                                                    uint32_t* __restrict__ counts) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  uint32_t q[3];
+  for (int a = 0; a < 3; ++a) {
+    float lo = ordered_to_float(bbox[a]), hi = ordered_to_float(bbox[3 + a]);
+    float f = pts[3 * i + a];
+    float ext = hi - lo;
+    float s = ext > 0.0f ? (f - lo) / ext : 0.0f;
+    int c = (int)(s * (float)(1 << kCellBits));
+    c = (f == f) ? c : 0;
+    q[a] = (uint32_t)min(max(c, 0), (1 << kCellBits) - 1);
+  }
+  uint32_t k = spread3(q[0]) | (spread3(q[1]) << 1) | (spread3(q[2]) << 2);
+  key[i] = k;
+  atomicAdd(&counts[k], 1u);
+}
+
+// Exclusive scan of kCells counts by one workgroup of 1024 threads; writes
+// the cell start offsets into `cursor` (the scatter advances them).
+__global__ __launch_bounds__(1024) void k_cell_scan(const uint32_t* __restrict__ counts,
+                                                    uint32_t* __restrict__ cursor) {
+  constexpr int per = kCells / 1024;
+  __shared__ uint32_t wsum[16];
+  const int t = threadIdx.x;
+  uint32_t local = 0;
+  for (int j = 0; j < per; ++j) local += counts[t * per + j];
+  // inclusive scan of `local` across the block
+  uint32_t v = local;
+  const int lane = t & 63, w = t >> 6;
+  for (int off = 1; off < 64; off <<= 1) {
+    uint32_t o = __shfl_up(v, off, 64);
+    if (lane >= off) v += o;
+  }
+  if (lane == 63) wsum[w] = v;
+  __syncthreads();
+  if (w == 0) {
+    uint32_t s = lane < 16 ? wsum[lane] : 0u;
+    for (int off = 1; off < 16; off <<= 1) {
+      uint32_t o = __shfl_up(s, off, 64);
+      if (lane >= off) s += o;
+    }
+    if (lane < 16) wsum[lane] = s;
+  }
+  __syncthreads();
+  uint32_t base = v - local + (w > 0 ? wsum[w - 1] : 0u);
+  for (int j = 0; j < per; ++j) {
+    cursor[t * per + j] = base;
+    base += counts[t * per + j];
+  }
+}
+
+__global__ __launch_bounds__(256) void k_cell_scatter(const uint32_t* __restrict__ key,
+                                                      int64_t n,
+                                                      uint32_t* __restrict__ cursor,
+                                                      uint32_t* __restrict__ perm) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  uint32_t pos = atomicAdd(&cursor[key[i]], 1u);
+  perm[pos] = (uint32_t)i;
+}
+
+__global__ void k_iota(uint32_t* __restrict__ perm, int64_t n) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) perm[i] = (uint32_t)i;
+}
+
+hipError_t launch_tiling(const float* pts, int64_t n, TileWork w, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  const int bs = 256;
+  const int64_t nb = (n + bs - 1) / bs;
+  // bbox <- (INT_MAX x3, INT_MIN x3), counts <- 0, through fill kernels so
+  // the sequence stays valid under stream capture
+  hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, st, (uint32_t*)w.bbox, (int64_t)3,
+                     (uint32_t)INT32_MAX);
+  hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, st, (uint32_t*)(w.bbox + 3),
+                     (int64_t)3, (uint32_t)INT32_MIN);
+  hipLaunchKernelGGL(k_fill_u32, dim3(256), dim3(256), 0, st, w.counts, (int64_t)kCells, 0u);
+  int gb = (int)(nb < 1024 ? nb : 1024);
+  hipLaunchKernelGGL(k_bbox, dim3(gb), dim3(bs), 0, st, pts, n, w.bbox);
+  hipLaunchKernelGGL(k_cell_count, dim3((unsigned)nb), dim3(bs), 0, st, pts, n, w.bbox,
+                     w.key, w.counts);
+  hipLaunchKernelGGL(k_cell_scan, dim3(1), dim3(1024), 0, st, w.counts, w.cursor);
+  hipLaunchKernelGGL(k_cell_scatter, dim3((unsigned)nb), dim3(bs), 0, st, w.key, n, w.cursor,
+                     w.perm);
+  return hipGetLastError();
+}
+
+hipError_t launch_identity_perm(int64_t n, uint32_t* perm, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_iota, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, perm, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_u32(uint32_t* p, int64_t n, uint32_t v, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  int64_t nb = (n + 255) / 256;
+  hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)(nb < 4096 ? nb : 4096)), dim3(256), 0, st, p,
+                     n, v);
+  return hipGetLastError();
+}
+
+int tile_cells() { return kCells; }
+
+}  // namespace fd

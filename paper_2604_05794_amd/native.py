@@ -1,0 +1,244 @@
+"""ctypes binding of libfusedir.so (include/fusedir.h).
+
+Argument marshalling only: every step of the fusion runs in the library's HIP
+kernels.  Tensors are torch CUDA (ROCm) tensors; torch provides device memory
+and streams.  If the library is missing or fails to load, every call raises:
+there is no other implementation behind these names.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+from typing import Optional, Sequence
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libfusedir.so")
+
+FD_OK, FD_E_INVAL, FD_E_UNSUPPORTED, FD_E_HIP, FD_E_NOMEM = range(5)
+FD_F32, FD_F16 = 0, 1
+FD_MODE_PLAIN, FD_MODE_LEARNED = 0, 1
+FD_PROPOSAL_MLP, FD_PROPOSAL_GIVEN, FD_PROPOSAL_NAN = 0, 1, 2
+FD_MLP_N_PARAMS = 161283
+FD_FEATURE_DIM = 112
+
+EXPORTS = (
+    "fd_params_init", "fd_context_create", "fd_context_reserve", "fd_context_destroy",
+    "fd_fuse_directions", "fd_last_fallback_count", "fd_fuse_directions_batched",
+    "fd_mlp_create", "fd_mlp_set_params", "fd_mlp_get_params", "fd_mlp_set_calibration",
+    "fd_mlp_get_calibration", "fd_mlp_save", "fd_mlp_load", "fd_mlp_forward",
+    "fd_mlp_loss_grad", "fd_mlp_train_step", "fd_mlp_destroy", "fd_features", "fd_autotune",
+    "fd_last_error",
+)
+
+
+class FdError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"fusedir error {code}: {msg}")
+        self.code = code
+
+
+class Params(ctypes.Structure):
+    _fields_ = [
+        ("width", ctypes.c_int32), ("height", ctypes.c_int32),
+        ("map_dtype", ctypes.c_int32), ("patch", ctypes.c_int32),
+        ("n_candidates", ctypes.c_int32), ("refine_iters", ctypes.c_int32),
+        ("refine_step0", ctypes.c_float), ("top_k", ctypes.c_int32),
+        ("z_near", ctypes.c_float), ("mode", ctypes.c_int32),
+        ("mlp", ctypes.c_void_p), ("learned_iters", ctypes.c_int32),
+        ("learned_step0", ctypes.c_float), ("fallback_cost", ctypes.c_float),
+        ("proposal", ctypes.c_int32), ("proposal_dirs", ctypes.c_void_p),
+        ("head_centre", ctypes.c_float * 3), ("stream", ctypes.c_void_p),
+        ("ctx", ctypes.c_void_p),
+    ]
+
+
+class Scene(ctypes.Structure):
+    _fields_ = [
+        ("points", ctypes.c_void_p), ("n_points", ctypes.c_int64),
+        ("cams", ctypes.c_void_p), ("n_views", ctypes.c_int32),
+        ("width", ctypes.c_int32), ("height", ctypes.c_int32),
+        ("orient_maps", ctypes.c_void_p), ("conf_maps", ctypes.c_void_p),
+        ("dirs", ctypes.c_void_p), ("costs", ctypes.c_void_p),
+        ("head_centre", ctypes.c_float * 3),
+    ]
+
+
+class Adam(ctypes.Structure):
+    _fields_ = [("lr", ctypes.c_float), ("beta1", ctypes.c_float),
+                ("beta2", ctypes.c_float), ("eps", ctypes.c_float)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libfusedir.so; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with "
+                          "`python -m paper_2604_05794_amd.build` (hipcc, gfx950)")
+    L = ctypes.CDLL(LIB_PATH)
+    P, i32, i64, u64, f32 = (ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64,
+                             ctypes.c_float)
+    pp = ctypes.POINTER(Params)
+    sig = {
+        "fd_params_init": (None, [pp]),
+        "fd_context_create": (ctypes.c_int, [ctypes.POINTER(P)]),
+        "fd_context_reserve": (ctypes.c_int, [P, i64, i32, i32]),
+        "fd_context_destroy": (None, [P]),
+        "fd_fuse_directions": (ctypes.c_int, [P, i64, P, i32, P, P, pp, P, P]),
+        "fd_last_fallback_count": (ctypes.c_int, [P, P, ctypes.POINTER(i64)]),
+        "fd_fuse_directions_batched": (ctypes.c_int, [P, i32, pp, P]),
+        "fd_mlp_create": (ctypes.c_int, [ctypes.POINTER(P), u64]),
+        "fd_mlp_set_params": (ctypes.c_int, [P, P]),
+        "fd_mlp_get_params": (ctypes.c_int, [P, P]),
+        "fd_mlp_set_calibration": (ctypes.c_int, [P, f32, f32]),
+        "fd_mlp_get_calibration": (ctypes.c_int, [P, ctypes.POINTER(f32), ctypes.POINTER(f32)]),
+        "fd_mlp_save": (ctypes.c_int, [P, ctypes.c_char_p]),
+        "fd_mlp_load": (ctypes.c_int, [P, ctypes.c_char_p]),
+        "fd_mlp_forward": (ctypes.c_int, [P, P, i64, P, P]),
+        "fd_mlp_loss_grad": (ctypes.c_int, [P, P, P, i32, P, P, P]),
+        "fd_mlp_train_step": (ctypes.c_int, [P, P, P, i32, ctypes.POINTER(Adam), P, P]),
+        "fd_mlp_destroy": (None, [P]),
+        "fd_features": (ctypes.c_int, [P, i64, P, i32, P, P, pp, P]),
+        "fd_autotune": (ctypes.c_int, [P, P, i32, pp, ctypes.c_char_p]),
+        "fd_last_error": (ctypes.c_char_p, []),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(L, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = L
+    return L
+
+
+def _check(rc):
+    if rc != FD_OK:
+        raise FdError(rc, lib().fd_last_error().decode(errors="replace"))
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _dev_tensor(t, name, dtype=None, shape_tail=None):
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA (HIP) tensor")
+    if dtype is not None and t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if shape_tail is not None and tuple(t.shape[-len(shape_tail):]) != tuple(shape_tail):
+        raise ValueError(f"{name} must have trailing shape {shape_tail}, got {tuple(t.shape)}")
+    return t
+
+
+def _stream_handle(stream):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+class Context:
+    """Library-owned workspace (fd_context)."""
+
+    def __init__(self, max_points=0, max_views=0, max_scenes=0):
+        h = ctypes.c_void_p()
+        _check(lib().fd_context_create(ctypes.byref(h)))
+        self.handle = h
+        if max_points or max_scenes:
+            self.reserve(max_points, max_views, max_scenes)
+
+    def reserve(self, max_points, max_views=0, max_scenes=0):
+        _check(lib().fd_context_reserve(self.handle, int(max_points), int(max_views),
+                                        int(max_scenes)))
+
+    def fallback_count(self, stream=None) -> int:
+        out = ctypes.c_int64()
+        _check(lib().fd_last_fallback_count(self.handle, _stream_handle(stream),
+                                            ctypes.byref(out)))
+        return int(out.value)
+
+    def close(self):
+        if self.handle:
+            lib().fd_context_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def make_params(width, height, map_dtype, *, patch=5, n_candidates=128, refine_iters=8,
+                refine_step0=0.0, top_k=5, z_near=1e-3, mode=FD_MODE_PLAIN, mlp=None,
+                learned_iters=2, learned_step0=0.0, fallback_cost=math.inf,
+                proposal=FD_PROPOSAL_MLP, proposal_dirs=None, head_centre=(0.0, 0.0, 0.0),
+                stream=None, ctx: Optional[Context] = None) -> Params:
+    p = Params()
+    lib().fd_params_init(ctypes.byref(p))
+    p.width, p.height = int(width), int(height)
+    p.map_dtype = int(map_dtype)
+    p.patch = int(patch)
+    p.n_candidates = int(n_candidates)
+    p.refine_iters = int(refine_iters)
+    p.refine_step0 = float(refine_step0)
+    p.top_k = int(top_k)
+    p.z_near = float(z_near)
+    p.mode = int(mode)
+    p.mlp = mlp.handle if mlp is not None else None
+    p.learned_iters = int(learned_iters)
+    p.learned_step0 = float(learned_step0)
+    p.fallback_cost = float(fallback_cost)
+    p.proposal = int(proposal)
+    p.proposal_dirs = proposal_dirs.data_ptr() if proposal_dirs is not None else None
+    for k in range(3):
+        p.head_centre[k] = float(head_centre[k])
+    p.stream = _stream_handle(stream).value
+    p.ctx = ctx.handle.value if ctx is not None else None
+    return p
+
+
+def map_dtype_of(t: torch.Tensor) -> int:
+    if t.dtype == torch.float16:
+        return FD_F16
+    if t.dtype == torch.float32:
+        return FD_F32
+    raise TypeError(f"maps must be float16 or float32, got {t.dtype}")
+
+
+def fuse_directions(points, cams, orient_maps, conf_maps, *, dirs=None, costs=None,
+                    **kw):
+    """fd_fuse_directions on torch tensors.
+
+    points (N, 3) float32, cams (V, 16) float32, maps (V, H, W) float16 or
+    float32 (same dtype), all on the current HIP device.  Keyword arguments
+    are the fields of fd_params (see make_params).  Returns (dirs (N, 3),
+    costs (N,)) float32, enqueued on `stream` (default: torch's current
+    stream).
+    """
+    _dev_tensor(points, "points", torch.float32, (3,))
+    _dev_tensor(cams, "cams", torch.float32, (16,))
+    _dev_tensor(orient_maps, "orient_maps")
+    _dev_tensor(conf_maps, "conf_maps", orient_maps.dtype)
+    if orient_maps.dim() != 3 or conf_maps.shape != orient_maps.shape:
+        raise ValueError("orient_maps and conf_maps must both be (V, H, W)")
+    V, H, W = orient_maps.shape
+    if cams.shape[0] != V:
+        raise ValueError(f"{cams.shape[0]} cameras for {V} maps")
+    n = points.shape[0]
+    if dirs is None:
+        dirs = torch.empty((n, 3), dtype=torch.float32, device=points.device)
+    if costs is None:
+        costs = torch.empty((n,), dtype=torch.float32, device=points.device)
+    _dev_tensor(dirs, "dirs", torch.float32, (3,))
+    _dev_tensor(costs, "costs", torch.float32)
+    p = make_params(W, H, map_dtype_of(orient_maps), **kw)
+    _check(lib().fd_fuse_directions(_ptr(points), n, _ptr(cams), V, _ptr(orient_maps),
+                                    _ptr(conf_maps), ctypes.byref(p), _ptr(dirs), _ptr(costs)))
+    return dirs, costs
