@@ -212,6 +212,25 @@ int fd_features(const float* points, int64_t n_points, const fd_camera* cams,
 int fd_autotune(fd_context* ctx, const fd_scene* sample, int32_t n_scenes,
                 const fd_params* params, const char* cache_path);
 
+/* ---- stage timing -----------------------------------------------------------
+ * While enabled on a context, every call through it records a pair of HIP
+ * events on its stream around each stage's kernels.  fd_profile_read waits
+ * for the recorded events and returns the summed GPU time (ms) and the
+ * number of timed launches of one stage; fd_profile_enable also clears. */
+enum {
+  FD_STAGE_TILING = 0,    /* spatial key, counting sort */
+  FD_STAGE_TOPK = 1,      /* Eq. (4) view selection */
+  FD_STAGE_FUSE = 2,      /* plain search: patch, lattice, refinement */
+  FD_STAGE_FEATURES = 3,  /* proposal-network input */
+  FD_STAGE_MLP = 4,       /* proposal network */
+  FD_STAGE_REFINE = 5,    /* learned: refinement from the proposal, threshold */
+  FD_STAGE_FALLBACK = 6,  /* learned: plain search of the fallback list */
+  FD_STAGE_BATCHED = 7,   /* persistent batched launch */
+  FD_N_STAGES = 8
+};
+int fd_profile_enable(fd_context* ctx, int on);
+int fd_profile_read(fd_context* ctx, int stage, double* total_ms, int64_t* count);
+
 const char* fd_last_error(void);
 
 #ifdef __cplusplus

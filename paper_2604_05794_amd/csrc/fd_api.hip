@@ -103,6 +103,7 @@ extern "C" int fd_context_create(fd_context** out) {
   if ((r = grow(&c->bbox, &cap, 6, "bbox")) ||
       (r = grow(&c->counts, &(cap = 0), (size_t)tile_cells(), "cell counts")) ||
       (r = grow(&c->cursor, &(cap = 0), (size_t)tile_cells(), "cell cursor")) ||
+      (r = grow(&c->scan_sums, &(cap = 0), (size_t)tile_cells() / 1024, "scan sums")) ||
       (r = grow(&c->lattice, &(cap = 0), (size_t)3 * FD_MAX_CANDIDATES, "lattice")) ||
       (r = grow(&c->fb_count, &(cap = 0), (size_t)4, "fallback counter"))) {
     fd_context_destroy(c);
@@ -130,11 +131,15 @@ extern "C" int fd_context_reserve(fd_context* c, int64_t max_points, int32_t max
 extern "C" void fd_context_destroy(fd_context* c) {
   if (!c) return;
   (void)hipDeviceSynchronize();
-  void* bufs[] = {c->bbox, c->counts, c->cursor, c->lattice, c->fb_count, c->key,
+  void* bufs[] = {c->bbox, c->counts, c->cursor, c->scan_sums, c->lattice, c->fb_count, c->key,
                   c->perm, c->views, c->kcount, c->fb_list, c->prop, c->feats,
                   c->scene_tab, c->tile_tab, c->tile_queue, c->batch_key, c->batch_perm};
   for (void* p : bufs)
     if (p) (void)hipFree(p);
+  for (auto& p : c->pending) {
+    (void)hipEventDestroy(p.a);
+    (void)hipEventDestroy(p.b);
+  }
   if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
   if (c->graph) (void)hipGraphDestroy(c->graph);
   delete c;
@@ -158,6 +163,65 @@ fd_context* fd::default_context(int dev, int64_t n, int* err) {
   }
   *err = FD_OK;
   return c;
+}
+
+// ---- stage timing ------------------------------------------------------------------
+
+fd::StageTimer::StageTimer(fd_context* c_, int stage_, hipStream_t st_)
+    : c(c_), stage(stage_), st(st_) {
+  if (!c || !c->profiling) return;
+  if (hipEventCreate(&a) != hipSuccess) {
+    a = nullptr;
+    return;
+  }
+  (void)hipEventRecord(a, st);
+}
+
+void fd::StageTimer::stop() {
+  if (!a) return;
+  hipEvent_t b;
+  if (hipEventCreate(&b) != hipSuccess) {
+    (void)hipEventDestroy(a);
+    a = nullptr;
+    return;
+  }
+  (void)hipEventRecord(b, st);
+  c->pending.push_back({stage, a, b});
+  a = nullptr;
+}
+
+static void drain_pending(fd_context* c) {
+  for (auto& p : c->pending) {
+    float ms = 0.0f;
+    if (hipEventSynchronize(p.b) == hipSuccess && hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
+      c->stage_ms[p.stage] += ms;
+      c->stage_n[p.stage] += 1;
+    }
+    (void)hipEventDestroy(p.a);
+    (void)hipEventDestroy(p.b);
+  }
+  c->pending.clear();
+}
+
+extern "C" int fd_profile_enable(fd_context* c, int on) {
+  if (!c) return set_error(FD_E_INVAL, "fd_profile_enable: ctx is NULL");
+  drain_pending(c);
+  for (int s = 0; s < FD_N_STAGES; ++s) {
+    c->stage_ms[s] = 0.0;
+    c->stage_n[s] = 0;
+  }
+  c->profiling = on != 0;
+  return FD_OK;
+}
+
+extern "C" int fd_profile_read(fd_context* c, int stage, double* total_ms, int64_t* count) {
+  if (!c || !total_ms || !count) return set_error(FD_E_INVAL, "fd_profile_read: null argument");
+  if (stage < 0 || stage >= FD_N_STAGES)
+    return set_error(FD_E_INVAL, "fd_profile_read: unknown stage %d", stage);
+  drain_pending(c);
+  *total_ms = c->stage_ms[stage];
+  *count = c->stage_n[stage];
+  return FD_OK;
 }
 
 // ---- params ------------------------------------------------------------------------
@@ -286,9 +350,11 @@ extern "C" int fd_fuse_directions(const float* points, int64_t n_points, const f
 int fd::run_scene(fd_context* c, const SceneArgs& a, const fd_params* p, hipStream_t st) {
   int r;
   if ((r = ensure_lattice(c, p->n_candidates, st))) return r;
-  TileWork tw{c->bbox, c->key, c->counts, c->cursor, c->perm};
+  TileWork tw{c->bbox, c->key, c->counts, c->cursor, c->scan_sums, c->perm};
+  StageTimer t_tile(c, FD_STAGE_TILING, st);
   hipError_t e = launch_tiling(a.points, a.n, tw, st);
   if (e != hipSuccess) return hip_error(e, "tiling kernels");
+  t_tile.stop();
   SceneDev s;
   s.pts = a.points;
   s.cams = a.cams;
@@ -311,11 +377,15 @@ int fd::run_scene(fd_context* c, const SceneArgs& a, const fd_params* p, hipStre
   q.step0 = p->refine_step0 > 0.0f ? p->refine_step0 : default_step0(p->n_candidates);
   q.K = p->top_k;
   q.z_near = p->z_near;
+  StageTimer t_topk(c, FD_STAGE_TOPK, st);
   if ((e = launch_topk(s, q, p->map_dtype, st)) != hipSuccess)
     return hip_error(e, "view selection kernel");
+  t_topk.stop();
   if (p->mode == FD_MODE_PLAIN) {
+    StageTimer t_fuse(c, FD_STAGE_FUSE, st);
     if ((e = launch_fuse(s, q, p->map_dtype, p->patch, nullptr, nullptr, st)) != hipSuccess)
       return hip_error(e, "fusion kernel");
+    t_fuse.stop();
     return FD_OK;
   }
   return run_learned(c, s, q, p, st);

@@ -5,6 +5,7 @@
 #include <stdint.h>
 
 #include <algorithm>
+#include <vector>
 
 #include "../../include/fusedir.h"
 #include "fd_kernels.hpp"
@@ -16,6 +17,7 @@ struct fd_context {
   int* bbox = nullptr;
   uint32_t* counts = nullptr;
   uint32_t* cursor = nullptr;
+  uint32_t* scan_sums = nullptr;
   float* lattice = nullptr;
   int lattice_n = -1;
   uint32_t* fb_count = nullptr;
@@ -51,6 +53,15 @@ struct fd_context {
   uint64_t graph_sig = 0;
   // tuned tile shapes: waves per workgroup for the batched kernel
   int tuned_wpb = 0;
+  // stage timing
+  bool profiling = false;
+  struct Pending {
+    int stage;
+    hipEvent_t a, b;
+  };
+  std::vector<Pending> pending;
+  double stage_ms[FD_N_STAGES] = {};
+  int64_t stage_n[FD_N_STAGES] = {};
 };
 
 namespace fd {
@@ -77,6 +88,19 @@ int context_reserve_scenes(fd_context* c, int32_t n_scenes, int64_t total_points
 fd_context* default_context(int dev, int64_t n, int* err);
 int ensure_lattice(fd_context* c, int n, hipStream_t st);
 int run_scene(fd_context* c, const SceneArgs& a, const fd_params* p, hipStream_t st);
+// Records HIP events around one stage when the context profiles.
+struct StageTimer {
+  fd_context* c;
+  int stage;
+  hipStream_t st;
+  hipEvent_t a = nullptr;
+  StageTimer(fd_context* c_, int stage_, hipStream_t st_);
+  ~StageTimer() {
+    if (a) (void)hipEventDestroy(a);
+  }
+  void stop();
+};
+
 int run_learned(fd_context* c, const SceneDev& s, const SearchDev& q, const fd_params* p,
                 hipStream_t st);
 

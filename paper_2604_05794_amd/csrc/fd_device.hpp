@@ -31,6 +31,21 @@ __device__ __forceinline__ float tex_load<__half>(const __half* __restrict__ m,
   return __half2float(m[(size_t)y * W + x]);
 }
 
+// Same value as tex_load, but the load itself is unconditional (at a clamped
+// address), so a run of them can be issued back to back.
+template <typename T>
+__device__ __forceinline__ float tex_load_nb(const T* __restrict__ m, int W, int H, int x,
+                                             int y) {
+  const bool in = (unsigned)x < (unsigned)W && (unsigned)y < (unsigned)H;
+  const int xc = min(max(x, 0), W - 1), yc = min(max(y, 0), H - 1);
+  float v;
+  if constexpr (sizeof(T) == 2)
+    v = __half2float(((const __half*)m)[(size_t)yc * W + xc]);
+  else
+    v = ((const float*)m)[(size_t)yc * W + xc];
+  return in ? v : 0.0f;
+}
+
 // Projection and eligibility, in binary32 with the fixed operation order
 // every implementation of the method shares (view selection is a discrete
 // decision and must come out the same everywhere):
@@ -68,10 +83,10 @@ __device__ __forceinline__ float centre_conf32(const T* __restrict__ cm, int W,
   float fx = u - x0, fy = v - y0;
   float gx = 1.0f - fx, gy = 1.0f - fy;
   int ix = (int)x0, iy = (int)y0;
-  float c00 = tex_load<T>(cm, W, H, ix, iy);
-  float c10 = tex_load<T>(cm, W, H, ix + 1, iy);
-  float c01 = tex_load<T>(cm, W, H, ix, iy + 1);
-  float c11 = tex_load<T>(cm, W, H, ix + 1, iy + 1);
+  float c00 = tex_load_nb<T>(cm, W, H, ix, iy);
+  float c10 = tex_load_nb<T>(cm, W, H, ix + 1, iy);
+  float c01 = tex_load_nb<T>(cm, W, H, ix, iy + 1);
+  float c11 = tex_load_nb<T>(cm, W, H, ix + 1, iy + 1);
   float w00 = gx * gy, w10 = fx * gy, w01 = gx * fy, w11 = fx * fy;
   return __builtin_fmaf(w11, c11, __builtin_fmaf(w01, c01, __builtin_fmaf(w10, c10, w00 * c00)));
 }

@@ -70,24 +70,37 @@ __global__ __launch_bounds__(256) void k_topk(SceneDev s, SearchDev q) {
   }
   const T* conf = (const T*)s.conf;
   const size_t plane = (size_t)s.W * s.H;
-  for (int v = 0; v < s.V; ++v) {
-    Proj pr;
-    if (!project32(s.cams + 16 * v, px, py, pz, s.W, s.H, q.z_near, pr)) continue;
-    float c = centre_conf32<T>(conf + plane * v, s.W, s.H, pr.u, pr.v);
-    if (!(c > 0.0f)) continue;
-    float cs = c;
-    int cv = v;
-    bool ins = false;
+  // views in groups of four: projections and the 16 texel loads of a group
+  // are independent, so they are issued before the (ordered) insertions
+  constexpr int kGroup = 4;
+  for (int v0 = 0; v0 < s.V; v0 += kGroup) {
+    float cg[kGroup];
 #pragma unroll
-    for (int k = 0; k < FD_TOPK_SLOTS; ++k) {
-      bool take = ins || (cs > sc[k]);
-      float ts = sc[k];
-      int tv = id[k];
-      sc[k] = take ? cs : ts;
-      id[k] = take ? cv : tv;
-      cs = take ? ts : cs;
-      cv = take ? tv : cv;
-      ins = take;
+    for (int u = 0; u < kGroup; ++u) {
+      const int v = min(v0 + u, s.V - 1);
+      Proj pr;
+      const bool ok = project32(s.cams + 16 * v, px, py, pz, s.W, s.H, q.z_near, pr);
+      const float c = centre_conf32<T>(conf + plane * v, s.W, s.H, ok ? pr.u : 0.0f,
+                                       ok ? pr.v : 0.0f);
+      cg[u] = (ok && v0 + u < s.V) ? c : 0.0f;
+    }
+#pragma unroll
+    for (int u = 0; u < kGroup; ++u) {
+      if (!(cg[u] > 0.0f)) continue;
+      float cs = cg[u];
+      int cv = v0 + u;
+      bool ins = false;
+#pragma unroll
+      for (int k = 0; k < FD_TOPK_SLOTS; ++k) {
+        bool take = ins || (cs > sc[k]);
+        float ts = sc[k];
+        int tv = id[k];
+        sc[k] = take ? cs : ts;
+        id[k] = take ? cv : tv;
+        cs = take ? ts : cs;
+        cv = take ? tv : cv;
+        ins = take;
+      }
     }
   }
   int keff = 0;
@@ -158,8 +171,8 @@ __device__ __forceinline__ void build_patch(const SceneDev& s, const SearchDev& 
   auto load_row = [&](int slot, int y) {
 #pragma unroll
     for (int a = 0; a <= P; ++a) {
-      float t = tex_load<T>(th, s.W, s.H, ix + a, y);
-      float c = tex_load<T>(cf, s.W, s.H, ix + a, y);
+      float t = tex_load_nb<T>(th, s.W, s.H, ix + a, y);
+      float c = tex_load_nb<T>(cf, s.W, s.H, ix + a, y);
       float turns = t * kInvPi;  // 2 theta in revolutions
       rc[slot][a] = c;
       rx[slot][a] = c * __builtin_amdgcn_cosf(turns);

@@ -15,6 +15,7 @@ struct TileWork {
   uint32_t* key;     // n
   uint32_t* counts;  // tile_cells()
   uint32_t* cursor;  // tile_cells()
+  uint32_t* sums;    // tile_cells() / 1024
   uint32_t* perm;    // n
 };
 

@@ -31,33 +31,42 @@ __global__ void k_fill_u32(uint32_t* __restrict__ p, int64_t n, uint32_t v) {
 }
 
 // bbox[0..2] = ordered min, bbox[3..5] = ordered max (pre-filled by the host
-// path with INT_MAX / INT_MIN through k_fill_u32).
+// path with INT_MAX / INT_MIN through k_fill_u32).  Grid-stride loop, then a
+// wave and a workgroup reduction, so there are 6 atomics per workgroup.
 __global__ __launch_bounds__(256) void k_bbox(const float* __restrict__ pts,
                                               int64_t n, int* __restrict__ bbox) {
-  int mn[3] = {INT32_MAX, INT32_MAX, INT32_MAX};
-  int mx[3] = {INT32_MIN, INT32_MIN, INT32_MIN};
+  __shared__ int red[4][6];
+  int v[6] = {INT32_MAX, INT32_MAX, INT32_MAX, INT32_MIN, INT32_MIN, INT32_MIN};
   int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
     for (int a = 0; a < 3; ++a) {
       float f = pts[3 * i + a];
       if (f == f) {  // skip NaN
         int o = float_to_ordered(f);
-        mn[a] = min(mn[a], o);
-        mx[a] = max(mx[a], o);
+        v[a] = min(v[a], o);
+        v[3 + a] = max(v[3 + a], o);
       }
     }
   }
   for (int a = 0; a < 3; ++a) {
     for (int off = 32; off > 0; off >>= 1) {
-      mn[a] = min(mn[a], __shfl_xor(mn[a], off, 64));
-      mx[a] = max(mx[a], __shfl_xor(mx[a], off, 64));
+      v[a] = min(v[a], __shfl_xor(v[a], off, 64));
+      v[3 + a] = max(v[3 + a], __shfl_xor(v[3 + a], off, 64));
     }
   }
-  if ((threadIdx.x & 63) == 0) {
-    for (int a = 0; a < 3; ++a) {
-      atomicMin(&bbox[a], mn[a]);
-      atomicMax(&bbox[3 + a], mx[a]);
-    }
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0)
+    for (int a = 0; a < 6; ++a) red[w][a] = v[a];
+  __syncthreads();
+  if (threadIdx.x < 6) {
+    const int a = threadIdx.x;
+    int r = red[0][a];
+    for (int k = 1; k < (int)(blockDim.x >> 6); ++k)
+      r = a < 3 ? min(r, red[k][a]) : max(r, red[k][a]);
+    if (a < 3)
+      atomicMin(&bbox[a], r);
+    else
+      atomicMax(&bbox[a], r);
   }
 }
 
@@ -89,18 +98,15 @@ __global__ __launch_bounds__(256) void k_cell_count(const float* __restrict__ pt
   atomicAdd(&counts[k], 1u);
 }
 
-// Exclusive scan of kCells counts by one workgroup of 1024 threads; writes
-// the cell start offsets into `cursor` (the scatter advances them).
-__global__ __launch_bounds__(1024) void k_cell_scan(const uint32_t* __restrict__ counts,
-                                                    uint32_t* __restrict__ cursor) {
-  constexpr int per = kCells / 1024;
-  __shared__ uint32_t wsum[16];
-  const int t = threadIdx.x;
-  uint32_t local = 0;
-  for (int j = 0; j < per; ++j) local += counts[t * per + j];
-  // inclusive scan of `local` across the block
-  uint32_t v = local;
-  const int lane = t & 63, w = t >> 6;
+// Exclusive scan of the kCells counts in two passes: k_cell_block_sums
+// reduces each run of 1024 cells; k_cell_scan scans those sums and then its
+// own run, writing the cell start offsets into `cursor` (the scatter
+// advances them).  Both read coalesced.
+constexpr int kScanRun = 1024;
+constexpr int kScanRuns = kCells / kScanRun;  // 256
+
+__device__ __forceinline__ uint32_t block_incl_scan(uint32_t v, uint32_t* wsum) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
   for (int off = 1; off < 64; off <<= 1) {
     uint32_t o = __shfl_up(v, off, 64);
     if (lane >= off) v += o;
@@ -108,19 +114,46 @@ __global__ __launch_bounds__(1024) void k_cell_scan(const uint32_t* __restrict__
   if (lane == 63) wsum[w] = v;
   __syncthreads();
   if (w == 0) {
-    uint32_t s = lane < 16 ? wsum[lane] : 0u;
+    uint32_t s = lane < nw ? wsum[lane] : 0u;
     for (int off = 1; off < 16; off <<= 1) {
       uint32_t o = __shfl_up(s, off, 64);
       if (lane >= off) s += o;
     }
-    if (lane < 16) wsum[lane] = s;
+    if (lane < nw) wsum[lane] = s;
   }
   __syncthreads();
-  uint32_t base = v - local + (w > 0 ? wsum[w - 1] : 0u);
-  for (int j = 0; j < per; ++j) {
-    cursor[t * per + j] = base;
-    base += counts[t * per + j];
+  return v + (w > 0 ? wsum[w - 1] : 0u);
+}
+
+__global__ __launch_bounds__(1024) void k_cell_block_sums(const uint32_t* __restrict__ counts,
+                                                          uint32_t* __restrict__ sums) {
+  __shared__ uint32_t wsum[16];
+  uint32_t v = counts[blockIdx.x * kScanRun + threadIdx.x];
+  uint32_t incl = block_incl_scan(v, wsum);
+  if (threadIdx.x == kScanRun - 1) sums[blockIdx.x] = incl;
+}
+
+__global__ __launch_bounds__(1024) void k_cell_scan(const uint32_t* __restrict__ counts,
+                                                    const uint32_t* __restrict__ sums,
+                                                    uint32_t* __restrict__ cursor) {
+  __shared__ uint32_t wsum[16];
+  __shared__ uint32_t base;
+  // prefix of the run sums before this block (kScanRuns <= 1024)
+  uint32_t s = threadIdx.x < (unsigned)blockIdx.x ? sums[threadIdx.x] : 0u;
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+  if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t b = 0;
+    for (int k = 0; k < (int)(blockDim.x >> 6); ++k) b += wsum[k];
+    base = b;
   }
+  __syncthreads();
+  const uint32_t b = base;
+  __syncthreads();
+  uint32_t v = counts[blockIdx.x * kScanRun + threadIdx.x];
+  uint32_t incl = block_incl_scan(v, wsum);
+  cursor[blockIdx.x * kScanRun + threadIdx.x] = b + incl - v;
 }
 
 __global__ __launch_bounds__(256) void k_cell_scatter(const uint32_t* __restrict__ key,
@@ -149,11 +182,14 @@ hipError_t launch_tiling(const float* pts, int64_t n, TileWork w, hipStream_t st
   hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, st, (uint32_t*)(w.bbox + 3),
                      (int64_t)3, (uint32_t)INT32_MIN);
   hipLaunchKernelGGL(k_fill_u32, dim3(256), dim3(256), 0, st, w.counts, (int64_t)kCells, 0u);
-  int gb = (int)(nb < 1024 ? nb : 1024);
+  int gb = (int)(nb < 256 ? nb : 256);
   hipLaunchKernelGGL(k_bbox, dim3(gb), dim3(bs), 0, st, pts, n, w.bbox);
   hipLaunchKernelGGL(k_cell_count, dim3((unsigned)nb), dim3(bs), 0, st, pts, n, w.bbox,
                      w.key, w.counts);
-  hipLaunchKernelGGL(k_cell_scan, dim3(1), dim3(1024), 0, st, w.counts, w.cursor);
+  hipLaunchKernelGGL(k_cell_block_sums, dim3(kScanRuns), dim3(kScanRun), 0, st, w.counts,
+                     w.sums);
+  hipLaunchKernelGGL(k_cell_scan, dim3(kScanRuns), dim3(kScanRun), 0, st, w.counts, w.sums,
+                     w.cursor);
   hipLaunchKernelGGL(k_cell_scatter, dim3((unsigned)nb), dim3(bs), 0, st, w.key, n, w.cursor,
                      w.perm);
   return hipGetLastError();

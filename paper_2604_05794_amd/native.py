@@ -30,8 +30,11 @@ EXPORTS = (
     "fd_mlp_create", "fd_mlp_set_params", "fd_mlp_get_params", "fd_mlp_set_calibration",
     "fd_mlp_get_calibration", "fd_mlp_save", "fd_mlp_load", "fd_mlp_forward",
     "fd_mlp_loss_grad", "fd_mlp_train_step", "fd_mlp_destroy", "fd_features", "fd_autotune",
-    "fd_last_error",
+    "fd_profile_enable", "fd_profile_read", "fd_last_error",
 )
+
+FD_STAGE_TILING, FD_STAGE_TOPK, FD_STAGE_FUSE, FD_STAGE_FEATURES, FD_STAGE_MLP, \
+    FD_STAGE_REFINE, FD_STAGE_FALLBACK, FD_STAGE_BATCHED = range(8)
 
 
 class FdError(RuntimeError):
@@ -107,6 +110,9 @@ def lib():
         "fd_mlp_destroy": (None, [P]),
         "fd_features": (ctypes.c_int, [P, i64, P, i32, P, P, pp, P]),
         "fd_autotune": (ctypes.c_int, [P, P, i32, pp, ctypes.c_char_p]),
+        "fd_profile_enable": (ctypes.c_int, [P, ctypes.c_int]),
+        "fd_profile_read": (ctypes.c_int, [P, ctypes.c_int, ctypes.POINTER(ctypes.c_double),
+                                           ctypes.POINTER(i64)]),
         "fd_last_error": (ctypes.c_char_p, []),
     }
     for name, (res, args) in sig.items():
@@ -162,6 +168,17 @@ class Context:
         _check(lib().fd_last_fallback_count(self.handle, _stream_handle(stream),
                                             ctypes.byref(out)))
         return int(out.value)
+
+    def profile(self, on=True):
+        _check(lib().fd_profile_enable(self.handle, int(bool(on))))
+
+    def stage_time(self, stage):
+        """(total ms, launches) recorded for one FD_STAGE_* since profile()."""
+        ms = ctypes.c_double()
+        cnt = ctypes.c_int64()
+        _check(lib().fd_profile_read(self.handle, int(stage), ctypes.byref(ms),
+                                     ctypes.byref(cnt)))
+        return float(ms.value), int(cnt.value)
 
     def close(self):
         if self.handle:
