@@ -382,4 +382,82 @@ hipError_t launch_fuse(const SceneDev& s, const SearchDev& q, int dtype, int pat
                     : launch_fuse_t<float>(s, q, patch, list, list_count, st);
 }
 
+// ---- learned form: refinement from a proposal, threshold, compaction ------------
+// prop: proposals (x, y, z); in processing order (index j) when prop_by_j,
+// else in point order (index i); NULL = every proposal invalid.  A point is
+// kept when its proposal is a finite non-zero direction and the refined cost
+// satisfies J <= tau; otherwise its processing-order index is appended to
+// the fallback list (plain search).
+template <typename T, int P>
+__global__ __launch_bounds__(256) void k_learned(SceneDev s, SearchDev q, LearnedDev l,
+                                                 int prop_by_j) {
+  const Group gr = make_group(q.K);
+  const int64_t blk = xcd_tile(gridDim.x);
+  const int64_t wave = blk * (blockDim.x / kWave) + (threadIdx.x / kWave);
+  const int64_t j = wave * gr.G + gr.g;
+  if (wave * gr.G >= s.n) return;
+  const bool pt_ok = gr.lane_ok && j < s.n;
+  const uint32_t i = pt_ok ? s.perm[j] : 0u;
+  const int keff = pt_ok ? (int)s.kcount[j] : 0;
+  const bool slot_ok = pt_ok && gr.slot < keff;
+  const int view = slot_ok ? (int)s.views[FD_TOPK_SLOTS * j + gr.slot] : 0;
+  const float px = s.pts[3 * (size_t)i], py = s.pts[3 * (size_t)i + 1],
+              pz = s.pts[3 * (size_t)i + 2];
+  ViewPatch<P> vp;
+  build_patch<T, P>(s, q, view, slot_ok, px, py, pz, vp);
+  const float kinv = keff > 0 ? 1.0f / (float)keff : 0.0f;
+  float dx = 0.0f, dy = 0.0f, dz = 0.0f;
+  if (pt_ok && l.proposals) {
+    const size_t k = 3 * (size_t)(prop_by_j ? (uint32_t)j : i);
+    dx = l.proposals[k];
+    dy = l.proposals[k + 1];
+    dz = l.proposals[k + 2];
+  }
+  const float len = sqrtf(dx * dx + dy * dy + dz * dz);
+  const bool valid = keff > 0 && isfinite(len) && len > 0.0f;
+  const float il = valid ? 1.0f / len : 0.0f;
+  dx = valid ? dx * il : 0.0f;
+  dy = valid ? dy * il : 0.0f;
+  dz = valid ? dz * il : 1.0f;
+  float J = 1.0f - group_sum(eval_view<P>(vp, dx, dy, dz), gr.base, gr.K) * kinv;
+  refine<P>(vp, gr, kinv, l.iters, l.step0, dx, dy, dz, J);
+  if (pt_ok && gr.slot == 0) {
+    if (valid && J <= l.tau) {
+      write_result(s, i, dx, dy, dz, J);
+    } else {
+      const uint32_t pos = atomicAdd(l.fb_count, 1u);
+      l.fb_list[pos] = (uint32_t)j;
+    }
+  }
+}
+
+hipError_t launch_learned_refine(const SceneDev& s, const SearchDev& q, const LearnedDev& l,
+                                 int dtype, int patch, int prop_by_j, hipStream_t st) {
+  if (s.n <= 0) return hipSuccess;
+  const int G = kWave / q.K;
+  const int64_t nb = (s.n + 4 * (int64_t)G - 1) / (4 * (int64_t)G);
+  dim3 grid((unsigned)nb), block(256);
+#define FD_LEARNED_CASE(T, P)                                                          \
+  hipLaunchKernelGGL((k_learned<T, P>), grid, block, 0, st, s, q, l, prop_by_j);
+  if (dtype == 1) {
+    switch (patch) {
+      case 1: FD_LEARNED_CASE(__half, 1) break;
+      case 3: FD_LEARNED_CASE(__half, 3) break;
+      case 5: FD_LEARNED_CASE(__half, 5) break;
+      case 7: FD_LEARNED_CASE(__half, 7) break;
+      default: return hipErrorInvalidValue;
+    }
+  } else {
+    switch (patch) {
+      case 1: FD_LEARNED_CASE(float, 1) break;
+      case 3: FD_LEARNED_CASE(float, 3) break;
+      case 5: FD_LEARNED_CASE(float, 5) break;
+      case 7: FD_LEARNED_CASE(float, 7) break;
+      default: return hipErrorInvalidValue;
+    }
+  }
+#undef FD_LEARNED_CASE
+  return hipGetLastError();
+}
+
 }  // namespace fd

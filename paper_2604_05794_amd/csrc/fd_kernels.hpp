@@ -64,8 +64,6 @@ hipError_t launch_topk(const SceneDev& s, const SearchDev& q, int dtype, hipStre
 hipError_t launch_fuse(const SceneDev& s, const SearchDev& q, int dtype, int patch,
                        const uint32_t* list, const uint32_t* list_count, hipStream_t st);
 hipError_t launch_learned_refine(const SceneDev& s, const SearchDev& q, const LearnedDev& l,
-                                 int dtype, int patch, hipStream_t st);
-hipError_t launch_features(const SceneDev& s, int dtype, float z_near, uint16_t* feats,
-                           hipStream_t st);
+                                 int dtype, int patch, int prop_by_j, hipStream_t st);
 
 }  // namespace fd

@@ -259,3 +259,105 @@ def fuse_directions(points, cams, orient_maps, conf_maps, *, dirs=None, costs=No
     _check(lib().fd_fuse_directions(_ptr(points), n, _ptr(cams), V, _ptr(orient_maps),
                                     _ptr(conf_maps), ctypes.byref(p), _ptr(dirs), _ptr(costs)))
     return dirs, costs
+
+
+def _np_f32(a):
+    import numpy as np
+    return np.ascontiguousarray(a, dtype=np.float32)
+
+
+class MLP:
+    """Direction-proposal network (fd_mlp): 112 -> 256 -> 256 -> 256 -> 3."""
+
+    def __init__(self, seed=0, path=None):
+        h = ctypes.c_void_p()
+        _check(lib().fd_mlp_create(ctypes.byref(h), int(seed)))
+        self.handle = h
+        if path is not None:
+            self.load(path)
+
+    def set_params(self, params):
+        import numpy as np
+        p = _np_f32(params)
+        assert p.size == FD_MLP_N_PARAMS
+        _check(lib().fd_mlp_set_params(self.handle, p.ctypes.data_as(ctypes.c_void_p)))
+
+    def get_params(self):
+        import numpy as np
+        p = np.empty(FD_MLP_N_PARAMS, np.float32)
+        _check(lib().fd_mlp_get_params(self.handle, p.ctypes.data_as(ctypes.c_void_p)))
+        return p
+
+    def set_calibration(self, learned_step0, fallback_cost):
+        _check(lib().fd_mlp_set_calibration(self.handle, float(learned_step0),
+                                            float(fallback_cost)))
+
+    def calibration(self):
+        s0 = ctypes.c_float()
+        tau = ctypes.c_float()
+        _check(lib().fd_mlp_get_calibration(self.handle, ctypes.byref(s0), ctypes.byref(tau)))
+        return float(s0.value), float(tau.value)
+
+    def save(self, path):
+        _check(lib().fd_mlp_save(self.handle, os.fsencode(path)))
+
+    def load(self, path):
+        _check(lib().fd_mlp_load(self.handle, os.fsencode(path)))
+
+    def forward(self, feats, out=None, stream=None):
+        """feats: (B, 112) bfloat16 CUDA tensor -> (B, 3) float32 unit directions."""
+        _dev_tensor(feats, "feats", torch.bfloat16, (FD_FEATURE_DIM,))
+        B = feats.shape[0]
+        if out is None:
+            out = torch.empty((B, 3), dtype=torch.float32, device=feats.device)
+        _dev_tensor(out, "out", torch.float32, (3,))
+        _check(lib().fd_mlp_forward(self.handle, _ptr(feats), B, _ptr(out),
+                                    _stream_handle(stream)))
+        return out
+
+    def loss_grad(self, feats, targets, stream=None):
+        _dev_tensor(feats, "feats", torch.bfloat16, (FD_FEATURE_DIM,))
+        _dev_tensor(targets, "targets", torch.float32, (3,))
+        grad = torch.empty(FD_MLP_N_PARAMS, dtype=torch.float32, device=feats.device)
+        loss = torch.empty(1, dtype=torch.float32, device=feats.device)
+        _check(lib().fd_mlp_loss_grad(self.handle, _ptr(feats), _ptr(targets), feats.shape[0],
+                                      _ptr(grad), _ptr(loss), _stream_handle(stream)))
+        return loss, grad
+
+    def train_step(self, feats, targets, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8,
+                   loss=None, stream=None):
+        _dev_tensor(feats, "feats", torch.bfloat16, (FD_FEATURE_DIM,))
+        _dev_tensor(targets, "targets", torch.float32, (3,))
+        opt = Adam(float(lr), float(beta1), float(beta2), float(eps))
+        _check(lib().fd_mlp_train_step(self.handle, _ptr(feats), _ptr(targets), feats.shape[0],
+                                       ctypes.byref(opt), _ptr(loss), _stream_handle(stream)))
+        return loss
+
+    def close(self):
+        if self.handle:
+            lib().fd_mlp_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def features(points, cams, orient_maps, conf_maps, head_centre=(0.0, 0.0, 0.0), out=None,
+             stream=None, z_near=1e-3):
+    """fd_features: (N, 112) bfloat16 proposal-network inputs, point order."""
+    _dev_tensor(points, "points", torch.float32, (3,))
+    _dev_tensor(cams, "cams", torch.float32, (16,))
+    _dev_tensor(orient_maps, "orient_maps")
+    _dev_tensor(conf_maps, "conf_maps", orient_maps.dtype)
+    V, H, W = orient_maps.shape
+    n = points.shape[0]
+    if out is None:
+        out = torch.empty((n, FD_FEATURE_DIM), dtype=torch.bfloat16, device=points.device)
+    p = make_params(W, H, map_dtype_of(orient_maps), head_centre=head_centre, stream=stream,
+                    z_near=z_near)
+    _check(lib().fd_features(_ptr(points), n, _ptr(cams), V, _ptr(orient_maps), _ptr(conf_maps),
+                             ctypes.byref(p), _ptr(out)))
+    return out

@@ -1,0 +1,276 @@
+"""GPU parity of the learned form: proposal-network forward and gradients
+(bfloat16 matrix cores vs the oracle's bfloat16 emulation), Adam, features,
+and the proposal -> refinement -> threshold -> fallback sequence."""
+import math
+import os
+import tempfile
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import scenegen
+from parity import assert_parity, axial_angle, compare
+
+pytestmark = pytest.mark.gpu
+
+DEV = torch.device("cuda:0")
+
+
+def _native():
+    from paper_2604_05794_amd import native
+    native.lib()
+    return native
+
+
+def _rand_params(seed):
+    rng = np.random.default_rng(seed)
+    parts = []
+    for (W, b) in oracle.mlp_split(np.zeros(oracle.mlp_n_params())):
+        parts.append(rng.normal(0, 1.0 / math.sqrt(W.shape[0]), W.size))
+        parts.append(rng.normal(0, 0.1, b.size))
+    return np.concatenate(parts).astype(np.float32)
+
+
+def _rand_feats(seed, B):
+    rng = np.random.default_rng(seed)
+    x = rng.normal(0, 1, (B, 112)).astype(np.float32)
+    return oracle.round_bf16(x)
+
+
+def _bf16_dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x, np.float32)).to(DEV).to(torch.bfloat16)
+
+
+def test_forward_matches_bfloat16_oracle():
+    nat = _native()
+    p = _rand_params(1)
+    x = _rand_feats(1, 1000)
+    net = nat.MLP(seed=0)
+    net.set_params(p)
+    y = net.forward(_bf16_dev(x))
+    torch.cuda.synchronize()
+    y = y.cpu().numpy().astype(np.float64)
+    yo = oracle.mlp_forward(p.astype(np.float64), x, bf16=True)
+    ang = np.arccos(np.clip(np.sum(y * yo, 1), -1, 1))
+    print("forward angle median", np.median(ang), "max", ang.max(), flush=True)
+    assert np.median(ang) <= 1e-3 and ang.max() <= 1e-2
+    assert np.allclose(np.linalg.norm(y, axis=1), 1, atol=1e-5)
+
+
+def test_forward_ragged_batches():
+    nat = _native()
+    p = _rand_params(2)
+    net = nat.MLP(seed=0)
+    net.set_params(p)
+    x = _rand_feats(2, 300)
+    full = net.forward(_bf16_dev(x))
+    torch.cuda.synchronize()
+    for B in (1, 5, 127, 128, 129, 255):
+        part = net.forward(_bf16_dev(x[:B]))
+        torch.cuda.synchronize()
+        assert torch.equal(part, full[:B]), B
+
+
+def test_gradient_matches_bfloat16_oracle():
+    nat = _native()
+    p = _rand_params(3)
+    x = _rand_feats(3, 64)
+    rng = np.random.default_rng(3)
+    t = rng.normal(size=(64, 3))
+    t = (t / np.linalg.norm(t, axis=1, keepdims=True)).astype(np.float32)
+    net = nat.MLP(seed=0)
+    net.set_params(p)
+    loss, grad = net.loss_grad(_bf16_dev(x), torch.from_numpy(t).to(DEV))
+    torch.cuda.synchronize()
+    g = grad.cpu().numpy().astype(np.float64)
+    lo, go = oracle.mlp_loss_grad(p.astype(np.float64), x, t, bf16=True)
+    assert abs(float(loss.item()) - lo) <= 1e-3 * max(1.0, abs(lo))
+    off = 0
+    rels = []
+    for (W, b) in oracle.mlp_split(np.zeros(oracle.mlp_n_params())):
+        for size in (W.size, b.size):
+            a, r = g[off:off + size], go[off:off + size]
+            rel = np.linalg.norm(a - r) / max(np.linalg.norm(r), 1e-30)
+            print("tensor at", off, "rel-L2", rel, "norms", np.linalg.norm(a), np.linalg.norm(r),
+                  "cos", float(a @ r / (np.linalg.norm(a) * np.linalg.norm(r) + 1e-30)), flush=True)
+            rels.append(rel)
+            off += size
+    assert max(rels) <= 1e-2, rels
+
+
+def test_adam_step_matches_oracle():
+    nat = _native()
+    p = _rand_params(4)
+    x = _rand_feats(4, 64)
+    rng = np.random.default_rng(4)
+    t = rng.normal(size=(64, 3))
+    t = (t / np.linalg.norm(t, axis=1, keepdims=True)).astype(np.float32)
+    net = nat.MLP(seed=0)
+    net.set_params(p)
+    _, grad = net.loss_grad(_bf16_dev(x), torch.from_numpy(t).to(DEV))
+    g = grad.cpu().numpy().astype(np.float32)
+    net.train_step(_bf16_dev(x), torch.from_numpy(t).to(DEV), lr=1e-3)
+    torch.cuda.synchronize()
+    w = p.copy()
+    m = np.zeros_like(w)
+    v = np.zeros_like(w)
+    oracle.adam_step(w, m, v, g, 1, 1e-3)
+    got = net.get_params()
+    assert np.max(np.abs(got - w)) <= 1e-6
+
+
+def test_training_reduces_the_loss():
+    nat = _native()
+    rng = np.random.default_rng(5)
+    # a learnable map: the target is a fixed smooth function of the input
+    B = 256
+    A = rng.normal(size=(112, 3))
+    net = nat.MLP(seed=5)
+    losses = []
+    for step in range(150):
+        x = oracle.round_bf16(rng.normal(0, 1, (B, 112)).astype(np.float32))
+        t = x.astype(np.float64) @ A
+        t = (t / np.linalg.norm(t, axis=1, keepdims=True)).astype(np.float32)
+        loss = torch.empty(1, device=DEV)
+        net.train_step(_bf16_dev(x), torch.from_numpy(t).to(DEV), lr=2e-3, loss=loss)
+        losses.append(float(loss.item()))
+    print("loss first/last", losses[:3], losses[-3:], flush=True)
+    assert np.mean(losses[-10:]) < 0.5 * np.mean(losses[:10])
+
+
+def test_checkpoint_round_trip_and_resume():
+    nat = _native()
+    rng = np.random.default_rng(6)
+    data = []
+    for _ in range(6):
+        x = oracle.round_bf16(rng.normal(0, 1, (64, 112)).astype(np.float32))
+        t = rng.normal(size=(64, 3))
+        t = (t / np.linalg.norm(t, axis=1, keepdims=True)).astype(np.float32)
+        data.append((_bf16_dev(x), torch.from_numpy(t).to(DEV)))
+    a = nat.MLP(seed=11)
+    for x, t in data:
+        a.train_step(x, t, lr=1e-3)
+    b = nat.MLP(seed=11)
+    for x, t in data[:3]:
+        b.train_step(x, t, lr=1e-3)
+    b.set_calibration(0.05, 0.2)
+    with tempfile.TemporaryDirectory() as d:
+        path = os.path.join(d, "net.fdmlp")
+        b.save(path)
+        c = nat.MLP(seed=99, path=path)
+    assert c.calibration() == pytest.approx((0.05, 0.2))
+    for x, t in data[3:]:
+        c.train_step(x, t, lr=1e-3)
+    torch.cuda.synchronize()
+    assert np.array_equal(a.get_params(), c.get_params())
+
+
+def test_features_match_oracle():
+    nat = _native()
+    rec = dict(scenegen.RECIPES["tiny"])
+    rec["n_points"] = 2000
+    rec["n_views"] = 24
+    rec["arc_deg"] = 360.0
+    sc = scenegen.make_scene(rec, 3)
+    head = np.array([0.0, 0.0, 0.02], np.float32)
+    pts = torch.from_numpy(sc.points).to(DEV)
+    f = nat.features(pts, torch.from_numpy(sc.cams).to(DEV), torch.from_numpy(sc.theta).to(DEV),
+                     torch.from_numpy(sc.conf).to(DEV), head_centre=head)
+    torch.cuda.synchronize()
+    f = f.float().cpu().numpy().astype(np.float64)
+    fo = oracle.Oracle(sc.cams, sc.theta, sc.conf, patch=1).features(sc.points, head)
+    fo_q = oracle.round_bf16(fo.astype(np.float32)).astype(np.float64)
+    # slot validity and view choice are exact; values within a bfloat16 step
+    valid_g = f[:, 6::7]
+    valid_o = fo[:, 6::7]
+    assert np.array_equal(valid_g, valid_o)
+    err = np.abs(f - fo_q)
+    tol = 2.0 ** -7 * np.abs(fo) + 1e-5
+    bad = err > tol
+    print("features: max err", err.max(), "bad", bad.sum(), flush=True)
+    assert bad.sum() <= 1e-4 * bad.size
+
+
+def _dev_scene(sc):
+    return (torch.from_numpy(sc.points).to(DEV), torch.from_numpy(sc.cams).to(DEV),
+            torch.from_numpy(sc.theta).to(DEV), torch.from_numpy(sc.conf).to(DEV))
+
+
+def _tiny(n=3000):
+    rec = dict(scenegen.RECIPES["tiny"])
+    rec["n_points"] = n
+    return scenegen.make_scene(rec, 7)
+
+
+KW = dict(patch=3, n_candidates=48, refine_iters=8, top_k=5)
+
+
+def test_learned_with_tau_minus_infinity_is_the_plain_method():
+    nat = _native()
+    sc = _tiny()
+    pts, cams, th, cf = _dev_scene(sc)
+    ctx = nat.Context(max_points=sc.n_points)
+    d0, c0 = nat.fuse_directions(pts, cams, th, cf, ctx=ctx, **KW)
+    prop = torch.from_numpy(sc.gt).to(DEV)
+    d1, c1 = nat.fuse_directions(pts, cams, th, cf, ctx=ctx, mode=nat.FD_MODE_LEARNED,
+                                 proposal=nat.FD_PROPOSAL_GIVEN, proposal_dirs=prop,
+                                 fallback_cost=-math.inf, learned_iters=2, **KW)
+    torch.cuda.synchronize()
+    assert ctx.fallback_count() == sc.n_points
+    assert torch.equal(d0, d1) and torch.equal(c0, c1)
+
+
+def test_nan_proposals_all_fall_back():
+    nat = _native()
+    sc = _tiny()
+    pts, cams, th, cf = _dev_scene(sc)
+    ctx = nat.Context(max_points=sc.n_points)
+    d0, c0 = nat.fuse_directions(pts, cams, th, cf, ctx=ctx, **KW)
+    d1, c1 = nat.fuse_directions(pts, cams, th, cf, ctx=ctx, mode=nat.FD_MODE_LEARNED,
+                                 proposal=nat.FD_PROPOSAL_NAN, fallback_cost=math.inf, **KW)
+    torch.cuda.synchronize()
+    assert ctx.fallback_count() == sc.n_points
+    assert torch.equal(d0, d1) and torch.equal(c0, c1)
+    # an invalid given proposal (NaN or zero vector) falls back too
+    prop = torch.from_numpy(sc.gt).to(DEV).clone()
+    prop[::2] = float("nan")
+    prop[1::4] = 0.0
+    d2, c2 = nat.fuse_directions(pts, cams, th, cf, ctx=ctx, mode=nat.FD_MODE_LEARNED,
+                                 proposal=nat.FD_PROPOSAL_GIVEN, proposal_dirs=prop,
+                                 fallback_cost=math.inf, **KW)
+    torch.cuda.synchronize()
+    n_bad = len(range(0, sc.n_points, 2)) + len(range(1, sc.n_points, 4))
+    assert ctx.fallback_count() >= n_bad
+    assert torch.equal(d2[::2], d0[::2]) and torch.equal(d2[1::4], d0[1::4])
+
+
+@pytest.mark.parametrize("tau", [math.inf, 0.25, 0.1])
+def test_given_proposal_parity_with_oracle(tau):
+    nat = _native()
+    sc = _tiny(2500)
+    pts, cams, th, cf = _dev_scene(sc)
+    rng = np.random.default_rng(8)
+    # ground-truth tangents perturbed by ~3 degrees: a realistic proposal
+    prop = sc.gt.astype(np.float64) + rng.normal(0, 0.05, sc.gt.shape)
+    prop32 = prop.astype(np.float32)
+    ctx = nat.Context(max_points=sc.n_points)
+    step0 = 0.05
+    d, c = nat.fuse_directions(pts, cams, th, cf, ctx=ctx, mode=nat.FD_MODE_LEARNED,
+                               proposal=nat.FD_PROPOSAL_GIVEN,
+                               proposal_dirs=torch.from_numpy(prop32).to(DEV),
+                               fallback_cost=tau, learned_iters=2, learned_step0=step0, **KW)
+    torch.cuda.synchronize()
+    n_fb = ctx.fallback_count()
+    d = d.cpu().numpy()
+    c = c.cpu().numpy()
+    orc = oracle.Oracle(sc.cams, sc.theta, sc.conf, **KW)
+    do, co, fb = orc.fuse_learned(sc.points, prop32.astype(np.float64), 2, step0, tau)
+    res = compare(orc, sc.points, d, c, do, co)
+    print("learned tau", tau, {k: v for k, v in res.items() if not k.endswith("_idx")},
+          "fallbacks gpu", n_fb, "oracle", int(fb.sum()), flush=True)
+    assert_parity(res, max_fail_frac=5e-3)
+    # the fallback decision is a threshold on a float cost: equal up to the
+    # points whose refined cost lies within rounding of tau
+    assert abs(n_fb - int(fb.sum())) <= max(3, 0.002 * sc.n_points)
