@@ -67,6 +67,116 @@ def cpu_baseline(sc, kw, seconds):
                       f"{el:.1f} s, binary64 oracle, OpenMP over points"}
 
 
+def _axial_deg(a, b):
+    import torch
+    c = torch.linalg.norm(torch.cross(a, b, dim=1), dim=1)
+    d = torch.abs((a * b).sum(1))
+    return torch.rad2deg(torch.atan2(c, d))
+
+
+def _timed(step, args, ctx, stages_list):
+    import torch
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    ctx.profile(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    stages = {}
+    for nm, st in stages_list:
+        ms, cnt = ctx.stage_time(st)
+        if cnt:
+            stages[nm] = ms / cnt
+    ctx.profile(False)
+    return el, stages
+
+
+def run_learned(args):
+    """Learned form on the realistic scene: network proposal, 2 refinement
+    iterations, plain search where the refined cost exceeds the calibrated
+    threshold.  Compared with the plain search on the same scene."""
+    import numpy as np
+    import torch
+    import scenegen
+    from paper_2604_05794_amd import native
+
+    name = "realistic"
+    rec = scenegen.RECIPES[name]
+    kw = dict(patch=rec["patch"], n_candidates=rec["n_candidates"],
+              refine_iters=rec["refine_iters"], top_k=5)
+    t = time.perf_counter()
+    sc = scenegen.make_scene(name, args.seed)
+    log(f"generated {name}: {sc.n_points} points in {time.perf_counter() - t:.1f} s")
+    dev = torch.device("cuda:0")
+    pts = torch.from_numpy(sc.points).to(dev)
+    cams = torch.from_numpy(sc.cams).to(dev)
+    th = torch.from_numpy(sc.theta).to(dev)
+    cf = torch.from_numpy(sc.conf).to(dev)
+    gt = torch.from_numpy(sc.gt).to(dev)
+    n = sc.n_points
+    ctx = native.Context(max_points=n)
+    net = native.MLP(path=args.mlp)
+    step0, tau = net.calibration()
+    log(f"network {args.mlp}: learned_step0 {step0:.4f} rad, fallback_cost {tau:.4f}")
+    stream = torch.cuda.current_stream()
+    dp = torch.empty((n, 3), dtype=torch.float32, device=dev)
+    cp = torch.empty((n,), dtype=torch.float32, device=dev)
+    dl = torch.empty_like(dp)
+    cl = torch.empty_like(cp)
+    stg = [("tiling", native.FD_STAGE_TILING), ("topk", native.FD_STAGE_TOPK),
+           ("fuse", native.FD_STAGE_FUSE), ("features", native.FD_STAGE_FEATURES),
+           ("mlp", native.FD_STAGE_MLP), ("refine", native.FD_STAGE_REFINE),
+           ("fallback", native.FD_STAGE_FALLBACK)]
+
+    def plain():
+        native.fuse_directions(pts, cams, th, cf, dirs=dp, costs=cp, ctx=ctx, stream=stream, **kw)
+
+    def learned():
+        native.fuse_directions(pts, cams, th, cf, dirs=dl, costs=cl, ctx=ctx, stream=stream,
+                               mode=native.FD_MODE_LEARNED, mlp=net, learned_iters=2,
+                               learned_step0=step0, fallback_cost=tau,
+                               head_centre=sc.head_centre, **kw)
+
+    el_p, st_p = _timed(plain, args, ctx, stg)
+    el_l, st_l = _timed(learned, args, ctx, stg)
+    n_fb = ctx.fallback_count()
+    fin = torch.isfinite(cp)
+    err = _axial_deg(dl[fin], dp[fin])
+    err_gt_l = _axial_deg(dl[fin], gt[fin])
+    err_gt_p = _axial_deg(dp[fin], gt[fin])
+    v_p = n / (el_p / args.steps)
+    v_l = n / (el_l / args.steps)
+    log(f"plain {v_p / 1e6:.1f} M points/s {json.dumps({k: round(v, 4) for k, v in st_p.items()})}")
+    log(f"learned {v_l / 1e6:.1f} M points/s {json.dumps({k: round(v, 4) for k, v in st_l.items()})}"
+        f" fallback {n_fb / n:.4f}, mean err vs plain {float(err.mean()):.3f} deg")
+    flop = plain_flop_per_point(kw["patch"], kw["n_candidates"], kw["refine_iters"], 5)
+    achieved = flop * n / (st_p["fuse"] * 1e-3) / 1e12
+    out = {
+        "metric": METRIC, "value": v_l, "unit": "points/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": el_l * 1e3 / args.steps,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "learned (unbatched): 500k points, 64 views 1024^2 f16, 10% "
+                               "outliers, P=5; network proposal + 2 refinement iterations, "
+                               "plain fallback (128 candidates + 8 iterations)",
+                   "mode": "learned", "points": n, "views": sc.n_views, **kw},
+        "plain_points_per_s": v_p, "speedup_vs_plain": v_l / v_p,
+        "mean_err_vs_plain_deg": float(err.mean()),
+        "median_err_vs_plain_deg": float(err.median()),
+        "mean_err_vs_gt_deg": {"learned": float(err_gt_l.mean()), "plain": float(err_gt_p.mean())},
+        "fallback_frac": n_fb / n,
+        "stages_ms_per_launch": {"plain": st_p, "learned": st_l},
+        "roofline": {"bound": "alu", "kernel": "k_fuse", "achieved": achieved,
+                     "peak": PEAK_FP32_FMA, "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_FMA,
+                     "traffic": None, "avg_launch_ms": st_p["fuse"], "flop_per_point": flop},
+    }
+    return out
+
+
 def run_plain(args):
     import numpy as np
     import torch
@@ -149,7 +259,9 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--seed", type=int, default=0)
-    ap.add_argument("--workload", default="plain", choices=["plain"])
+    ap.add_argument("--workload", default="plain", choices=["plain", "learned"])
+    ap.add_argument("--mlp", default=os.path.join(ROOT, "paper_2604_05794_amd", "weights",
+                                                  "proposal_mlp.fdmlp"))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     args = ap.parse_args()
@@ -159,7 +271,7 @@ def main():
               f"{world}); the fusion shards by scene or by point range with no exchange, and "
               "this build runs the one-GPU share.", file=sys.stderr)
         sys.exit(2)
-    out = run_plain(args)
+    out = run_learned(args) if args.workload == "learned" else run_plain(args)
     print(json.dumps(out), flush=True)
 
 

@@ -65,6 +65,7 @@ enum { FD_PROPOSAL_MLP = 0, FD_PROPOSAL_GIVEN = 1, FD_PROPOSAL_NAN = 2 };
 #define FD_MAX_REFINE 32
 #define FD_FEATURE_SLOTS 16
 #define FD_FEATURE_DIM 112 /* 16 slots x 7 */
+#define FD_MAX_BATCH_SCENES 32
 
 typedef struct fd_camera {
   float fx, fy, cx, cy;
@@ -140,9 +141,15 @@ int fd_last_fallback_count(fd_context* ctx, void* stream, int64_t* out);
 
 /* ---- many scenes in one launch --------------------------------------------
  * Every scene has its own points, cameras, maps (own W x H and view count)
- * and outputs; all use params' search settings and map dtype.  The scenes
- * array is host memory holding device pointers.  Results equal those of
- * fd_fuse_directions on each scene alone, bit for bit. */
+ * and outputs; all use params' search settings and map dtype (params->width
+ * and height are ignored).  The scenes array is host memory holding device
+ * pointers; at most FD_MAX_BATCH_SCENES scenes.  The context is required and
+ * must be reserved for the total point count and the scene count.  The
+ * launch sequence is captured into a HIP graph on the first call and
+ * replayed while the scene array and params are unchanged (a changed array
+ * re-captures, which synchronises params->stream).  The learned form takes
+ * the network proposal only.  Results equal those of fd_fuse_directions on
+ * each scene alone, bit for bit. */
 typedef struct fd_scene {
   const float* points;
   int64_t n_points;
@@ -196,19 +203,26 @@ void fd_mlp_destroy(fd_mlp* mlp);
 
 /* Proposal-network input of every point: the FD_FEATURE_SLOTS most frontal
  * eligible views (largest cosine between the point->camera direction and
- * p - params->head_centre), each (m_x, m_y, C, v_x, v_y, v_z, valid): the
- * bilinear confidence-weighted doubled-angle vector, the bilinear
- * confidence, the unit point->camera direction, 1.  feats: device
- * n_points x 112 bfloat16. */
+ * p - params->head_centre), each (q_x, q_y, C, v_x, v_y, v_z, valid):
+ * v is the unit point->camera direction, C the bilinear confidence and
+ * (q_x, q_y) = |m| (cos 2psi, sin 2psi), where m is the bilinear
+ * confidence-weighted doubled-angle vector (Eq. 9's orientation sample) and
+ * psi the angle, in the frame e1 = normalize(z x v), e2 = v x e1, of the
+ * direction across v of the plane that the observed image orientation
+ * back-projects to; empty slots are 0.  feats: device n_points x 112
+ * bfloat16 (16-byte aligned). */
 int fd_features(const float* points, int64_t n_points, const fd_camera* cams,
                 int32_t n_views, const void* orient_maps,
                 const void* conf_maps, const fd_params* params, void* feats);
 
 /* ---- tuning ---------------------------------------------------------------
- * Times the batched launch for each tile shape on the sample scenes and
- * stores the fastest per shape class in the context (and, if cache_path is
- * not NULL, in that JSON file, which later contexts read).  Offline: it
- * synchronises and is not meant for timed regions. */
+ * Times the batched launch on the sample scenes for each shape of the
+ * persistent search (tiles per queue pop, resident grid size) and keeps the
+ * fastest in the context.  With cache_path, a shape class (patch, top_k,
+ * map dtype, mode, point-count octave) already in that JSON file is taken
+ * from it without timing, and a newly timed one is added to it.  Offline: it
+ * synchronises and is not meant for timed regions.  Tile shapes never change
+ * results. */
 int fd_autotune(fd_context* ctx, const fd_scene* sample, int32_t n_scenes,
                 const fd_params* params, const char* cache_path);
 

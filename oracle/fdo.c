@@ -634,6 +634,45 @@ int fdo_features(const float* points, int64_t n_points, const float* cams,
         c[k] = -(R[k] * t[0] + R[3 + k] * t[1] + R[6 + k] * t[2]);
       for (int k = 0; k < 3; ++k) v[k] = c[k] - (double)p[k];
       normalize3(v);
+      /* The observed image line through the projection back-projects to a
+       * plane through the camera centre that contains the line of sight v.
+       * Its direction across the line of sight, t = n x v (n the plane
+       * normal), is expressed by its angle psi in the frame
+       * e1 = normalize(z x v) (x instead of z if v is vertical), e2 = v x e1
+       * perpendicular to v, so the input does not depend on the camera's
+       * roll or on where the point falls in the image; the doubled angle is
+       * carried with the sample's magnitude |m|. */
+      double mag = hypot(mx, my);
+      double qx = 0.0, qy = 0.0;
+      if (mag > 0.0) {
+        double th = 0.5 * atan2(my, mx);
+        double Xc[3];
+        for (int r = 0; r < 3; ++r)
+          Xc[r] = R[3 * r] * p[0] + R[3 * r + 1] * p[1] + R[3 * r + 2] * p[2] + t[r];
+        double dl[3] = {cos(th) / cam[0], sin(th) / cam[1], 0.0};
+        double nc[3] = {Xc[1] * dl[2] - Xc[2] * dl[1], Xc[2] * dl[0] - Xc[0] * dl[2],
+                        Xc[0] * dl[1] - Xc[1] * dl[0]};
+        double nw[3];
+        for (int k = 0; k < 3; ++k) nw[k] = R[k] * nc[0] + R[3 + k] * nc[1] + R[6 + k] * nc[2];
+        double tt[3] = {nw[1] * v[2] - nw[2] * v[1], nw[2] * v[0] - nw[0] * v[2],
+                        nw[0] * v[1] - nw[1] * v[0]};
+        double up[3] = {0.0, 0.0, 1.0};
+        if (fabs(v[2]) > 1.0 - 1e-9) {
+          up[0] = 1.0;
+          up[2] = 0.0;
+        }
+        double e1[3] = {up[1] * v[2] - up[2] * v[1], up[2] * v[0] - up[0] * v[2],
+                        up[0] * v[1] - up[1] * v[0]};
+        normalize3(e1);
+        double e2[3] = {v[1] * e1[2] - v[2] * e1[1], v[2] * e1[0] - v[0] * e1[2],
+                        v[0] * e1[1] - v[1] * e1[0]};
+        double psi = atan2(tt[0] * e2[0] + tt[1] * e2[1] + tt[2] * e2[2],
+                           tt[0] * e1[0] + tt[1] * e1[1] + tt[2] * e1[2]);
+        qx = mag * cos(2.0 * psi);
+        qy = mag * sin(2.0 * psi);
+      }
+      mx = qx;
+      my = qy;
       f[7 * j + 0] = mx;
       f[7 * j + 1] = my;
       f[7 * j + 2] = cbar;

@@ -122,9 +122,13 @@ int fdo_fuse_learned(const float* points, int64_t n_points, const float* cams,
 /* Proposal-network input features: the n_slots most frontal views (ranked by
  * the cosine between the point->camera direction and the outward direction
  * p - head_centre, decided in binary32), each slot
- * (m_x, m_y, C, v_x, v_y, v_z, valid) where (m_x, m_y) is the bilinear
- * confidence-weighted doubled-angle vector, C the bilinear confidence and v
- * the unit point->camera direction.  feats: N x (7 n_slots). */
+ * (q_x, q_y, C, v_x, v_y, v_z, valid): v is the unit point->camera
+ * direction, C the bilinear confidence, and (q_x, q_y) = |m| (cos 2psi,
+ * sin 2psi) where m is the bilinear confidence-weighted doubled-angle vector
+ * and psi the angle, in a frame perpendicular to v, of the plane that the
+ * observed image orientation back-projects to (see fdo.c).
+ * feats: N x (7 n_slots).  Parity unpinned against the paper (the network
+ * and its inputs are not in it); pinned by geometry in the tests. */
 int fdo_features(const float* points, int64_t n_points, const float* cams,
                  int32_t n_views, const void* theta_maps,
                  const void* conf_maps, const fdo_params* prm,

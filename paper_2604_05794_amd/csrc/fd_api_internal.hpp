@@ -51,8 +51,10 @@ struct fd_context {
   hipGraph_t graph = nullptr;
   hipGraphExec_t graph_exec = nullptr;
   uint64_t graph_sig = 0;
-  // tuned tile shapes: waves per workgroup for the batched kernel
-  int tuned_wpb = 0;
+  hipStream_t cap_stream = nullptr;
+  // tuned shape of the persistent search: tiles per queue pop, resident grid
+  int tuned_chunk = 0;
+  int tuned_grid = 0;
   // stage timing
   bool profiling = false;
   struct Pending {

@@ -1,0 +1,635 @@
+// fd_batched.hip -- many scenes (uneven point counts, view counts and map
+// sizes) fused by one captured launch sequence on gfx950.
+//
+// All scenes share one concatenated point range; a scene table (one SceneDev
+// per scene, its per-point workspace pointers offset to the scene's range)
+// lets every kernel find its scene: per-point kernels from a block table
+// (blocks never straddle scenes), the search kernels by a binary search of
+// the point offsets per lane group.  The plain search and the fallback search
+// are persistent: a grid sized to what stays resident pops tiles of points
+// from one atomic queue until it is empty, so uneven scenes balance across
+// the compute units.  The sequence (tiling, view selection, [features,
+// network, refinement,] search) is captured once into a HIP graph and
+// replayed while the scene set and the parameters stay the same.  Every
+// point runs the same per-point code as a single-scene call, so results are
+// bit-identical to fd_fuse_directions on each scene.
+#include <hip/hip_fp16.h>
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/fusedir.h"
+#include "fd_api_internal.hpp"
+#include "fd_features.hpp"
+#include "fd_kernels.hpp"
+#include "fd_search.hpp"
+
+using namespace fd;
+
+namespace fd {
+int mlp_forward_dev(const fd_mlp* m, const uint16_t* feats, int64_t n, float* out, hipStream_t st);
+}
+
+namespace {
+
+constexpr int kBCellBits = 5;  // per axis: 32^3 cells per scene
+constexpr int kBCells = 1 << (3 * kBCellBits);
+constexpr int kBlock = 256;
+
+struct BatchDev {
+  const SceneDev* tab;    // n_scenes
+  const int64_t* pt_off;  // n_scenes + 1, global point offsets
+  const int64_t* blk_off; // n_scenes + 1, first 256-thread block of each scene
+  int n_scenes;
+  int64_t total;
+};
+
+// largest s with off[s] <= x (off ascending, off[0] = 0)
+__device__ __forceinline__ int find_scene(const int64_t* off, int n, int64_t x) {
+  int lo = 0, hi = n - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (off[mid] <= x)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  return lo;
+}
+
+__device__ __forceinline__ int float_to_ordered(float f) {
+  int i = __float_as_int(f);
+  return i >= 0 ? i : i ^ 0x7fffffff;
+}
+__device__ __forceinline__ float ordered_to_float(int i) {
+  return __int_as_float(i >= 0 ? i : i ^ 0x7fffffff);
+}
+
+// per-scene point index of this thread (block table), or -1
+__device__ __forceinline__ int64_t block_point(const BatchDev& b, int* scene) {
+  const int s = find_scene(b.blk_off, b.n_scenes, (int64_t)blockIdx.x);
+  *scene = s;
+  const int64_t j = ((int64_t)blockIdx.x - b.blk_off[s]) * blockDim.x + threadIdx.x;
+  return j < b.tab[s].n ? j : -1;
+}
+
+__global__ void k_b_init(uint32_t* counts, int64_t n_counts, int* bbox, int n_scenes) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t k = i; k < n_counts; k += stride) counts[k] = 0u;
+  if (i < 6 * n_scenes) bbox[i] = (i % 6) < 3 ? INT32_MAX : INT32_MIN;
+}
+
+__global__ __launch_bounds__(kBlock) void k_b_bbox(BatchDev b, int* __restrict__ bbox) {
+  __shared__ int red[kBlock / 64][6];
+  int s;
+  const int64_t j = block_point(b, &s);
+  int v[6] = {INT32_MAX, INT32_MAX, INT32_MAX, INT32_MIN, INT32_MIN, INT32_MIN};
+  if (j >= 0) {
+    const float* p = b.tab[s].pts + 3 * j;
+    for (int a = 0; a < 3; ++a) {
+      const float f = p[a];
+      if (f == f) {
+        v[a] = float_to_ordered(f);
+        v[3 + a] = v[a];
+      }
+    }
+  }
+  for (int a = 0; a < 3; ++a)
+    for (int off = 32; off > 0; off >>= 1) {
+      v[a] = min(v[a], __shfl_xor(v[a], off, 64));
+      v[3 + a] = max(v[3 + a], __shfl_xor(v[3 + a], off, 64));
+    }
+  if ((threadIdx.x & 63) == 0)
+    for (int a = 0; a < 6; ++a) red[threadIdx.x >> 6][a] = v[a];
+  __syncthreads();
+  if (threadIdx.x < 6) {
+    const int a = threadIdx.x;
+    int r = red[0][a];
+    for (int k = 1; k < kBlock / 64; ++k) r = a < 3 ? min(r, red[k][a]) : max(r, red[k][a]);
+    if (a < 3)
+      atomicMin(&bbox[6 * s + a], r);
+    else
+      atomicMax(&bbox[6 * s + a], r);
+  }
+}
+
+__device__ __forceinline__ uint32_t spread3_b(uint32_t x) {
+  uint32_t r = 0;
+  for (int k = 0; k < kBCellBits; ++k) r |= ((x >> k) & 1u) << (3 * k);
+  return r;
+}
+
+__global__ __launch_bounds__(kBlock) void k_b_count(BatchDev b, const int* __restrict__ bbox,
+                                                    uint32_t* __restrict__ key,
+                                                    uint32_t* __restrict__ counts) {
+  int s;
+  const int64_t j = block_point(b, &s);
+  if (j < 0) return;
+  const float* p = b.tab[s].pts + 3 * j;
+  uint32_t q[3];
+  for (int a = 0; a < 3; ++a) {
+    const float lo = ordered_to_float(bbox[6 * s + a]), hi = ordered_to_float(bbox[6 * s + 3 + a]);
+    const float f = p[a];
+    const float ext = hi - lo;
+    const float u = ext > 0.0f ? (f - lo) / ext : 0.0f;
+    int c = (int)(u * (float)(1 << kBCellBits));
+    c = (f == f) ? c : 0;
+    q[a] = (uint32_t)min(max(c, 0), (1 << kBCellBits) - 1);
+  }
+  const uint32_t k = spread3_b(q[0]) | (spread3_b(q[1]) << 1) | (spread3_b(q[2]) << 2);
+  key[b.pt_off[s] + j] = k;
+  atomicAdd(&counts[(size_t)s * kBCells + k], 1u);
+}
+
+// cursor holds global positions (scenes concatenated, cells scene-major);
+// perm receives the scene-local point index
+__global__ __launch_bounds__(kBlock) void k_b_scatter(BatchDev b, const uint32_t* __restrict__ key,
+                                                      uint32_t* __restrict__ cursor,
+                                                      uint32_t* __restrict__ perm) {
+  int s;
+  const int64_t j = block_point(b, &s);
+  if (j < 0) return;
+  const uint32_t pos = atomicAdd(&cursor[(size_t)s * kBCells + key[b.pt_off[s] + j]], 1u);
+  perm[pos] = (uint32_t)j;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_b_topk(BatchDev b, SearchDev q) {
+  int s;
+  const int64_t j = block_point(b, &s);
+  if (j < 0) return;
+  const SceneDev sc = b.tab[s];
+  topk_point<T>(sc, q, j);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_b_features(BatchDev b, float z_near,
+                                                       uint16_t* __restrict__ feats) {
+  int s;
+  const int64_t j = block_point(b, &s);
+  if (j < 0) return;
+  const SceneDev sc = b.tab[s];
+  features_point<T>(sc, z_near, j, 1, b.pt_off[s], feats);
+}
+
+// Persistent search over items 0..n_items-1 (item = global point position, or
+// list[item] when a list is given; n_items = *count then).  Each wave pops
+// `chunk` tiles of G items at a time; lane 0 pops and broadcasts, so the
+// whole wave leaves the loop together once the queue is exhausted.
+template <typename T, int P>
+__global__ __launch_bounds__(kBlock) void k_b_fuse(BatchDev b, SearchDev q, const uint32_t* list,
+                                                   const uint32_t* list_count,
+                                                   uint32_t* __restrict__ queue, int chunk) {
+  const Group gr = make_group(q.K);
+  const int64_t n_items = list ? (int64_t)*list_count : b.total;
+  const int64_t n_tiles = (n_items + gr.G - 1) / gr.G;
+  for (;;) {
+    uint32_t t0 = 0;
+    if ((threadIdx.x & 63) == 0) t0 = atomicAdd(queue, (uint32_t)chunk);
+    t0 = __builtin_amdgcn_readfirstlane(t0);
+    if ((int64_t)t0 >= n_tiles) break;
+    for (int c = 0; c < chunk; ++c) {
+      const int64_t tile = (int64_t)t0 + c;
+      if (tile >= n_tiles) break;  // uniform
+      const int64_t item = tile * gr.G + gr.g;
+      const bool pt_ok = gr.lane_ok && item < n_items;
+      const int64_t gpos = pt_ok ? (list ? (int64_t)list[item] : item) : 0;
+      const int s = find_scene(b.pt_off, b.n_scenes, gpos);
+      const SceneDev sc = b.tab[s];
+      fuse_group<T, P>(sc, q, gr, pt_ok, gpos - b.pt_off[s]);
+    }
+  }
+}
+
+template <typename T, int P>
+__global__ __launch_bounds__(kBlock) void k_b_learned(BatchDev b, SearchDev q, LearnedDev l) {
+  const Group gr = make_group(q.K);
+  const int64_t wave = (int64_t)blockIdx.x * (blockDim.x / kWave) + (threadIdx.x / kWave);
+  if (wave * gr.G >= b.total) return;
+  const int64_t item = wave * gr.G + gr.g;
+  const bool pt_ok = gr.lane_ok && item < b.total;
+  const int64_t gpos = pt_ok ? item : 0;
+  const int s = find_scene(b.pt_off, b.n_scenes, gpos);
+  const SceneDev sc = b.tab[s];
+  const int64_t j = gpos - b.pt_off[s];
+  learned_group<T, P>(sc, q, l, gr, pt_ok, j, 1, b.pt_off[s], b.pt_off[s]);
+}
+
+template <typename T, int P>
+hipError_t launch_b_search(const BatchDev& b, const SearchDev& q, const LearnedDev* l,
+                           const uint32_t* list, const uint32_t* count, uint32_t* queue,
+                           int chunk, int grid, hipStream_t st) {
+  if (l) {
+    const int G = kWave / q.K;
+    const int64_t nb = (b.total + 4 * (int64_t)G - 1) / (4 * (int64_t)G);
+    hipLaunchKernelGGL((k_b_learned<T, P>), dim3((unsigned)nb), dim3(kBlock), 0, st, b, q, *l);
+  } else {
+    hipLaunchKernelGGL((k_b_fuse<T, P>), dim3(grid), dim3(kBlock), 0, st, b, q, list, count,
+                       queue, chunk);
+  }
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t dispatch_search(int patch, const BatchDev& b, const SearchDev& q, const LearnedDev* l,
+                           const uint32_t* list, const uint32_t* count, uint32_t* queue,
+                           int chunk, int grid, hipStream_t st) {
+  switch (patch) {
+    case 1: return launch_b_search<T, 1>(b, q, l, list, count, queue, chunk, grid, st);
+    case 3: return launch_b_search<T, 3>(b, q, l, list, count, queue, chunk, grid, st);
+    case 5: return launch_b_search<T, 5>(b, q, l, list, count, queue, chunk, grid, st);
+    case 7: return launch_b_search<T, 7>(b, q, l, list, count, queue, chunk, grid, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t search(int dtype, int patch, const BatchDev& b, const SearchDev& q, const LearnedDev* l,
+                  const uint32_t* list, const uint32_t* count, uint32_t* queue, int chunk,
+                  int grid, hipStream_t st) {
+  return dtype == 1 ? dispatch_search<__half>(patch, b, q, l, list, count, queue, chunk, grid, st)
+                    : dispatch_search<float>(patch, b, q, l, list, count, queue, chunk, grid, st);
+}
+
+// resident workgroups of the persistent search kernel on this device
+int persistent_grid(int dtype, int patch, int per_cu_cap) {
+  static int cache[2][8][2] = {};  // [dtype][patch][0 = grid]
+  int& g = cache[dtype & 1][patch & 7][0];
+  if (g) return per_cu_cap > 0 ? std::min(g, per_cu_cap) : g;
+  int dev = 0, cus = 256, occ = 1;
+  (void)hipGetDevice(&dev);
+  (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  const void* fn = nullptr;
+#define FD_FN(T, P) (const void*)(&k_b_fuse<T, P>)
+  if (dtype == 1)
+    fn = patch == 1 ? FD_FN(__half, 1) : patch == 3 ? FD_FN(__half, 3) : patch == 5 ? FD_FN(__half, 5) : FD_FN(__half, 7);
+  else
+    fn = patch == 1 ? FD_FN(float, 1) : patch == 3 ? FD_FN(float, 3) : patch == 5 ? FD_FN(float, 5) : FD_FN(float, 7);
+#undef FD_FN
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, fn, kBlock, 0) != hipSuccess || occ < 1)
+    occ = 1;
+  g = cus * occ;
+  return g;
+}
+
+uint64_t fnv(uint64_t h, const void* p, size_t n) {
+  const unsigned char* c = (const unsigned char*)p;
+  for (size_t i = 0; i < n; ++i) h = (h ^ c[i]) * 1099511628211ull;
+  return h;
+}
+
+}  // namespace
+
+// ---- workspace --------------------------------------------------------------------------
+
+int fd::context_reserve_scenes(fd_context* c, int32_t n_scenes, int64_t total_points) {
+  if (n_scenes <= 0) return FD_OK;
+  if (n_scenes > FD_MAX_BATCH_SCENES)
+    return set_error(FD_E_INVAL, "fd_context_reserve: at most %d scenes per batched call",
+                     FD_MAX_BATCH_SCENES);
+  if (c->max_scenes >= n_scenes && c->scene_tab) return FD_OK;
+  auto fr = [](void* p) {
+    if (p) (void)hipFree(p);
+  };
+  fr(c->scene_tab);
+  fr(c->tile_tab);
+  fr(c->tile_queue);
+  fr(c->batch_key);
+  fr(c->batch_perm);
+  c->scene_tab = c->tile_tab = nullptr;
+  c->tile_queue = c->batch_key = c->batch_perm = nullptr;
+  const size_t S = (size_t)FD_MAX_BATCH_SCENES;
+  hipError_t e = hipMalloc(&c->scene_tab, S * sizeof(SceneDev) + 2 * (S + 1) * sizeof(int64_t));
+  if (e == hipSuccess) e = hipMalloc(&c->tile_tab, S * 6 * sizeof(int));              // bboxes
+  if (e == hipSuccess) e = hipMalloc((void**)&c->tile_queue, 4 * sizeof(uint32_t));  // queue
+  if (e == hipSuccess) e = hipMalloc((void**)&c->batch_key, S * kBCells * sizeof(uint32_t));
+  if (e == hipSuccess) e = hipMalloc((void**)&c->batch_perm, (S * kBCells + 1024) * sizeof(uint32_t));
+  if (e != hipSuccess) {
+    c->max_scenes = 0;
+    return hip_error(e, "batched workspace");
+  }
+  c->max_scenes = (int32_t)S;
+  (void)total_points;
+  return FD_OK;
+}
+
+// ---- the batched call --------------------------------------------------------------------
+
+static int record_batch(fd_context* c, const fd_params* p, int n_scenes, int64_t total,
+                        const int64_t* blk_off_host, hipStream_t st) {
+  SceneDev* tab = (SceneDev*)c->scene_tab;
+  int64_t* pt_off = (int64_t*)(tab + FD_MAX_BATCH_SCENES);
+  int64_t* blk_off = pt_off + (FD_MAX_BATCH_SCENES + 1);
+  BatchDev b{tab, pt_off, blk_off, n_scenes, total};
+  const int64_t nblocks = blk_off_host[n_scenes];
+  uint32_t* counts = c->batch_key;
+  uint32_t* cursor = c->batch_perm;
+  uint32_t* sums = c->batch_perm + FD_MAX_BATCH_SCENES * kBCells;
+  int* bbox = (int*)c->tile_tab;
+  hipError_t e;
+  // tiling
+  hipLaunchKernelGGL(k_b_init, dim3(256), dim3(256), 0, st, counts, (int64_t)n_scenes * kBCells,
+                     bbox, n_scenes);
+  hipLaunchKernelGGL(k_b_bbox, dim3((unsigned)nblocks), dim3(kBlock), 0, st, b, bbox);
+  hipLaunchKernelGGL(k_b_count, dim3((unsigned)nblocks), dim3(kBlock), 0, st, b, bbox, c->key,
+                     counts);
+  if ((e = launch_scan_runs(counts, n_scenes * (kBCells / 1024), sums, cursor, st)) != hipSuccess)
+    return hip_error(e, "batched scan");
+  hipLaunchKernelGGL(k_b_scatter, dim3((unsigned)nblocks), dim3(kBlock), 0, st, b, c->key, cursor,
+                     c->perm);
+  SearchDev q;
+  q.lattice = c->lattice;
+  q.n_candidates = p->n_candidates;
+  q.refine_iters = p->refine_iters;
+  q.step0 = p->refine_step0 > 0.0f ? p->refine_step0 : default_step0(p->n_candidates);
+  q.K = p->top_k;
+  q.z_near = p->z_near;
+  if (p->map_dtype == FD_F16)
+    hipLaunchKernelGGL(k_b_topk<__half>, dim3((unsigned)nblocks), dim3(kBlock), 0, st, b, q);
+  else
+    hipLaunchKernelGGL(k_b_topk<float>, dim3((unsigned)nblocks), dim3(kBlock), 0, st, b, q);
+  if ((e = hipGetLastError()) != hipSuccess) return hip_error(e, "batched view selection");
+  const int chunk = c->tuned_chunk > 0 ? c->tuned_chunk : 2;
+  const int grid = persistent_grid(p->map_dtype, p->patch, c->tuned_grid);
+  uint32_t* queue = c->tile_queue;
+  if (p->mode == FD_MODE_PLAIN) {
+    if ((e = launch_fill_u32(queue, 1, 0u, st)) != hipSuccess) return hip_error(e, "queue reset");
+    if ((e = search(p->map_dtype, p->patch, b, q, nullptr, nullptr, nullptr, queue, chunk, grid,
+                    st)) != hipSuccess)
+      return hip_error(e, "batched search");
+    return FD_OK;
+  }
+  // learned
+  LearnedDev l;
+  l.iters = p->learned_iters;
+  l.tau = p->fallback_cost;
+  l.fb_list = c->fb_list;
+  l.fb_count = c->fb_count;
+  float step0 = p->learned_step0;
+  if (!(step0 > 0.0f)) {
+    float s0 = 0.0f, tau = 0.0f;
+    fd_mlp_get_calibration(p->mlp, &s0, &tau);
+    step0 = s0 > 0.0f ? s0 : default_step0(p->n_candidates);
+  }
+  l.step0 = step0;
+  if (p->map_dtype == FD_F16)
+    hipLaunchKernelGGL(k_b_features<__half>, dim3((unsigned)nblocks), dim3(kBlock), 0, st, b,
+                       p->z_near, c->feats);
+  else
+    hipLaunchKernelGGL(k_b_features<float>, dim3((unsigned)nblocks), dim3(kBlock), 0, st, b,
+                       p->z_near, c->feats);
+  int r = mlp_forward_dev(p->mlp, c->feats, total, c->prop, st);
+  if (r) return r;
+  l.proposals = c->prop;
+  if ((e = launch_fill_u32(c->fb_count, 1, 0u, st)) != hipSuccess)
+    return hip_error(e, "fallback counter reset");
+  if ((e = search(p->map_dtype, p->patch, b, q, &l, nullptr, nullptr, queue, chunk, grid, st)) !=
+      hipSuccess)
+    return hip_error(e, "batched learned refinement");
+  if ((e = launch_fill_u32(queue, 1, 0u, st)) != hipSuccess) return hip_error(e, "queue reset");
+  if ((e = search(p->map_dtype, p->patch, b, q, nullptr, c->fb_list, c->fb_count, queue, chunk,
+                  grid, st)) != hipSuccess)
+    return hip_error(e, "batched fallback search");
+  return FD_OK;
+}
+
+extern "C" int fd_fuse_directions_batched(const fd_scene* scenes, int32_t n_scenes,
+                                          const fd_params* params, fd_context* ctx) {
+  const char* fn = "fd_fuse_directions_batched";
+  int r;
+  if ((r = check_search_params(params, fn))) return r;
+  if (!ctx) return set_error(FD_E_INVAL, "%s: a context is required", fn);
+  if (n_scenes < 0 || (n_scenes > 0 && !scenes))
+    return set_error(FD_E_INVAL, "%s: bad scene array", fn);
+  if (n_scenes > FD_MAX_BATCH_SCENES)
+    return set_error(FD_E_INVAL, "%s: at most %d scenes per call, got %d", fn,
+                     FD_MAX_BATCH_SCENES, n_scenes);
+  if (params->proposal != FD_PROPOSAL_MLP && params->mode == FD_MODE_LEARNED)
+    return set_error(FD_E_INVAL, "%s: the batched learned form takes the network proposal", fn);
+  int64_t total = 0;
+  std::vector<int64_t> pt_off(n_scenes + 1, 0), blk_off(n_scenes + 1, 0);
+  for (int s = 0; s < n_scenes; ++s) {
+    const fd_scene& sc = scenes[s];
+    if (sc.n_points < 0) return set_error(FD_E_INVAL, "%s: scene %d has n_points < 0", fn, s);
+    if (sc.n_views < 1 || sc.n_views > FD_MAX_VIEWS)
+      return set_error(FD_E_INVAL, "%s: scene %d n_views out of range", fn, s);
+    if (params->top_k > sc.n_views)
+      return set_error(FD_E_INVAL, "%s: scene %d has fewer views than top_k", fn, s);
+    if (sc.width < 1 || sc.height < 1 || sc.width > 32768 || sc.height > 32768)
+      return set_error(FD_E_INVAL, "%s: scene %d map size out of range", fn, s);
+    if (sc.n_points > 0 && (!sc.points || !sc.cams || !sc.orient_maps || !sc.conf_maps ||
+                            !sc.dirs || !sc.costs))
+      return set_error(FD_E_INVAL, "%s: scene %d has a null pointer", fn, s);
+    total += sc.n_points;
+    pt_off[s + 1] = total;
+    blk_off[s + 1] = blk_off[s] + (sc.n_points + kBlock - 1) / kBlock;
+  }
+  if (total > (int64_t)UINT32_MAX) return set_error(FD_E_INVAL, "%s: too many points", fn);
+  if ((r = check_device(nullptr))) return r;
+  if (total == 0) return FD_OK;
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  if (ctx->device != dev)
+    return set_error(FD_E_INVAL, "%s: context belongs to device %d", fn, ctx->device);
+  if (ctx->max_points < total)
+    return set_error(FD_E_NOMEM, "%s: context reserved for %lld points, call has %lld", fn,
+                     (long long)ctx->max_points, (long long)total);
+  if (ctx->max_scenes < n_scenes || !ctx->scene_tab)
+    return set_error(FD_E_NOMEM, "%s: context has no batched workspace (fd_context_reserve "
+                     "with max_scenes)", fn);
+  hipStream_t st = (hipStream_t)params->stream;
+  // signature of everything the captured sequence depends on
+  uint64_t sig = 1469598103934665603ull;
+  sig = fnv(sig, scenes, sizeof(fd_scene) * (size_t)n_scenes);
+  fd_params pc = *params;
+  pc.stream = nullptr;
+  sig = fnv(sig, &pc, sizeof pc);
+  sig = fnv(sig, &ctx->tuned_chunk, sizeof ctx->tuned_chunk);
+  sig = fnv(sig, &ctx->tuned_grid, sizeof ctx->tuned_grid);
+  StageTimer tb(ctx, FD_STAGE_BATCHED, st);
+  if (!ctx->graph_exec || ctx->graph_sig != sig) {
+    if (ctx->graph_exec) (void)hipGraphExecDestroy(ctx->graph_exec);
+    if (ctx->graph) (void)hipGraphDestroy(ctx->graph);
+    ctx->graph_exec = nullptr;
+    ctx->graph = nullptr;
+    // scene table (host -> device once per scene set, outside the graph)
+    std::vector<SceneDev> tab(n_scenes);
+    for (int s = 0; s < n_scenes; ++s) {
+      const fd_scene& sc = scenes[s];
+      SceneDev d{};
+      d.pts = sc.points;
+      d.cams = (const float*)sc.cams;
+      d.theta = sc.orient_maps;
+      d.conf = sc.conf_maps;
+      d.dirs = sc.dirs;
+      d.costs = sc.costs;
+      d.perm = ctx->perm + pt_off[s];
+      d.views = ctx->views + (size_t)FD_TOPK_SLOTS * pt_off[s];
+      d.kcount = ctx->kcount + pt_off[s];
+      d.n = sc.n_points;
+      d.V = sc.n_views;
+      d.W = sc.width;
+      d.H = sc.height;
+      for (int k = 0; k < 3; ++k) d.hc[k] = sc.head_centre[k];
+      tab[s] = d;
+    }
+    SceneDev* dtab = (SceneDev*)ctx->scene_tab;
+    int64_t* dpt = (int64_t*)(dtab + FD_MAX_BATCH_SCENES);
+    int64_t* dblk = dpt + (FD_MAX_BATCH_SCENES + 1);
+    hipError_t e = hipStreamSynchronize(st);
+    if (e == hipSuccess) e = hipMemcpy(dtab, tab.data(), sizeof(SceneDev) * n_scenes, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(dpt, pt_off.data(), sizeof(int64_t) * (n_scenes + 1), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(dblk, blk_off.data(), sizeof(int64_t) * (n_scenes + 1), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_error(e, "batched scene table upload");
+    if ((r = ensure_lattice(ctx, params->n_candidates, st))) return r;
+    if ((e = hipStreamSynchronize(st)) != hipSuccess) return hip_error(e, "lattice");
+    (void)persistent_grid(params->map_dtype, params->patch, 0);  // host query, before capture
+    if (!ctx->cap_stream) {
+      e = hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking);
+      if (e != hipSuccess) return hip_error(e, "capture stream");
+    }
+    e = hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return hip_error(e, "hipStreamBeginCapture");
+    const bool prof = ctx->profiling;
+    ctx->profiling = false;  // no event records inside the graph
+    r = record_batch(ctx, params, n_scenes, total, blk_off.data(), ctx->cap_stream);
+    ctx->profiling = prof;
+    hipGraph_t g = nullptr;
+    e = hipStreamEndCapture(ctx->cap_stream, &g);
+    if (r) {
+      if (g) (void)hipGraphDestroy(g);
+      return r;
+    }
+    if (e != hipSuccess) return hip_error(e, "hipStreamEndCapture");
+    hipGraphExec_t ge = nullptr;
+    e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+      (void)hipGraphDestroy(g);
+      return hip_error(e, "hipGraphInstantiate");
+    }
+    ctx->graph = g;
+    ctx->graph_exec = ge;
+    ctx->graph_sig = sig;
+  }
+  hipError_t e = hipGraphLaunch(ctx->graph_exec, st);
+  if (e != hipSuccess) return hip_error(e, "hipGraphLaunch");
+  tb.stop();
+  return FD_OK;
+}
+
+// ---- tuning --------------------------------------------------------------------------------
+
+struct TuneEntry {
+  std::string key;
+  int chunk, grid;
+};
+
+// Cache file: one JSON object {"<shape class>": {"chunk": c, "grid": g}, ...}.
+static std::vector<TuneEntry> load_cache(const char* path) {
+  std::vector<TuneEntry> out;
+  FILE* f = fopen(path, "r");
+  if (!f) return out;
+  std::string s;
+  char buf[4096];
+  size_t n;
+  while ((n = fread(buf, 1, sizeof buf, f)) > 0) s.append(buf, n);
+  fclose(f);
+  size_t pos = 0;
+  while ((pos = s.find('"', pos)) != std::string::npos) {
+    const size_t end = s.find('"', pos + 1);
+    if (end == std::string::npos) break;
+    const std::string key = s.substr(pos + 1, end - pos - 1);
+    int chunk = 0, grid = 0;
+    if (key != "chunk" && key != "grid" &&
+        sscanf(s.c_str() + end + 1, " : {\"chunk\": %d, \"grid\": %d}", &chunk, &grid) == 2)
+      out.push_back({key, chunk, grid});
+    pos = end + 1;
+  }
+  return out;
+}
+
+static void save_cache(const char* path, const std::vector<TuneEntry>& es) {
+  FILE* f = fopen(path, "w");
+  if (!f) return;
+  fprintf(f, "{\n");
+  for (size_t i = 0; i < es.size(); ++i)
+    fprintf(f, "  \"%s\": {\"chunk\": %d, \"grid\": %d}%s\n", es[i].key.c_str(), es[i].chunk,
+            es[i].grid, i + 1 < es.size() ? "," : "");
+  fprintf(f, "}\n");
+  fclose(f);
+}
+
+static std::string shape_class(const fd_params* p, int64_t total) {
+  int lg = 0;
+  while ((int64_t)1 << (lg + 1) <= total) ++lg;
+  char buf[96];
+  snprintf(buf, sizeof buf, "P%d_K%d_%s_%s_n2e%d", p->patch, p->top_k,
+           p->map_dtype == FD_F16 ? "f16" : "f32", p->mode == FD_MODE_PLAIN ? "plain" : "learned",
+           lg);
+  return buf;
+}
+
+extern "C" int fd_autotune(fd_context* ctx, const fd_scene* sample, int32_t n_scenes,
+                           const fd_params* params, const char* cache_path) {
+  const char* fn = "fd_autotune";
+  int r;
+  if (!ctx || !params) return set_error(FD_E_INVAL, "%s: null argument", fn);
+  int64_t total = 0;
+  for (int s = 0; s < n_scenes; ++s) total += sample[s].n_points;
+  const std::string key = shape_class(params, total);
+  std::vector<TuneEntry> cache;
+  if (cache_path) {
+    cache = load_cache(cache_path);
+    for (const TuneEntry& t : cache)
+      if (t.key == key && t.chunk > 0) {
+        ctx->tuned_chunk = t.chunk;
+        ctx->tuned_grid = t.grid;
+        return FD_OK;
+      }
+  }
+  hipStream_t st = (hipStream_t)params->stream;
+  const int full = persistent_grid(params->map_dtype, params->patch, 0);
+  const int chunks[] = {1, 2, 4, 8};
+  const int grids[] = {full / 2, (3 * full) / 4, full};
+  float best = INFINITY;
+  int best_chunk = 2, best_grid = full;
+  hipEvent_t a, b;
+  if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess)
+    return set_error(FD_E_HIP, "%s: event creation failed", fn);
+  for (int ci : chunks) {
+    for (int gi : grids) {
+      if (gi < 1) continue;
+      ctx->tuned_chunk = ci;
+      ctx->tuned_grid = gi;
+      if ((r = fd_fuse_directions_batched(sample, n_scenes, params, ctx))) goto done;  // capture
+      (void)hipEventRecord(a, st);
+      for (int rep = 0; rep < 3; ++rep)
+        if ((r = fd_fuse_directions_batched(sample, n_scenes, params, ctx))) goto done;
+      (void)hipEventRecord(b, st);
+      (void)hipEventSynchronize(b);
+      float ms = 0.0f;
+      (void)hipEventElapsedTime(&ms, a, b);
+      if (ms < best) {
+        best = ms;
+        best_chunk = ci;
+        best_grid = gi;
+      }
+    }
+  }
+  r = FD_OK;
+done:
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  ctx->tuned_chunk = best_chunk;
+  ctx->tuned_grid = best_grid;
+  if (r) return r;
+  if (cache_path) {
+    cache.push_back({key, best_chunk, best_grid});
+    save_cache(cache_path, cache);
+  }
+  return FD_OK;
+}

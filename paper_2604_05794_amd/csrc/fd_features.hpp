@@ -1,0 +1,177 @@
+// fd_features.hpp -- per-point device code of the proposal-network input
+// (the most frontal views of a point and what each of them observes).
+#pragma once
+
+#include <hip/hip_fp16.h>
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+#include "../../include/fusedir.h"
+#include "fd_device.hpp"
+#include "fd_kernels.hpp"
+#include "fd_search.hpp"
+
+namespace fd {
+
+constexpr int kSlots = FD_FEATURE_SLOTS;
+
+__device__ __forceinline__ uint16_t feat_bf16(float x) {
+  // round to nearest even
+  uint32_t u = __float_as_uint(x);
+  if ((u & 0x7f800000u) == 0x7f800000u) return (uint16_t)((u >> 16) | ((u & 0xffffu) ? 0x40u : 0u));
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+
+// Frontal ranking key of a view, decided in binary32 with a fixed order:
+//   c = -R^T t  (c_x = -fma(R0, t0, fma(R3, t1, R6*t2)), likewise y, z)
+//   a = c - p, b = p - o
+//   score = fma(a_x, b_x, fma(a_y, b_y, a_z*b_z)) / sqrt(fma(a_x, a_x, fma(a_y, a_y, a_z*a_z)))
+// i.e. the cosine between the point->camera direction and the outward
+// direction p - o, times |p - o| (common to every view of the point).
+__device__ __forceinline__ float frontal_score32(const float* cam, float px, float py, float pz,
+                                                 const float* o, float* vdir) {
+  const float* R = cam + 4;
+  const float* t = cam + 13;
+  const float cx = -__builtin_fmaf(R[0], t[0], __builtin_fmaf(R[3], t[1], R[6] * t[2]));
+  const float cy = -__builtin_fmaf(R[1], t[0], __builtin_fmaf(R[4], t[1], R[7] * t[2]));
+  const float cz = -__builtin_fmaf(R[2], t[0], __builtin_fmaf(R[5], t[1], R[8] * t[2]));
+  const float ax = cx - px, ay = cy - py, az = cz - pz;
+  const float bx = px - o[0], by = py - o[1], bz = pz - o[2];
+  const float dot = __builtin_fmaf(ax, bx, __builtin_fmaf(ay, by, az * bz));
+  const float la = sqrtf(__builtin_fmaf(ax, ax, __builtin_fmaf(ay, ay, az * az)));
+  if (vdir) {
+    vdir[0] = ax / la;
+    vdir[1] = ay / la;
+    vdir[2] = az / la;
+  }
+  return dot / la;
+}
+
+// One lane per point: the kSlots most frontal eligible views (stable: equal
+// scores keep the lower view index first), then per slot the observed
+// orientation as (q_x, q_y) = |m| (cos 2psi, sin 2psi) (m the bilinear
+// confidence-weighted doubled-angle vector, psi the angle of the plane it
+// back-projects to, in a frame tied to the line of sight), the bilinear
+// confidence C, the unit point->camera direction and 1; empty slots are 0.
+// Row r of `feats` (112 bfloat16) is the processing-order index when by_j,
+// else the point index.
+template <typename T>
+__device__ __forceinline__ void features_point(const SceneDev& s, float z_near, int64_t j,
+                                               int by_j, int64_t row_base,
+                                               uint16_t* __restrict__ feats) {
+  const uint32_t i = s.perm ? s.perm[j] : (uint32_t)j;
+  const float px = s.pts[3 * (size_t)i], py = s.pts[3 * (size_t)i + 1],
+              pz = s.pts[3 * (size_t)i + 2];
+  float sc[kSlots];
+  int id[kSlots];
+#pragma unroll
+  for (int k = 0; k < kSlots; ++k) {
+    sc[k] = -INFINITY;
+    id[k] = -1;
+  }
+  for (int v = 0; v < s.V; ++v) {
+    Proj pr;
+    if (!project32(s.cams + 16 * v, px, py, pz, s.W, s.H, z_near, pr)) continue;
+    float cs = frontal_score32(s.cams + 16 * v, px, py, pz, s.hc, nullptr);
+    int cv = v;
+    bool ins = false;
+#pragma unroll
+    for (int k = 0; k < kSlots; ++k) {
+      bool take = ins || (cs > sc[k]) || (!ins && id[k] < 0);
+      float ts = sc[k];
+      int tv = id[k];
+      sc[k] = take ? cs : ts;
+      id[k] = take ? cv : tv;
+      cs = take ? ts : cs;
+      cv = take ? tv : cv;
+      ins = ins || take;
+    }
+  }
+  const T* th = (const T*)s.theta;
+  const T* cf = (const T*)s.conf;
+  const size_t plane = (size_t)s.W * s.H;
+  uint16_t out[7 * kSlots];
+#pragma unroll
+  for (int k = 0; k < kSlots; ++k) {
+    float f[7] = {0, 0, 0, 0, 0, 0, 0};
+    if (id[k] >= 0) {
+      const int v = id[k];
+      const float* cam = s.cams + 16 * v;
+      Proj pr;
+      project32(cam, px, py, pz, s.W, s.H, z_near, pr);
+      const float x0 = floorf(pr.u), y0 = floorf(pr.v);
+      const float fx = pr.u - x0, fy = pr.v - y0;
+      const int ix = (int)x0, iy = (int)y0;
+      float cb = 0.0f, mx = 0.0f, my = 0.0f;
+#pragma unroll
+      for (int b = 0; b < 2; ++b)
+#pragma unroll
+        for (int a = 0; a < 2; ++a) {
+          const float w = (a ? fx : 1.0f - fx) * (b ? fy : 1.0f - fy);
+          const float t = tex_load_nb<T>(th + plane * v, s.W, s.H, ix + a, iy + b);
+          const float c = tex_load_nb<T>(cf + plane * v, s.W, s.H, ix + a, iy + b);
+          const float wc = w * c;
+          cb += wc;
+          mx += wc * __builtin_amdgcn_cosf(t * kInvPi);
+          my += wc * __builtin_amdgcn_sinf(t * kInvPi);
+        }
+      float vd[3];
+      frontal_score32(cam, px, py, pz, s.hc, vd);
+      // The observed image line back-projects to a plane through the camera
+      // centre containing the line of sight vd; its direction across vd,
+      // tt = n x vd, is given by the angle psi in the frame
+      // e1 = normalize(z x vd), e2 = vd x e1, carried as |m| (cos 2psi, sin 2psi).
+      float qx = 0.0f, qy = 0.0f;
+      const float mag = sqrtf(mx * mx + my * my);
+      if (mag > 0.0f) {
+        const float ch = mx / mag, sh = my / mag;  // cos, sin of 2 theta
+        const float ox = sqrtf(fmaxf(0.5f * (1.0f + ch), 0.0f));
+        const float oy = copysignf(sqrtf(fmaxf(0.5f * (1.0f - ch), 0.0f)), sh);
+        const float dlx = ox / cam[0], dly = oy / cam[1];
+        const float ncx = -pr.Z * dly, ncy = pr.Z * dlx, ncz = pr.X * dly - pr.Y * dlx;
+        const float* R = cam + 4;
+        const float nwx = R[0] * ncx + R[3] * ncy + R[6] * ncz;
+        const float nwy = R[1] * ncx + R[4] * ncy + R[7] * ncz;
+        const float nwz = R[2] * ncx + R[5] * ncy + R[8] * ncz;
+        const float tx = nwy * vd[2] - nwz * vd[1];
+        const float ty = nwz * vd[0] - nwx * vd[2];
+        const float tz = nwx * vd[1] - nwy * vd[0];
+        const bool vert = fabsf(vd[2]) > 1.0f - 1e-6f;
+        const float ux = vert ? 1.0f : 0.0f, uz = vert ? 0.0f : 1.0f;
+        // e1 = up x vd, up = (ux, 0, uz)
+        float e1x = -uz * vd[1], e1y = uz * vd[0] - ux * vd[2], e1z = ux * vd[1];
+        const float il = 1.0f / sqrtf(e1x * e1x + e1y * e1y + e1z * e1z);
+        e1x *= il;
+        e1y *= il;
+        e1z *= il;
+        const float e2x = vd[1] * e1z - vd[2] * e1y;
+        const float e2y = vd[2] * e1x - vd[0] * e1z;
+        const float e2z = vd[0] * e1y - vd[1] * e1x;
+        const float t1 = tx * e1x + ty * e1y + tz * e1z;
+        const float t2 = tx * e2x + ty * e2y + tz * e2z;
+        const float tn = t1 * t1 + t2 * t2;
+        if (tn > 0.0f) {
+          qx = mag * (t1 * t1 - t2 * t2) / tn;
+          qy = mag * 2.0f * t1 * t2 / tn;
+        }
+      }
+      f[0] = qx;
+      f[1] = qy;
+      f[2] = cb;
+      f[3] = vd[0];
+      f[4] = vd[1];
+      f[5] = vd[2];
+      f[6] = 1.0f;
+    }
+#pragma unroll
+    for (int e = 0; e < 7; ++e) out[7 * k + e] = feat_bf16(f[e]);
+  }
+  uint4* dst = (uint4*)(feats + (size_t)(row_base + (by_j ? j : (int64_t)i)) * (7 * kSlots));
+  const uint4* src = (const uint4*)out;
+#pragma unroll
+  for (int e = 0; e < (7 * kSlots * 2) / 16; ++e) dst[e] = src[e];
+}
+
+}  // namespace fd

@@ -25,10 +25,9 @@
 
 #include "fd_device.hpp"
 #include "fd_kernels.hpp"
+#include "fd_search.hpp"
 
 namespace fd {
-
-constexpr float kInvPi = 0.318309886183790671538f;
 
 // ---- candidate lattice ------------------------------------------------------
 // Hemisphere Fibonacci lattice (Gonzalez 2010): z_k = 1 - (k + 1/2)/n,
@@ -50,66 +49,11 @@ hipError_t launch_lattice(float* lattice, int n, hipStream_t st) {
   return hipGetLastError();
 }
 
-// ---- Eq. (4): top-K views by centre confidence ------------------------------
-// One lane per point (processing order).  Stable insertion into a register
-// list of 8: a view enters ahead of a listed one only if strictly more
-// confident, so equal confidences keep the lower view index first.
 template <typename T>
 __global__ __launch_bounds__(256) void k_topk(SceneDev s, SearchDev q) {
   int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= s.n) return;
-  const uint32_t i = s.perm[j];
-  const float px = s.pts[3 * (size_t)i], py = s.pts[3 * (size_t)i + 1],
-              pz = s.pts[3 * (size_t)i + 2];
-  float sc[FD_TOPK_SLOTS];
-  int id[FD_TOPK_SLOTS];
-#pragma unroll
-  for (int k = 0; k < FD_TOPK_SLOTS; ++k) {
-    sc[k] = -1.0f;
-    id[k] = 0;
-  }
-  const T* conf = (const T*)s.conf;
-  const size_t plane = (size_t)s.W * s.H;
-  // views in groups of four: projections and the 16 texel loads of a group
-  // are independent, so they are issued before the (ordered) insertions
-  constexpr int kGroup = 4;
-  for (int v0 = 0; v0 < s.V; v0 += kGroup) {
-    float cg[kGroup];
-#pragma unroll
-    for (int u = 0; u < kGroup; ++u) {
-      const int v = min(v0 + u, s.V - 1);
-      Proj pr;
-      const bool ok = project32(s.cams + 16 * v, px, py, pz, s.W, s.H, q.z_near, pr);
-      const float c = centre_conf32<T>(conf + plane * v, s.W, s.H, ok ? pr.u : 0.0f,
-                                       ok ? pr.v : 0.0f);
-      cg[u] = (ok && v0 + u < s.V) ? c : 0.0f;
-    }
-#pragma unroll
-    for (int u = 0; u < kGroup; ++u) {
-      if (!(cg[u] > 0.0f)) continue;
-      float cs = cg[u];
-      int cv = v0 + u;
-      bool ins = false;
-#pragma unroll
-      for (int k = 0; k < FD_TOPK_SLOTS; ++k) {
-        bool take = ins || (cs > sc[k]);
-        float ts = sc[k];
-        int tv = id[k];
-        sc[k] = take ? cs : ts;
-        id[k] = take ? cv : tv;
-        cs = take ? ts : cs;
-        cv = take ? tv : cv;
-        ins = take;
-      }
-    }
-  }
-  int keff = 0;
-#pragma unroll
-  for (int k = 0; k < FD_TOPK_SLOTS; ++k) {
-    if (k < q.K && sc[k] > 0.0f) keff = k + 1;
-    s.views[FD_TOPK_SLOTS * j + k] = (uint16_t)id[k];
-  }
-  s.kcount[j] = (uint8_t)keff;
+  topk_point<T>(s, q, j);
 }
 
 hipError_t launch_topk(const SceneDev& s, const SearchDev& q, int dtype, hipStream_t st) {
@@ -120,195 +64,6 @@ hipError_t launch_topk(const SceneDev& s, const SearchDev& q, int dtype, hipStre
   else
     hipLaunchKernelGGL(k_topk<float>, grid, dim3(256), 0, st, s, q);
   return hipGetLastError();
-}
-
-// ---- per-lane view state ------------------------------------------------------
-
-template <int P>
-struct ViewPatch {
-  static constexpr int P2 = P * P;
-  float a[P2], b[P2], c[P2];  // quadratic-form coefficients per patch sample
-  float M[6];                  // image direction r = M d (rows of the projection Jacobian)
-};
-
-// Build the lane's view state: Jacobian rows and the P x P patch of Sec. 3.1.3
-// centred on the projection (offsets (a, b) in {-h..h}^2 pixels from the
-// sub-pixel centre, each a bilinear sample of the doubled-angle vector
-// weighted by bilinear weight times confidence, zero outside the image).
-template <typename T, int P>
-__device__ __forceinline__ void build_patch(const SceneDev& s, const SearchDev& q, int view,
-                                            bool active, float px, float py, float pz,
-                                            ViewPatch<P>& vp) {
-  constexpr int P2 = P * P, HP = (P - 1) / 2;
-#pragma unroll
-  for (int k = 0; k < P2; ++k) vp.a[k] = vp.b[k] = vp.c[k] = 0.0f;
-#pragma unroll
-  for (int k = 0; k < 6; ++k) vp.M[k] = 0.0f;
-  if (!active) return;
-  const float* cam = s.cams + 16 * view;
-  Proj pr;
-  project32(cam, px, py, pz, s.W, s.H, q.z_near, pr);
-  // r = J_pi d up to the positive factor 1/Z^2:
-  //   r_x = fx (Z (R0 . d) - X (R2 . d)),  r_y = fy (Z (R1 . d) - Y (R2 . d))
-  const float* R = cam + 4;
-  vp.M[0] = cam[0] * (pr.Z * R[0] - pr.X * R[6]);
-  vp.M[1] = cam[0] * (pr.Z * R[1] - pr.X * R[7]);
-  vp.M[2] = cam[0] * (pr.Z * R[2] - pr.X * R[8]);
-  vp.M[3] = cam[1] * (pr.Z * R[3] - pr.Y * R[6]);
-  vp.M[4] = cam[1] * (pr.Z * R[4] - pr.Y * R[7]);
-  vp.M[5] = cam[1] * (pr.Z * R[5] - pr.Y * R[8]);
-
-  const size_t plane = (size_t)s.W * s.H;
-  const T* th = (const T*)s.theta + plane * view;
-  const T* cf = (const T*)s.conf + plane * view;
-  const float x0 = floorf(pr.u), y0 = floorf(pr.v);
-  const float fx = pr.u - x0, fy = pr.v - y0;
-  const float gx = 1.0f - fx, gy = 1.0f - fy;
-  const float w00 = gx * gy, w10 = fx * gy, w01 = gx * fy, w11 = fx * fy;
-  const int ix = (int)x0 - HP, iy = (int)y0 - HP;
-  // texel rows of the (P+1)^2 footprint: C, C cos 2theta, C sin 2theta
-  float rc[2][P + 1], rx[2][P + 1], ry[2][P + 1];
-  auto load_row = [&](int slot, int y) {
-#pragma unroll
-    for (int a = 0; a <= P; ++a) {
-      float t = tex_load_nb<T>(th, s.W, s.H, ix + a, y);
-      float c = tex_load_nb<T>(cf, s.W, s.H, ix + a, y);
-      float turns = t * kInvPi;  // 2 theta in revolutions
-      rc[slot][a] = c;
-      rx[slot][a] = c * __builtin_amdgcn_cosf(turns);
-      ry[slot][a] = c * __builtin_amdgcn_sinf(turns);
-    }
-  };
-  load_row(0, iy);
-#pragma unroll
-  for (int b = 0; b < P; ++b) {
-    const int r0 = b & 1, r1 = (b + 1) & 1;
-    load_row(r1, iy + b + 1);
-#pragma unroll
-    for (int a = 0; a < P; ++a) {
-      float cb = w00 * rc[r0][a] + w10 * rc[r0][a + 1] + w01 * rc[r1][a] + w11 * rc[r1][a + 1];
-      float mx = w00 * rx[r0][a] + w10 * rx[r0][a + 1] + w01 * rx[r1][a] + w11 * rx[r1][a + 1];
-      float my = w00 * ry[r0][a] + w10 * ry[r0][a + 1] + w01 * ry[r1][a] + w11 * ry[r1][a + 1];
-      float n2 = mx * mx + my * my;
-      float al = 0.5f * cb * cb;
-      float inv = n2 > 0.0f ? __builtin_amdgcn_rsqf(n2) : 0.0f;
-      const int k = b * P + a;
-      vp.a[k] = n2 > 0.0f ? al : 0.0f;
-      vp.b[k] = al * mx * inv;
-      vp.c[k] = al * my * inv;
-    }
-  }
-}
-
-// max_p C_p |cos(phi(d) - theta_p)| for this lane's view (0 if the tangent
-// projects to a point or the lane has no view).
-template <int P>
-__device__ __forceinline__ float eval_view(const ViewPatch<P>& vp, float dx, float dy,
-                                           float dz) {
-  constexpr int P2 = P * P;
-  float rx = __builtin_fmaf(vp.M[0], dx, __builtin_fmaf(vp.M[1], dy, vp.M[2] * dz));
-  float ry = __builtin_fmaf(vp.M[3], dx, __builtin_fmaf(vp.M[4], dy, vp.M[5] * dz));
-  float xx = rx * rx, yy = ry * ry;
-  float n2 = xx + yy;
-  float inv = n2 > 0.0f ? __builtin_amdgcn_rcpf(n2) : 0.0f;
-  float c2 = (xx - yy) * inv;
-  float s2 = 2.0f * rx * ry * inv;
-  float m = 0.0f;
-#pragma unroll
-  for (int k = 0; k + 1 < P2; k += 2) {
-    float q0 = __builtin_fmaf(vp.b[k], c2, __builtin_fmaf(vp.c[k], s2, vp.a[k]));
-    float q1 = __builtin_fmaf(vp.b[k + 1], c2, __builtin_fmaf(vp.c[k + 1], s2, vp.a[k + 1]));
-    m = __builtin_fmaxf(m, __builtin_fmaxf(q0, q1));
-  }
-  if (P2 & 1) {
-    float q0 = __builtin_fmaf(vp.b[P2 - 1], c2, __builtin_fmaf(vp.c[P2 - 1], s2, vp.a[P2 - 1]));
-    m = __builtin_fmaxf(m, q0);
-  }
-  return n2 > 0.0f ? __builtin_amdgcn_sqrtf(m) : 0.0f;
-}
-
-struct Group {
-  int K, G, g, slot, base;
-  bool lane_ok;
-};
-
-__device__ __forceinline__ Group make_group(int K) {
-  Group gr;
-  const int lane = threadIdx.x & (kWave - 1);
-  gr.K = K;
-  gr.G = kWave / K;
-  gr.g = lane / K;
-  gr.slot = lane - gr.g * K;
-  gr.lane_ok = gr.g < gr.G;
-  gr.base = (gr.lane_ok ? gr.g : gr.G - 1) * K;
-  return gr;
-}
-
-// Pattern search (six directions at angle alpha around d in the basis of
-// Duff et al. 2017, best strictly-better one taken, alpha halves).
-template <int P>
-__device__ __forceinline__ void refine(const ViewPatch<P>& vp, const Group& gr, float kinv,
-                                       int iters, float alpha, float& dx, float& dy, float& dz,
-                                       float& Jd) {
-  const float cj[6] = {1.0f, 0.5f, -0.5f, -1.0f, -0.5f, 0.5f};
-  const float sj[6] = {0.0f, 0.86602540378443865f, 0.86602540378443865f, 0.0f,
-                       -0.86602540378443865f, -0.86602540378443865f};
-  for (int t = 0; t < iters; ++t) {
-    const float sg = copysignf(1.0f, dz);
-    const float aa = -1.0f / (sg + dz);
-    const float bb = dx * dy * aa;
-    const float e1x = 1.0f + sg * dx * dx * aa, e1y = sg * bb, e1z = -sg * dx;
-    const float e2x = bb, e2y = sg + dy * dy * aa, e2z = -dy;
-    const float ca = cosf(alpha), sa = sinf(alpha);
-    float bJ = INFINITY, bx = dx, by = dy, bz = dz;
-#pragma unroll
-    for (int j = 0; j < 6; ++j) {
-      float ux = ca * dx + sa * (cj[j] * e1x + sj[j] * e2x);
-      float uy = ca * dy + sa * (cj[j] * e1y + sj[j] * e2y);
-      float uz = ca * dz + sa * (cj[j] * e1z + sj[j] * e2z);
-      float il = 1.0f / sqrtf(ux * ux + uy * uy + uz * uz);
-      ux *= il;
-      uy *= il;
-      uz *= il;
-      float L = eval_view<P>(vp, ux, uy, uz);
-      float J = 1.0f - group_sum(L, gr.base, gr.K) * kinv;
-      if (J < bJ) {
-        bJ = J;
-        bx = ux;
-        by = uy;
-        bz = uz;
-      }
-    }
-    if (bJ < Jd) {
-      Jd = bJ;
-      dx = bx;
-      dy = by;
-      dz = bz;
-    }
-    alpha *= 0.5f;
-  }
-}
-
-__device__ __forceinline__ void write_result(const SceneDev& s, uint32_t i, float dx, float dy,
-                                             float dz, float J) {
-  const bool flip = dz != 0.0f ? dz < 0.0f : (dy != 0.0f ? dy < 0.0f : dx < 0.0f);
-  const float sgn = flip ? -1.0f : 1.0f;
-  s.dirs[3 * (size_t)i] = sgn * dx;
-  s.dirs[3 * (size_t)i + 1] = sgn * dy;
-  s.dirs[3 * (size_t)i + 2] = sgn * dz;
-  s.costs[i] = J;
-}
-
-// Wave index with blocks of one XCD covering a contiguous range of tiles:
-// the dispatcher deals workgroups to the 8 XCDs round-robin, so remap
-// blockIdx so that neighbouring (spatially sorted) tiles share an L2.
-__device__ __forceinline__ int64_t xcd_tile(int64_t nblocks) {
-  const int64_t b = blockIdx.x;
-  const int64_t per = nblocks / 8, rem = nblocks % 8;
-  const int64_t xcd = b % 8, k = b / 8;
-  // XCD x owns logical blocks [start(x), start(x) + per + (x < rem))
-  const int64_t start = xcd * per + (xcd < rem ? xcd : rem);
-  return start + k;
 }
 
 // ---- plain search: lattice argmin + refinement ---------------------------------
@@ -325,35 +80,7 @@ __global__ __launch_bounds__(256) void k_fuse(SceneDev s, SearchDev q, const uin
   if (wave * gr.G >= limit) return;  // whole wave idle (uniform exit)
   const bool pt_ok = gr.lane_ok && t < limit;
   const int64_t j = pt_ok ? (list ? (int64_t)list[t] : t) : 0;
-  const uint32_t i = pt_ok ? s.perm[j] : 0u;
-  const int keff = pt_ok ? (int)s.kcount[j] : 0;
-  const bool slot_ok = pt_ok && gr.slot < keff;
-  const int view = slot_ok ? (int)s.views[FD_TOPK_SLOTS * j + gr.slot] : 0;
-  const float px = s.pts[3 * (size_t)i], py = s.pts[3 * (size_t)i + 1],
-              pz = s.pts[3 * (size_t)i + 2];
-  ViewPatch<P> vp;
-  build_patch<T, P>(s, q, view, slot_ok, px, py, pz, vp);
-  const float kinv = keff > 0 ? 1.0f / (float)keff : 0.0f;
-
-  float Jb = INFINITY;
-  int kb = 0;
-  for (int k = 0; k < q.n_candidates; ++k) {
-    const float dx = q.lattice[3 * k], dy = q.lattice[3 * k + 1], dz = q.lattice[3 * k + 2];
-    float L = eval_view<P>(vp, dx, dy, dz);
-    float J = 1.0f - group_sum(L, gr.base, gr.K) * kinv;
-    if (J < Jb) {
-      Jb = J;
-      kb = k;
-    }
-  }
-  float dx = q.lattice[3 * kb], dy = q.lattice[3 * kb + 1], dz = q.lattice[3 * kb + 2];
-  refine<P>(vp, gr, kinv, q.refine_iters, q.step0, dx, dy, dz, Jb);
-  if (pt_ok && gr.slot == 0) {
-    if (keff == 0)
-      write_result(s, i, 0.0f, 0.0f, 0.0f, INFINITY);
-    else
-      write_result(s, i, dx, dy, dz, Jb);
-  }
+  fuse_group<T, P>(s, q, gr, pt_ok, j);
 }
 
 template <typename T>
@@ -382,12 +109,6 @@ hipError_t launch_fuse(const SceneDev& s, const SearchDev& q, int dtype, int pat
                     : launch_fuse_t<float>(s, q, patch, list, list_count, st);
 }
 
-// ---- learned form: refinement from a proposal, threshold, compaction ------------
-// prop: proposals (x, y, z); in processing order (index j) when prop_by_j,
-// else in point order (index i); NULL = every proposal invalid.  A point is
-// kept when its proposal is a finite non-zero direction and the refined cost
-// satisfies J <= tau; otherwise its processing-order index is appended to
-// the fallback list (plain search).
 template <typename T, int P>
 __global__ __launch_bounds__(256) void k_learned(SceneDev s, SearchDev q, LearnedDev l,
                                                  int prop_by_j) {
@@ -397,38 +118,7 @@ __global__ __launch_bounds__(256) void k_learned(SceneDev s, SearchDev q, Learne
   const int64_t j = wave * gr.G + gr.g;
   if (wave * gr.G >= s.n) return;
   const bool pt_ok = gr.lane_ok && j < s.n;
-  const uint32_t i = pt_ok ? s.perm[j] : 0u;
-  const int keff = pt_ok ? (int)s.kcount[j] : 0;
-  const bool slot_ok = pt_ok && gr.slot < keff;
-  const int view = slot_ok ? (int)s.views[FD_TOPK_SLOTS * j + gr.slot] : 0;
-  const float px = s.pts[3 * (size_t)i], py = s.pts[3 * (size_t)i + 1],
-              pz = s.pts[3 * (size_t)i + 2];
-  ViewPatch<P> vp;
-  build_patch<T, P>(s, q, view, slot_ok, px, py, pz, vp);
-  const float kinv = keff > 0 ? 1.0f / (float)keff : 0.0f;
-  float dx = 0.0f, dy = 0.0f, dz = 0.0f;
-  if (pt_ok && l.proposals) {
-    const size_t k = 3 * (size_t)(prop_by_j ? (uint32_t)j : i);
-    dx = l.proposals[k];
-    dy = l.proposals[k + 1];
-    dz = l.proposals[k + 2];
-  }
-  const float len = sqrtf(dx * dx + dy * dy + dz * dz);
-  const bool valid = keff > 0 && isfinite(len) && len > 0.0f;
-  const float il = valid ? 1.0f / len : 0.0f;
-  dx = valid ? dx * il : 0.0f;
-  dy = valid ? dy * il : 0.0f;
-  dz = valid ? dz * il : 1.0f;
-  float J = 1.0f - group_sum(eval_view<P>(vp, dx, dy, dz), gr.base, gr.K) * kinv;
-  refine<P>(vp, gr, kinv, l.iters, l.step0, dx, dy, dz, J);
-  if (pt_ok && gr.slot == 0) {
-    if (valid && J <= l.tau) {
-      write_result(s, i, dx, dy, dz, J);
-    } else {
-      const uint32_t pos = atomicAdd(l.fb_count, 1u);
-      l.fb_list[pos] = (uint32_t)j;
-    }
-  }
+  learned_group<T, P>(s, q, l, gr, pt_ok, pt_ok ? j : 0, prop_by_j, 0, 0);
 }
 
 hipError_t launch_learned_refine(const SceneDev& s, const SearchDev& q, const LearnedDev& l,

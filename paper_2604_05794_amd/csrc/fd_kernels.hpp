@@ -56,6 +56,8 @@ struct LearnedDev {
 
 hipError_t launch_tiling(const float* pts, int64_t n, TileWork w, hipStream_t st);
 hipError_t launch_identity_perm(int64_t n, uint32_t* perm, hipStream_t st);
+hipError_t launch_scan_runs(const uint32_t* counts, int n_runs, uint32_t* sums, uint32_t* cursor,
+                            hipStream_t st);
 hipError_t launch_fill_u32(uint32_t* p, int64_t n, uint32_t v, hipStream_t st);
 int tile_cells();
 

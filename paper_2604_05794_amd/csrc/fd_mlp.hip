@@ -101,12 +101,20 @@ __global__ void k_mlp_pack(const float* __restrict__ m, Packed p) {
 // ---- inference: fused four-layer forward ----------------------------------------------
 // One workgroup (4 waves) = 128 rows.  Activations stay in LDS (128 x 256
 // bfloat16, rows padded by 16 bytes); wave w produces output columns
-// [64w, 64w + 64) of every hidden layer (8 row tiles x 4 column tiles), its B
-// fragments read straight from the L2-resident packed weights.
+// [64w, 64w + 64) of every hidden layer for all 128 rows.  The product is
+// issued as Z^T = W^T X^T (weights as the A operand, activations as B), so
+// that each lane ends up holding four consecutive output columns of one row
+// and writes them to LDS with one 8-byte store.  Weight fragments come
+// straight from the L2-resident packed weights, one k-step ahead.
 constexpr int FWD_ROWS = 128;
 constexpr int ACT_LD = DH + 8;
 
-__global__ __launch_bounds__(256) void k_mlp_fwd(const uint16_t* __restrict__ x, int64_t n,
+__device__ __forceinline__ float gelu_fast(float x) {
+  const float u = 0.7978845608028654f * (x + 0.044715f * x * x * x);
+  return x * __builtin_amdgcn_rcpf(1.0f + __expf(-2.0f * u));
+}
+
+__global__ __launch_bounds__(256, 2) void k_mlp_fwd(const uint16_t* __restrict__ x, int64_t n,
                                                  Packed p, float* __restrict__ out) {
   __shared__ __attribute__((aligned(16))) uint16_t act[FWD_ROWS * ACT_LD];
   __shared__ float yout[FWD_ROWS][4];
@@ -122,44 +130,54 @@ __global__ __launch_bounds__(256) void k_mlp_fwd(const uint16_t* __restrict__ x,
   }
   __syncthreads();
 
-  const uint16_t* wts[3] = {p.w1t, p.w2t, p.w3t};
+#pragma unroll 1
   for (int layer = 0; layer < 3; ++layer) {
     const int K = layer == 0 ? D0P : DH;
-    const uint16_t* wt = wts[layer];
+    const uint16_t* wt = layer == 0 ? p.w1t : (layer == 1 ? p.w2t : p.w3t);
+    // acc[mt][nt]: rows (output columns) 64w + 16nt + 4g + r, column (batch row) 16mt + c16
     f32x4 acc[8][4];
 #pragma unroll
     for (int mt = 0; mt < 8; ++mt)
 #pragma unroll
       for (int nt = 0; nt < 4; ++nt) acc[mt][nt] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+    bf16x8 wa[4], wn[4];
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt)
+      wa[nt] = *(const bf16x8*)(wt + (size_t)(64 * w + 16 * nt + c16) * K + 8 * g);
+#pragma unroll 1
     for (int kc = 0; kc < K; kc += 32) {
-      bf16x8 b[4];
+      const int kn = kc + 32 < K ? kc + 32 : kc;
 #pragma unroll
       for (int nt = 0; nt < 4; ++nt)
-        b[nt] = *(const bf16x8*)(wt + (size_t)(64 * w + 16 * nt + c16) * K + kc + 8 * g);
+        wn[nt] = *(const bf16x8*)(wt + (size_t)(64 * w + 16 * nt + c16) * K + kn + 8 * g);
 #pragma unroll
       for (int mt = 0; mt < 8; ++mt) {
-        const bf16x8 a = *(const bf16x8*)(act + (16 * mt + c16) * ACT_LD + kc + 8 * g);
+        const bf16x8 xb = *(const bf16x8*)(act + (16 * mt + c16) * ACT_LD + kc + 8 * g);
 #pragma unroll
-        for (int nt = 0; nt < 4; ++nt) acc[mt][nt] = mfma(a, b[nt], acc[mt][nt]);
+        for (int nt = 0; nt < 4; ++nt) acc[mt][nt] = mfma(wa[nt], xb, acc[mt][nt]);
       }
+#pragma unroll
+      for (int nt = 0; nt < 4; ++nt) wa[nt] = wn[nt];
     }
     __syncthreads();  // every wave has read this layer's input
     const float* bias = p.bias + layer * DH;
 #pragma unroll
     for (int nt = 0; nt < 4; ++nt) {
-      const int col = 64 * w + 16 * nt + c16;
-      const float bb = bias[col];
+      const int col = 64 * w + 16 * nt + 4 * g;
+      const float4 bb = *(const float4*)(bias + col);
 #pragma unroll
-      for (int mt = 0; mt < 8; ++mt)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int row = 16 * mt + 4 * g + r;
-          act[row * ACT_LD + col] = f2bf(gelu(acc[mt][nt][r] + bb));
-        }
+      for (int mt = 0; mt < 8; ++mt) {
+        const int row = 16 * mt + c16;
+        const uint32_t lo = (uint32_t)f2bf(gelu_fast(acc[mt][nt][0] + bb.x)) |
+                            ((uint32_t)f2bf(gelu_fast(acc[mt][nt][1] + bb.y)) << 16);
+        const uint32_t hi = (uint32_t)f2bf(gelu_fast(acc[mt][nt][2] + bb.z)) |
+                            ((uint32_t)f2bf(gelu_fast(acc[mt][nt][3] + bb.w)) << 16);
+        *(uint2*)(act + row * ACT_LD + col) = make_uint2(lo, hi);
+      }
     }
     __syncthreads();
   }
-  // output layer: 256 -> 16 (3 real); wave w takes row tiles 2w, 2w + 1
+  // output layer: 256 -> 16 (3 real); wave w takes batch-row tiles 2w, 2w + 1
   f32x4 o[2] = {f32x4{0.0f, 0.0f, 0.0f, 0.0f}, f32x4{0.0f, 0.0f, 0.0f, 0.0f}};
   for (int kc = 0; kc < DH; kc += 32) {
     const bf16x8 b = *(const bf16x8*)(p.w4t + (size_t)c16 * DH + kc + 8 * g);

@@ -195,6 +195,15 @@ hipError_t launch_tiling(const float* pts, int64_t n, TileWork w, hipStream_t st
   return hipGetLastError();
 }
 
+// Exclusive scan of n_runs x 1024 counts (n_runs <= 1024) into cursor.
+hipError_t launch_scan_runs(const uint32_t* counts, int n_runs, uint32_t* sums, uint32_t* cursor,
+                            hipStream_t st) {
+  if (n_runs < 1 || n_runs > 1024) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_cell_block_sums, dim3(n_runs), dim3(kScanRun), 0, st, counts, sums);
+  hipLaunchKernelGGL(k_cell_scan, dim3(n_runs), dim3(kScanRun), 0, st, counts, sums, cursor);
+  return hipGetLastError();
+}
+
 hipError_t launch_identity_perm(int64_t n, uint32_t* perm, hipStream_t st) {
   if (n <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_iota, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, perm, n);

@@ -96,7 +96,7 @@ def lib():
         "fd_context_destroy": (None, [P]),
         "fd_fuse_directions": (ctypes.c_int, [P, i64, P, i32, P, P, pp, P, P]),
         "fd_last_fallback_count": (ctypes.c_int, [P, P, ctypes.POINTER(i64)]),
-        "fd_fuse_directions_batched": (ctypes.c_int, [P, i32, pp, P]),
+        "fd_fuse_directions_batched": (ctypes.c_int, [ctypes.POINTER(Scene), i32, pp, P]),
         "fd_mlp_create": (ctypes.c_int, [ctypes.POINTER(P), u64]),
         "fd_mlp_set_params": (ctypes.c_int, [P, P]),
         "fd_mlp_get_params": (ctypes.c_int, [P, P]),
@@ -109,7 +109,7 @@ def lib():
         "fd_mlp_train_step": (ctypes.c_int, [P, P, P, i32, ctypes.POINTER(Adam), P, P]),
         "fd_mlp_destroy": (None, [P]),
         "fd_features": (ctypes.c_int, [P, i64, P, i32, P, P, pp, P]),
-        "fd_autotune": (ctypes.c_int, [P, P, i32, pp, ctypes.c_char_p]),
+        "fd_autotune": (ctypes.c_int, [P, ctypes.POINTER(Scene), i32, pp, ctypes.c_char_p]),
         "fd_profile_enable": (ctypes.c_int, [P, ctypes.c_int]),
         "fd_profile_read": (ctypes.c_int, [P, ctypes.c_int, ctypes.POINTER(ctypes.c_double),
                                            ctypes.POINTER(i64)]),
@@ -361,3 +361,58 @@ def features(points, cams, orient_maps, conf_maps, head_centre=(0.0, 0.0, 0.0), 
     _check(lib().fd_features(_ptr(points), n, _ptr(cams), V, _ptr(orient_maps), _ptr(conf_maps),
                              ctypes.byref(p), _ptr(out)))
     return out
+
+
+def _scene_struct(sc):
+    """sc: dict with points, cams, orient_maps, conf_maps, dirs, costs and
+    optional head_centre (CUDA tensors)."""
+    s = Scene()
+    pts, cams, th, cf = sc["points"], sc["cams"], sc["orient_maps"], sc["conf_maps"]
+    _dev_tensor(pts, "points", torch.float32, (3,))
+    _dev_tensor(cams, "cams", torch.float32, (16,))
+    _dev_tensor(th, "orient_maps")
+    _dev_tensor(cf, "conf_maps", th.dtype)
+    _dev_tensor(sc["dirs"], "dirs", torch.float32, (3,))
+    _dev_tensor(sc["costs"], "costs", torch.float32)
+    V, H, W = th.shape
+    s.points = pts.data_ptr()
+    s.n_points = pts.shape[0]
+    s.cams = cams.data_ptr()
+    s.n_views = V
+    s.width, s.height = W, H
+    s.orient_maps = th.data_ptr()
+    s.conf_maps = cf.data_ptr()
+    s.dirs = sc["dirs"].data_ptr()
+    s.costs = sc["costs"].data_ptr()
+    hc = sc.get("head_centre", (0.0, 0.0, 0.0))
+    for k in range(3):
+        s.head_centre[k] = float(hc[k])
+    return s, map_dtype_of(th)
+
+
+def _scene_array(scenes):
+    arr = (Scene * max(1, len(scenes)))()
+    dt = None
+    for k, sc in enumerate(scenes):
+        arr[k], d = _scene_struct(sc)
+        if dt is not None and d != dt:
+            raise TypeError("all scenes of a batch need the same map dtype")
+        dt = d
+    return arr, (FD_F16 if dt is None else dt)
+
+
+def fuse_batched(scenes, ctx: Context, **kw):
+    """fd_fuse_directions_batched: scenes is a list of dicts (points, cams,
+    orient_maps, conf_maps, dirs, costs[, head_centre]); outputs are written
+    into each scene's dirs / costs."""
+    arr, dt = _scene_array(scenes)
+    p = make_params(1, 1, dt, ctx=ctx, **kw)
+    _check(lib().fd_fuse_directions_batched(arr, len(scenes), ctypes.byref(p), ctx.handle))
+
+
+def autotune(scenes, ctx: Context, cache_path=None, **kw):
+    """fd_autotune on sample scenes (same form as fuse_batched)."""
+    arr, dt = _scene_array(scenes)
+    p = make_params(1, 1, dt, ctx=ctx, **kw)
+    _check(lib().fd_autotune(ctx.handle, arr, len(scenes), ctypes.byref(p),
+                             os.fsencode(cache_path) if cache_path else None))

@@ -1,0 +1,168 @@
+"""Batched persistent launch (fd_fuse_directions_batched): bit-identical to
+per-scene calls, graph replay, autotuned shapes, learned form."""
+import math
+import os
+import tempfile
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import scenegen
+from parity import assert_parity, compare
+
+pytestmark = pytest.mark.gpu
+
+DEV = torch.device("cuda:0")
+KW = dict(patch=3, n_candidates=48, refine_iters=6, top_k=5)
+
+
+def _native():
+    from paper_2604_05794_amd import native
+    native.lib()
+    return native
+
+
+def _uneven_scenes(dtype=np.float16):
+    """Uneven point counts, view counts and map sizes (one empty scene)."""
+    out = []
+    specs = [(1500, 10, 96, 0), (0, 6, 64, 1), (4097, 16, 128, 2), (333, 7, 80, 3),
+             (2600, 12, 112, 4)]
+    for n, V, res, seed in specs:
+        rec = dict(scenegen.RECIPES["tiny"])
+        rec.update(n_points=max(n, 1), n_views=V, res=res, arc_deg=300.0, n_strands=120,
+                   dtype="f16" if dtype == np.float16 else "f32", outliers=0.1)
+        sc = scenegen.make_scene(rec, 50 + seed)
+        if n == 0:
+            sc.points = sc.points[:0]
+            sc.gt = sc.gt[:0]
+        out.append(sc)
+    return out
+
+
+def _dev_scene(sc):
+    n = sc.n_points
+    return dict(points=torch.from_numpy(np.ascontiguousarray(sc.points)).to(DEV),
+                cams=torch.from_numpy(sc.cams).to(DEV),
+                orient_maps=torch.from_numpy(sc.theta).to(DEV),
+                conf_maps=torch.from_numpy(sc.conf).to(DEV),
+                dirs=torch.full((n, 3), 9.0, device=DEV),
+                costs=torch.full((n,), 9.0, device=DEV),
+                head_centre=sc.head_centre)
+
+
+def _single(nat, d, **kw):
+    return nat.fuse_directions(d["points"], d["cams"], d["orient_maps"], d["conf_maps"], **kw)
+
+
+def test_batched_plain_is_bitwise_per_scene():
+    nat = _native()
+    scenes = _uneven_scenes()
+    devs = [_dev_scene(s) for s in scenes]
+    total = sum(s.n_points for s in scenes)
+    ctx = nat.Context(max_points=total, max_scenes=len(scenes))
+    nat.fuse_batched(devs, ctx, **KW)
+    torch.cuda.synchronize()
+    for d in devs:
+        if d["points"].shape[0] == 0:
+            continue
+        d1, c1 = _single(nat, d, **KW)
+        torch.cuda.synchronize()
+        assert torch.equal(d1, d["dirs"]) and torch.equal(c1, d["costs"])
+    # one scene against the oracle, through the batched launch
+    sc, d = scenes[2], devs[2]
+    orc = oracle.Oracle(sc.cams, sc.theta, sc.conf, **KW)
+    do, co = orc.fuse(sc.points)
+    res = compare(orc, sc.points, d["dirs"].cpu().numpy(), d["costs"].cpu().numpy(), do, co)
+    print("batched vs oracle", {k: v for k, v in res.items() if not k.endswith("_idx")})
+    assert_parity(res, max_fail_frac=5e-3)
+
+
+def test_graph_replay_follows_new_input_values():
+    nat = _native()
+    scenes = _uneven_scenes()
+    devs = [_dev_scene(s) for s in scenes]
+    total = sum(s.n_points for s in scenes)
+    ctx = nat.Context(max_points=total, max_scenes=len(scenes))
+    nat.fuse_batched(devs, ctx, **KW)
+    first = [d["dirs"].clone() for d in devs]
+    for rep in range(3):
+        # eager work between the replays, then replay over shifted points
+        # (same buffers, new values)
+        for d in devs:
+            d["costs"].fill_(-1.0)
+        devs[0]["points"].add_(0.001 if rep == 1 else 0.0)
+        nat.fuse_batched(devs, ctx, **KW)
+        torch.cuda.synchronize()
+        d1, c1 = _single(nat, devs[0], **KW)
+        torch.cuda.synchronize()
+        assert torch.equal(d1, devs[0]["dirs"]) and torch.equal(c1, devs[0]["costs"])
+        for k in range(2, len(devs)):
+            assert torch.equal(first[k], devs[k]["dirs"])
+
+
+def test_autotuned_shapes_do_not_change_results():
+    nat = _native()
+    scenes = _uneven_scenes()
+    devs = [_dev_scene(s) for s in scenes]
+    total = sum(s.n_points for s in scenes)
+    ctx = nat.Context(max_points=total, max_scenes=len(scenes))
+    nat.fuse_batched(devs, ctx, **KW)
+    torch.cuda.synchronize()
+    ref = [d["dirs"].clone() for d in devs]
+    with tempfile.TemporaryDirectory() as tmp:
+        path = os.path.join(tmp, "tune.json")
+        nat.autotune(devs, ctx, cache_path=path, **KW)
+        txt = open(path).read()
+        import json
+        cache = json.loads(txt)
+        assert len(cache) == 1
+        (key, val), = cache.items()
+        assert val["chunk"] >= 1 and val["grid"] >= 1
+        ctx2 = nat.Context(max_points=total, max_scenes=len(scenes))
+        nat.autotune(devs, ctx2, cache_path=path, **KW)   # read from the cache
+        nat.fuse_batched(devs, ctx2, **KW)
+        torch.cuda.synchronize()
+        for r, d in zip(ref, devs):
+            assert torch.equal(r, d["dirs"])
+
+
+def test_batched_learned_is_bitwise_per_scene():
+    nat = _native()
+    scenes = _uneven_scenes()
+    devs = [_dev_scene(s) for s in scenes]
+    total = sum(s.n_points for s in scenes)
+    ctx = nat.Context(max_points=total, max_scenes=len(scenes))
+    net = nat.MLP(seed=3)
+    kw = dict(KW, mode=nat.FD_MODE_LEARNED, mlp=net, learned_iters=2, learned_step0=0.05,
+              fallback_cost=0.3)
+    nat.fuse_batched(devs, ctx, **kw)
+    torch.cuda.synchronize()
+    for d in devs:
+        if d["points"].shape[0] == 0:
+            continue
+        d1, c1 = _single(nat, d, head_centre=d["head_centre"], **kw)
+        torch.cuda.synchronize()
+        assert torch.equal(d1, d["dirs"]) and torch.equal(c1, d["costs"])
+
+
+def test_batched_errors():
+    nat = _native()
+    scenes = _uneven_scenes()[:2]
+    devs = [_dev_scene(s) for s in scenes]
+    total = sum(s.n_points for s in scenes)
+    small = nat.Context(max_points=10, max_scenes=2)
+    with pytest.raises(nat.FdError) as e:
+        nat.fuse_batched(devs, small, **KW)
+    assert e.value.code == nat.FD_E_NOMEM
+    no_scenes = nat.Context(max_points=total)
+    with pytest.raises(nat.FdError) as e:
+        nat.fuse_batched(devs, no_scenes, **KW)
+    assert e.value.code == nat.FD_E_NOMEM
+    ctx = nat.Context(max_points=total, max_scenes=2)
+    with pytest.raises(nat.FdError) as e:
+        nat.fuse_batched(devs * 17, ctx, **KW)
+    assert e.value.code == nat.FD_E_INVAL
+    torch.cuda.synchronize()
+    assert (devs[0]["dirs"] == 9.0).all()

@@ -161,8 +161,51 @@ def test_features_rank_frontal_views_and_describe_them():
             assert f[2] == pytest.approx(s[0], abs=1e-5)
             mag = math.hypot(f[0], f[1])
             assert mag <= f[2] + 1e-12
-            if s[2] and mag > 1e-6:
-                assert abs(math.remainder(math.atan2(f[1], f[0]) - 2 * s[1], 2 * math.pi)) < 1e-3
+            if not s[2]:
+                assert mag == 0.0
+
+
+def _plane_normal(f):
+    """Normal of the plane a feature slot describes: line of sight v and the
+    direction at angle psi across it (frame e1 = z x v, e2 = v x e1)."""
+    v = np.asarray(f[3:6], np.float64)
+    e1 = np.cross([0.0, 0.0, 1.0], v)
+    e1 /= np.linalg.norm(e1)
+    e2 = np.cross(v, e1)
+    psi = 0.5 * math.atan2(f[1], f[0])
+    t = math.cos(psi) * e1 + math.sin(psi) * e2
+    n = np.cross(v, t)
+    return n / np.linalg.norm(n)
+
+
+def test_feature_planes_contain_the_true_direction():
+    """On a noise-free straight strand every observed slot describes a plane
+    through the line of sight that contains the strand direction."""
+    sc = scenegen.straight_strand_scene(seed=21, n_points=30, n_views=24, res=256,
+                                        arc_deg=330.0)
+    o = oracle.Oracle(sc.cams, sc.theta, sc.conf, patch=1)
+    F = o.features(sc.points, np.zeros(3, np.float32), n_slots=16)
+    checked = 0
+    for i in range(len(sc.points)):
+        d = sc.gt[i].astype(np.float64)
+        for j in range(16):
+            f = F[i, 7 * j:7 * j + 7]
+            if f[6] == 0 or math.hypot(f[0], f[1]) < 0.05:
+                continue
+            assert abs(_plane_normal(f) @ d) < 1e-4
+            checked += 1
+    assert checked >= 60
+    # and a wrong direction is not in those planes
+    rng = np.random.default_rng(21)
+    far = 0
+    for i in range(5):
+        q = rng.normal(size=3)
+        q /= np.linalg.norm(q)
+        for j in range(16):
+            f = F[i, 7 * j:7 * j + 7]
+            if f[6] and math.hypot(f[0], f[1]) >= 0.05:
+                far += abs(_plane_normal(f) @ q) > 1e-2
+    assert far > 0
 
 
 # ---- learned search and fallback --------------------------------------------
