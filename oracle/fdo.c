@@ -60,7 +60,7 @@ static const void* view_map(const void* maps, int dtype, int W, int H, int v) {
  * operations that any implementation can reproduce bit for bit:
  *   X = fma(R0, px, fma(R1, py, fma(R2, pz, t0)))   (likewise Y, Z)
  *   eligible-front  : Z > z_near
- *   u = fma(fx, X / Z, cx),  v = fma(fy, Y / Z, cy)   (correctly rounded /)
+ *   iz = 1 / Z (correctly rounded),  u = fma(fx, X * iz, cx),  v = fma(fy, Y * iz, cy)
  *   eligible-inside : 0 <= u <= W-1 and 0 <= v <= H-1
  *   x0 = floor(u), fx = u - x0, gx = 1 - fx (likewise y)
  *   w00 = gx*gy, w10 = fx*gy, w01 = gx*fy, w11 = fx*fy
@@ -77,8 +77,9 @@ static int project32(const float* cam, const float* p, int W, int H,
   float Y = fmaf(R[3], p[0], fmaf(R[4], p[1], fmaf(R[5], p[2], t[1])));
   float Z = fmaf(R[6], p[0], fmaf(R[7], p[1], fmaf(R[8], p[2], t[2])));
   if (!(Z > z_near)) return 0;
-  float ux = fmaf(cam[0], X / Z, cam[2]);
-  float uy = fmaf(cam[1], Y / Z, cam[3]);
+  float iz = 1.0f / Z;
+  float ux = fmaf(cam[0], X * iz, cam[2]);
+  float uy = fmaf(cam[1], Y * iz, cam[3]);
   if (!(ux >= 0.0f && ux <= (float)(W - 1) && uy >= 0.0f &&
         uy <= (float)(H - 1)))
     return 0;

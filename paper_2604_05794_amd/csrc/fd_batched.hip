@@ -181,7 +181,7 @@ __global__ __launch_bounds__(kBlock) void k_b_features(BatchDev b, float z_near,
 // list[item] when a list is given; n_items = *count then).  Each wave pops
 // `chunk` tiles of G items at a time; lane 0 pops and broadcasts, so the
 // whole wave leaves the loop together once the queue is exhausted.
-template <typename T, int P>
+template <typename T, int P, int KT>
 __global__ __launch_bounds__(kBlock) void k_b_fuse(BatchDev b, SearchDev q, const uint32_t* list,
                                                    const uint32_t* list_count,
                                                    uint32_t* __restrict__ queue, int chunk) {
@@ -201,12 +201,12 @@ __global__ __launch_bounds__(kBlock) void k_b_fuse(BatchDev b, SearchDev q, cons
       const int64_t gpos = pt_ok ? (list ? (int64_t)list[item] : item) : 0;
       const int s = find_scene(b.pt_off, b.n_scenes, gpos);
       const SceneDev sc = b.tab[s];
-      fuse_group<T, P>(sc, q, gr, pt_ok, gpos - b.pt_off[s]);
+      fuse_group<T, P, KT>(sc, q, gr, pt_ok, gpos - b.pt_off[s]);
     }
   }
 }
 
-template <typename T, int P>
+template <typename T, int P, int KT>
 __global__ __launch_bounds__(kBlock) void k_b_learned(BatchDev b, SearchDev q, LearnedDev l) {
   const Group gr = make_group(q.K);
   const int64_t wave = (int64_t)blockIdx.x * (blockDim.x / kWave) + (threadIdx.x / kWave);
@@ -217,19 +217,19 @@ __global__ __launch_bounds__(kBlock) void k_b_learned(BatchDev b, SearchDev q, L
   const int s = find_scene(b.pt_off, b.n_scenes, gpos);
   const SceneDev sc = b.tab[s];
   const int64_t j = gpos - b.pt_off[s];
-  learned_group<T, P>(sc, q, l, gr, pt_ok, j, 1, b.pt_off[s], b.pt_off[s]);
+  learned_group<T, P, KT>(sc, q, l, gr, pt_ok, j, 1, b.pt_off[s], b.pt_off[s]);
 }
 
-template <typename T, int P>
+template <typename T, int P, int KT>
 hipError_t launch_b_search(const BatchDev& b, const SearchDev& q, const LearnedDev* l,
                            const uint32_t* list, const uint32_t* count, uint32_t* queue,
                            int chunk, int grid, hipStream_t st) {
   if (l) {
     const int G = kWave / q.K;
     const int64_t nb = (b.total + 4 * (int64_t)G - 1) / (4 * (int64_t)G);
-    hipLaunchKernelGGL((k_b_learned<T, P>), dim3((unsigned)nb), dim3(kBlock), 0, st, b, q, *l);
+    hipLaunchKernelGGL((k_b_learned<T, P, KT>), dim3((unsigned)nb), dim3(kBlock), 0, st, b, q, *l);
   } else {
-    hipLaunchKernelGGL((k_b_fuse<T, P>), dim3(grid), dim3(kBlock), 0, st, b, q, list, count,
+    hipLaunchKernelGGL((k_b_fuse<T, P, KT>), dim3(grid), dim3(kBlock), 0, st, b, q, list, count,
                        queue, chunk);
   }
   return hipGetLastError();
@@ -239,13 +239,17 @@ template <typename T>
 hipError_t dispatch_search(int patch, const BatchDev& b, const SearchDev& q, const LearnedDev* l,
                            const uint32_t* list, const uint32_t* count, uint32_t* queue,
                            int chunk, int grid, hipStream_t st) {
+#define FD_B_CASE(P)                                                                   \
+  return q.K == 5 ? launch_b_search<T, P, 5>(b, q, l, list, count, queue, chunk, grid, st) \
+                  : launch_b_search<T, P, 0>(b, q, l, list, count, queue, chunk, grid, st);
   switch (patch) {
-    case 1: return launch_b_search<T, 1>(b, q, l, list, count, queue, chunk, grid, st);
-    case 3: return launch_b_search<T, 3>(b, q, l, list, count, queue, chunk, grid, st);
-    case 5: return launch_b_search<T, 5>(b, q, l, list, count, queue, chunk, grid, st);
-    case 7: return launch_b_search<T, 7>(b, q, l, list, count, queue, chunk, grid, st);
+    case 1: FD_B_CASE(1)
+    case 3: FD_B_CASE(3)
+    case 5: FD_B_CASE(5)
+    case 7: FD_B_CASE(7)
     default: return hipErrorInvalidValue;
   }
+#undef FD_B_CASE
 }
 
 hipError_t search(int dtype, int patch, const BatchDev& b, const SearchDev& q, const LearnedDev* l,
@@ -264,7 +268,7 @@ int persistent_grid(int dtype, int patch, int per_cu_cap) {
   (void)hipGetDevice(&dev);
   (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
   const void* fn = nullptr;
-#define FD_FN(T, P) (const void*)(&k_b_fuse<T, P>)
+#define FD_FN(T, P) (const void*)(&k_b_fuse<T, P, 5>)
   if (dtype == 1)
     fn = patch == 1 ? FD_FN(__half, 1) : patch == 3 ? FD_FN(__half, 3) : patch == 5 ? FD_FN(__half, 5) : FD_FN(__half, 7);
   else

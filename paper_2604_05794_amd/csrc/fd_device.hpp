@@ -50,9 +50,9 @@ __device__ __forceinline__ float tex_load_nb(const T* __restrict__ m, int W, int
 // every implementation of the method shares (view selection is a discrete
 // decision and must come out the same everywhere):
 //   X = fma(R0, px, fma(R1, py, fma(R2, pz, t0)))  (likewise Y, Z)
-//   front: Z > z_near;  u = fma(fx, X / Z, cx), v = fma(fy, Y / Z, cy)
+//   front: Z > z_near;  iz = 1 / Z,  u = fma(fx, X * iz, cx), v = fma(fy, Y * iz, cy)
 //   inside: 0 <= u <= W-1 and 0 <= v <= H-1
-// Division is IEEE (the library is built without fast-math).
+// The reciprocal is IEEE (the library is built without fast-math).
 struct Proj {
   float X, Y, Z, u, v;
 };
@@ -66,8 +66,9 @@ __device__ __forceinline__ bool project32(const float* __restrict__ cam,
   o.Y = __builtin_fmaf(R[3], px, __builtin_fmaf(R[4], py, __builtin_fmaf(R[5], pz, t[1])));
   o.Z = __builtin_fmaf(R[6], px, __builtin_fmaf(R[7], py, __builtin_fmaf(R[8], pz, t[2])));
   if (!(o.Z > z_near)) return false;
-  o.u = __builtin_fmaf(cam[0], o.X / o.Z, cam[2]);
-  o.v = __builtin_fmaf(cam[1], o.Y / o.Z, cam[3]);
+  const float iz = 1.0f / o.Z;
+  o.u = __builtin_fmaf(cam[0], o.X * iz, cam[2]);
+  o.v = __builtin_fmaf(cam[1], o.Y * iz, cam[3]);
   return o.u >= 0.0f && o.u <= (float)(W - 1) && o.v >= 0.0f &&
          o.v <= (float)(H - 1);
 }
@@ -98,6 +99,23 @@ __device__ __forceinline__ float group_sum(float v, int group_base, int k) {
   float s = __shfl(v, group_base, kWave);
   for (int j = 1; j < k; ++j) s += __shfl(v, group_base + j, kWave);
   return s;
+}
+
+// group_sum with the group size known at compile time (KT > 0): the K
+// shuffles are issued back to back and waited for once.
+template <int KT>
+__device__ __forceinline__ float group_sum_t(float v, int group_base, int k) {
+  if constexpr (KT > 0) {
+    float x[KT];
+#pragma unroll
+    for (int j = 0; j < KT; ++j) x[j] = __shfl(v, group_base + j, kWave);
+    float s = x[0];
+#pragma unroll
+    for (int j = 1; j < KT; ++j) s += x[j];
+    return s;
+  } else {
+    return group_sum(v, group_base, k);
+  }
 }
 
 }  // namespace fd

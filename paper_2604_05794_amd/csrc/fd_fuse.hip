@@ -69,7 +69,7 @@ hipError_t launch_topk(const SceneDev& s, const SearchDev& q, int dtype, hipStre
 // ---- plain search: lattice argmin + refinement ---------------------------------
 // `list` (optional): processing-order indices to fuse, *list_count of them
 // (read on the device; the grid is sized for the worst case).
-template <typename T, int P>
+template <typename T, int P, int KT>
 __global__ __launch_bounds__(256) void k_fuse(SceneDev s, SearchDev q, const uint32_t* list,
                                               const uint32_t* list_count) {
   const Group gr = make_group(q.K);
@@ -80,7 +80,7 @@ __global__ __launch_bounds__(256) void k_fuse(SceneDev s, SearchDev q, const uin
   if (wave * gr.G >= limit) return;  // whole wave idle (uniform exit)
   const bool pt_ok = gr.lane_ok && t < limit;
   const int64_t j = pt_ok ? (list ? (int64_t)list[t] : t) : 0;
-  fuse_group<T, P>(s, q, gr, pt_ok, j);
+  fuse_group<T, P, KT>(s, q, gr, pt_ok, j);
 }
 
 template <typename T>
@@ -92,13 +92,19 @@ static hipError_t launch_fuse_t(const SceneDev& s, const SearchDev& q, int patch
   const int64_t nb = (s.n + pts_per_block - 1) / pts_per_block;
   if (nb <= 0) return hipSuccess;
   dim3 grid((unsigned)nb), block(256);
+#define FD_FUSE_CASE(P)                                                                  \
+  if (q.K == 5)                                                                          \
+    hipLaunchKernelGGL((k_fuse<T, P, 5>), grid, block, 0, st, s, q, list, list_count);    \
+  else                                                                                   \
+    hipLaunchKernelGGL((k_fuse<T, P, 0>), grid, block, 0, st, s, q, list, list_count);
   switch (patch) {
-    case 1: hipLaunchKernelGGL((k_fuse<T, 1>), grid, block, 0, st, s, q, list, list_count); break;
-    case 3: hipLaunchKernelGGL((k_fuse<T, 3>), grid, block, 0, st, s, q, list, list_count); break;
-    case 5: hipLaunchKernelGGL((k_fuse<T, 5>), grid, block, 0, st, s, q, list, list_count); break;
-    case 7: hipLaunchKernelGGL((k_fuse<T, 7>), grid, block, 0, st, s, q, list, list_count); break;
+    case 1: FD_FUSE_CASE(1) break;
+    case 3: FD_FUSE_CASE(3) break;
+    case 5: FD_FUSE_CASE(5) break;
+    case 7: FD_FUSE_CASE(7) break;
     default: return hipErrorInvalidValue;
   }
+#undef FD_FUSE_CASE
   return hipGetLastError();
 }
 
@@ -109,7 +115,7 @@ hipError_t launch_fuse(const SceneDev& s, const SearchDev& q, int dtype, int pat
                     : launch_fuse_t<float>(s, q, patch, list, list_count, st);
 }
 
-template <typename T, int P>
+template <typename T, int P, int KT>
 __global__ __launch_bounds__(256) void k_learned(SceneDev s, SearchDev q, LearnedDev l,
                                                  int prop_by_j) {
   const Group gr = make_group(q.K);
@@ -118,7 +124,7 @@ __global__ __launch_bounds__(256) void k_learned(SceneDev s, SearchDev q, Learne
   const int64_t j = wave * gr.G + gr.g;
   if (wave * gr.G >= s.n) return;
   const bool pt_ok = gr.lane_ok && j < s.n;
-  learned_group<T, P>(s, q, l, gr, pt_ok, pt_ok ? j : 0, prop_by_j, 0, 0);
+  learned_group<T, P, KT>(s, q, l, gr, pt_ok, pt_ok ? j : 0, prop_by_j, 0, 0);
 }
 
 hipError_t launch_learned_refine(const SceneDev& s, const SearchDev& q, const LearnedDev& l,
@@ -127,8 +133,11 @@ hipError_t launch_learned_refine(const SceneDev& s, const SearchDev& q, const Le
   const int G = kWave / q.K;
   const int64_t nb = (s.n + 4 * (int64_t)G - 1) / (4 * (int64_t)G);
   dim3 grid((unsigned)nb), block(256);
-#define FD_LEARNED_CASE(T, P)                                                          \
-  hipLaunchKernelGGL((k_learned<T, P>), grid, block, 0, st, s, q, l, prop_by_j);
+#define FD_LEARNED_CASE(T, P)                                                             \
+  if (q.K == 5)                                                                           \
+    hipLaunchKernelGGL((k_learned<T, P, 5>), grid, block, 0, st, s, q, l, prop_by_j);     \
+  else                                                                                    \
+    hipLaunchKernelGGL((k_learned<T, P, 0>), grid, block, 0, st, s, q, l, prop_by_j);
   if (dtype == 1) {
     switch (patch) {
       case 1: FD_LEARNED_CASE(__half, 1) break;

@@ -123,15 +123,44 @@ __device__ __forceinline__ void build_patch(const SceneDev& s, const SearchDev& 
   const int ix = (int)x0 - HP, iy = (int)y0 - HP;
   // texel rows of the (P+1)^2 footprint: C, C cos 2theta, C sin 2theta
   float rc[2][P + 1], rx[2][P + 1], ry[2][P + 1];
+  // binary16 rows away from the right edge of an even-width map: one 16-byte
+  // load per map covers texels [ix & ~1, (ix & ~1) + 7] of the row
+  const bool wide_ok = sizeof(T) == 2 && P <= 5 && (s.W & 1) == 0;
   auto load_row = [&](int slot, int y) {
+    float tv[P + 1], cv[P + 1];
+    const int a0 = ix & ~1;
+    if (wide_ok && ix >= 0 && a0 + 7 <= s.W - 1 && (unsigned)y < (unsigned)s.H) {
+      const size_t off = (size_t)y * s.W + a0;
+      const uint4 wt = *(const uint4*)((const uint16_t*)th + off);
+      const uint4 wc = *(const uint4*)((const uint16_t*)cf + off);
+      // shift the 8 halves right by one half for an odd start (funnel shift)
+      const uint32_t sh = (ix & 1) ? 16u : 0u;
+      const uint32_t t0 = __builtin_amdgcn_alignbit(wt.y, wt.x, sh);
+      const uint32_t t1 = __builtin_amdgcn_alignbit(wt.z, wt.y, sh);
+      const uint32_t t2 = __builtin_amdgcn_alignbit(wt.w, wt.z, sh);
+      const uint32_t c0 = __builtin_amdgcn_alignbit(wc.y, wc.x, sh);
+      const uint32_t c1 = __builtin_amdgcn_alignbit(wc.z, wc.y, sh);
+      const uint32_t c2 = __builtin_amdgcn_alignbit(wc.w, wc.z, sh);
+      const uint32_t tw[3] = {t0, t1, t2}, cw[3] = {c0, c1, c2};
+#pragma unroll
+      for (int a = 0; a <= P; ++a) {
+        const uint32_t wtv = tw[a >> 1], wcv = cw[a >> 1];
+        tv[a] = __half2float(__ushort_as_half((unsigned short)((a & 1) ? (wtv >> 16) : (wtv & 0xffffu))));
+        cv[a] = __half2float(__ushort_as_half((unsigned short)((a & 1) ? (wcv >> 16) : (wcv & 0xffffu))));
+      }
+    } else {
+#pragma unroll
+      for (int a = 0; a <= P; ++a) {
+        tv[a] = tex_load_nb<T>(th, s.W, s.H, ix + a, y);
+        cv[a] = tex_load_nb<T>(cf, s.W, s.H, ix + a, y);
+      }
+    }
 #pragma unroll
     for (int a = 0; a <= P; ++a) {
-      float t = tex_load_nb<T>(th, s.W, s.H, ix + a, y);
-      float c = tex_load_nb<T>(cf, s.W, s.H, ix + a, y);
-      float turns = t * kInvPi;  // 2 theta in revolutions
-      rc[slot][a] = c;
-      rx[slot][a] = c * __builtin_amdgcn_cosf(turns);
-      ry[slot][a] = c * __builtin_amdgcn_sinf(turns);
+      const float turns = tv[a] * kInvPi;  // 2 theta in revolutions
+      rc[slot][a] = cv[a];
+      rx[slot][a] = cv[a] * __builtin_amdgcn_cosf(turns);
+      ry[slot][a] = cv[a] * __builtin_amdgcn_sinf(turns);
     }
   };
   load_row(0, iy);
@@ -150,36 +179,38 @@ __device__ __forceinline__ void build_patch(const SceneDev& s, const SearchDev& 
       const int k = b * P + a;
       vp.a[k] = n2 > 0.0f ? al : 0.0f;
       vp.b[k] = al * mx * inv;
-      vp.c[k] = al * my * inv;
+      vp.c[k] = 2.0f * al * my * inv;  // the factor 2 of 2 rx ry folded in
     }
   }
 }
 
 // max_p C_p |cos(phi(d) - theta_p)| for this lane's view (0 if the tangent
-// projects to a point or the lane has no view).
+// projects to a point or the lane has no view).  With r = M d, n2 = |r|^2:
+// C^2 cos^2(phi - theta) = a + b (rx^2 - ry^2)/n2 + c (rx ry)/n2, c = 2 gamma.
+// For n2 = 0 the reciprocal is +inf, every q is NaN, fmaxf keeps the other
+// operand, and the maximum stays 0.
 template <int P>
 __device__ __forceinline__ float eval_view(const ViewPatch<P>& vp, float dx, float dy,
                                            float dz) {
   constexpr int P2 = P * P;
-  float rx = __builtin_fmaf(vp.M[0], dx, __builtin_fmaf(vp.M[1], dy, vp.M[2] * dz));
-  float ry = __builtin_fmaf(vp.M[3], dx, __builtin_fmaf(vp.M[4], dy, vp.M[5] * dz));
-  float xx = rx * rx, yy = ry * ry;
-  float n2 = xx + yy;
-  float inv = n2 > 0.0f ? __builtin_amdgcn_rcpf(n2) : 0.0f;
-  float c2 = (xx - yy) * inv;
-  float s2 = 2.0f * rx * ry * inv;
+  const float rx = __builtin_fmaf(vp.M[0], dx, __builtin_fmaf(vp.M[1], dy, vp.M[2] * dz));
+  const float ry = __builtin_fmaf(vp.M[3], dx, __builtin_fmaf(vp.M[4], dy, vp.M[5] * dz));
+  const float xx = rx * rx;
+  const float inv = __builtin_amdgcn_rcpf(__builtin_fmaf(ry, ry, xx));
+  const float c2 = __builtin_fmaf(-ry, ry, xx) * inv;
+  const float s2 = (rx * ry) * inv;
   float m = 0.0f;
 #pragma unroll
   for (int k = 0; k + 1 < P2; k += 2) {
-    float q0 = __builtin_fmaf(vp.b[k], c2, __builtin_fmaf(vp.c[k], s2, vp.a[k]));
-    float q1 = __builtin_fmaf(vp.b[k + 1], c2, __builtin_fmaf(vp.c[k + 1], s2, vp.a[k + 1]));
-    m = __builtin_fmaxf(m, __builtin_fmaxf(q0, q1));
+    const float q0 = __builtin_fmaf(vp.b[k], c2, __builtin_fmaf(vp.c[k], s2, vp.a[k]));
+    const float q1 = __builtin_fmaf(vp.b[k + 1], c2, __builtin_fmaf(vp.c[k + 1], s2, vp.a[k + 1]));
+    m = __builtin_fmaxf(__builtin_fmaxf(m, q0), q1);
   }
   if (P2 & 1) {
-    float q0 = __builtin_fmaf(vp.b[P2 - 1], c2, __builtin_fmaf(vp.c[P2 - 1], s2, vp.a[P2 - 1]));
+    const float q0 = __builtin_fmaf(vp.b[P2 - 1], c2, __builtin_fmaf(vp.c[P2 - 1], s2, vp.a[P2 - 1]));
     m = __builtin_fmaxf(m, q0);
   }
-  return n2 > 0.0f ? __builtin_amdgcn_sqrtf(m) : 0.0f;
+  return __builtin_amdgcn_sqrtf(m);
 }
 
 struct Group {
@@ -200,11 +231,11 @@ __device__ __forceinline__ Group make_group(int K) {
 }
 
 // Pattern search (six directions at angle alpha around d in the basis of
-// Duff et al. 2017, best strictly-better one taken, alpha halves).
-template <int P>
-__device__ __forceinline__ void refine(const ViewPatch<P>& vp, const Group& gr, float kinv,
-                                       int iters, float alpha, float& dx, float& dy, float& dz,
-                                       float& Jd) {
+// Duff et al. 2017, best strictly-better one taken, alpha halves).  Works on
+// the view sum S = sum_v L_v (J = 1 - S / K_eff), larger is better.
+template <int P, int KT>
+__device__ __forceinline__ void refine(const ViewPatch<P>& vp, const Group& gr, int iters,
+                                       float alpha, float& dx, float& dy, float& dz, float& Sd) {
   const float cj[6] = {1.0f, 0.5f, -0.5f, -1.0f, -0.5f, 0.5f};
   const float sj[6] = {0.0f, 0.86602540378443865f, 0.86602540378443865f, 0.0f,
                        -0.86602540378443865f, -0.86602540378443865f};
@@ -215,27 +246,26 @@ __device__ __forceinline__ void refine(const ViewPatch<P>& vp, const Group& gr, 
     const float e1x = 1.0f + sg * dx * dx * aa, e1y = sg * bb, e1z = -sg * dx;
     const float e2x = bb, e2y = sg + dy * dy * aa, e2z = -dy;
     const float ca = cosf(alpha), sa = sinf(alpha);
-    float bJ = INFINITY, bx = dx, by = dy, bz = dz;
+    float bS = -INFINITY, bx = dx, by = dy, bz = dz;
 #pragma unroll
     for (int j = 0; j < 6; ++j) {
       float ux = ca * dx + sa * (cj[j] * e1x + sj[j] * e2x);
       float uy = ca * dy + sa * (cj[j] * e1y + sj[j] * e2y);
       float uz = ca * dz + sa * (cj[j] * e1z + sj[j] * e2z);
-      float il = 1.0f / sqrtf(ux * ux + uy * uy + uz * uz);
+      const float il = __builtin_amdgcn_rsqf(ux * ux + uy * uy + uz * uz);
       ux *= il;
       uy *= il;
       uz *= il;
-      float L = eval_view<P>(vp, ux, uy, uz);
-      float J = 1.0f - group_sum(L, gr.base, gr.K) * kinv;
-      if (J < bJ) {
-        bJ = J;
+      const float S = group_sum_t<KT>(eval_view<P>(vp, ux, uy, uz), gr.base, gr.K);
+      if (S > bS) {
+        bS = S;
         bx = ux;
         by = uy;
         bz = uz;
       }
     }
-    if (bJ < Jd) {
-      Jd = bJ;
+    if (bS > Sd) {
+      Sd = bS;
       dx = bx;
       dy = by;
       dz = bz;
@@ -269,7 +299,7 @@ __device__ __forceinline__ int64_t xcd_tile(int64_t nblocks) {
 // ---- plain search of one point per lane group ---------------------------------
 // The K lanes of the caller's group fuse processing-order point j of scene s
 // (pt_ok false: the group has no point but still takes part in the shuffles).
-template <typename T, int P>
+template <typename T, int P, int KT>
 __device__ __forceinline__ void fuse_group(const SceneDev& s, const SearchDev& q, const Group& gr,
                                            bool pt_ok, int64_t j) {
   const uint32_t i = pt_ok ? s.perm[j] : 0u;
@@ -282,24 +312,25 @@ __device__ __forceinline__ void fuse_group(const SceneDev& s, const SearchDev& q
   build_patch<T, P>(s, q, view, slot_ok, px, py, pz, vp);
   const float kinv = keff > 0 ? 1.0f / (float)keff : 0.0f;
 
-  float Jb = INFINITY;
+  // Eq. (12): lattice argmin of J = argmax of the view sum (first of equals)
+  float Sb = -INFINITY;
   int kb = 0;
+#pragma unroll 2
   for (int k = 0; k < q.n_candidates; ++k) {
     const float dx = q.lattice[3 * k], dy = q.lattice[3 * k + 1], dz = q.lattice[3 * k + 2];
-    float L = eval_view<P>(vp, dx, dy, dz);
-    float J = 1.0f - group_sum(L, gr.base, gr.K) * kinv;
-    if (J < Jb) {
-      Jb = J;
+    const float S = group_sum_t<KT>(eval_view<P>(vp, dx, dy, dz), gr.base, gr.K);
+    if (S > Sb) {
+      Sb = S;
       kb = k;
     }
   }
   float dx = q.lattice[3 * kb], dy = q.lattice[3 * kb + 1], dz = q.lattice[3 * kb + 2];
-  refine<P>(vp, gr, kinv, q.refine_iters, q.step0, dx, dy, dz, Jb);
+  refine<P, KT>(vp, gr, q.refine_iters, q.step0, dx, dy, dz, Sb);
   if (pt_ok && gr.slot == 0) {
     if (keff == 0)
       write_result(s, i, 0.0f, 0.0f, 0.0f, INFINITY);
     else
-      write_result(s, i, dx, dy, dz, Jb);
+      write_result(s, i, dx, dy, dz, 1.0f - Sb * kinv);
   }
 }
 
@@ -308,7 +339,7 @@ __device__ __forceinline__ void fuse_group(const SceneDev& s, const SearchDev& q
 // index i; NULL = every proposal invalid.  A point is kept when its proposal
 // is a finite non-zero direction and the refined cost satisfies J <= tau;
 // otherwise list_base + j is appended to the fallback list (plain search).
-template <typename T, int P>
+template <typename T, int P, int KT>
 __device__ __forceinline__ void learned_group(const SceneDev& s, const SearchDev& q,
                                               const LearnedDev& l, const Group& gr, bool pt_ok,
                                               int64_t j, int prop_by_j, int64_t prop_base,
@@ -335,8 +366,9 @@ __device__ __forceinline__ void learned_group(const SceneDev& s, const SearchDev
   dx = valid ? dx * il : 0.0f;
   dy = valid ? dy * il : 0.0f;
   dz = valid ? dz * il : 1.0f;
-  float J = 1.0f - group_sum(eval_view<P>(vp, dx, dy, dz), gr.base, gr.K) * kinv;
-  refine<P>(vp, gr, kinv, l.iters, l.step0, dx, dy, dz, J);
+  float S = group_sum_t<KT>(eval_view<P>(vp, dx, dy, dz), gr.base, gr.K);
+  refine<P, KT>(vp, gr, l.iters, l.step0, dx, dy, dz, S);
+  const float J = 1.0f - S * kinv;
   if (pt_ok && gr.slot == 0) {
     if (valid && J <= l.tau) {
       write_result(s, i, dx, dy, dz, J);

@@ -127,7 +127,13 @@ def calibrate(net, pairs, budget_deg, learned_iters):
         tau = float(cs[k].item()) if k + 1 == len(cs) else float(
             0.5 * (cs[k].item() + cs[k + 1].item()))
         frac = (k + 1) / len(cs)
+    per = {}
+    for p, e in zip(pairs, errs):
+        key = p["scene"].meta["recipe"].get("kinds") and ("curls" if p["kw"]["n_candidates"] and
+                                                          p["scene"].n_views == 128 else "realistic")
+        per[key] = float(e.median().item())
     stats = dict(proposal_median_deg=float(e_all.median().item()),
+                 proposal_median_deg_by_scene=per,
                  proposal_mean_deg=float(e_all.mean().item()),
                  refined_mean_deg_no_fallback=float(r_all.mean().item()),
                  learned_step0=step0, fallback_cost=tau, kept_fraction=frac,
@@ -139,7 +145,7 @@ def main():
     ap = argparse.ArgumentParser(description=__doc__,
                                  formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--out", default=DEFAULT_OUT)
-    ap.add_argument("--epochs", type=int, default=12)
+    ap.add_argument("--epochs", type=int, default=30)
     ap.add_argument("--batch", type=int, default=4096)
     ap.add_argument("--lr", type=float, default=2e-3)
     ap.add_argument("--seed", type=int, default=1)
