@@ -378,10 +378,13 @@ int fd::run_scene(fd_context* c, const SceneArgs& a, const fd_params* p, hipStre
   q.step0 = p->refine_step0 > 0.0f ? p->refine_step0 : default_step0(p->n_candidates);
   q.K = p->top_k;
   q.z_near = p->z_near;
-  StageTimer t_topk(c, FD_STAGE_TOPK, st);
-  if ((e = launch_topk(s, q, p->map_dtype, st)) != hipSuccess)
-    return hip_error(e, "view selection kernel");
-  t_topk.stop();
+  const bool fused_topk = p->mode == FD_MODE_LEARNED && p->proposal == FD_PROPOSAL_MLP;
+  if (!fused_topk) {  // the learned network path selects views with its features
+    StageTimer t_topk(c, FD_STAGE_TOPK, st);
+    if ((e = launch_topk(s, q, p->map_dtype, st)) != hipSuccess)
+      return hip_error(e, "view selection kernel");
+    t_topk.stop();
+  }
   if (p->mode == FD_MODE_PLAIN) {
     StageTimer t_fuse(c, FD_STAGE_FUSE, st);
     if ((e = launch_fuse(s, q, p->map_dtype, p->patch, nullptr, nullptr, st)) != hipSuccess)

@@ -168,13 +168,13 @@ __global__ __launch_bounds__(kBlock) void k_b_topk(BatchDev b, SearchDev q) {
 }
 
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_b_features(BatchDev b, float z_near,
-                                                       uint16_t* __restrict__ feats) {
+__global__ __launch_bounds__(kBlock) void k_b_topk_features(BatchDev b, SearchDev q,
+                                                            uint16_t* __restrict__ feats) {
   int s;
   const int64_t j = block_point(b, &s);
   if (j < 0) return;
   const SceneDev sc = b.tab[s];
-  features_point<T>(sc, z_near, j, 1, b.pt_off[s], feats);
+  topk_features_point<T>(sc, q, j, b.pt_off[s], feats);
 }
 
 // Persistent search over items 0..n_items-1 (item = global point position, or
@@ -352,11 +352,13 @@ static int record_batch(fd_context* c, const fd_params* p, int n_scenes, int64_t
   q.step0 = p->refine_step0 > 0.0f ? p->refine_step0 : default_step0(p->n_candidates);
   q.K = p->top_k;
   q.z_near = p->z_near;
-  if (p->map_dtype == FD_F16)
-    hipLaunchKernelGGL(k_b_topk<__half>, dim3((unsigned)nblocks), dim3(kBlock), 0, st, b, q);
-  else
-    hipLaunchKernelGGL(k_b_topk<float>, dim3((unsigned)nblocks), dim3(kBlock), 0, st, b, q);
-  if ((e = hipGetLastError()) != hipSuccess) return hip_error(e, "batched view selection");
+  if (p->mode == FD_MODE_PLAIN) {  // the learned form selects views with its features
+    if (p->map_dtype == FD_F16)
+      hipLaunchKernelGGL(k_b_topk<__half>, dim3((unsigned)nblocks), dim3(kBlock), 0, st, b, q);
+    else
+      hipLaunchKernelGGL(k_b_topk<float>, dim3((unsigned)nblocks), dim3(kBlock), 0, st, b, q);
+    if ((e = hipGetLastError()) != hipSuccess) return hip_error(e, "batched view selection");
+  }
   const int chunk = c->tuned_chunk > 0 ? c->tuned_chunk : 2;
   const int grid = persistent_grid(p->map_dtype, p->patch, c->tuned_grid);
   uint32_t* queue = c->tile_queue;
@@ -381,11 +383,11 @@ static int record_batch(fd_context* c, const fd_params* p, int n_scenes, int64_t
   }
   l.step0 = step0;
   if (p->map_dtype == FD_F16)
-    hipLaunchKernelGGL(k_b_features<__half>, dim3((unsigned)nblocks), dim3(kBlock), 0, st, b,
-                       p->z_near, c->feats);
+    hipLaunchKernelGGL(k_b_topk_features<__half>, dim3((unsigned)nblocks), dim3(kBlock), 0, st,
+                       b, q, c->feats);
   else
-    hipLaunchKernelGGL(k_b_features<float>, dim3((unsigned)nblocks), dim3(kBlock), 0, st, b,
-                       p->z_near, c->feats);
+    hipLaunchKernelGGL(k_b_topk_features<float>, dim3((unsigned)nblocks), dim3(kBlock), 0, st,
+                       b, q, c->feats);
   int r = mlp_forward_dev(p->mlp, c->feats, total, c->prop, st);
   if (r) return r;
   l.proposals = c->prop;

@@ -49,46 +49,36 @@ __device__ __forceinline__ float frontal_score32(const float* cam, float px, flo
   return dot / la;
 }
 
-// One lane per point: the kSlots most frontal eligible views (stable: equal
-// scores keep the lower view index first), then per slot the observed
-// orientation as (q_x, q_y) = |m| (cos 2psi, sin 2psi) (m the bilinear
-// confidence-weighted doubled-angle vector, psi the angle of the plane it
-// back-projects to, in a frame tied to the line of sight), the bilinear
-// confidence C, the unit point->camera direction and 1; empty slots are 0.
-// Row r of `feats` (112 bfloat16) is the processing-order index when by_j,
-// else the point index.
-template <typename T>
-__device__ __forceinline__ void features_point(const SceneDev& s, float z_near, int64_t j,
-                                               int by_j, int64_t row_base,
-                                               uint16_t* __restrict__ feats) {
-  const uint32_t i = s.perm ? s.perm[j] : (uint32_t)j;
-  const float px = s.pts[3 * (size_t)i], py = s.pts[3 * (size_t)i + 1],
-              pz = s.pts[3 * (size_t)i + 2];
-  float sc[kSlots];
-  int id[kSlots];
+// Stable insertion of view v with frontal score cs into the descending list
+// (sc, id) of kSlots entries: equal scores keep the lower view index first;
+// a view that does not beat the last entry is skipped.
+__device__ __forceinline__ void frontal_insert(float (&sc)[kSlots], int (&id)[kSlots], float cs,
+                                               int cv) {
+  if (!(cs > sc[kSlots - 1]) && id[kSlots - 1] >= 0) return;
+  bool ins = false;
 #pragma unroll
   for (int k = 0; k < kSlots; ++k) {
-    sc[k] = -INFINITY;
-    id[k] = -1;
+    const bool take = ins || (cs > sc[k]) || (!ins && id[k] < 0);
+    const float ts = sc[k];
+    const int tv = id[k];
+    sc[k] = take ? cs : ts;
+    id[k] = take ? cv : tv;
+    cs = take ? ts : cs;
+    cv = take ? tv : cv;
+    ins = ins || take;
   }
-  for (int v = 0; v < s.V; ++v) {
-    Proj pr;
-    if (!project32(s.cams + 16 * v, px, py, pz, s.W, s.H, z_near, pr)) continue;
-    float cs = frontal_score32(s.cams + 16 * v, px, py, pz, s.hc, nullptr);
-    int cv = v;
-    bool ins = false;
-#pragma unroll
-    for (int k = 0; k < kSlots; ++k) {
-      bool take = ins || (cs > sc[k]) || (!ins && id[k] < 0);
-      float ts = sc[k];
-      int tv = id[k];
-      sc[k] = take ? cs : ts;
-      id[k] = take ? cv : tv;
-      cs = take ? ts : cs;
-      cv = take ? tv : cv;
-      ins = ins || take;
-    }
-  }
+}
+
+// Per slot of the frontal list: the observed orientation as
+// (q_x, q_y) = |m| (cos 2psi, sin 2psi) (m the bilinear confidence-weighted
+// doubled-angle vector, psi the angle of the plane it back-projects to, in a
+// frame tied to the line of sight), the bilinear confidence C, the unit
+// point->camera direction and 1; empty slots are 0.  Written as 112
+// bfloat16 to feats row `row`.
+template <typename T>
+__device__ __forceinline__ void write_feature_row(const SceneDev& s, float z_near, float px,
+                                                  float py, float pz, const int (&id)[kSlots],
+                                                  int64_t row, uint16_t* __restrict__ feats) {
   const T* th = (const T*)s.theta;
   const T* cf = (const T*)s.conf;
   const size_t plane = (size_t)s.W * s.H;
@@ -168,10 +158,93 @@ __device__ __forceinline__ void features_point(const SceneDev& s, float z_near, 
 #pragma unroll
     for (int e = 0; e < 7; ++e) out[7 * k + e] = feat_bf16(f[e]);
   }
-  uint4* dst = (uint4*)(feats + (size_t)(row_base + (by_j ? j : (int64_t)i)) * (7 * kSlots));
+  uint4* dst = (uint4*)(feats + (size_t)row * (7 * kSlots));
   const uint4* src = (const uint4*)out;
 #pragma unroll
   for (int e = 0; e < (7 * kSlots * 2) / 16; ++e) dst[e] = src[e];
+}
+
+// One lane per point: the kSlots most frontal eligible views, then their
+// feature row (processing-order index j when by_j, else the point index,
+// plus row_base).
+template <typename T>
+__device__ __forceinline__ void features_point(const SceneDev& s, float z_near, int64_t j,
+                                               int by_j, int64_t row_base,
+                                               uint16_t* __restrict__ feats) {
+  const uint32_t i = s.perm ? s.perm[j] : (uint32_t)j;
+  const float px = s.pts[3 * (size_t)i], py = s.pts[3 * (size_t)i + 1],
+              pz = s.pts[3 * (size_t)i + 2];
+  float sc[kSlots];
+  int id[kSlots];
+#pragma unroll
+  for (int k = 0; k < kSlots; ++k) {
+    sc[k] = -INFINITY;
+    id[k] = -1;
+  }
+  for (int v = 0; v < s.V; ++v) {
+    Proj pr;
+    if (!project32(s.cams + 16 * v, px, py, pz, s.W, s.H, z_near, pr)) continue;
+    frontal_insert(sc, id, frontal_score32(s.cams + 16 * v, px, py, pz, s.hc, nullptr), v);
+  }
+  write_feature_row<T>(s, z_near, px, py, pz, id, row_base + (by_j ? j : (int64_t)i), feats);
+}
+
+// Eq. (4) view selection and the proposal features in one pass over the
+// views (one projection per view): writes views / kcount like topk_point
+// and feature row row_base + j.
+template <typename T>
+__device__ __forceinline__ void topk_features_point(const SceneDev& s, const SearchDev& q,
+                                                    int64_t j, int64_t row_base,
+                                                    uint16_t* __restrict__ feats) {
+  const uint32_t i = s.perm[j];
+  const float px = s.pts[3 * (size_t)i], py = s.pts[3 * (size_t)i + 1],
+              pz = s.pts[3 * (size_t)i + 2];
+  float ck[FD_TOPK_SLOTS];
+  int vk[FD_TOPK_SLOTS];
+#pragma unroll
+  for (int k = 0; k < FD_TOPK_SLOTS; ++k) {
+    ck[k] = -1.0f;
+    vk[k] = 0;
+  }
+  float sc[kSlots];
+  int id[kSlots];
+#pragma unroll
+  for (int k = 0; k < kSlots; ++k) {
+    sc[k] = -INFINITY;
+    id[k] = -1;
+  }
+  const T* conf = (const T*)s.conf;
+  const size_t plane = (size_t)s.W * s.H;
+  for (int v = 0; v < s.V; ++v) {
+    Proj pr;
+    if (!project32(s.cams + 16 * v, px, py, pz, s.W, s.H, q.z_near, pr)) continue;
+    const float c = centre_conf32<T>(conf + plane * v, s.W, s.H, pr.u, pr.v);
+    if (c > 0.0f) {
+      float cs = c;
+      int cv = v;
+      bool ins = false;
+#pragma unroll
+      for (int k = 0; k < FD_TOPK_SLOTS; ++k) {
+        const bool take = ins || (cs > ck[k]);
+        const float ts = ck[k];
+        const int tv = vk[k];
+        ck[k] = take ? cs : ts;
+        vk[k] = take ? cv : tv;
+        cs = take ? ts : cs;
+        cv = take ? tv : cv;
+        ins = take;
+      }
+    }
+    frontal_insert(sc, id, frontal_score32(s.cams + 16 * v, px, py, pz, s.hc, nullptr), v);
+  }
+  int keff = 0;
+#pragma unroll
+  for (int k = 0; k < FD_TOPK_SLOTS; ++k) {
+    if (k < q.K && ck[k] > 0.0f) keff = k + 1;
+    s.views[FD_TOPK_SLOTS * j + k] = (uint16_t)vk[k];
+  }
+  s.kcount[j] = (uint8_t)keff;
+  write_feature_row<T>(s, q.z_near, px, py, pz, id, row_base + j, feats);
 }
 
 }  // namespace fd

@@ -28,6 +28,14 @@ __global__ __launch_bounds__(256) void k_features(SceneDev s, float z_near, int 
   features_point<T>(s, z_near, j, by_j, 0, feats);
 }
 
+template <typename T>
+__global__ __launch_bounds__(256) void k_topk_features(SceneDev s, SearchDev q,
+                                                       uint16_t* __restrict__ feats) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= s.n) return;
+  topk_features_point<T>(s, q, j, 0, feats);
+}
+
 }  // namespace
 
 static hipError_t launch_features_rows(const SceneDev& s, int dtype, float z_near, int by_j,
@@ -61,9 +69,15 @@ int fd::run_learned(fd_context* c, const SceneDev& s, const SearchDev& q, const 
   l.step0 = step0;
   int prop_by_j = 0;
   if (p->proposal == FD_PROPOSAL_MLP) {
+    // view selection was done together with the features (run_scene skips
+    // its own top-K pass in this mode)
     StageTimer tf(c, FD_STAGE_FEATURES, st);
-    if ((e = launch_features_rows(s, p->map_dtype, p->z_near, 1, c->feats, st)) != hipSuccess)
-      return hip_error(e, "feature kernel");
+    dim3 grid((unsigned)((s.n + 255) / 256));
+    if (p->map_dtype == FD_F16)
+      hipLaunchKernelGGL(k_topk_features<__half>, grid, dim3(256), 0, st, s, q, c->feats);
+    else
+      hipLaunchKernelGGL(k_topk_features<float>, grid, dim3(256), 0, st, s, q, c->feats);
+    if ((e = hipGetLastError()) != hipSuccess) return hip_error(e, "view selection + features");
     tf.stop();
     StageTimer tm(c, FD_STAGE_MLP, st);
     int r = mlp_forward_dev(p->mlp, c->feats, s.n, c->prop, st);
