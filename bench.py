@@ -6,7 +6,10 @@ every input already resident in HBM.  Prints ONE JSON line on stdout (logs go
 to stderr).  Only one GPU is used; --gpus above 1 exits with a message.
 
 Workloads (synthetic scenes from ``scenegen``; they stand in for the paper's
-rendered Hair20K hairstyles and captured videos, which are not available):
+rendered Hair20K hairstyles and captured videos, which are not available).
+Points lie on the visible outer layer of the hair and every form applies the
+depth visibility test of Sec. 3.1.1 with the scene's rendered depth maps
+(--no-depth switches it off):
   metric     (default) 8 heads x 250k points of tight curls, 128 views at
              1024^2 float16, kappa 10, 30% outliers: learned+batched (value)
              against plain per head, plus plain+batched and learned per head.
@@ -47,13 +50,13 @@ def plain_flop_per_point(patch, n_cand, iters, top_k):
     return D * top_k * (12 + 4 * patch * patch)
 
 
-def cpu_baseline(sc, kw, seconds):
+def cpu_baseline(sc, kw, seconds, depth=True):
     """The oracle, untuned, on a bounded stride sample of the same scene."""
     import numpy as np
     import oracle
     threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or (os.cpu_count() or 1)
     threads = min(threads, os.cpu_count() or threads)
-    orc = oracle.Oracle(sc.cams, sc.theta, sc.conf, **kw)
+    orc = oracle.Oracle(sc.cams, sc.theta, sc.conf, depth=sc.depth if depth else None, **kw)
     n = sc.n_points
     chunk = 64 * threads
     stride = 7919
@@ -121,6 +124,8 @@ def run_learned(args):
     th = torch.from_numpy(sc.theta).to(dev)
     cf = torch.from_numpy(sc.conf).to(dev)
     gt = torch.from_numpy(sc.gt).to(dev)
+    if not args.no_depth:
+        kw["depth_maps"] = torch.from_numpy(sc.depth).to(dev)
     n = sc.n_points
     ctx = native.Context(max_points=n)
     net = native.MLP(path=args.mlp)
@@ -157,6 +162,7 @@ def run_learned(args):
     log(f"plain {v_p / 1e6:.1f} M points/s {json.dumps({k: round(v, 4) for k, v in st_p.items()})}")
     log(f"learned {v_l / 1e6:.1f} M points/s {json.dumps({k: round(v, 4) for k, v in st_l.items()})}"
         f" fallback {n_fb / n:.4f}, mean err vs plain {float(err.mean()):.3f} deg")
+    kw.pop("depth_maps", None)
     flop = plain_flop_per_point(kw["patch"], kw["n_candidates"], kw["refine_iters"], 5)
     achieved = flop * n / (st_p["fuse"] * 1e-3) / 1e12
     out = {
@@ -167,7 +173,8 @@ def run_learned(args):
         "config": {"workload": "learned (unbatched): 500k points, 64 views 1024^2 f16, 10% "
                                "outliers, P=5; network proposal + 2 refinement iterations, "
                                "plain fallback (128 candidates + 8 iterations)",
-                   "mode": "learned", "points": n, "views": sc.n_views, **kw},
+                   "mode": "learned", "points": n, "views": sc.n_views,
+                   "depth_test": not args.no_depth, **kw},
         "plain_points_per_s": v_p, "speedup_vs_plain": v_l / v_p,
         "mean_err_vs_plain_deg": float(err.mean()),
         "median_err_vs_plain_deg": float(err.median()),
@@ -209,6 +216,8 @@ def run_metric(args):
                  dirs=torch.empty((sc.n_points, 3), dtype=torch.float32, device=dev),
                  costs=torch.empty((sc.n_points,), dtype=torch.float32, device=dev),
                  head_centre=sc.head_centre, gt=torch.from_numpy(sc.gt).to(dev))
+        if not args.no_depth:
+            d["depth_maps"] = torch.from_numpy(sc.depth).to(dev)
         heads.append((sc, d))
         log(f"head {h}: {sc.n_points} points, {sc.n_views} views "
             f"({time.perf_counter() - t:.1f} s)")
@@ -230,7 +239,8 @@ def run_metric(args):
             for sc, d in heads:
                 native.fuse_directions(d["points"], d["cams"], d["orient_maps"], d["conf_maps"],
                                        dirs=d["dirs"], costs=d["costs"], ctx=ctx, stream=stream,
-                                       head_centre=sc.head_centre, **kw, **extra)
+                                       head_centre=sc.head_centre,
+                                       depth_maps=d.get("depth_maps"), **kw, **extra)
         return step
 
     def batched(extra):
@@ -265,7 +275,8 @@ def run_metric(args):
     for sc, d in heads:
         native.fuse_directions(d["points"], d["cams"], d["orient_maps"], d["conf_maps"],
                                dirs=d["dirs"], costs=d["costs"], ctx=ctx, stream=stream,
-                               head_centre=sc.head_centre, **kw, **lkw)
+                               head_centre=sc.head_centre, depth_maps=d.get("depth_maps"),
+                               **kw, **lkw)
         fb += ctx.fallback_count(stream)
     log(f"mean err vs plain (deg) {json.dumps({k: round(v, 3) for k, v in errs.items()})}; "
         f"fallback {fb / n:.3f}; batched == per-head: plain {same_pb}, learned {same_lb}")
@@ -284,11 +295,13 @@ def run_metric(args):
                                "the network proposal, plain fallback (128 candidates + 8 "
                                "iterations), one captured batched launch",
                    "mode": "learned+batched", "points": n, "heads": len(heads), "views": 128,
+                   "depth_test": not args.no_depth,
                    "learned_step0": step0, "fallback_cost": tau, **kw},
         "plain_points_per_s": v_p, "speedup_vs_plain": v_lb / v_p,
         "points_per_s": {k: v[0] for k, v in res.items()},
         "ms_per_step_by_form": {k: v[1] for k, v in res.items()},
         "mean_err_vs_plain_deg": errs, "mean_err_vs_gt_deg": err_gt,
+        "median_err_vs_gt_deg_plain": float(_axial_deg(dp[fin], gt[fin]).median()),
         "fallback_frac": fb / n, "batched_bitwise_equal": {"plain": same_pb, "learned": same_lb},
         "stages_ms_per_launch_plain": st_p,
         "roofline": {"bound": "alu", "kernel": "k_fuse (plain search, per-head launches)",
@@ -299,7 +312,8 @@ def run_metric(args):
                      "frac_vs_vendor_packed": achieved / PEAK_FP32_VENDOR},
     }
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(heads[0][0], kw, args.cpu_seconds)
+        out["cpu_baseline"] = cpu_baseline(heads[0][0], kw, args.cpu_seconds,
+                                           depth=not args.no_depth)
         log(f"cpu baseline: {out['cpu_baseline']}")
     return out
 
@@ -327,10 +341,11 @@ def run_plain(args):
     costs = torch.empty((sc.n_points,), dtype=torch.float32, device=dev)
     ctx = native.Context(max_points=sc.n_points)
     stream = torch.cuda.current_stream()
+    dm = None if args.no_depth else torch.from_numpy(sc.depth).to(dev)
 
     def step():
         native.fuse_directions(pts, cams, th, cf, dirs=dirs, costs=costs, ctx=ctx,
-                               stream=stream, **kw)
+                               stream=stream, depth_maps=dm, **kw)
 
     for _ in range(args.warmup):
         step()
@@ -354,6 +369,8 @@ def run_plain(args):
     fuse_s = stages["fuse"] * 1e-3
     achieved = flop * sc.n_points / fuse_s / 1e12
     c = costs.cpu().numpy()
+    fin = torch.isfinite(costs)
+    err_gt = _axial_deg(dirs[fin], torch.from_numpy(sc.gt).to(dev)[fin])
     log(f"steps {args.steps}: {ms_step:.3f} ms/step, {value / 1e6:.1f} M points/s; "
         f"stages (ms/launch) {json.dumps({k: round(v, 4) for k, v in stages.items()})}; "
         f"finite costs {np.isfinite(c).mean():.4f}")
@@ -365,6 +382,7 @@ def run_plain(args):
         "config": {"workload": "plain: 500k points, 20k strands, 64 views 1024^2 f16 maps, "
                                "10% outliers, P=5, 128 candidates + 8 refinement iterations",
                    "mode": "plain", "points": sc.n_points, "views": sc.n_views,
+                   "depth_test": not args.no_depth,
                    "map": f"{sc.width}x{sc.height} f16", **kw},
         "roofline": {"bound": "alu", "kernel": "k_fuse", "achieved": achieved,
                      "peak": PEAK_FP32_FMA, "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_FMA,
@@ -372,9 +390,10 @@ def run_plain(args):
                      "flop_per_point": flop, "peak_vendor_packed": PEAK_FP32_VENDOR,
                      "frac_vs_vendor_packed": achieved / PEAK_FP32_VENDOR},
         "stages_ms_per_launch": stages,
+        "err_vs_gt_deg": {"mean": float(err_gt.mean()), "median": float(err_gt.median())},
     }
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(sc, kw, args.cpu_seconds)
+        out["cpu_baseline"] = cpu_baseline(sc, kw, args.cpu_seconds, depth=not args.no_depth)
         log(f"cpu baseline: {out['cpu_baseline']}")
     return out
 
@@ -391,6 +410,8 @@ def main():
     ap.add_argument("--mlp", default=os.path.join(ROOT, "paper_2604_05794_amd", "weights",
                                                   "proposal_mlp.fdmlp"))
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-depth", action="store_true",
+                    help="run without the depth visibility test")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))

@@ -94,13 +94,21 @@ typedef struct fd_params {
   int32_t proposal;        /* FD_PROPOSAL_* */
   const float* proposal_dirs; /* device N x 3, for FD_PROPOSAL_GIVEN */
   float head_centre[3];    /* world point the frontal-view ranking is relative to */
+  float vis_tau;           /* visibility tolerance (metres) on |Z - D|, finite, >= 0 */
+  const void* depth_maps;  /* device n_views x H x W of map_dtype: rendered camera-space
+                              depth D_v (+inf where empty), or NULL.  When set, a view is
+                              eligible for a point (view selection and the proposal
+                              features alike) only if the point is visible in it:
+                              |Z - D_v(nearest texel of u)| <= vis_tau, decided in
+                              binary32 (Sec. 3.1.1, visibility score V_i^v) */
   void* stream;            /* hipStream_t */
   fd_context* ctx;         /* workspace; NULL = a per-device default that grows */
 } fd_params;
 
 /* Defaults: K = 5 (Sec. 3.1.2, Eq. 4), P = 5 (Sec. 4), 128 candidates,
  * 8 refinement iterations, z_near = 1e-3, plain mode, FD_F16 maps,
- * learned_iters = 2. */
+ * learned_iters = 2, no depth maps, vis_tau = 5e-3 (half the 10 mm depth
+ * range of Sec. 3.1.1). */
 void fd_params_init(fd_params* params);
 
 /* ---- context: library-owned workspace ------------------------------------
@@ -141,8 +149,8 @@ int fd_last_fallback_count(fd_context* ctx, void* stream, int64_t* out);
 
 /* ---- many scenes in one launch --------------------------------------------
  * Every scene has its own points, cameras, maps (own W x H and view count)
- * and outputs; all use params' search settings and map dtype (params->width
- * and height are ignored).  The scenes array is host memory holding device
+ * and outputs; all use params' search settings and map dtype (params->width,
+ * height and depth_maps are ignored: each scene brings its own).  The scenes array is host memory holding device
  * pointers; at most FD_MAX_BATCH_SCENES scenes.  The context is required and
  * must be reserved for the total point count and the scene count.  The
  * launch sequence is captured into a HIP graph on the first call and
@@ -158,6 +166,7 @@ typedef struct fd_scene {
   int32_t width, height;
   const void* orient_maps;
   const void* conf_maps;
+  const void* depth_maps;  /* as fd_params.depth_maps, per scene (NULL: no test) */
   float* dirs;
   float* costs;
   float head_centre[3];
@@ -202,7 +211,8 @@ int fd_mlp_train_step(fd_mlp* mlp, const void* feats, const float* targets,
 void fd_mlp_destroy(fd_mlp* mlp);
 
 /* Proposal-network input of every point: the FD_FEATURE_SLOTS most frontal
- * eligible views (largest cosine between the point->camera direction and
+ * eligible views (in front, inside the image and, with params->depth_maps,
+ * visible; ranked by the largest cosine between the point->camera direction and
  * p - params->head_centre), each (q_x, q_y, C, v_x, v_y, v_z, valid):
  * v is the unit point->camera direction, C the bilinear confidence and
  * (q_x, q_y) = |m| (cos 2psi, sin 2psi), where m is the bilinear

@@ -44,6 +44,8 @@ class Params(ctypes.Structure):
         ("refine_step0", ctypes.c_double),
         ("top_k", ctypes.c_int32),
         ("z_near", ctypes.c_double),
+        ("depth_maps", ctypes.c_void_p),
+        ("vis_tau", ctypes.c_double),
     ]
 
 
@@ -96,10 +98,11 @@ def _c(a, dtype):
 
 
 def make_params(width, height, map_dtype=0, patch=5, n_candidates=128,
-                refine_iters=8, refine_step0=0.0, top_k=5, z_near=1e-3) -> Params:
+                refine_iters=8, refine_step0=0.0, top_k=5, z_near=1e-3,
+                depth_ptr=None, vis_tau=5e-3) -> Params:
     return Params(int(width), int(height), int(map_dtype), int(patch),
                   int(n_candidates), int(refine_iters), float(refine_step0),
-                  int(top_k), float(z_near))
+                  int(top_k), float(z_near), depth_ptr, float(vis_tau))
 
 
 def _maps(scene_theta, scene_conf):
@@ -112,20 +115,34 @@ def _maps(scene_theta, scene_conf):
 
 class Oracle:
     """Oracle bound to one scene: points (N,3) f32, cams (V,16) f32,
-    theta/conf maps (V,H,W) f32 or f16."""
+    theta/conf maps (V,H,W) f32 or f16; optional depth maps (V,H,W) of the
+    same dtype switch on the visibility test with tolerance vis_tau."""
 
     def __init__(self, cams, theta, conf, patch=5, n_candidates=128,
-                 refine_iters=8, refine_step0=0.0, top_k=5, z_near=1e-3):
+                 refine_iters=8, refine_step0=0.0, top_k=5, z_near=1e-3,
+                 depth=None, vis_tau=5e-3):
         self.cams = _c(cams, np.float32)
         self.theta, self.conf, dt = _maps(theta, conf)
         V, H, W = self.theta.shape
         self.V = V
+        self.depth = None
+        if depth is not None:
+            d = np.ascontiguousarray(depth)
+            if d.shape != self.theta.shape:
+                raise ValueError("depth maps must have the shape of the orientation maps")
+            if dt == 1:
+                self.depth = _c(d, np.float16).view(np.uint16)
+            else:
+                self.depth = _c(d, np.float32)
         self.prm = make_params(W, H, dt, patch, n_candidates, refine_iters,
-                               refine_step0, top_k, z_near)
+                               refine_step0, top_k, z_near,
+                               None if self.depth is None else self.depth.ctypes.data,
+                               vis_tau)
 
     def with_params(self, **kw):
         o = Oracle.__new__(Oracle)
         o.cams, o.theta, o.conf, o.V = self.cams, self.theta, self.conf, self.V
+        o.depth = self.depth
         fields = {f[0]: getattr(self.prm, f[0]) for f in Params._fields_}
         fields.update(kw)
         o.prm = Params(**fields)

@@ -66,11 +66,14 @@ static const void* view_map(const void* maps, int dtype, int W, int H, int v) {
  *   w00 = gx*gy, w10 = fx*gy, w01 = gx*fy, w11 = fx*fy
  *   Cbar = fma(w11, C11, fma(w01, C01, fma(w10, C10, w00*C00)))
  *   eligible : front and inside and Cbar > 0
+ *   with depth maps, also visible:
+ *     ix = (int)floor(u + 0.5f), iy = (int)floor(v + 0.5f)   (nearest texel)
+ *     visible : |Z - D(ix, iy)| <= (float)vis_tau   (Sec. 3.1.1, V_i^v)
  * The pixel position u computed here is also the patch centre (Sec. 3.1.3:
  * the patch is centred on the projection of the point).
  */
 static int project32(const float* cam, const float* p, int W, int H,
-                     float z_near, float* u) {
+                     float z_near, float* u, float* z_out) {
   const float* R = cam + 4;
   const float* t = cam + 13;
   float X = fmaf(R[0], p[0], fmaf(R[1], p[1], fmaf(R[2], p[2], t[0])));
@@ -85,7 +88,19 @@ static int project32(const float* cam, const float* p, int W, int H,
     return 0;
   u[0] = ux;
   u[1] = uy;
+  *z_out = Z;
   return 1;
+}
+
+/* Sec. 3.1.1 visibility: the point's camera-space depth agrees with the
+ * rendered depth at the nearest texel of its projection.  Always true
+ * without depth maps. */
+static int visible32(const fdo_params* prm, int v, const float* u, float Z) {
+  if (!prm->depth_maps) return 1;
+  const int W = prm->width, H = prm->height, dt = prm->map_dtype;
+  int ix = (int)floorf(u[0] + 0.5f), iy = (int)floorf(u[1] + 0.5f);
+  float D = texel(view_map(prm->depth_maps, dt, W, H, v), dt, W, H, ix, iy);
+  return fabsf(Z - D) <= (float)prm->vis_tau;
 }
 
 static float centre_conf32(const void* cmap, int dtype, int W, int H,
@@ -114,8 +129,9 @@ int fdo_select_views(const float* p, const float* cams, int32_t n_views,
   int ids[FDO_MAX_K];
   float sc[FDO_MAX_K], us[FDO_MAX_K][2];
   for (int v = 0; v < n_views; ++v) {
-    float u[2];
-    if (!project32(cams + 16 * v, p, W, H, (float)prm->z_near, u)) continue;
+    float u[2], Z;
+    if (!project32(cams + 16 * v, p, W, H, (float)prm->z_near, u, &Z)) continue;
+    if (!visible32(prm, v, u, Z)) continue;
     float s = centre_conf32(view_map(conf_maps, dt, W, H, v), dt, W, H, u[0],
                             u[1]);
     if (!(s > 0.0f)) continue;
@@ -554,7 +570,7 @@ int fdo_fuse_learned(const float* points, int64_t n_points, const float* cams,
  *   a = c - p, b = p - o (componentwise binary32 subtraction)
  *   score = fma(a_x, b_x, fma(a_y, b_y, a_z*b_z)) /
  *           sqrt(fma(a_x, a_x, fma(a_y, a_y, a_z*a_z)))
- * eligible views are those of project32(); the n_slots largest scores are
+ * eligible views are those that project32() and visible32() accept; the n_slots largest scores are
  * kept, equal scores to the lower view index.  |b| is common to every view of
  * a point and does not change the ranking.
  */
@@ -589,8 +605,9 @@ int fdo_features(const float* points, int64_t n_points, const float* cams,
     float sc[64], us[64][2];
     int kept = 0, S = n_slots > 64 ? 64 : n_slots;
     for (int v = 0; v < n_views; ++v) {
-      float u[2];
-      if (!project32(cams + 16 * v, p, W, H, (float)prm->z_near, u)) continue;
+      float u[2], Z;
+      if (!project32(cams + 16 * v, p, W, H, (float)prm->z_near, u, &Z)) continue;
+      if (!visible32(prm, v, u, Z)) continue;
       float s = frontal_score32(cams + 16 * v, p, head_centre);
       int pos = kept;
       while (pos > 0 && s > sc[pos - 1]) --pos;

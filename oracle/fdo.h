@@ -45,6 +45,12 @@ typedef struct fdo_params {
   double refine_step0;  /* first stencil angle in radians; <= 0 -> 0.5*sqrt(2*pi/n_candidates) */
   int32_t top_k;        /* K of Eq. (4) */
   double z_near;        /* eligibility: camera-space Z > z_near */
+  /* Optional visibility test of Sec. 3.1.1 (the score V_i^v): when
+   * depth_maps is not NULL (V x H x W, camera-space Z in the map dtype,
+   * +inf where nothing was rendered) a view is eligible only if
+   * |Z - D_v(nearest texel of u)| <= vis_tau, decided in binary32. */
+  const void* depth_maps;
+  double vis_tau;
 } fdo_params;
 
 /* binary16 -> binary32, exact. */

@@ -245,6 +245,8 @@ extern "C" void fd_params_init(fd_params* p) {
   p->fallback_cost = INFINITY;
   p->proposal = FD_PROPOSAL_MLP;
   p->proposal_dirs = nullptr;
+  p->vis_tau = 5e-3f;
+  p->depth_maps = nullptr;
   p->stream = nullptr;
   p->ctx = nullptr;
 }
@@ -267,6 +269,8 @@ int fd::check_search_params(const fd_params* p, const char* fn) {
                      p->top_k);
   if (!(p->z_near >= 0.0f) || !std::isfinite(p->z_near))
     return set_error(FD_E_INVAL, "%s: z_near must be finite and >= 0", fn);
+  if (!(p->vis_tau >= 0.0f) || !std::isfinite(p->vis_tau))
+    return set_error(FD_E_INVAL, "%s: vis_tau must be finite and >= 0", fn);
   if (p->mode != FD_MODE_PLAIN && p->mode != FD_MODE_LEARNED)
     return set_error(FD_E_INVAL, "%s: unknown mode %d", fn, p->mode);
   if (p->mode == FD_MODE_LEARNED) {
@@ -342,6 +346,7 @@ extern "C" int fd_fuse_directions(const float* points, int64_t n_points, const f
   sa.H = params->height;
   sa.theta = orient_maps;
   sa.conf = conf_maps;
+  sa.depth = params->depth_maps;
   sa.dirs = dirs;
   sa.costs = costs;
   for (int k = 0; k < 3; ++k) sa.hc[k] = params->head_centre[k];
@@ -361,6 +366,8 @@ int fd::run_scene(fd_context* c, const SceneArgs& a, const fd_params* p, hipStre
   s.cams = a.cams;
   s.theta = a.theta;
   s.conf = a.conf;
+  s.depth = a.depth;
+  s.vis_tau = p->vis_tau;
   s.dirs = a.dirs;
   s.costs = a.costs;
   s.perm = c->perm;

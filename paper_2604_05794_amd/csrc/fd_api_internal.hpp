@@ -75,6 +75,7 @@ struct SceneArgs {
   int V, W, H;
   const void* theta;
   const void* conf;
+  const void* depth;
   float* dirs;
   float* costs;
   float hc[3];

@@ -471,6 +471,8 @@ extern "C" int fd_fuse_directions_batched(const fd_scene* scenes, int32_t n_scen
       d.cams = (const float*)sc.cams;
       d.theta = sc.orient_maps;
       d.conf = sc.conf_maps;
+      d.depth = sc.depth_maps;
+      d.vis_tau = params->vis_tau;
       d.dirs = sc.dirs;
       d.costs = sc.costs;
       d.perm = ctx->perm + pt_off[s];

@@ -92,6 +92,20 @@ __device__ __forceinline__ float centre_conf32(const T* __restrict__ cm, int W,
   return __builtin_fmaf(w11, c11, __builtin_fmaf(w01, c01, __builtin_fmaf(w10, c10, w00 * c00)));
 }
 
+// Visibility of Sec. 3.1.1 (the score V_i^v), decided in binary32: the
+// camera-space depth of the point agrees with the rendered depth at the
+// nearest texel of its projection,
+//   ix = (int)floor(u + 0.5f), iy = (int)floor(v + 0.5f),  |Z - D(ix, iy)| <= tau.
+// No depth maps: always visible.  A +inf (background) or NaN depth never is.
+template <typename T>
+__device__ __forceinline__ bool visible32(const void* depth, size_t plane, int view, int W,
+                                          int H, const Proj& pr, float tau) {
+  if (depth == nullptr) return true;
+  const int ix = (int)floorf(pr.u + 0.5f), iy = (int)floorf(pr.v + 0.5f);
+  const float D = tex_load_nb<T>((const T*)depth + plane * view, W, H, ix, iy);
+  return fabsf(pr.Z - D) <= tau;
+}
+
 // Lanes of a wave are split into groups of `k` consecutive lanes; returns the
 // sum of v over the caller's group, added in lane order (slot 0 first) so
 // every lane of the group gets the same bits.

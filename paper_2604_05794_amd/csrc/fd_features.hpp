@@ -181,9 +181,11 @@ __device__ __forceinline__ void features_point(const SceneDev& s, float z_near, 
     sc[k] = -INFINITY;
     id[k] = -1;
   }
+  const size_t plane = (size_t)s.W * s.H;
   for (int v = 0; v < s.V; ++v) {
     Proj pr;
     if (!project32(s.cams + 16 * v, px, py, pz, s.W, s.H, z_near, pr)) continue;
+    if (!visible32<T>(s.depth, plane, v, s.W, s.H, pr, s.vis_tau)) continue;
     frontal_insert(sc, id, frontal_score32(s.cams + 16 * v, px, py, pz, s.hc, nullptr), v);
   }
   write_feature_row<T>(s, z_near, px, py, pz, id, row_base + (by_j ? j : (int64_t)i), feats);
@@ -218,6 +220,7 @@ __device__ __forceinline__ void topk_features_point(const SceneDev& s, const Sea
   for (int v = 0; v < s.V; ++v) {
     Proj pr;
     if (!project32(s.cams + 16 * v, px, py, pz, s.W, s.H, q.z_near, pr)) continue;
+    if (!visible32<T>(s.depth, plane, v, s.W, s.H, pr, s.vis_tau)) continue;
     const float c = centre_conf32<T>(conf + plane * v, s.W, s.H, pr.u, pr.v);
     if (c > 0.0f) {
       float cs = c;

@@ -30,9 +30,11 @@ struct SceneDev {
   const uint32_t* perm; // n, processing order -> point index
   uint16_t* views;      // n x 8, selected views (processing order)
   uint8_t* kcount;      // n, K_eff (processing order)
+  const void* depth;    // V x H x W camera-space Z, or NULL (no visibility test)
   int64_t n;
   int V, W, H;
   float hc[3];          // head centre (frontal ranking)
+  float vis_tau;        // visibility tolerance on |Z - D|
 };
 
 struct SearchDev {

@@ -128,6 +128,8 @@ extern "C" int fd_features(const float* points, int64_t n_points, const fd_camer
   if (n_points > 0 && (!points || !cams || !orient_maps || !conf_maps || !feats))
     return set_error(FD_E_INVAL, "%s: null pointer argument", fn);
   if (((uintptr_t)feats & 15) != 0) return set_error(FD_E_INVAL, "%s: feats must be 16-byte aligned", fn);
+  if (!(params->vis_tau >= 0.0f) || !std::isfinite(params->vis_tau))
+    return set_error(FD_E_INVAL, "%s: vis_tau must be finite and >= 0", fn);
   if ((r = check_device(nullptr))) return r;
   if (n_points == 0) return FD_OK;
   SceneDev s{};
@@ -135,6 +137,8 @@ extern "C" int fd_features(const float* points, int64_t n_points, const fd_camer
   s.cams = (const float*)cams;
   s.theta = orient_maps;
   s.conf = conf_maps;
+  s.depth = params->depth_maps;
+  s.vis_tau = params->vis_tau;
   s.perm = nullptr;
   s.n = n_points;
   s.V = n_views;

@@ -44,9 +44,10 @@ __device__ __forceinline__ void topk_point(const SceneDev& s, const SearchDev& q
     for (int u = 0; u < kGroup; ++u) {
       const int v = min(v0 + u, s.V - 1);
       Proj pr;
-      const bool ok = project32(s.cams + 16 * v, px, py, pz, s.W, s.H, q.z_near, pr);
-      const float c = centre_conf32<T>(conf + plane * v, s.W, s.H, ok ? pr.u : 0.0f,
-                                       ok ? pr.v : 0.0f);
+      bool ok = project32(s.cams + 16 * v, px, py, pz, s.W, s.H, q.z_near, pr);
+      if (!ok) pr.u = pr.v = pr.Z = 0.0f;
+      const float c = centre_conf32<T>(conf + plane * v, s.W, s.H, pr.u, pr.v);
+      ok = ok && visible32<T>(s.depth, plane, v, s.W, s.H, pr, s.vis_tau);
       cg[u] = (ok && v0 + u < s.V) ? c : 0.0f;
     }
 #pragma unroll

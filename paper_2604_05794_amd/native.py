@@ -53,7 +53,8 @@ class Params(ctypes.Structure):
         ("mlp", ctypes.c_void_p), ("learned_iters", ctypes.c_int32),
         ("learned_step0", ctypes.c_float), ("fallback_cost", ctypes.c_float),
         ("proposal", ctypes.c_int32), ("proposal_dirs", ctypes.c_void_p),
-        ("head_centre", ctypes.c_float * 3), ("stream", ctypes.c_void_p),
+        ("head_centre", ctypes.c_float * 3), ("vis_tau", ctypes.c_float),
+        ("depth_maps", ctypes.c_void_p), ("stream", ctypes.c_void_p),
         ("ctx", ctypes.c_void_p),
     ]
 
@@ -64,6 +65,7 @@ class Scene(ctypes.Structure):
         ("cams", ctypes.c_void_p), ("n_views", ctypes.c_int32),
         ("width", ctypes.c_int32), ("height", ctypes.c_int32),
         ("orient_maps", ctypes.c_void_p), ("conf_maps", ctypes.c_void_p),
+        ("depth_maps", ctypes.c_void_p),
         ("dirs", ctypes.c_void_p), ("costs", ctypes.c_void_p),
         ("head_centre", ctypes.c_float * 3),
     ]
@@ -196,7 +198,8 @@ def make_params(width, height, map_dtype, *, patch=5, n_candidates=128, refine_i
                 refine_step0=0.0, top_k=5, z_near=1e-3, mode=FD_MODE_PLAIN, mlp=None,
                 learned_iters=2, learned_step0=0.0, fallback_cost=math.inf,
                 proposal=FD_PROPOSAL_MLP, proposal_dirs=None, head_centre=(0.0, 0.0, 0.0),
-                stream=None, ctx: Optional[Context] = None) -> Params:
+                depth_maps=None, vis_tau=5e-3, stream=None,
+                ctx: Optional[Context] = None) -> Params:
     p = Params()
     lib().fd_params_init(ctypes.byref(p))
     p.width, p.height = int(width), int(height)
@@ -216,6 +219,8 @@ def make_params(width, height, map_dtype, *, patch=5, n_candidates=128, refine_i
     p.proposal_dirs = proposal_dirs.data_ptr() if proposal_dirs is not None else None
     for k in range(3):
         p.head_centre[k] = float(head_centre[k])
+    p.vis_tau = float(vis_tau)
+    p.depth_maps = depth_maps.data_ptr() if depth_maps is not None else None
     p.stream = _stream_handle(stream).value
     p.ctx = ctx.handle.value if ctx is not None else None
     return p
@@ -227,6 +232,14 @@ def map_dtype_of(t: torch.Tensor) -> int:
     if t.dtype == torch.float32:
         return FD_F32
     raise TypeError(f"maps must be float16 or float32, got {t.dtype}")
+
+
+def _check_depth(depth, orient_maps):
+    if depth is None:
+        return
+    _dev_tensor(depth, "depth_maps", orient_maps.dtype)
+    if depth.shape != orient_maps.shape:
+        raise ValueError("depth_maps must have the shape of orient_maps")
 
 
 def fuse_directions(points, cams, orient_maps, conf_maps, *, dirs=None, costs=None,
@@ -255,6 +268,7 @@ def fuse_directions(points, cams, orient_maps, conf_maps, *, dirs=None, costs=No
         costs = torch.empty((n,), dtype=torch.float32, device=points.device)
     _dev_tensor(dirs, "dirs", torch.float32, (3,))
     _dev_tensor(costs, "costs", torch.float32)
+    _check_depth(kw.get("depth_maps"), orient_maps)
     p = make_params(W, H, map_dtype_of(orient_maps), **kw)
     _check(lib().fd_fuse_directions(_ptr(points), n, _ptr(cams), V, _ptr(orient_maps),
                                     _ptr(conf_maps), ctypes.byref(p), _ptr(dirs), _ptr(costs)))
@@ -346,7 +360,7 @@ class MLP:
 
 
 def features(points, cams, orient_maps, conf_maps, head_centre=(0.0, 0.0, 0.0), out=None,
-             stream=None, z_near=1e-3):
+             stream=None, z_near=1e-3, depth_maps=None, vis_tau=5e-3):
     """fd_features: (N, 112) bfloat16 proposal-network inputs, point order."""
     _dev_tensor(points, "points", torch.float32, (3,))
     _dev_tensor(cams, "cams", torch.float32, (16,))
@@ -356,8 +370,9 @@ def features(points, cams, orient_maps, conf_maps, head_centre=(0.0, 0.0, 0.0), 
     n = points.shape[0]
     if out is None:
         out = torch.empty((n, FD_FEATURE_DIM), dtype=torch.bfloat16, device=points.device)
+    _check_depth(depth_maps, orient_maps)
     p = make_params(W, H, map_dtype_of(orient_maps), head_centre=head_centre, stream=stream,
-                    z_near=z_near)
+                    z_near=z_near, depth_maps=depth_maps, vis_tau=vis_tau)
     _check(lib().fd_features(_ptr(points), n, _ptr(cams), V, _ptr(orient_maps), _ptr(conf_maps),
                              ctypes.byref(p), _ptr(out)))
     return out
@@ -365,7 +380,7 @@ def features(points, cams, orient_maps, conf_maps, head_centre=(0.0, 0.0, 0.0), 
 
 def _scene_struct(sc):
     """sc: dict with points, cams, orient_maps, conf_maps, dirs, costs and
-    optional head_centre (CUDA tensors)."""
+    optional head_centre and depth_maps (CUDA tensors)."""
     s = Scene()
     pts, cams, th, cf = sc["points"], sc["cams"], sc["orient_maps"], sc["conf_maps"]
     _dev_tensor(pts, "points", torch.float32, (3,))
@@ -382,6 +397,9 @@ def _scene_struct(sc):
     s.width, s.height = W, H
     s.orient_maps = th.data_ptr()
     s.conf_maps = cf.data_ptr()
+    dep = sc.get("depth_maps")
+    _check_depth(dep, th)
+    s.depth_maps = dep.data_ptr() if dep is not None else None
     s.dirs = sc["dirs"].data_ptr()
     s.costs = sc["costs"].data_ptr()
     hc = sc.get("head_centre", (0.0, 0.0, 0.0))

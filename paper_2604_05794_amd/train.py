@@ -47,7 +47,8 @@ def axial_deg(a, b):
 
 
 def scene_pairs(recipe, seed, n_points=None):
-    """Features and plain-fused labels of one synthetic scene (GPU)."""
+    """Features and plain-fused labels of one synthetic scene (GPU), with
+    the depth visibility test on."""
     rec = dict(scenegen.RECIPES[recipe])
     if n_points:
         rec["n_points"] = n_points
@@ -56,10 +57,11 @@ def scene_pairs(recipe, seed, n_points=None):
     cams = torch.from_numpy(sc.cams).to(DEV)
     th = torch.from_numpy(sc.theta).to(DEV)
     cf = torch.from_numpy(sc.conf).to(DEV)
+    dm = torch.from_numpy(sc.depth).to(DEV)
     kw = dict(patch=rec["patch"], n_candidates=rec["n_candidates"],
-              refine_iters=rec["refine_iters"], top_k=5)
+              refine_iters=rec["refine_iters"], top_k=5, depth_maps=dm)
     d, c = native.fuse_directions(pts, cams, th, cf, **kw)
-    f = native.features(pts, cams, th, cf, head_centre=sc.head_centre)
+    f = native.features(pts, cams, th, cf, head_centre=sc.head_centre, depth_maps=dm)
     torch.cuda.synchronize()
     keep = torch.isfinite(c)
     return dict(feats=f[keep].contiguous(), dirs=d[keep].contiguous(), scene=sc,

@@ -60,6 +60,10 @@ def _raster_lib():
         L.scenegen_raster.restype = ctypes.c_int
         L.scenegen_raster.argtypes = [P, P, ctypes.c_int64, P, ctypes.c_int32, ctypes.c_int32,
                                       ctypes.c_int32, ctypes.c_double, P, P, P, ctypes.c_int32]
+        L.scenegen_visible_views.restype = ctypes.c_int
+        L.scenegen_visible_views.argtypes = [P, ctypes.c_int64, P, ctypes.c_int32, ctypes.c_int32,
+                                             ctypes.c_int32, P, ctypes.c_double, P,
+                                             ctypes.c_int32]
         _lib = L
     return _lib
 
@@ -71,7 +75,7 @@ class Scene:
     cams: np.ndarray            # (V, 16) float32
     theta: np.ndarray           # (V, H, W) float32 or float16, radians in [0, pi]
     conf: np.ndarray            # (V, H, W) same dtype, [0, 1]
-    depth: Optional[np.ndarray]  # (V, H, W) float32 camera-space Z, +inf background
+    depth: Optional[np.ndarray]  # (V, H, W) camera-space Z (map dtype), +inf background
     head_centre: np.ndarray     # (3,) float32
     meta: dict
 
@@ -234,14 +238,16 @@ def sample_points(rng, verts, offs, n_points, jitter_sigma):
 # ---- maps ---------------------------------------------------------------------
 
 def render_maps(rng_views, verts, offs, cams, width, height, kappa, outlier_frac,
-                dtype, head_radius=SCALP_RADIUS, with_depth=False, n_threads=0):
-    """Orientation and confidence maps of every view.
+                dtype, head_radius=SCALP_RADIUS, n_threads=0):
+    """Orientation, confidence and depth maps of every view.
 
     Covered texels get the strand image angle, then (if kappa is not None)
     von Mises noise of concentration kappa on the angle and confidence
     ~ U(0.6, 1); a fraction ``outlier_frac`` of covered texels is replaced by
     angle ~ U[0, pi) and confidence ~ U(0, 1).  kappa None means noise-free:
     confidence 1 and the exact angle.  Background: angle 0, confidence 0.
+    Depth: camera-space Z of the nearest strand or head surface, +inf where
+    the ray meets neither (float32; the caller casts it with the maps).
     """
     V = len(cams)
     v32 = np.ascontiguousarray(verts, np.float32)
@@ -275,8 +281,25 @@ def render_maps(rng_views, verts, offs, cams, width, height, kappa, outlier_frac
     if dtype == np.float16:
         theta16 = theta.astype(np.float16)
         conf16 = conf.astype(np.float16)
-        return theta16, conf16, (depth if with_depth else None)
-    return theta, conf, (depth if with_depth else None)
+        return theta16, conf16, depth
+    return theta, conf, depth
+
+
+VIS_TAU = 5e-3   # visibility tolerance: half the paper's 2 Delta = 10 mm depth range
+
+
+def visible_views(points, cams, depth, tau=VIS_TAU, n_threads=0):
+    """Number of views in which each point is visible (in front, inside the
+    image, within tau of the nearest-texel depth)."""
+    pts = np.ascontiguousarray(points, np.float32)
+    cams = np.ascontiguousarray(cams, np.float32)
+    dep = np.ascontiguousarray(depth, np.float32)
+    V, H, W = dep.shape
+    out = np.empty(len(pts), np.int32)
+    _raster_lib().scenegen_visible_views(pts.ctypes.data, len(pts), cams.ctypes.data, V, W, H,
+                                         dep.ctypes.data, float(tau), out.ctypes.data,
+                                         int(n_threads))
+    return out
 
 
 # ---- recipes ------------------------------------------------------------------
@@ -318,8 +341,10 @@ def batched_recipes(n_scenes=16):
     return out
 
 
-def make_scene(recipe, seed, scale_points=1.0, with_depth=False, n_threads=0) -> Scene:
-    """Build one scene from a recipe dict (or a RECIPES key)."""
+def make_scene(recipe, seed, scale_points=1.0, n_threads=0) -> Scene:
+    """Build one scene from a recipe dict (or a RECIPES key).  Points lie on
+    the visible outer layer of the hair (seen in at least two views) unless
+    the recipe sets outer=False, which samples the whole hair volume."""
     if isinstance(recipe, str):
         recipe = RECIPES[recipe]
     r = dict(recipe)
@@ -335,16 +360,34 @@ def make_scene(recipe, seed, scale_points=1.0, with_depth=False, n_threads=0) ->
         wave_len_mm=r.get("wave_len_mm", (20.0, 60.0)),
         length_mm=r.get("length_mm", (60.0, 150.0)))
     n_points = max(1, int(round(r["n_points"] * scale_points)))
-    pts, gt = sample_points(rng_p, verts, offs, n_points, r.get("jitter", 2e-3))
     res = r["res"]
     cams = orbit_cameras(r["n_views"], res, res, r["arc_deg"])
     dtype = np.float16 if r["dtype"] == "f16" else np.float32
     theta, conf, depth = render_maps(rng_v, verts, offs, cams, res, res, r.get("kappa"),
                                      r.get("outliers", 0.0), dtype,
                                      head_radius=r.get("head_radius", SCALP_RADIUS),
-                                     with_depth=with_depth, n_threads=n_threads)
+                                     n_threads=n_threads)
+    if r.get("outer", True):
+        # the visible outer layer of the hair, as a reconstructed outer point
+        # cloud would hold it: points (jitter included) visible in at least
+        # two views; drawn in rounds until n_points are kept
+        keep_p, keep_g, have = [], [], 0
+        for _ in range(64):
+            cand, cgt = sample_points(rng_p, verts, offs, max(4 * (n_points - have), 1024),
+                                      r.get("jitter", 2e-3))
+            ok = visible_views(cand, cams, depth, n_threads=n_threads) >= 2
+            keep_p.append(cand[ok])
+            keep_g.append(cgt[ok])
+            have += int(ok.sum())
+            if have >= n_points:
+                break
+        pts = np.concatenate(keep_p)[:n_points]
+        gt = np.concatenate(keep_g)[:n_points]
+    else:
+        pts, gt = sample_points(rng_p, verts, offs, n_points, r.get("jitter", 2e-3))
+    depth_out = depth.astype(dtype) if dtype == np.float16 else depth
     meta = dict(recipe=r, seed=int(seed), n_vertices=len(verts), n_strands=len(offs) - 1)
-    return Scene(pts, gt, cams, theta, conf, depth, np.zeros(3, np.float32), meta)
+    return Scene(pts, gt, cams, theta, conf, depth_out, np.zeros(3, np.float32), meta)
 
 
 def method_params(recipe):
@@ -371,7 +414,8 @@ def straight_strand_scene(seed=0, n_points=50, n_views=8, res=256, arc_deg=120.0
     pts, gt = sample_points(rng, verts, offs, n_points, jitter)
     cams = orbit_cameras(n_views, res, res, arc_deg)
     th, c, dep = render_maps([None] * n_views, verts, offs, cams, res, res, None, 0.0, dtype,
-                             head_radius=0.0, with_depth=True)
+                             head_radius=0.0)
+    dep = dep.astype(dtype)
     return Scene(pts, gt, cams, th, c, dep, np.zeros(3, np.float32),
                  dict(kind="straight_strand", seed=seed, direction=d.tolist()))
 

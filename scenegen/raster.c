@@ -116,3 +116,31 @@ int scenegen_raster(const float* verts, const int64_t* offs, int64_t n_strands,
   }
   return 0;
 }
+
+/* For each point, the number of views in which it is visible: in front of
+ * the camera, projecting inside the image, and within tau of the depth
+ * stored at the nearest texel (depth maps V x H x W, float). */
+int scenegen_visible_views(const float* pts, int64_t n, const float* cams,
+                           int32_t n_views, int32_t W, int32_t H,
+                           const float* depth, double tau, int32_t* count,
+                           int32_t n_threads) {
+#ifdef _OPENMP
+  if (n_threads > 0) omp_set_num_threads(n_threads);
+#pragma omp parallel for schedule(static)
+#endif
+  for (int64_t i = 0; i < n; ++i) {
+    double p[3] = {pts[3 * i], pts[3 * i + 1], pts[3 * i + 2]};
+    int c = 0;
+    for (int v = 0; v < n_views; ++v) {
+      double u[2], z;
+      proj(cams + 16 * v, p, u, &z);
+      if (!(z > 1e-3)) continue;
+      if (!(u[0] >= 0 && u[0] <= W - 1 && u[1] >= 0 && u[1] <= H - 1)) continue;
+      long ix = (long)floor(u[0] + 0.5), iy = (long)floor(u[1] + 0.5);
+      double d = depth[(size_t)v * W * H + (size_t)iy * W + ix];
+      if (fabs(z - d) <= tau) ++c;
+    }
+    count[i] = c;
+  }
+  return 0;
+}

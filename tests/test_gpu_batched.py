@@ -41,25 +41,32 @@ def _uneven_scenes(dtype=np.float16):
     return out
 
 
-def _dev_scene(sc):
+def _dev_scene(sc, depth=False):
     n = sc.n_points
-    return dict(points=torch.from_numpy(np.ascontiguousarray(sc.points)).to(DEV),
-                cams=torch.from_numpy(sc.cams).to(DEV),
-                orient_maps=torch.from_numpy(sc.theta).to(DEV),
-                conf_maps=torch.from_numpy(sc.conf).to(DEV),
-                dirs=torch.full((n, 3), 9.0, device=DEV),
-                costs=torch.full((n,), 9.0, device=DEV),
-                head_centre=sc.head_centre)
+    d = dict(points=torch.from_numpy(np.ascontiguousarray(sc.points)).to(DEV),
+             cams=torch.from_numpy(sc.cams).to(DEV),
+             orient_maps=torch.from_numpy(sc.theta).to(DEV),
+             conf_maps=torch.from_numpy(sc.conf).to(DEV),
+             dirs=torch.full((n, 3), 9.0, device=DEV),
+             costs=torch.full((n,), 9.0, device=DEV),
+             head_centre=sc.head_centre)
+    if depth:
+        d["depth_maps"] = torch.from_numpy(np.ascontiguousarray(sc.depth)).to(DEV)
+    return d
 
 
 def _single(nat, d, **kw):
+    if "depth_maps" in d:
+        kw = dict(kw, depth_maps=d["depth_maps"])
     return nat.fuse_directions(d["points"], d["cams"], d["orient_maps"], d["conf_maps"], **kw)
 
 
-def test_batched_plain_is_bitwise_per_scene():
+@pytest.mark.parametrize("depth", [False, True])
+def test_batched_plain_is_bitwise_per_scene(depth):
     nat = _native()
     scenes = _uneven_scenes()
-    devs = [_dev_scene(s) for s in scenes]
+    # with depth: every other scene brings depth maps, the rest run without
+    devs = [_dev_scene(s, depth and k % 2 == 0) for k, s in enumerate(scenes)]
     total = sum(s.n_points for s in scenes)
     ctx = nat.Context(max_points=total, max_scenes=len(scenes))
     nat.fuse_batched(devs, ctx, **KW)
@@ -72,7 +79,7 @@ def test_batched_plain_is_bitwise_per_scene():
         assert torch.equal(d1, d["dirs"]) and torch.equal(c1, d["costs"])
     # one scene against the oracle, through the batched launch
     sc, d = scenes[2], devs[2]
-    orc = oracle.Oracle(sc.cams, sc.theta, sc.conf, **KW)
+    orc = oracle.Oracle(sc.cams, sc.theta, sc.conf, depth=sc.depth if depth else None, **KW)
     do, co = orc.fuse(sc.points)
     res = compare(orc, sc.points, d["dirs"].cpu().numpy(), d["costs"].cpu().numpy(), do, co)
     print("batched vs oracle", {k: v for k, v in res.items() if not k.endswith("_idx")})
@@ -128,10 +135,11 @@ def test_autotuned_shapes_do_not_change_results():
             assert torch.equal(r, d["dirs"])
 
 
-def test_batched_learned_is_bitwise_per_scene():
+@pytest.mark.parametrize("depth", [False, True])
+def test_batched_learned_is_bitwise_per_scene(depth):
     nat = _native()
     scenes = _uneven_scenes()
-    devs = [_dev_scene(s) for s in scenes]
+    devs = [_dev_scene(s, depth and k % 2 == 0) for k, s in enumerate(scenes)]
     total = sum(s.n_points for s in scenes)
     ctx = nat.Context(max_points=total, max_scenes=len(scenes))
     net = nat.MLP(seed=3)

@@ -167,7 +167,8 @@ def test_checkpoint_round_trip_and_resume():
     assert np.array_equal(a.get_params(), c.get_params())
 
 
-def test_features_match_oracle():
+@pytest.mark.parametrize("depth", [False, True])
+def test_features_match_oracle(depth):
     nat = _native()
     rec = dict(scenegen.RECIPES["tiny"])
     rec["n_points"] = 2000
@@ -176,11 +177,13 @@ def test_features_match_oracle():
     sc = scenegen.make_scene(rec, 3)
     head = np.array([0.0, 0.0, 0.02], np.float32)
     pts = torch.from_numpy(sc.points).to(DEV)
+    dm = torch.from_numpy(sc.depth).to(DEV) if depth else None
     f = nat.features(pts, torch.from_numpy(sc.cams).to(DEV), torch.from_numpy(sc.theta).to(DEV),
-                     torch.from_numpy(sc.conf).to(DEV), head_centre=head)
+                     torch.from_numpy(sc.conf).to(DEV), head_centre=head, depth_maps=dm)
     torch.cuda.synchronize()
     f = f.float().cpu().numpy().astype(np.float64)
-    fo = oracle.Oracle(sc.cams, sc.theta, sc.conf, patch=1).features(sc.points, head)
+    fo = oracle.Oracle(sc.cams, sc.theta, sc.conf, patch=1,
+                       depth=sc.depth if depth else None).features(sc.points, head)
     fo_q = oracle.round_bf16(fo.astype(np.float32)).astype(np.float64)
     # slot validity and view choice are exact; values within a bfloat16 step
     valid_g = f[:, 6::7]
@@ -246,11 +249,13 @@ def test_nan_proposals_all_fall_back():
     assert torch.equal(d2[::2], d0[::2]) and torch.equal(d2[1::4], d0[1::4])
 
 
-@pytest.mark.parametrize("tau", [math.inf, 0.25, 0.1])
-def test_given_proposal_parity_with_oracle(tau):
+@pytest.mark.parametrize("tau,depth", [(math.inf, False), (0.25, False), (0.1, False),
+                                       (0.25, True)])
+def test_given_proposal_parity_with_oracle(tau, depth):
     nat = _native()
     sc = _tiny(2500)
     pts, cams, th, cf = _dev_scene(sc)
+    extra = dict(depth_maps=torch.from_numpy(sc.depth).to(DEV)) if depth else {}
     rng = np.random.default_rng(8)
     # ground-truth tangents perturbed by ~3 degrees: a realistic proposal
     prop = sc.gt.astype(np.float64) + rng.normal(0, 0.05, sc.gt.shape)
@@ -260,15 +265,16 @@ def test_given_proposal_parity_with_oracle(tau):
     d, c = nat.fuse_directions(pts, cams, th, cf, ctx=ctx, mode=nat.FD_MODE_LEARNED,
                                proposal=nat.FD_PROPOSAL_GIVEN,
                                proposal_dirs=torch.from_numpy(prop32).to(DEV),
-                               fallback_cost=tau, learned_iters=2, learned_step0=step0, **KW)
+                               fallback_cost=tau, learned_iters=2, learned_step0=step0,
+                               **extra, **KW)
     torch.cuda.synchronize()
     n_fb = ctx.fallback_count()
     d = d.cpu().numpy()
     c = c.cpu().numpy()
-    orc = oracle.Oracle(sc.cams, sc.theta, sc.conf, **KW)
+    orc = oracle.Oracle(sc.cams, sc.theta, sc.conf, depth=sc.depth if depth else None, **KW)
     do, co, fb = orc.fuse_learned(sc.points, prop32.astype(np.float64), 2, step0, tau)
     res = compare(orc, sc.points, d, c, do, co)
-    print("learned tau", tau, {k: v for k, v in res.items() if not k.endswith("_idx")},
+    print("learned tau", tau, "depth", depth, {k: v for k, v in res.items() if not k.endswith("_idx")},
           "fallbacks gpu", n_fb, "oracle", int(fb.sum()), flush=True)
     assert_parity(res, max_fail_frac=5e-3)
     # the fallback decision is a threshold on a float cost: equal up to the

@@ -28,9 +28,11 @@ def _dev(sc):
             torch.from_numpy(np.ascontiguousarray(sc.conf)).to(dev))
 
 
-def _gpu_fuse(sc, **kw):
+def _gpu_fuse(sc, depth=False, **kw):
     nat = _native()
     pts, cams, th, cf = _dev(sc)
+    if depth:
+        kw["depth_maps"] = torch.from_numpy(np.ascontiguousarray(sc.depth)).to(th.device)
     d, c = nat.fuse_directions(pts, cams, th, cf, **kw)
     torch.cuda.synchronize()
     return d.cpu().numpy(), c.cpu().numpy()
@@ -50,29 +52,33 @@ def _scene(name, seed=0):
     return _cache[key]
 
 
-def test_tiny_workload_all_points():
-    """10k points, 200 helices, 12 views at 256^2 float32, P = 3, 48 candidates."""
+@pytest.mark.parametrize("depth", [False, True])
+def test_tiny_workload_all_points(depth):
+    """10k points, 200 helices, 12 views at 256^2 float32, P = 3, 48
+    candidates; with and without the depth visibility test."""
     sc = _scene("tiny")
     kw = dict(patch=3, n_candidates=48, refine_iters=8, top_k=5)
-    d, c = _gpu_fuse(sc, **kw)
-    orc = oracle.Oracle(sc.cams, sc.theta, sc.conf, **kw)
+    d, c = _gpu_fuse(sc, depth=depth, **kw)
+    orc = oracle.Oracle(sc.cams, sc.theta, sc.conf, depth=sc.depth if depth else None, **kw)
     do, co = orc.fuse(sc.points)
     res = compare(orc, sc.points, d, c, do, co)
-    _log("tiny", res)
+    _log(f"tiny depth={depth}", res)
     assert_parity(res)
 
 
-def test_realistic_workload_sampled_points():
-    """500k points, 64 views at 1024^2 float16, P = 5, 128 candidates + 8
-    iterations: the full launch on the GPU, every 97th point by the oracle."""
+@pytest.mark.parametrize("depth", [True, False])
+def test_realistic_workload_sampled_points(depth):
+    """500k points, 64 views at 1024^2 float16 (binary16 depth maps), P = 5,
+    128 candidates + 8 iterations: the full launch on the GPU, every 97th
+    point by the oracle."""
     sc = _scene("realistic")
     kw = dict(patch=5, n_candidates=128, refine_iters=8, top_k=5)
-    d, c = _gpu_fuse(sc, **kw)
+    d, c = _gpu_fuse(sc, depth=depth, **kw)
     idx = np.arange(0, sc.n_points, 97)
-    orc = oracle.Oracle(sc.cams, sc.theta, sc.conf, **kw)
+    orc = oracle.Oracle(sc.cams, sc.theta, sc.conf, depth=sc.depth if depth else None, **kw)
     do, co = orc.fuse(sc.points[idx])
     res = compare(orc, sc.points[idx], d[idx], c[idx], do, co)
-    _log("realistic", res)
+    _log(f"realistic depth={depth}", res)
     assert_parity(res)
     # every point of the launch: finite cost in [0, 1] with a unit direction,
     # or +inf with a zero direction
