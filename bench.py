@@ -40,6 +40,39 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+# HBM bytes per launch of the search kernels, from rocprofv3 --pmc FETCH_SIZE
+# and WRITE_SIZE passes (summaries under profiles/), each scaled by what the
+# same counter reads for a 512 MiB device copy (FETCH_SIZE x 2, WRITE_SIZE
+# x 1).  A figure holds only for the kernel sources it was taken with: `src`
+# is a hash of them, and a changed source reports null.
+_SEARCH_SOURCES = ["fd_search.hpp", "fd_fuse.hip", "fd_device.hpp", "fd_kernels.hpp"]
+_BATCHED_SOURCES = _SEARCH_SOURCES + ["fd_batched.hip"]
+TRAFFIC = {
+    "k_fuse, realistic 500k": {"read": 374.60e6, "write": 37.66e6, "files": _SEARCH_SOURCES,
+                               "src": "39e8c75206e119fe"},
+    "k_fuse, metric workload, per head": {"read": 289.8e6, "write": 19.1e6,
+                                          "files": _SEARCH_SOURCES, "src": "39e8c75206e119fe"},
+    "k_b_fuse fallback, metric workload": {"read": 11353.8e6, "write": 147.1e6,
+                                           "files": _BATCHED_SOURCES, "src": "f0619f03f951c43e"},
+}
+
+
+def _src_hash(files):
+    import hashlib
+    h = hashlib.sha256()
+    for f in files:
+        with open(os.path.join(ROOT, "paper_2604_05794_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_of(key):
+    t = TRAFFIC.get(key)
+    if t is None or _src_hash(t["files"]) != t["src"]:
+        return None
+    return t["read"] + t["write"]
+
+
 def plain_flop_per_point(patch, n_cand, iters, top_k):
     """Algorithmic flop of the plain search per point: every evaluated
     direction d (lattice + 6 per refinement iteration) in every selected view
@@ -81,25 +114,48 @@ def _axial_deg(a, b):
     return torch.rad2deg(torch.atan2(c, d))
 
 
-def _timed(step, args, ctx, stages_list):
+def _stage_times(ctx, stages_list):
+    stages = {}
+    for nm, st in stages_list:
+        ms, cnt = ctx.stage_time(st)
+        if cnt:
+            stages[nm] = ms / cnt
+    return stages
+
+
+def _timed(step, args, ctx, stages_list, profile=True):
+    """Wall time of args.steps steps after args.warmup; with profile, the
+    per-stage kernel times (HIP events on the launch stream) of the timed
+    steps."""
     import torch
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
-    ctx.profile(True)
+    ctx.profile(profile)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
         step()
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
-    stages = {}
-    for nm, st in stages_list:
-        ms, cnt = ctx.stage_time(st)
-        if cnt:
-            stages[nm] = ms / cnt
+    stages = _stage_times(ctx, stages_list) if profile else {}
     ctx.profile(False)
     return el, stages
+
+
+def _stage_pass(step, ctx, stages_list, reps=3):
+    """Per-stage kernel times of `reps` extra steps run with stage timing on
+    (the batched form then launches its kernels directly rather than from
+    its graph, so that HIP events can sit between its stages)."""
+    import torch
+    torch.cuda.synchronize()
+    ctx.profile(True)
+    for _ in range(reps):
+        step()
+    torch.cuda.synchronize()
+    stages = _stage_times(ctx, stages_list)
+    ctx.profile(False)
+    return stages
 
 
 def run_learned(args):
@@ -183,7 +239,8 @@ def run_learned(args):
         "stages_ms_per_launch": {"plain": st_p, "learned": st_l},
         "roofline": {"bound": "alu", "kernel": "k_fuse", "achieved": achieved,
                      "peak": PEAK_FP32_FMA, "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_FMA,
-                     "traffic": None, "avg_launch_ms": st_p["fuse"], "flop_per_point": flop},
+                     "traffic": traffic_of("k_fuse, realistic 500k"),
+                     "avg_launch_ms": st_p["fuse"], "flop_per_point": flop},
     }
     return out
 
@@ -255,11 +312,19 @@ def run_metric(args):
                 torch.cat([d["costs"] for _, d in heads]).clone())
 
     res = {}
+    n_fb_batched = None
     for name, fn in (("plain", per_head({})), ("plain_batched", batched({})),
                      ("learned", per_head(lkw)), ("learned_batched", batched(lkw))):
-        el, st = _timed(fn, args, ctx, stg)
-        res[name] = (n / (el / args.steps), el * 1e3 / args.steps, st)
+        is_batched = name.endswith("batched")
+        # the batched forms are timed replaying their graph; their stage
+        # times come from a separate pass that launches the same kernels
+        el, st = _timed(fn, args, ctx, stg, profile=not is_batched)
         outs[name] = snap()
+        if is_batched:
+            st = _stage_pass(fn, ctx, stg)
+            if name == "learned_batched":
+                n_fb_batched = ctx.fallback_count(stream)
+        res[name] = (n / (el / args.steps), el * 1e3 / args.steps, st)
         log(f"{name}: {res[name][0] / 1e6:.1f} M points/s, {res[name][1]:.3f} ms/step, "
             f"{json.dumps({k: round(v, 4) for k, v in st.items()})}")
     dp, cp = outs["plain"]
@@ -278,12 +343,16 @@ def run_metric(args):
                                head_centre=sc.head_centre, depth_maps=d.get("depth_maps"),
                                **kw, **lkw)
         fb += ctx.fallback_count(stream)
-    log(f"mean err vs plain (deg) {json.dumps({k: round(v, 3) for k, v in errs.items()})}; "
+    log(f"learned+batched fallback {n_fb_batched} of {n} points; "
+        f"mean err vs plain (deg) {json.dumps({k: round(v, 3) for k, v in errs.items()})}; "
         f"fallback {fb / n:.3f}; batched == per-head: plain {same_pb}, learned {same_lb}")
-    v_lb, ms_lb, _ = res["learned_batched"]
+    v_lb, ms_lb, st_lb = res["learned_batched"]
     v_p, _, st_p = res["plain"]
     flop = plain_flop_per_point(kw["patch"], kw["n_candidates"], kw["refine_iters"], 5)
-    achieved = flop * n / (st_p["fuse"] * len(heads) * 1e-3) / 1e12
+    # dominant kernel of the learned+batched step: the persistent search over
+    # the fallback list (the same per-point search as the plain form)
+    achieved = flop * n_fb_batched / (st_lb["fallback"] * 1e-3) / 1e12
+    achieved_plain = flop * n / (st_p["fuse"] * len(heads) * 1e-3) / 1e12
     out = {
         "metric": METRIC, "value": v_lb, "unit": "points/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_lb,
@@ -304,12 +373,21 @@ def run_metric(args):
         "median_err_vs_gt_deg_plain": float(_axial_deg(dp[fin], gt[fin]).median()),
         "fallback_frac": fb / n, "batched_bitwise_equal": {"plain": same_pb, "learned": same_lb},
         "stages_ms_per_launch_plain": st_p,
-        "roofline": {"bound": "alu", "kernel": "k_fuse (plain search, per-head launches)",
+        "roofline": {"bound": "alu",
+                     "kernel": "k_b_fuse: persistent plain search over the fallback list of the "
+                               "learned+batched step",
                      "achieved": achieved, "peak": PEAK_FP32_FMA, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_FP32_FMA, "traffic": None,
-                     "avg_launch_ms": st_p["fuse"], "points_per_launch": n // len(heads),
+                     "frac": achieved / PEAK_FP32_FMA,
+                     "traffic": traffic_of("k_b_fuse fallback, metric workload"),
+                     "avg_launch_ms": st_lb["fallback"], "points_per_launch": n_fb_batched,
                      "flop_per_point": flop, "peak_vendor_packed": PEAK_FP32_VENDOR,
                      "frac_vs_vendor_packed": achieved / PEAK_FP32_VENDOR},
+        "roofline_plain_per_head": {
+            "bound": "alu", "kernel": "k_fuse (plain search, one launch per head)",
+            "achieved": achieved_plain, "peak": PEAK_FP32_FMA, "unit": "TFLOP/s",
+            "frac": achieved_plain / PEAK_FP32_FMA, "avg_launch_ms": st_p["fuse"],
+            "points_per_launch": n // len(heads),
+            "traffic": traffic_of("k_fuse, metric workload, per head")},
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(heads[0][0], kw, args.cpu_seconds,
@@ -386,7 +464,8 @@ def run_plain(args):
                    "map": f"{sc.width}x{sc.height} f16", **kw},
         "roofline": {"bound": "alu", "kernel": "k_fuse", "achieved": achieved,
                      "peak": PEAK_FP32_FMA, "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_FMA,
-                     "traffic": None, "avg_launch_ms": stages["fuse"],
+                     "traffic": traffic_of("k_fuse, realistic 500k"),
+                     "avg_launch_ms": stages["fuse"],
                      "flop_per_point": flop, "peak_vendor_packed": PEAK_FP32_VENDOR,
                      "frac_vs_vendor_packed": achieved / PEAK_FP32_VENDOR},
         "stages_ms_per_launch": stages,
@@ -398,6 +477,23 @@ def run_plain(args):
     return out
 
 
+def run_copy(args):
+    """Counter calibration: a plain device-to-device copy of 512 MiB, so the
+    FETCH_SIZE / WRITE_SIZE counters can be read against known bytes."""
+    import torch
+    n = 512 << 20
+    src = torch.empty(n, dtype=torch.uint8, device="cuda:0").fill_(1)
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    return {"workload": "copy calibration", "bytes_read_per_copy": n, "bytes_written_per_copy": n,
+            "copies": args.steps, "GB_per_s": 2 * n * args.steps / el / 1e9}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__,
                                  formatter_class=argparse.RawDescriptionHelpFormatter)
@@ -405,7 +501,8 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--seed", type=int, default=0)
-    ap.add_argument("--workload", default="metric", choices=["metric", "plain", "learned"])
+    ap.add_argument("--workload", default="metric",
+                    choices=["metric", "plain", "learned", "copy"])
     ap.add_argument("--heads", type=int, default=8)
     ap.add_argument("--mlp", default=os.path.join(ROOT, "paper_2604_05794_amd", "weights",
                                                   "proposal_mlp.fdmlp"))
@@ -420,7 +517,8 @@ def main():
               f"{world}); the fusion shards by scene or by point range with no exchange, and "
               "this build runs the one-GPU share.", file=sys.stderr)
         sys.exit(2)
-    run = {"metric": run_metric, "plain": run_plain, "learned": run_learned}[args.workload]
+    run = {"metric": run_metric, "plain": run_plain, "learned": run_learned,
+           "copy": run_copy}[args.workload]
     out = run(args)
     print(json.dumps(out), flush=True)
 

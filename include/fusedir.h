@@ -240,7 +240,10 @@ int fd_autotune(fd_context* ctx, const fd_scene* sample, int32_t n_scenes,
  * While enabled on a context, every call through it records a pair of HIP
  * events on its stream around each stage's kernels.  fd_profile_read waits
  * for the recorded events and returns the summed GPU time (ms) and the
- * number of timed launches of one stage; fd_profile_enable also clears. */
+ * number of timed launches of one stage; fd_profile_enable also clears.
+ * A batched call made while timing is on launches its kernels directly
+ * instead of replaying its graph (a graph holds no event records), so each
+ * of its stages is timed; its results are the same. */
 enum {
   FD_STAGE_TILING = 0,    /* spatial key, counting sort */
   FD_STAGE_TOPK = 1,      /* Eq. (4) view selection */

@@ -51,6 +51,7 @@ struct fd_context {
   hipGraph_t graph = nullptr;
   hipGraphExec_t graph_exec = nullptr;
   uint64_t graph_sig = 0;
+  uint64_t table_sig = 0;   // scene set whose table is on the device
   hipStream_t cap_stream = nullptr;
   // tuned shape of the persistent search: tiles per queue pop, resident grid
   int tuned_chunk = 0;

@@ -158,23 +158,23 @@ __global__ __launch_bounds__(kBlock) void k_b_scatter(BatchDev b, const uint32_t
   perm[pos] = (uint32_t)j;
 }
 
-template <typename T>
+template <typename T, int KS>
 __global__ __launch_bounds__(kBlock) void k_b_topk(BatchDev b, SearchDev q) {
   int s;
   const int64_t j = block_point(b, &s);
   if (j < 0) return;
   const SceneDev sc = b.tab[s];
-  topk_point<T>(sc, q, j);
+  topk_point<T, KS>(sc, q, j);
 }
 
-template <typename T>
+template <typename T, int KS>
 __global__ __launch_bounds__(kBlock) void k_b_topk_features(BatchDev b, SearchDev q,
                                                             uint16_t* __restrict__ feats) {
   int s;
   const int64_t j = block_point(b, &s);
   if (j < 0) return;
   const SceneDev sc = b.tab[s];
-  topk_features_point<T>(sc, q, j, b.pt_off[s], feats);
+  topk_features_point<T, KS>(sc, q, j, b.pt_off[s], feats);
 }
 
 // Persistent search over items 0..n_items-1 (item = global point position, or
@@ -336,6 +336,7 @@ static int record_batch(fd_context* c, const fd_params* p, int n_scenes, int64_t
   int* bbox = (int*)c->tile_tab;
   hipError_t e;
   // tiling
+  StageTimer t_tile(c, FD_STAGE_TILING, st);
   hipLaunchKernelGGL(k_b_init, dim3(256), dim3(256), 0, st, counts, (int64_t)n_scenes * kBCells,
                      bbox, n_scenes);
   hipLaunchKernelGGL(k_b_bbox, dim3((unsigned)nblocks), dim3(kBlock), 0, st, b, bbox);
@@ -345,6 +346,7 @@ static int record_batch(fd_context* c, const fd_params* p, int n_scenes, int64_t
     return hip_error(e, "batched scan");
   hipLaunchKernelGGL(k_b_scatter, dim3((unsigned)nblocks), dim3(kBlock), 0, st, b, c->key, cursor,
                      c->perm);
+  t_tile.stop();
   SearchDev q;
   q.lattice = c->lattice;
   q.n_candidates = p->n_candidates;
@@ -353,20 +355,33 @@ static int record_batch(fd_context* c, const fd_params* p, int n_scenes, int64_t
   q.K = p->top_k;
   q.z_near = p->z_near;
   if (p->mode == FD_MODE_PLAIN) {  // the learned form selects views with its features
-    if (p->map_dtype == FD_F16)
-      hipLaunchKernelGGL(k_b_topk<__half>, dim3((unsigned)nblocks), dim3(kBlock), 0, st, b, q);
-    else
-      hipLaunchKernelGGL(k_b_topk<float>, dim3((unsigned)nblocks), dim3(kBlock), 0, st, b, q);
+    StageTimer t_topk(c, FD_STAGE_TOPK, st);
+    const dim3 grid((unsigned)nblocks), block(kBlock);
+    const bool k5 = q.K <= 5;  // a list of 5 slots holds any top-K with K <= 5
+    if (p->map_dtype == FD_F16) {
+      if (k5)
+        hipLaunchKernelGGL((k_b_topk<__half, 5>), grid, block, 0, st, b, q);
+      else
+        hipLaunchKernelGGL((k_b_topk<__half, FD_TOPK_SLOTS>), grid, block, 0, st, b, q);
+    } else {
+      if (k5)
+        hipLaunchKernelGGL((k_b_topk<float, 5>), grid, block, 0, st, b, q);
+      else
+        hipLaunchKernelGGL((k_b_topk<float, FD_TOPK_SLOTS>), grid, block, 0, st, b, q);
+    }
     if ((e = hipGetLastError()) != hipSuccess) return hip_error(e, "batched view selection");
+    t_topk.stop();
   }
   const int chunk = c->tuned_chunk > 0 ? c->tuned_chunk : 2;
   const int grid = persistent_grid(p->map_dtype, p->patch, c->tuned_grid);
   uint32_t* queue = c->tile_queue;
   if (p->mode == FD_MODE_PLAIN) {
     if ((e = launch_fill_u32(queue, 1, 0u, st)) != hipSuccess) return hip_error(e, "queue reset");
+    StageTimer t_fuse(c, FD_STAGE_FUSE, st);
     if ((e = search(p->map_dtype, p->patch, b, q, nullptr, nullptr, nullptr, queue, chunk, grid,
                     st)) != hipSuccess)
       return hip_error(e, "batched search");
+    t_fuse.stop();
     return FD_OK;
   }
   // learned
@@ -382,24 +397,45 @@ static int record_batch(fd_context* c, const fd_params* p, int n_scenes, int64_t
     step0 = s0 > 0.0f ? s0 : default_step0(p->n_candidates);
   }
   l.step0 = step0;
-  if (p->map_dtype == FD_F16)
-    hipLaunchKernelGGL(k_b_topk_features<__half>, dim3((unsigned)nblocks), dim3(kBlock), 0, st,
-                       b, q, c->feats);
-  else
-    hipLaunchKernelGGL(k_b_topk_features<float>, dim3((unsigned)nblocks), dim3(kBlock), 0, st,
-                       b, q, c->feats);
+  {
+    StageTimer t_feat(c, FD_STAGE_FEATURES, st);
+    const dim3 grid((unsigned)nblocks), block(kBlock);
+    const bool k5 = q.K <= 5;
+    if (p->map_dtype == FD_F16) {
+      if (k5)
+        hipLaunchKernelGGL((k_b_topk_features<__half, 5>), grid, block, 0, st, b, q, c->feats);
+      else
+        hipLaunchKernelGGL((k_b_topk_features<__half, FD_TOPK_SLOTS>), grid, block, 0, st, b, q,
+                           c->feats);
+    } else {
+      if (k5)
+        hipLaunchKernelGGL((k_b_topk_features<float, 5>), grid, block, 0, st, b, q, c->feats);
+      else
+        hipLaunchKernelGGL((k_b_topk_features<float, FD_TOPK_SLOTS>), grid, block, 0, st, b, q,
+                           c->feats);
+    }
+    if ((e = hipGetLastError()) != hipSuccess)
+      return hip_error(e, "batched view selection + features");
+    t_feat.stop();
+  }
+  StageTimer t_mlp(c, FD_STAGE_MLP, st);
   int r = mlp_forward_dev(p->mlp, c->feats, total, c->prop, st);
   if (r) return r;
+  t_mlp.stop();
   l.proposals = c->prop;
   if ((e = launch_fill_u32(c->fb_count, 1, 0u, st)) != hipSuccess)
     return hip_error(e, "fallback counter reset");
+  StageTimer t_ref(c, FD_STAGE_REFINE, st);
   if ((e = search(p->map_dtype, p->patch, b, q, &l, nullptr, nullptr, queue, chunk, grid, st)) !=
       hipSuccess)
     return hip_error(e, "batched learned refinement");
+  t_ref.stop();
   if ((e = launch_fill_u32(queue, 1, 0u, st)) != hipSuccess) return hip_error(e, "queue reset");
+  StageTimer t_fb(c, FD_STAGE_FALLBACK, st);
   if ((e = search(p->map_dtype, p->patch, b, q, nullptr, c->fb_list, c->fb_count, queue, chunk,
                   grid, st)) != hipSuccess)
     return hip_error(e, "batched fallback search");
+  t_fb.stop();
   return FD_OK;
 }
 
@@ -456,12 +492,7 @@ extern "C" int fd_fuse_directions_batched(const fd_scene* scenes, int32_t n_scen
   sig = fnv(sig, &pc, sizeof pc);
   sig = fnv(sig, &ctx->tuned_chunk, sizeof ctx->tuned_chunk);
   sig = fnv(sig, &ctx->tuned_grid, sizeof ctx->tuned_grid);
-  StageTimer tb(ctx, FD_STAGE_BATCHED, st);
-  if (!ctx->graph_exec || ctx->graph_sig != sig) {
-    if (ctx->graph_exec) (void)hipGraphExecDestroy(ctx->graph_exec);
-    if (ctx->graph) (void)hipGraphDestroy(ctx->graph);
-    ctx->graph_exec = nullptr;
-    ctx->graph = nullptr;
+  if (ctx->table_sig != sig) {
     // scene table (host -> device once per scene set, outside the graph)
     std::vector<SceneDev> tab(n_scenes);
     for (int s = 0; s < n_scenes; ++s) {
@@ -495,17 +526,31 @@ extern "C" int fd_fuse_directions_batched(const fd_scene* scenes, int32_t n_scen
     if (e != hipSuccess) return hip_error(e, "batched scene table upload");
     if ((r = ensure_lattice(ctx, params->n_candidates, st))) return r;
     if ((e = hipStreamSynchronize(st)) != hipSuccess) return hip_error(e, "lattice");
+    ctx->table_sig = sig;
+  }
+  StageTimer tb(ctx, FD_STAGE_BATCHED, st);
+  if (ctx->profiling) {
+    // stage timing: the same kernels launched directly, with events between
+    // the stages (a graph would hold no event records)
+    r = record_batch(ctx, params, n_scenes, total, blk_off.data(), st);
+    if (r) return r;
+    tb.stop();
+    return FD_OK;
+  }
+  if (!ctx->graph_exec || ctx->graph_sig != sig) {
+    if (ctx->graph_exec) (void)hipGraphExecDestroy(ctx->graph_exec);
+    if (ctx->graph) (void)hipGraphDestroy(ctx->graph);
+    ctx->graph_exec = nullptr;
+    ctx->graph = nullptr;
     (void)persistent_grid(params->map_dtype, params->patch, 0);  // host query, before capture
+    hipError_t e;
     if (!ctx->cap_stream) {
       e = hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking);
       if (e != hipSuccess) return hip_error(e, "capture stream");
     }
     e = hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess) return hip_error(e, "hipStreamBeginCapture");
-    const bool prof = ctx->profiling;
-    ctx->profiling = false;  // no event records inside the graph
     r = record_batch(ctx, params, n_scenes, total, blk_off.data(), ctx->cap_stream);
-    ctx->profiling = prof;
     hipGraph_t g = nullptr;
     e = hipStreamEndCapture(ctx->cap_stream, &g);
     if (r) {

@@ -92,6 +92,58 @@ __device__ __forceinline__ float centre_conf32(const T* __restrict__ cm, int W,
   return __builtin_fmaf(w11, c11, __builtin_fmaf(w01, c01, __builtin_fmaf(w10, c10, w00 * c00)));
 }
 
+// Texel at a 32-bit offset from a view's base pointer (the base is the same
+// for the whole wave, so the load takes a scalar base and a vector offset).
+template <typename T>
+__device__ __forceinline__ float ld_texel(const T* __restrict__ base, uint32_t off) {
+  // a 32-bit byte offset (a plane holds at most 2^30 texels, so it cannot
+  // wrap) lets the load use the scalar-base addressing form
+  const char* b = (const char*)base + (uint32_t)(off * (uint32_t)sizeof(T));
+  if constexpr (sizeof(T) == 2)
+    return __half2float(*(const __half*)b);
+  else
+    return *(const float*)b;
+}
+
+// Centre confidence of a projection for Eq. (4), or 0 when the view is not
+// eligible (ok false) or, with depth maps, the point is hidden in it.  Same
+// value and operation order as centre_conf32 and visible32; since an eligible
+// projection lies inside the image, only the +1 neighbours need the zero
+// border check.  cb / db: this view's confidence and depth planes (db NULL:
+// no visibility test).  *seen (optional): eligible and visible.
+template <typename T>
+__device__ __forceinline__ float eligible_conf32(const T* __restrict__ cb,
+                                                 const T* __restrict__ db, int W, int H,
+                                                 bool ok, const Proj& pr, float tau,
+                                                 bool* seen = nullptr) {
+  const float u = ok ? pr.u : 0.0f, v = ok ? pr.v : 0.0f;
+  const float x0 = floorf(u), y0 = floorf(v);
+  const float fx = u - x0, fy = v - y0;
+  const float gx = 1.0f - fx, gy = 1.0f - fy;
+  const uint32_t ix = (uint32_t)x0, iy = (uint32_t)y0;
+  const uint32_t o00 = iy * (uint32_t)W + ix;
+  const bool xin = ix + 1u < (uint32_t)W, yin = iy + 1u < (uint32_t)H;
+  const uint32_t dx = xin ? 1u : 0u, dy = yin ? (uint32_t)W : 0u;
+  float c00 = ld_texel<T>(cb, o00);
+  float c10 = ld_texel<T>(cb, o00 + dx);
+  float c01 = ld_texel<T>(cb, o00 + dy);
+  float c11 = ld_texel<T>(cb, o00 + dx + dy);
+  bool vis = true;
+  if (db != nullptr) {
+    const uint32_t xn = (uint32_t)floorf(u + 0.5f), yn = (uint32_t)floorf(v + 0.5f);
+    const float D = ld_texel<T>(db, yn * (uint32_t)W + xn);
+    vis = fabsf(pr.Z - D) <= tau;
+  }
+  c10 = xin ? c10 : 0.0f;
+  c01 = yin ? c01 : 0.0f;
+  c11 = (xin && yin) ? c11 : 0.0f;
+  const float w00 = gx * gy, w10 = fx * gy, w01 = gx * fy, w11 = fx * fy;
+  const float c =
+      __builtin_fmaf(w11, c11, __builtin_fmaf(w01, c01, __builtin_fmaf(w10, c10, w00 * c00)));
+  if (seen) *seen = ok && vis;  // eligible and visible, whatever the confidence
+  return (ok && vis) ? c : 0.0f;
+}
+
 // Visibility of Sec. 3.1.1 (the score V_i^v), decided in binary32: the
 // camera-space depth of the point agrees with the rendered depth at the
 // nearest texel of its projection,
@@ -104,6 +156,19 @@ __device__ __forceinline__ bool visible32(const void* depth, size_t plane, int v
   const int ix = (int)floorf(pr.u + 0.5f), iy = (int)floorf(pr.v + 0.5f);
   const float D = tex_load_nb<T>((const T*)depth + plane * view, W, H, ix, iy);
   return fabsf(pr.Z - D) <= tau;
+}
+
+// Logical block index such that the blocks of one XCD cover a contiguous
+// range of tiles:
+// the dispatcher deals workgroups to the 8 XCDs round-robin, so remap
+// blockIdx so that neighbouring (spatially sorted) tiles share an L2.
+__device__ __forceinline__ int64_t xcd_tile(int64_t nblocks) {
+  const int64_t b = blockIdx.x;
+  const int64_t per = nblocks / 8, rem = nblocks % 8;
+  const int64_t xcd = b % 8, k = b / 8;
+  // XCD x owns logical blocks [start(x), start(x) + per + (x < rem))
+  const int64_t start = xcd * per + (xcd < rem ? xcd : rem);
+  return start + k;
 }
 
 // Lanes of a wave are split into groups of `k` consecutive lanes; returns the

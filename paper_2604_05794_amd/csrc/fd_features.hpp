@@ -194,17 +194,17 @@ __device__ __forceinline__ void features_point(const SceneDev& s, float z_near, 
 // Eq. (4) view selection and the proposal features in one pass over the
 // views (one projection per view): writes views / kcount like topk_point
 // and feature row row_base + j.
-template <typename T>
+template <typename T, int KS>
 __device__ __forceinline__ void topk_features_point(const SceneDev& s, const SearchDev& q,
                                                     int64_t j, int64_t row_base,
                                                     uint16_t* __restrict__ feats) {
   const uint32_t i = s.perm[j];
   const float px = s.pts[3 * (size_t)i], py = s.pts[3 * (size_t)i + 1],
               pz = s.pts[3 * (size_t)i + 2];
-  float ck[FD_TOPK_SLOTS];
-  int vk[FD_TOPK_SLOTS];
+  float ck[KS];
+  int vk[KS];
 #pragma unroll
-  for (int k = 0; k < FD_TOPK_SLOTS; ++k) {
+  for (int k = 0; k < KS; ++k) {
     ck[k] = -1.0f;
     vk[k] = 0;
   }
@@ -216,33 +216,22 @@ __device__ __forceinline__ void topk_features_point(const SceneDev& s, const Sea
     id[k] = -1;
   }
   const T* conf = (const T*)s.conf;
+  const T* depth = (const T*)s.depth;
   const size_t plane = (size_t)s.W * s.H;
   for (int v = 0; v < s.V; ++v) {
     Proj pr;
-    if (!project32(s.cams + 16 * v, px, py, pz, s.W, s.H, q.z_near, pr)) continue;
-    if (!visible32<T>(s.depth, plane, v, s.W, s.H, pr, s.vis_tau)) continue;
-    const float c = centre_conf32<T>(conf + plane * v, s.W, s.H, pr.u, pr.v);
-    if (c > 0.0f) {
-      float cs = c;
-      int cv = v;
-      bool ins = false;
-#pragma unroll
-      for (int k = 0; k < FD_TOPK_SLOTS; ++k) {
-        const bool take = ins || (cs > ck[k]);
-        const float ts = ck[k];
-        const int tv = vk[k];
-        ck[k] = take ? cs : ts;
-        vk[k] = take ? cv : tv;
-        cs = take ? ts : cs;
-        cv = take ? tv : cv;
-        ins = take;
-      }
-    }
-    frontal_insert(sc, id, frontal_score32(s.cams + 16 * v, px, py, pz, s.hc, nullptr), v);
+    const bool ok = project32(s.cams + 16 * v, px, py, pz, s.W, s.H, q.z_near, pr);
+    bool seen;
+    const float c = eligible_conf32<T>(conf + plane * v, depth ? depth + plane * v : nullptr,
+                                       s.W, s.H, ok, pr, s.vis_tau, &seen);
+    if (c > 0.0f) topk_insert<KS>(ck, vk, c, v);
+    // frontal slots: eligible and visible views, whatever their confidence
+    if (seen)
+      frontal_insert(sc, id, frontal_score32(s.cams + 16 * v, px, py, pz, s.hc, nullptr), v);
   }
   int keff = 0;
 #pragma unroll
-  for (int k = 0; k < FD_TOPK_SLOTS; ++k) {
+  for (int k = 0; k < KS; ++k) {
     if (k < q.K && ck[k] > 0.0f) keff = k + 1;
     s.views[FD_TOPK_SLOTS * j + k] = (uint16_t)vk[k];
   }

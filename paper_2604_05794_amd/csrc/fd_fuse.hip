@@ -49,20 +49,28 @@ hipError_t launch_lattice(float* lattice, int n, hipStream_t st) {
   return hipGetLastError();
 }
 
-template <typename T>
+template <typename T, int KS>
 __global__ __launch_bounds__(256) void k_topk(SceneDev s, SearchDev q) {
-  int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t j = xcd_tile(gridDim.x) * blockDim.x + threadIdx.x;
   if (j >= s.n) return;
-  topk_point<T>(s, q, j);
+  topk_point<T, KS>(s, q, j);
 }
 
 hipError_t launch_topk(const SceneDev& s, const SearchDev& q, int dtype, hipStream_t st) {
   if (s.n <= 0) return hipSuccess;
   dim3 grid((unsigned)((s.n + 255) / 256));
-  if (dtype == 1)
-    hipLaunchKernelGGL(k_topk<__half>, grid, dim3(256), 0, st, s, q);
-  else
-    hipLaunchKernelGGL(k_topk<float>, grid, dim3(256), 0, st, s, q);
+  const bool k5 = q.K <= 5;  // a list of 5 slots holds any top-K with K <= 5
+  if (dtype == 1) {
+    if (k5)
+      hipLaunchKernelGGL((k_topk<__half, 5>), grid, dim3(256), 0, st, s, q);
+    else
+      hipLaunchKernelGGL((k_topk<__half, FD_TOPK_SLOTS>), grid, dim3(256), 0, st, s, q);
+  } else {
+    if (k5)
+      hipLaunchKernelGGL((k_topk<float, 5>), grid, dim3(256), 0, st, s, q);
+    else
+      hipLaunchKernelGGL((k_topk<float, FD_TOPK_SLOTS>), grid, dim3(256), 0, st, s, q);
+  }
   return hipGetLastError();
 }
 

@@ -23,17 +23,17 @@ namespace {
 template <typename T>
 __global__ __launch_bounds__(256) void k_features(SceneDev s, float z_near, int by_j,
                                                   uint16_t* __restrict__ feats) {
-  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t j = xcd_tile(gridDim.x) * blockDim.x + threadIdx.x;
   if (j >= s.n) return;
   features_point<T>(s, z_near, j, by_j, 0, feats);
 }
 
-template <typename T>
+template <typename T, int KS>
 __global__ __launch_bounds__(256) void k_topk_features(SceneDev s, SearchDev q,
                                                        uint16_t* __restrict__ feats) {
-  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t j = xcd_tile(gridDim.x) * blockDim.x + threadIdx.x;
   if (j >= s.n) return;
-  topk_features_point<T>(s, q, j, 0, feats);
+  topk_features_point<T, KS>(s, q, j, 0, feats);
 }
 
 }  // namespace
@@ -73,10 +73,20 @@ int fd::run_learned(fd_context* c, const SceneDev& s, const SearchDev& q, const 
     // its own top-K pass in this mode)
     StageTimer tf(c, FD_STAGE_FEATURES, st);
     dim3 grid((unsigned)((s.n + 255) / 256));
-    if (p->map_dtype == FD_F16)
-      hipLaunchKernelGGL(k_topk_features<__half>, grid, dim3(256), 0, st, s, q, c->feats);
-    else
-      hipLaunchKernelGGL(k_topk_features<float>, grid, dim3(256), 0, st, s, q, c->feats);
+    const bool k5 = q.K <= 5;  // a list of 5 slots holds any top-K with K <= 5
+    if (p->map_dtype == FD_F16) {
+      if (k5)
+        hipLaunchKernelGGL((k_topk_features<__half, 5>), grid, dim3(256), 0, st, s, q, c->feats);
+      else
+        hipLaunchKernelGGL((k_topk_features<__half, FD_TOPK_SLOTS>), grid, dim3(256), 0, st, s,
+                           q, c->feats);
+    } else {
+      if (k5)
+        hipLaunchKernelGGL((k_topk_features<float, 5>), grid, dim3(256), 0, st, s, q, c->feats);
+      else
+        hipLaunchKernelGGL((k_topk_features<float, FD_TOPK_SLOTS>), grid, dim3(256), 0, st, s,
+                           q, c->feats);
+    }
     if ((e = hipGetLastError()) != hipSuccess) return hip_error(e, "view selection + features");
     tf.stop();
     StageTimer tm(c, FD_STAGE_MLP, st);

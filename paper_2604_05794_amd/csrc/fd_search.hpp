@@ -19,23 +19,43 @@ constexpr float kInvPi = 0.318309886183790671538f;
 
 // ---- Eq. (4): top-K views by centre confidence ------------------------------
 // One lane per point (processing-order index j).  Stable insertion into a
-// register list of 8: a view enters ahead of a listed one only if strictly
-// more confident, so equal confidences keep the lower view index first.
-template <typename T>
+// register list of KS >= K slots: a view enters ahead of a listed one only if
+// strictly more confident, so equal confidences keep the lower view index
+// first.  Slots 0..KS-1 of the point's view row are written.
+template <int KS>
+__device__ __forceinline__ void topk_insert(float (&sc)[KS], int (&id)[KS], float c, int v) {
+  float cs = c;
+  int cv = v;
+  bool ins = false;
+#pragma unroll
+  for (int k = 0; k < KS; ++k) {
+    const bool take = ins || (cs > sc[k]);
+    const float ts = sc[k];
+    const int tv = id[k];
+    sc[k] = take ? cs : ts;
+    id[k] = take ? cv : tv;
+    cs = take ? ts : cs;
+    cv = take ? tv : cv;
+    ins = take;
+  }
+}
+
+template <typename T, int KS>
 __device__ __forceinline__ void topk_point(const SceneDev& s, const SearchDev& q, int64_t j) {
   const uint32_t i = s.perm[j];
   const float px = s.pts[3 * (size_t)i], py = s.pts[3 * (size_t)i + 1],
               pz = s.pts[3 * (size_t)i + 2];
-  float sc[FD_TOPK_SLOTS];
-  int id[FD_TOPK_SLOTS];
+  float sc[KS];
+  int id[KS];
 #pragma unroll
-  for (int k = 0; k < FD_TOPK_SLOTS; ++k) {
+  for (int k = 0; k < KS; ++k) {
     sc[k] = -1.0f;
     id[k] = 0;
   }
   const T* conf = (const T*)s.conf;
+  const T* depth = (const T*)s.depth;
   const size_t plane = (size_t)s.W * s.H;
-  // views in groups of four: projections and the 16 texel loads of a group
+  // views in groups of four: projections and the texel loads of a group
   // are independent, so they are issued before the (ordered) insertions
   constexpr int kGroup = 4;
   for (int v0 = 0; v0 < s.V; v0 += kGroup) {
@@ -44,34 +64,18 @@ __device__ __forceinline__ void topk_point(const SceneDev& s, const SearchDev& q
     for (int u = 0; u < kGroup; ++u) {
       const int v = min(v0 + u, s.V - 1);
       Proj pr;
-      bool ok = project32(s.cams + 16 * v, px, py, pz, s.W, s.H, q.z_near, pr);
-      if (!ok) pr.u = pr.v = pr.Z = 0.0f;
-      const float c = centre_conf32<T>(conf + plane * v, s.W, s.H, pr.u, pr.v);
-      ok = ok && visible32<T>(s.depth, plane, v, s.W, s.H, pr, s.vis_tau);
-      cg[u] = (ok && v0 + u < s.V) ? c : 0.0f;
+      const bool ok = project32(s.cams + 16 * v, px, py, pz, s.W, s.H, q.z_near, pr);
+      const float c = eligible_conf32<T>(conf + plane * v, depth ? depth + plane * v : nullptr,
+                                         s.W, s.H, ok, pr, s.vis_tau);
+      cg[u] = (v0 + u < s.V) ? c : 0.0f;
     }
 #pragma unroll
-    for (int u = 0; u < kGroup; ++u) {
-      if (!(cg[u] > 0.0f)) continue;
-      float cs = cg[u];
-      int cv = v0 + u;
-      bool ins = false;
-#pragma unroll
-      for (int k = 0; k < FD_TOPK_SLOTS; ++k) {
-        bool take = ins || (cs > sc[k]);
-        float ts = sc[k];
-        int tv = id[k];
-        sc[k] = take ? cs : ts;
-        id[k] = take ? cv : tv;
-        cs = take ? ts : cs;
-        cv = take ? tv : cv;
-        ins = take;
-      }
-    }
+    for (int u = 0; u < kGroup; ++u)
+      if (cg[u] > 0.0f) topk_insert<KS>(sc, id, cg[u], v0 + u);
   }
   int keff = 0;
 #pragma unroll
-  for (int k = 0; k < FD_TOPK_SLOTS; ++k) {
+  for (int k = 0; k < KS; ++k) {
     if (k < q.K && sc[k] > 0.0f) keff = k + 1;
     s.views[FD_TOPK_SLOTS * j + k] = (uint16_t)id[k];
   }
@@ -283,18 +287,6 @@ __device__ __forceinline__ void write_result(const SceneDev& s, uint32_t i, floa
   s.dirs[3 * (size_t)i + 1] = sgn * dy;
   s.dirs[3 * (size_t)i + 2] = sgn * dz;
   s.costs[i] = J;
-}
-
-// Wave index with blocks of one XCD covering a contiguous range of tiles:
-// the dispatcher deals workgroups to the 8 XCDs round-robin, so remap
-// blockIdx so that neighbouring (spatially sorted) tiles share an L2.
-__device__ __forceinline__ int64_t xcd_tile(int64_t nblocks) {
-  const int64_t b = blockIdx.x;
-  const int64_t per = nblocks / 8, rem = nblocks % 8;
-  const int64_t xcd = b % 8, k = b / 8;
-  // XCD x owns logical blocks [start(x), start(x) + per + (x < rem))
-  const int64_t start = xcd * per + (xcd < rem ? xcd : rem);
-  return start + k;
 }
 
 // ---- plain search of one point per lane group ---------------------------------

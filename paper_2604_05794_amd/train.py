@@ -8,9 +8,10 @@ network is trained by the library's own forward/backward kernels and Adam
   fallback_cost = the largest cost threshold for which the learned result
                   (proposal + short refinement, plain where the cost exceeds
                   the threshold) keeps a mean angle to the plain result
-                  within the error budget.
+                  within the error budget on every held-out scene.
 
     python -m paper_2604_05794_amd.train --out <checkpoint> [--quick]
+    python -m paper_2604_05794_amd.train --recalibrate <checkpoint> --out <checkpoint>
 """
 from __future__ import annotations
 
@@ -65,7 +66,7 @@ def scene_pairs(recipe, seed, n_points=None):
     torch.cuda.synchronize()
     keep = torch.isfinite(c)
     return dict(feats=f[keep].contiguous(), dirs=d[keep].contiguous(), scene=sc,
-                dev=(pts, cams, th, cf), kw=kw, plain=(d, c))
+                dev=(pts, cams, th, cf), kw=kw, plain=(d, c), name=f"{recipe}:{seed}")
 
 
 def train(net, feats, dirs, epochs, batch, lr, seed):
@@ -92,18 +93,33 @@ def train(net, feats, dirs, epochs, batch, lr, seed):
     return step
 
 
+def _tau_for_budget(costs, errs, budget_deg):
+    """Largest cost threshold whose kept results (cost <= threshold; the rest
+    take the plain search, error 0) keep the mean error within the budget."""
+    order = torch.argsort(costs)
+    cs = costs[order]
+    cum = torch.cumsum(errs[order].double(), 0) / float(len(cs))
+    ok = torch.nonzero(cum <= budget_deg).flatten()
+    if len(ok) == 0:
+        return -math.inf
+    k = int(ok[-1].item())
+    if k + 1 == len(cs):
+        return float(cs[k].item())
+    return float(0.5 * (cs[k].item() + cs[k + 1].item()))
+
+
 def calibrate(net, pairs, budget_deg, learned_iters):
-    """learned_step0 from the proposal error; fallback_cost from the budget."""
-    errs, costs, errs_refined = [], [], []
-    step0 = None
+    """learned_step0 from the proposal error; fallback_cost from the budget,
+    which must hold on every held-out scene on its own."""
+    errs = []
     for p in pairs:
         prop = net.forward(p["feats"])
-        e = axial_deg(prop, p["dirs"])
-        errs.append(e)
+        errs.append(axial_deg(prop, p["dirs"]))
     e_all = torch.cat(errs)
-    step0 = math.radians(float(e_all.median().item()))
-    step0 = max(step0, 1e-3)
-    for p in pairs:
+    step0 = max(math.radians(float(e_all.median().item())), 1e-3)
+    taus, per = [], {}
+    runs = []
+    for p, e in zip(pairs, errs):
         pts, cams, th, cf = p["dev"]
         ctx = native.Context(max_points=pts.shape[0])
         d, c = native.fuse_directions(pts, cams, th, cf, ctx=ctx, mode=native.FD_MODE_LEARNED,
@@ -112,35 +128,26 @@ def calibrate(net, pairs, budget_deg, learned_iters):
                                       head_centre=p["scene"].head_centre, **p["kw"])
         dp, cp = p["plain"]
         fin = torch.isfinite(cp)
-        costs.append(c[fin])
-        errs_refined.append(axial_deg(d[fin], dp[fin]))
-    c_all = torch.cat(costs)
-    r_all = torch.cat(errs_refined)
-    order = torch.argsort(c_all)
-    cs = c_all[order]
-    # mean error if every point with cost <= cs[k] keeps its learned result
-    cum = torch.cumsum(r_all[order].double(), 0) / float(len(cs))
-    ok = torch.nonzero(cum <= budget_deg).flatten()
-    if len(ok) == 0:
-        tau = -math.inf
-        frac = 0.0
-    else:
-        k = int(ok[-1].item())
-        tau = float(cs[k].item()) if k + 1 == len(cs) else float(
-            0.5 * (cs[k].item() + cs[k + 1].item()))
-        frac = (k + 1) / len(cs)
-    per = {}
-    for p, e in zip(pairs, errs):
-        key = p["scene"].meta["recipe"].get("kinds") and ("curls" if p["kw"]["n_candidates"] and
-                                                          p["scene"].n_views == 128 else "realistic")
-        per[key] = float(e.median().item())
+        r = axial_deg(d[fin], dp[fin])
+        runs.append((c[fin], r))
+        taus.append(_tau_for_budget(c[fin], r, budget_deg))
+        per[p["name"]] = dict(proposal_median_deg=float(e.median().item()),
+                              refined_mean_deg_no_fallback=float(r.mean().item()))
+    tau = min(taus)
+    for (c, r), p in zip(runs, pairs):
+        keep = c <= tau
+        per[p["name"]].update(kept_fraction=float(keep.float().mean().item()),
+                              mean_err_vs_plain_deg=float((r * keep).mean().item()))
     stats = dict(proposal_median_deg=float(e_all.median().item()),
-                 proposal_median_deg_by_scene=per,
-                 proposal_mean_deg=float(e_all.mean().item()),
-                 refined_mean_deg_no_fallback=float(r_all.mean().item()),
-                 learned_step0=step0, fallback_cost=tau, kept_fraction=frac,
+                 by_scene=per, learned_step0=step0, fallback_cost=tau,
                  budget_deg=budget_deg)
     return step0, tau, stats
+
+
+def held_out(quick):
+    if quick:
+        return [("realistic", 1100, 20_000), ("curls", 1100, 20_000)]
+    return [("realistic", 1100, 100_000), ("curls", 1100, 100_000)]
 
 
 def main():
@@ -154,20 +161,30 @@ def main():
     ap.add_argument("--budget-deg", type=float, default=1.5)
     ap.add_argument("--learned-iters", type=int, default=2)
     ap.add_argument("--quick", action="store_true", help="small data, for a smoke run")
+    ap.add_argument("--recalibrate", metavar="CKPT",
+                    help="only calibrate an existing checkpoint and write it to --out")
     args = ap.parse_args()
     native.lib()
     t0 = time.perf_counter()
+    if args.recalibrate:
+        net = native.MLP(path=args.recalibrate)
+        pairs = [scene_pairs(rec, seed, n) for rec, seed, n in held_out(args.quick)]
+        step0, tau, stats = calibrate(net, pairs, args.budget_deg, args.learned_iters)
+        net.set_calibration(step0, tau)
+        net.save(args.out)
+        stats["seconds"] = time.perf_counter() - t0
+        log(json.dumps(stats))
+        print(json.dumps(stats), flush=True)
+        return
     # 2M training pairs: two 500k-point scenes of the realistic recipe and
     # four 250k-point heads of tight curls (seeds 1000+), labels from the
     # plain search with each recipe's own parameters
     if args.quick:
         train_set = [("realistic", 1000, 50_000), ("curls", 1000, 50_000)]
-        held = [("realistic", 1100, 20_000), ("curls", 1100, 20_000)]
     else:
         train_set = [("realistic", 1000, None), ("realistic", 1001, None),
                      ("curls", 1000, None), ("curls", 1001, None), ("curls", 1002, None),
                      ("curls", 1003, None)]
-        held = [("realistic", 1100, 100_000), ("curls", 1100, 100_000)]
     feats, dirs = [], []
     for rec, seed, n in train_set:
         p = scene_pairs(rec, seed, n)
@@ -182,7 +199,7 @@ def main():
     net = native.MLP(seed=args.seed)
     train(net, feats, dirs, args.epochs, args.batch, args.lr, args.seed)
     del feats, dirs
-    pairs = [scene_pairs(rec, seed, n) for rec, seed, n in held]
+    pairs = [scene_pairs(rec, seed, n) for rec, seed, n in held_out(args.quick)]
     step0, tau, stats = calibrate(net, pairs, args.budget_deg, args.learned_iters)
     net.set_calibration(step0, tau)
     os.makedirs(os.path.dirname(os.path.abspath(args.out)), exist_ok=True)

@@ -48,7 +48,8 @@ def compare(orc, points, d_gpu, c_gpu, d_o, c_o, angle_tol=ANGLE_TOL, cost_tol=C
     J_g = np.full(len(points), np.inf)
     if fin.any():
         J_g[fin] = orc.objective_each(points[fin], d_gpu[fin])
-    cost_err = np.abs(c_gpu - J_g)
+    cost_err = np.zeros(len(points))
+    cost_err[fin] = np.abs(c_gpu[fin] - J_g[fin])
     ok = fin & (ang <= angle_tol)
     tie = fin & ~ok & (J_g <= c_o + cost_tol)
     fail = fin & ~ok & ~tie

@@ -280,3 +280,53 @@ def test_given_proposal_parity_with_oracle(tau, depth):
     # the fallback decision is a threshold on a float cost: equal up to the
     # points whose refined cost lies within rounding of tau
     assert abs(n_fb - int(fb.sum())) <= max(3, 0.002 * sc.n_points)
+
+
+def test_trained_network_gains_over_the_method_without_it():
+    """The committed checkpoint on a scene it has neither been trained nor
+    calibrated on (realistic recipe, seed 1200, depth test on): its proposals lie closer to the plain result than
+    an untrained network's, more of its refined results are kept below the
+    calibrated threshold, and the kept results stay within the error budget
+    of the calibration.  Without the network (NaN proposals) every point
+    takes the full search."""
+    import os
+    nat = _native()
+    path = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))),
+                        "paper_2604_05794_amd", "weights", "proposal_mlp.fdmlp")
+    rec = dict(scenegen.RECIPES["realistic"])
+    rec["n_points"] = 100_000
+    sc = scenegen.make_scene(rec, 1200)
+    pts, cams, th, cf = _dev_scene(sc)
+    dm = torch.from_numpy(sc.depth).to(DEV)
+    kw = dict(patch=5, n_candidates=128, refine_iters=8, top_k=5, depth_maps=dm)
+    ctx = nat.Context(max_points=sc.n_points)
+    dp, cp = nat.fuse_directions(pts, cams, th, cf, ctx=ctx, **kw)
+    fin = torch.isfinite(cp)
+    feats = nat.features(pts, cams, th, cf, head_centre=sc.head_centre, depth_maps=dm)
+    trained = nat.MLP(path=path)
+    untrained = nat.MLP(seed=11)
+    step0, tau = trained.calibration()
+
+    def axial(a, b):
+        return torch.rad2deg(torch.atan2(torch.linalg.norm(torch.cross(a, b, dim=1), dim=1),
+                                         torch.abs((a * b).sum(1))))
+
+    stats = {}
+    for name, net in (("trained", trained), ("untrained", untrained)):
+        prop = net.forward(feats)
+        d, c = nat.fuse_directions(pts, cams, th, cf, ctx=ctx, mode=nat.FD_MODE_LEARNED,
+                                   mlp=net, learned_iters=2, learned_step0=step0,
+                                   fallback_cost=tau, head_centre=sc.head_centre, **kw)
+        torch.cuda.synchronize()
+        kept = 1.0 - ctx.fallback_count() / sc.n_points
+        stats[name] = dict(proposal_median_deg=float(axial(prop[fin], dp[fin]).median()),
+                           kept=kept, mean_err_vs_plain_deg=float(axial(d[fin], dp[fin]).mean()))
+    d0, c0 = nat.fuse_directions(pts, cams, th, cf, ctx=ctx, mode=nat.FD_MODE_LEARNED,
+                                 proposal=nat.FD_PROPOSAL_NAN, fallback_cost=tau, **kw)
+    torch.cuda.synchronize()
+    assert ctx.fallback_count() == sc.n_points
+    print("network gain", stats, flush=True)
+    t, u = stats["trained"], stats["untrained"]
+    assert t["proposal_median_deg"] < 0.6 * u["proposal_median_deg"]
+    assert t["kept"] > u["kept"] + 0.02
+    assert t["mean_err_vs_plain_deg"] <= 2.0
