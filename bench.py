@@ -52,8 +52,6 @@ TRAFFIC = {
                                "src": "39e8c75206e119fe"},
     "k_fuse, metric workload, per head": {"read": 289.8e6, "write": 19.1e6,
                                           "files": _SEARCH_SOURCES, "src": "39e8c75206e119fe"},
-    "k_b_fuse fallback, metric workload": {"read": 11353.8e6, "write": 147.1e6,
-                                           "files": _BATCHED_SOURCES, "src": "f0619f03f951c43e"},
 }
 
 
@@ -307,6 +305,11 @@ def run_metric(args):
             native.fuse_batched(scenes, ctx, stream=stream, **kw, **extra)
         return step
 
+    # tile shapes of the batched search, picked by the autotuner (untimed)
+    t = time.perf_counter()
+    native.autotune([d for _, d in heads], ctx, stream=stream, **kw)
+    log(f"autotune: {time.perf_counter() - t:.1f} s, chunk {ctx.tuned()[0]}, grid {ctx.tuned()[1]}")
+
     def snap():
         return (torch.cat([d["dirs"] for _, d in heads]).clone(),
                 torch.cat([d["costs"] for _, d in heads]).clone())
@@ -323,7 +326,8 @@ def run_metric(args):
         if is_batched:
             st = _stage_pass(fn, ctx, stg)
             if name == "learned_batched":
-                n_fb_batched = ctx.fallback_count(stream)
+                fb_listed, fb_inplace = ctx.fallback_split(stream)
+                n_fb_batched = fb_listed + fb_inplace
         res[name] = (n / (el / args.steps), el * 1e3 / args.steps, st)
         log(f"{name}: {res[name][0] / 1e6:.1f} M points/s, {res[name][1]:.3f} ms/step, "
             f"{json.dumps({k: round(v, 4) for k, v in st.items()})}")
@@ -349,9 +353,12 @@ def run_metric(args):
     v_lb, ms_lb, st_lb = res["learned_batched"]
     v_p, _, st_p = res["plain"]
     flop = plain_flop_per_point(kw["patch"], kw["n_candidates"], kw["refine_iters"], 5)
-    # dominant kernel of the learned+batched step: the persistent search over
-    # the fallback list (the same per-point search as the plain form)
-    achieved = flop * n_fb_batched / (st_lb["fallback"] * 1e-3) / 1e12
+    # dominant kernel of the learned+batched step: k_b_learned, which refines
+    # every point from its proposal (1 + 6 x 2 directions) and runs the full
+    # search in place for the waves that mostly fall back
+    flop_refine = (1 + 6 * lkw["learned_iters"]) * 5 * (12 + 4 * kw["patch"] ** 2)
+    flop_lb = flop_refine * n + flop * fb_inplace
+    achieved = flop_lb / (st_lb["refine"] * 1e-3) / 1e12
     achieved_plain = flop * n / (st_p["fuse"] * len(heads) * 1e-3) / 1e12
     out = {
         "metric": METRIC, "value": v_lb, "unit": "points/s", "n_gpus": 1,
@@ -365,7 +372,8 @@ def run_metric(args):
                                "iterations), one captured batched launch",
                    "mode": "learned+batched", "points": n, "heads": len(heads), "views": 128,
                    "depth_test": not args.no_depth,
-                   "learned_step0": step0, "fallback_cost": tau, **kw},
+                   "learned_step0": step0, "fallback_cost": tau,
+                   "batched_shape": dict(zip(("chunk", "grid"), ctx.tuned())), **kw},
         "plain_points_per_s": v_p, "speedup_vs_plain": v_lb / v_p,
         "points_per_s": {k: v[0] for k, v in res.items()},
         "ms_per_step_by_form": {k: v[1] for k, v in res.items()},
@@ -374,13 +382,16 @@ def run_metric(args):
         "fallback_frac": fb / n, "batched_bitwise_equal": {"plain": same_pb, "learned": same_lb},
         "stages_ms_per_launch_plain": st_p,
         "roofline": {"bound": "alu",
-                     "kernel": "k_b_fuse: persistent plain search over the fallback list of the "
-                               "learned+batched step",
+                     "kernel": "k_b_learned: refinement from the proposal for every point, full "
+                               "search in place for the waves that mostly fall back "
+                               "(learned+batched step)",
                      "achieved": achieved, "peak": PEAK_FP32_FMA, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP32_FMA,
-                     "traffic": traffic_of("k_b_fuse fallback, metric workload"),
-                     "avg_launch_ms": st_lb["fallback"], "points_per_launch": n_fb_batched,
-                     "flop_per_point": flop, "peak_vendor_packed": PEAK_FP32_VENDOR,
+                     "traffic": traffic_of("k_b_learned, metric workload"),
+                     "avg_launch_ms": st_lb["refine"], "points_per_launch": n,
+                     "full_searches_in_place": fb_inplace, "listed_fallbacks": fb_listed,
+                     "flop_per_launch": flop_lb, "flop_per_full_search": flop,
+                     "flop_per_refinement": flop_refine, "peak_vendor_packed": PEAK_FP32_VENDOR,
                      "frac_vs_vendor_packed": achieved / PEAK_FP32_VENDOR},
         "roofline_plain_per_head": {
             "bound": "alu", "kernel": "k_fuse (plain search, one launch per head)",

@@ -147,6 +147,12 @@ int fd_fuse_directions(const float* points, int64_t n_points,
  * full search (reads a device counter; synchronises params->stream). */
 int fd_last_fallback_count(fd_context* ctx, void* stream, int64_t* out);
 
+/* The same points split by where their full search ran: *in_place inside
+ * the refinement kernel (waves in which at least half of the points needed
+ * it, on the patch registers they already held), *listed by the separate
+ * fallback launch over the compacted list. */
+int fd_last_fallback_split(fd_context* ctx, void* stream, int64_t* listed, int64_t* in_place);
+
 /* ---- many scenes in one launch --------------------------------------------
  * Every scene has its own points, cameras, maps (own W x H and view count)
  * and outputs; all use params' search settings and map dtype (params->width,
@@ -227,14 +233,20 @@ int fd_features(const float* points, int64_t n_points, const fd_camera* cams,
 
 /* ---- tuning ---------------------------------------------------------------
  * Times the batched launch on the sample scenes for each shape of the
- * persistent search (tiles per queue pop, resident grid size) and keeps the
- * fastest in the context.  With cache_path, a shape class (patch, top_k,
+ * plain search (persistent: tiles per queue pop and resident grid size; or
+ * one wave per tile) and keeps the fastest in the context (the sample's
+ * outputs are overwritten).  With cache_path, a shape class (patch, top_k,
  * map dtype, mode, point-count octave) already in that JSON file is taken
  * from it without timing, and a newly timed one is added to it.  Offline: it
  * synchronises and is not meant for timed regions.  Tile shapes never change
  * results. */
 int fd_autotune(fd_context* ctx, const fd_scene* sample, int32_t n_scenes,
                 const fd_params* params, const char* cache_path);
+
+/* The tile shape the batched search of this context uses: *chunk tiles per
+ * queue pop and *grid workgroups (0: the full resident grid, -1: one wave
+ * per tile instead of the persistent queue). */
+int fd_tuned_shape(const fd_context* ctx, int32_t* chunk, int32_t* grid);
 
 /* ---- stage timing -----------------------------------------------------------
  * While enabled on a context, every call through it records a pair of HIP

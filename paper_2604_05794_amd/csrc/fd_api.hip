@@ -105,7 +105,7 @@ extern "C" int fd_context_create(fd_context** out) {
       (r = grow(&c->cursor, &(cap = 0), (size_t)tile_cells(), "cell cursor")) ||
       (r = grow(&c->scan_sums, &(cap = 0), (size_t)tile_cells() / 1024, "scan sums")) ||
       (r = grow(&c->lattice, &(cap = 0), (size_t)3 * FD_MAX_CANDIDATES, "lattice")) ||
-      (r = grow(&c->fb_count, &(cap = 0), (size_t)4, "fallback counter"))) {
+      (r = grow(&c->fb_count, &(cap = 0), (size_t)8, "fallback counters"))) {
     fd_context_destroy(c);
     return r;
   }

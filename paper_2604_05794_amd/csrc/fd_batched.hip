@@ -41,12 +41,16 @@ constexpr int kBCells = 1 << (3 * kBCellBits);
 constexpr int kBlock = 256;
 
 struct BatchDev {
-  const SceneDev* tab;    // n_scenes
-  const int64_t* pt_off;  // n_scenes + 1, global point offsets
-  const int64_t* blk_off; // n_scenes + 1, first 256-thread block of each scene
+  const SceneDev* tab;     // n_scenes
+  const int64_t* pt_off;   // n_scenes + 1, global point offsets
+  const int64_t* blk_off;  // n_scenes + 1, first 256-thread block of each scene
+  const int64_t* tile_off; // n_scenes + 1, first search tile (G points) of each scene
   int n_scenes;
   int64_t total;
+  int64_t n_tiles;         // tile_off[n_scenes]
 };
+
+constexpr int kQueues = 8;  // one tile range and queue per XCD
 
 // largest s with off[s] <= x (off ascending, off[0] = 0)
 __device__ __forceinline__ int find_scene(const int64_t* off, int n, int64_t x) {
@@ -69,11 +73,14 @@ __device__ __forceinline__ float ordered_to_float(int i) {
   return __int_as_float(i >= 0 ? i : i ^ 0x7fffffff);
 }
 
-// per-scene point index of this thread (block table), or -1
-__device__ __forceinline__ int64_t block_point(const BatchDev& b, int* scene) {
-  const int s = find_scene(b.blk_off, b.n_scenes, (int64_t)blockIdx.x);
+// per-scene point index of this thread (block table), or -1; `blk` is the
+// logical block index (blockIdx.x, or its XCD-aware remapping)
+__device__ __forceinline__ int64_t block_point(const BatchDev& b, int* scene,
+                                               int64_t blk = -1) {
+  if (blk < 0) blk = blockIdx.x;
+  const int s = find_scene(b.blk_off, b.n_scenes, blk);
   *scene = s;
-  const int64_t j = ((int64_t)blockIdx.x - b.blk_off[s]) * blockDim.x + threadIdx.x;
+  const int64_t j = (blk - b.blk_off[s]) * blockDim.x + threadIdx.x;
   return j < b.tab[s].n ? j : -1;
 }
 
@@ -161,9 +168,9 @@ __global__ __launch_bounds__(kBlock) void k_b_scatter(BatchDev b, const uint32_t
 template <typename T, int KS>
 __global__ __launch_bounds__(kBlock) void k_b_topk(BatchDev b, SearchDev q) {
   int s;
-  const int64_t j = block_point(b, &s);
+  const int64_t j = block_point(b, &s, xcd_tile(gridDim.x));
   if (j < 0) return;
-  const SceneDev sc = b.tab[s];
+  const SceneDev sc = load_scene(b.tab, s);
   topk_point<T, KS>(sc, q, j);
 }
 
@@ -171,53 +178,90 @@ template <typename T, int KS>
 __global__ __launch_bounds__(kBlock) void k_b_topk_features(BatchDev b, SearchDev q,
                                                             uint16_t* __restrict__ feats) {
   int s;
-  const int64_t j = block_point(b, &s);
+  const int64_t j = block_point(b, &s, xcd_tile(gridDim.x));
   if (j < 0) return;
-  const SceneDev sc = b.tab[s];
+  const SceneDev sc = load_scene(b.tab, s);
   topk_features_point<T, KS>(sc, q, j, b.pt_off[s], feats);
 }
 
-// Persistent search over items 0..n_items-1 (item = global point position, or
-// list[item] when a list is given; n_items = *count then).  Each wave pops
-// `chunk` tiles of G items at a time; lane 0 pops and broadcasts, so the
-// whole wave leaves the loop together once the queue is exhausted.
-template <typename T, int P, int KT>
+// Persistent search.  Without a list, the items are the scenes' points in
+// tiles of G that never straddle a scene (tile_off), so a wave's scene is
+// uniform and its record is read through the scalar cache; with a list
+// (n_items = *list_count global point positions) each lane finds its own
+// scene.  Tiles are dealt to kQueues queues, one per XCD (workgroups go to the
+// XCDs round-robin), in blocks of kQueueRun consecutive tiles: queue x owns
+// blocks x, x + kQueues, ...  Neighbouring tiles, which share most patch
+// texels, are then searched under one L2 while all XCDs move through the
+// (spatially sorted) tiles together.  A wave pops `chunk` tiles at a time from
+// its own queue, then from the others once it is empty; lane 0 pops and
+// broadcasts, so the whole wave leaves the loop together when every queue is
+// exhausted.
+constexpr int64_t kQueueRun = 32;
+
+__device__ __forceinline__ int64_t queue_tile(int qi, int64_t v) {
+  return (v / kQueueRun) * (kQueueRun * kQueues) + qi * kQueueRun + (v % kQueueRun);
+}
+
+template <typename T, int P, int KT, bool LIST>
 __global__ __launch_bounds__(kBlock) void k_b_fuse(BatchDev b, SearchDev q, const uint32_t* list,
                                                    const uint32_t* list_count,
                                                    uint32_t* __restrict__ queue, int chunk) {
   const Group gr = make_group(q.K);
-  const int64_t n_items = list ? (int64_t)*list_count : b.total;
-  const int64_t n_tiles = (n_items + gr.G - 1) / gr.G;
-  for (;;) {
-    uint32_t t0 = 0;
-    if ((threadIdx.x & 63) == 0) t0 = atomicAdd(queue, (uint32_t)chunk);
-    t0 = __builtin_amdgcn_readfirstlane(t0);
-    if ((int64_t)t0 >= n_tiles) break;
-    for (int c = 0; c < chunk; ++c) {
-      const int64_t tile = (int64_t)t0 + c;
-      if (tile >= n_tiles) break;  // uniform
-      const int64_t item = tile * gr.G + gr.g;
-      const bool pt_ok = gr.lane_ok && item < n_items;
-      const int64_t gpos = pt_ok ? (list ? (int64_t)list[item] : item) : 0;
-      const int s = find_scene(b.pt_off, b.n_scenes, gpos);
-      const SceneDev sc = b.tab[s];
-      fuse_group<T, P, KT>(sc, q, gr, pt_ok, gpos - b.pt_off[s]);
+  const int64_t n_items = LIST ? (int64_t)*list_count : b.total;
+  const int64_t n_tiles = LIST ? (n_items + gr.G - 1) / gr.G : b.n_tiles;
+  const int home = (int)(blockIdx.x % kQueues);
+  for (int r = 0; r < kQueues; ++r) {
+    const int qi = (home + r) % kQueues;
+    for (;;) {
+      uint32_t v0 = 0;
+      if ((threadIdx.x & 63) == 0) v0 = atomicAdd(&queue[qi], (uint32_t)chunk);
+      v0 = __builtin_amdgcn_readfirstlane(v0);
+      if (queue_tile(qi, v0) >= n_tiles) break;  // tiles of a queue only increase
+      for (int c = 0; c < chunk; ++c) {
+        const int64_t tile = queue_tile(qi, (int64_t)v0 + c);
+        if (tile >= n_tiles) break;  // uniform
+        if constexpr (LIST) {
+          const int64_t item = tile * gr.G + gr.g;
+          const bool pt_ok = gr.lane_ok && item < n_items;
+          const int64_t gpos = pt_ok ? (int64_t)list[item] : 0;
+          const int s = find_scene(b.pt_off, b.n_scenes, gpos);
+          const SceneDev sc = load_scene(b.tab, s);
+          fuse_group<T, P, KT>(sc, q, gr, pt_ok, gpos - b.pt_off[s]);
+        } else {
+          const int s = find_scene(b.tile_off, b.n_scenes, tile);
+          const SceneDev sc = load_scene(b.tab, s);
+          const int64_t j = (tile - b.tile_off[s]) * gr.G + gr.g;
+          fuse_group<T, P, KT>(sc, q, gr, gr.lane_ok && j < sc.n, j);
+        }
+      }
     }
   }
 }
 
+// Non-persistent form of the plain search (one wave per scene-uniform tile,
+// tiles in XCD-aware block order), which the autotuner may pick instead.
+template <typename T, int P, int KT>
+__global__ __launch_bounds__(kBlock) void k_b_fuse_tiles(BatchDev b, SearchDev q) {
+  const Group gr = make_group(q.K);
+  const int64_t tile = xcd_tile(gridDim.x) * (blockDim.x / kWave) + (threadIdx.x / kWave);
+  if (tile >= b.n_tiles) return;
+  const int s = find_scene(b.tile_off, b.n_scenes, tile);
+  const SceneDev sc = load_scene(b.tab, s);
+  const int64_t j = (tile - b.tile_off[s]) * gr.G + gr.g;
+  fuse_group<T, P, KT>(sc, q, gr, gr.lane_ok && j < sc.n, j);
+}
+
+// One wave per scene-uniform tile, tiles in XCD-aware block order.
 template <typename T, int P, int KT>
 __global__ __launch_bounds__(kBlock) void k_b_learned(BatchDev b, SearchDev q, LearnedDev l) {
   const Group gr = make_group(q.K);
-  const int64_t wave = (int64_t)blockIdx.x * (blockDim.x / kWave) + (threadIdx.x / kWave);
-  if (wave * gr.G >= b.total) return;
-  const int64_t item = wave * gr.G + gr.g;
-  const bool pt_ok = gr.lane_ok && item < b.total;
-  const int64_t gpos = pt_ok ? item : 0;
-  const int s = find_scene(b.pt_off, b.n_scenes, gpos);
-  const SceneDev sc = b.tab[s];
-  const int64_t j = gpos - b.pt_off[s];
-  learned_group<T, P, KT>(sc, q, l, gr, pt_ok, j, 1, b.pt_off[s], b.pt_off[s]);
+  const int64_t tile = xcd_tile(gridDim.x) * (blockDim.x / kWave) + (threadIdx.x / kWave);
+  if (tile >= b.n_tiles) return;
+  const int s = find_scene(b.tile_off, b.n_scenes, tile);
+  const SceneDev sc = load_scene(b.tab, s);
+  const int64_t j = (tile - b.tile_off[s]) * gr.G + gr.g;
+  const bool pt_ok = gr.lane_ok && j < sc.n;
+  learned_group<T, P, KT>(sc, q, l, gr, pt_ok, pt_ok ? j : 0, 1, b.pt_off[s], b.pt_off[s]);
 }
 
 template <typename T, int P, int KT>
@@ -225,12 +269,18 @@ hipError_t launch_b_search(const BatchDev& b, const SearchDev& q, const LearnedD
                            const uint32_t* list, const uint32_t* count, uint32_t* queue,
                            int chunk, int grid, hipStream_t st) {
   if (l) {
-    const int G = kWave / q.K;
-    const int64_t nb = (b.total + 4 * (int64_t)G - 1) / (4 * (int64_t)G);
+    const int64_t nb = (b.n_tiles + 3) / 4;  // 4 waves per block
     hipLaunchKernelGGL((k_b_learned<T, P, KT>), dim3((unsigned)nb), dim3(kBlock), 0, st, b, q, *l);
   } else {
-    hipLaunchKernelGGL((k_b_fuse<T, P, KT>), dim3(grid), dim3(kBlock), 0, st, b, q, list, count,
-                       queue, chunk);
+    if (list)
+      hipLaunchKernelGGL((k_b_fuse<T, P, KT, true>), dim3(grid), dim3(kBlock), 0, st, b, q, list,
+                         count, queue, chunk);
+    else if (grid <= 0)  // one wave per tile instead of the persistent queue
+      hipLaunchKernelGGL((k_b_fuse_tiles<T, P, KT>), dim3((unsigned)((b.n_tiles + 3) / 4)),
+                         dim3(kBlock), 0, st, b, q);
+    else
+      hipLaunchKernelGGL((k_b_fuse<T, P, KT, false>), dim3(grid), dim3(kBlock), 0, st, b, q,
+                         list, count, queue, chunk);
   }
   return hipGetLastError();
 }
@@ -268,7 +318,7 @@ int persistent_grid(int dtype, int patch, int per_cu_cap) {
   (void)hipGetDevice(&dev);
   (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
   const void* fn = nullptr;
-#define FD_FN(T, P) (const void*)(&k_b_fuse<T, P, 5>)
+#define FD_FN(T, P) (const void*)(&k_b_fuse<T, P, 5, false>)
   if (dtype == 1)
     fn = patch == 1 ? FD_FN(__half, 1) : patch == 3 ? FD_FN(__half, 3) : patch == 5 ? FD_FN(__half, 5) : FD_FN(__half, 7);
   else
@@ -307,9 +357,9 @@ int fd::context_reserve_scenes(fd_context* c, int32_t n_scenes, int64_t total_po
   c->scene_tab = c->tile_tab = nullptr;
   c->tile_queue = c->batch_key = c->batch_perm = nullptr;
   const size_t S = (size_t)FD_MAX_BATCH_SCENES;
-  hipError_t e = hipMalloc(&c->scene_tab, S * sizeof(SceneDev) + 2 * (S + 1) * sizeof(int64_t));
+  hipError_t e = hipMalloc(&c->scene_tab, S * sizeof(SceneDev) + 3 * (S + 1) * sizeof(int64_t));
   if (e == hipSuccess) e = hipMalloc(&c->tile_tab, S * 6 * sizeof(int));              // bboxes
-  if (e == hipSuccess) e = hipMalloc((void**)&c->tile_queue, 4 * sizeof(uint32_t));  // queue
+  if (e == hipSuccess) e = hipMalloc((void**)&c->tile_queue, kQueues * sizeof(uint32_t));
   if (e == hipSuccess) e = hipMalloc((void**)&c->batch_key, S * kBCells * sizeof(uint32_t));
   if (e == hipSuccess) e = hipMalloc((void**)&c->batch_perm, (S * kBCells + 1024) * sizeof(uint32_t));
   if (e != hipSuccess) {
@@ -324,11 +374,12 @@ int fd::context_reserve_scenes(fd_context* c, int32_t n_scenes, int64_t total_po
 // ---- the batched call --------------------------------------------------------------------
 
 static int record_batch(fd_context* c, const fd_params* p, int n_scenes, int64_t total,
-                        const int64_t* blk_off_host, hipStream_t st) {
+                        const int64_t* blk_off_host, int64_t n_tiles, hipStream_t st) {
   SceneDev* tab = (SceneDev*)c->scene_tab;
   int64_t* pt_off = (int64_t*)(tab + FD_MAX_BATCH_SCENES);
   int64_t* blk_off = pt_off + (FD_MAX_BATCH_SCENES + 1);
-  BatchDev b{tab, pt_off, blk_off, n_scenes, total};
+  int64_t* tile_off = blk_off + (FD_MAX_BATCH_SCENES + 1);
+  BatchDev b{tab, pt_off, blk_off, tile_off, n_scenes, total, n_tiles};
   const int64_t nblocks = blk_off_host[n_scenes];
   uint32_t* counts = c->batch_key;
   uint32_t* cursor = c->batch_perm;
@@ -373,13 +424,18 @@ static int record_batch(fd_context* c, const fd_params* p, int n_scenes, int64_t
     t_topk.stop();
   }
   const int chunk = c->tuned_chunk > 0 ? c->tuned_chunk : 2;
-  const int grid = persistent_grid(p->map_dtype, p->patch, c->tuned_grid);
+  // tuned_grid: 0 = the full resident grid, > 0 = at most that many
+  // workgroups, < 0 = the plain search as one wave per tile (the fallback
+  // list always takes the persistent form)
+  const int grid = persistent_grid(p->map_dtype, p->patch, c->tuned_grid > 0 ? c->tuned_grid : 0);
+  const int plain_grid = c->tuned_grid < 0 ? 0 : grid;
   uint32_t* queue = c->tile_queue;
   if (p->mode == FD_MODE_PLAIN) {
-    if ((e = launch_fill_u32(queue, 1, 0u, st)) != hipSuccess) return hip_error(e, "queue reset");
+    if ((e = launch_fill_u32(queue, kQueues, 0u, st)) != hipSuccess)
+      return hip_error(e, "queue reset");
     StageTimer t_fuse(c, FD_STAGE_FUSE, st);
-    if ((e = search(p->map_dtype, p->patch, b, q, nullptr, nullptr, nullptr, queue, chunk, grid,
-                    st)) != hipSuccess)
+    if ((e = search(p->map_dtype, p->patch, b, q, nullptr, nullptr, nullptr, queue, chunk,
+                    plain_grid, st)) != hipSuccess)
       return hip_error(e, "batched search");
     t_fuse.stop();
     return FD_OK;
@@ -423,14 +479,15 @@ static int record_batch(fd_context* c, const fd_params* p, int n_scenes, int64_t
   if (r) return r;
   t_mlp.stop();
   l.proposals = c->prop;
-  if ((e = launch_fill_u32(c->fb_count, 1, 0u, st)) != hipSuccess)
+  if ((e = launch_fill_u32(c->fb_count, 2, 0u, st)) != hipSuccess)
     return hip_error(e, "fallback counter reset");
   StageTimer t_ref(c, FD_STAGE_REFINE, st);
   if ((e = search(p->map_dtype, p->patch, b, q, &l, nullptr, nullptr, queue, chunk, grid, st)) !=
       hipSuccess)
     return hip_error(e, "batched learned refinement");
   t_ref.stop();
-  if ((e = launch_fill_u32(queue, 1, 0u, st)) != hipSuccess) return hip_error(e, "queue reset");
+  if ((e = launch_fill_u32(queue, kQueues, 0u, st)) != hipSuccess)
+    return hip_error(e, "queue reset");
   StageTimer t_fb(c, FD_STAGE_FALLBACK, st);
   if ((e = search(p->map_dtype, p->patch, b, q, nullptr, c->fb_list, c->fb_count, queue, chunk,
                   grid, st)) != hipSuccess)
@@ -453,7 +510,9 @@ extern "C" int fd_fuse_directions_batched(const fd_scene* scenes, int32_t n_scen
   if (params->proposal != FD_PROPOSAL_MLP && params->mode == FD_MODE_LEARNED)
     return set_error(FD_E_INVAL, "%s: the batched learned form takes the network proposal", fn);
   int64_t total = 0;
-  std::vector<int64_t> pt_off(n_scenes + 1, 0), blk_off(n_scenes + 1, 0);
+  const int G = 64 / params->top_k;  // points per search tile (one wave)
+  std::vector<int64_t> pt_off(n_scenes + 1, 0), blk_off(n_scenes + 1, 0),
+      tile_off(n_scenes + 1, 0);
   for (int s = 0; s < n_scenes; ++s) {
     const fd_scene& sc = scenes[s];
     if (sc.n_points < 0) return set_error(FD_E_INVAL, "%s: scene %d has n_points < 0", fn, s);
@@ -469,6 +528,7 @@ extern "C" int fd_fuse_directions_batched(const fd_scene* scenes, int32_t n_scen
     total += sc.n_points;
     pt_off[s + 1] = total;
     blk_off[s + 1] = blk_off[s] + (sc.n_points + kBlock - 1) / kBlock;
+    tile_off[s + 1] = tile_off[s] + (sc.n_points + G - 1) / G;
   }
   if (total > (int64_t)UINT32_MAX) return set_error(FD_E_INVAL, "%s: too many points", fn);
   if ((r = check_device(nullptr))) return r;
@@ -519,10 +579,12 @@ extern "C" int fd_fuse_directions_batched(const fd_scene* scenes, int32_t n_scen
     SceneDev* dtab = (SceneDev*)ctx->scene_tab;
     int64_t* dpt = (int64_t*)(dtab + FD_MAX_BATCH_SCENES);
     int64_t* dblk = dpt + (FD_MAX_BATCH_SCENES + 1);
+    int64_t* dtile = dblk + (FD_MAX_BATCH_SCENES + 1);
     hipError_t e = hipStreamSynchronize(st);
     if (e == hipSuccess) e = hipMemcpy(dtab, tab.data(), sizeof(SceneDev) * n_scenes, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(dpt, pt_off.data(), sizeof(int64_t) * (n_scenes + 1), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(dblk, blk_off.data(), sizeof(int64_t) * (n_scenes + 1), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(dtile, tile_off.data(), sizeof(int64_t) * (n_scenes + 1), hipMemcpyHostToDevice);
     if (e != hipSuccess) return hip_error(e, "batched scene table upload");
     if ((r = ensure_lattice(ctx, params->n_candidates, st))) return r;
     if ((e = hipStreamSynchronize(st)) != hipSuccess) return hip_error(e, "lattice");
@@ -532,7 +594,7 @@ extern "C" int fd_fuse_directions_batched(const fd_scene* scenes, int32_t n_scen
   if (ctx->profiling) {
     // stage timing: the same kernels launched directly, with events between
     // the stages (a graph would hold no event records)
-    r = record_batch(ctx, params, n_scenes, total, blk_off.data(), st);
+    r = record_batch(ctx, params, n_scenes, total, blk_off.data(), tile_off[n_scenes], st);
     if (r) return r;
     tb.stop();
     return FD_OK;
@@ -550,7 +612,8 @@ extern "C" int fd_fuse_directions_batched(const fd_scene* scenes, int32_t n_scen
     }
     e = hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess) return hip_error(e, "hipStreamBeginCapture");
-    r = record_batch(ctx, params, n_scenes, total, blk_off.data(), ctx->cap_stream);
+    r = record_batch(ctx, params, n_scenes, total, blk_off.data(), tile_off[n_scenes],
+                     ctx->cap_stream);
     hipGraph_t g = nullptr;
     e = hipStreamEndCapture(ctx->cap_stream, &g);
     if (r) {
@@ -647,7 +710,7 @@ extern "C" int fd_autotune(fd_context* ctx, const fd_scene* sample, int32_t n_sc
   hipStream_t st = (hipStream_t)params->stream;
   const int full = persistent_grid(params->map_dtype, params->patch, 0);
   const int chunks[] = {1, 2, 4, 8};
-  const int grids[] = {full / 2, (3 * full) / 4, full};
+  const int grids[] = {-1, full / 2, (3 * full) / 4, full};  // -1: one wave per tile
   float best = INFINITY;
   int best_chunk = 2, best_grid = full;
   hipEvent_t a, b;
@@ -655,7 +718,7 @@ extern "C" int fd_autotune(fd_context* ctx, const fd_scene* sample, int32_t n_sc
     return set_error(FD_E_HIP, "%s: event creation failed", fn);
   for (int ci : chunks) {
     for (int gi : grids) {
-      if (gi < 1) continue;
+      if (gi == 0 || (gi < 0 && ci != chunks[0])) continue;  // the tile grid has no chunk
       ctx->tuned_chunk = ci;
       ctx->tuned_grid = gi;
       if ((r = fd_fuse_directions_batched(sample, n_scenes, params, ctx))) goto done;  // capture
@@ -684,5 +747,12 @@ done:
     cache.push_back({key, best_chunk, best_grid});
     save_cache(cache_path, cache);
   }
+  return FD_OK;
+}
+
+extern "C" int fd_tuned_shape(const fd_context* ctx, int32_t* chunk, int32_t* grid) {
+  if (!ctx || !chunk || !grid) return set_error(FD_E_INVAL, "fd_tuned_shape: null argument");
+  *chunk = ctx->tuned_chunk > 0 ? ctx->tuned_chunk : 2;
+  *grid = ctx->tuned_grid;
   return FD_OK;
 }

@@ -37,6 +37,54 @@ struct SceneDev {
   float vis_tau;        // visibility tolerance on |Z - D|
 };
 
+// A scene record read from device memory (the batched scene table) would
+// hold generic pointers, which the compiler addresses with flat
+// instructions.  The table is read through this layout-identical view whose
+// pointers are in the global address space, so everything derived from them
+// uses global loads and stores (the table only ever holds device-memory
+// pointers).
+#define FD_GLOBAL __attribute__((address_space(1)))
+struct SceneDevGlobal {
+  const FD_GLOBAL float* pts;
+  const FD_GLOBAL float* cams;
+  const FD_GLOBAL void* theta;
+  const FD_GLOBAL void* conf;
+  FD_GLOBAL float* dirs;
+  FD_GLOBAL float* costs;
+  const FD_GLOBAL uint32_t* perm;
+  FD_GLOBAL uint16_t* views;
+  FD_GLOBAL uint8_t* kcount;
+  const FD_GLOBAL void* depth;
+  int64_t n;
+  int V, W, H;
+  float hc[3];
+  float vis_tau;
+};
+static_assert(sizeof(SceneDevGlobal) == sizeof(SceneDev), "scene record views differ");
+
+__device__ __forceinline__ SceneDev load_scene(const SceneDev* tab, int s) {
+  const SceneDevGlobal& g = reinterpret_cast<const SceneDevGlobal*>(tab)[s];
+  SceneDev d;
+  d.pts = (const float*)g.pts;
+  d.cams = (const float*)g.cams;
+  d.theta = (const void*)g.theta;
+  d.conf = (const void*)g.conf;
+  d.dirs = (float*)g.dirs;
+  d.costs = (float*)g.costs;
+  d.perm = (const uint32_t*)g.perm;
+  d.views = (uint16_t*)g.views;
+  d.kcount = (uint8_t*)g.kcount;
+  d.depth = g.depth ? (const void*)g.depth : nullptr;
+  d.n = g.n;
+  d.V = g.V;
+  d.W = g.W;
+  d.H = g.H;
+  for (int k = 0; k < 3; ++k) d.hc[k] = g.hc[k];
+  d.vis_tau = g.vis_tau;
+  return d;
+}
+#undef FD_GLOBAL
+
 struct SearchDev {
   const float* lattice;  // n_candidates x 3
   int n_candidates;
@@ -53,7 +101,7 @@ struct LearnedDev {
   float step0;
   float tau;
   uint32_t* fb_list;       // processing-order indices that fall back
-  uint32_t* fb_count;      // 1 counter
+  uint32_t* fb_count;      // [0] fallback list length, [1] points searched in place
 };
 
 hipError_t launch_tiling(const float* pts, int64_t n, TileWork w, hipStream_t st);

@@ -52,7 +52,7 @@ static hipError_t launch_features_rows(const SceneDev& s, int dtype, float z_nea
 int fd::run_learned(fd_context* c, const SceneDev& s, const SearchDev& q, const fd_params* p,
                     hipStream_t st) {
   hipError_t e;
-  if ((e = launch_fill_u32(c->fb_count, 1, 0u, st)) != hipSuccess)
+  if ((e = launch_fill_u32(c->fb_count, 2, 0u, st)) != hipSuccess)
     return hip_error(e, "fallback counter reset");
   LearnedDev l;
   l.iters = p->learned_iters;
@@ -113,12 +113,26 @@ int fd::run_learned(fd_context* c, const SceneDev& s, const SearchDev& q, const 
 
 extern "C" int fd_last_fallback_count(fd_context* c, void* stream, int64_t* out) {
   if (!c || !out) return set_error(FD_E_INVAL, "fd_last_fallback_count: null argument");
-  uint32_t v = 0;
+  uint32_t v[2] = {0, 0};
   hipStream_t st = (hipStream_t)stream;
-  hipError_t e = hipMemcpyAsync(&v, c->fb_count, 4, hipMemcpyDeviceToHost, st);
+  hipError_t e = hipMemcpyAsync(v, c->fb_count, sizeof v, hipMemcpyDeviceToHost, st);
   if (e == hipSuccess) e = hipStreamSynchronize(st);
   if (e != hipSuccess) return hip_error(e, "fd_last_fallback_count");
-  *out = v;
+  *out = (int64_t)v[0] + (int64_t)v[1];  // listed + searched in place
+  return FD_OK;
+}
+
+extern "C" int fd_last_fallback_split(fd_context* c, void* stream, int64_t* listed,
+                                      int64_t* in_place) {
+  if (!c || !listed || !in_place)
+    return set_error(FD_E_INVAL, "fd_last_fallback_split: null argument");
+  uint32_t v[2] = {0, 0};
+  hipStream_t st = (hipStream_t)stream;
+  hipError_t e = hipMemcpyAsync(v, c->fb_count, sizeof v, hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return hip_error(e, "fd_last_fallback_split");
+  *listed = v[0];
+  *in_place = v[1];
   return FD_OK;
 }
 

@@ -290,6 +290,31 @@ __device__ __forceinline__ void write_result(const SceneDev& s, uint32_t i, floa
 }
 
 // ---- plain search of one point per lane group ---------------------------------
+// Eq. (12) lattice argmin of J (= argmax of the view sum, first of equals),
+// then the pattern-search refinement, on the group's patch registers.
+// Returns the direction in (dx, dy, dz) and the view sum in S.
+template <int P, int KT>
+__device__ __forceinline__ void full_search(const ViewPatch<P>& vp, const SearchDev& q,
+                                            const Group& gr, float& dx, float& dy, float& dz,
+                                            float& S) {
+  float Sb = -INFINITY;
+  int kb = 0;
+#pragma unroll 2
+  for (int k = 0; k < q.n_candidates; ++k) {
+    const float cx = q.lattice[3 * k], cy = q.lattice[3 * k + 1], cz = q.lattice[3 * k + 2];
+    const float Sk = group_sum_t<KT>(eval_view<P>(vp, cx, cy, cz), gr.base, gr.K);
+    if (Sk > Sb) {
+      Sb = Sk;
+      kb = k;
+    }
+  }
+  dx = q.lattice[3 * kb];
+  dy = q.lattice[3 * kb + 1];
+  dz = q.lattice[3 * kb + 2];
+  refine<P, KT>(vp, gr, q.refine_iters, q.step0, dx, dy, dz, Sb);
+  S = Sb;
+}
+
 // The K lanes of the caller's group fuse processing-order point j of scene s
 // (pt_ok false: the group has no point but still takes part in the shuffles).
 template <typename T, int P, int KT>
@@ -304,34 +329,26 @@ __device__ __forceinline__ void fuse_group(const SceneDev& s, const SearchDev& q
   ViewPatch<P> vp;
   build_patch<T, P>(s, q, view, slot_ok, px, py, pz, vp);
   const float kinv = keff > 0 ? 1.0f / (float)keff : 0.0f;
-
-  // Eq. (12): lattice argmin of J = argmax of the view sum (first of equals)
-  float Sb = -INFINITY;
-  int kb = 0;
-#pragma unroll 2
-  for (int k = 0; k < q.n_candidates; ++k) {
-    const float dx = q.lattice[3 * k], dy = q.lattice[3 * k + 1], dz = q.lattice[3 * k + 2];
-    const float S = group_sum_t<KT>(eval_view<P>(vp, dx, dy, dz), gr.base, gr.K);
-    if (S > Sb) {
-      Sb = S;
-      kb = k;
-    }
-  }
-  float dx = q.lattice[3 * kb], dy = q.lattice[3 * kb + 1], dz = q.lattice[3 * kb + 2];
-  refine<P, KT>(vp, gr, q.refine_iters, q.step0, dx, dy, dz, Sb);
+  float dx, dy, dz, S;
+  full_search<P, KT>(vp, q, gr, dx, dy, dz, S);
   if (pt_ok && gr.slot == 0) {
     if (keff == 0)
       write_result(s, i, 0.0f, 0.0f, 0.0f, INFINITY);
     else
-      write_result(s, i, dx, dy, dz, 1.0f - Sb * kinv);
+      write_result(s, i, dx, dy, dz, 1.0f - S * kinv);
   }
 }
 
-// ---- learned form: refinement from a proposal, threshold, compaction ------------
+// ---- learned form: refinement from a proposal, threshold, fallback -------------
 // prop: proposals (x, y, z); row prop_base + j when prop_by_j, else the point
 // index i; NULL = every proposal invalid.  A point is kept when its proposal
 // is a finite non-zero direction and the refined cost satisfies J <= tau;
-// otherwise list_base + j is appended to the fallback list (plain search).
+// otherwise it takes the plain search.  A wave in which at least half of its
+// points need the plain search runs it at once on the patch registers it
+// already holds (l.fb_count[1] counts those points); otherwise the points
+// that need it are appended as list_base + j to the fallback list
+// (l.fb_count[0] entries) for a later plain-search launch.  Either way a
+// point's result is the plain search's.
 template <typename T, int P, int KT>
 __device__ __forceinline__ void learned_group(const SceneDev& s, const SearchDev& q,
                                               const LearnedDev& l, const Group& gr, bool pt_ok,
@@ -362,13 +379,26 @@ __device__ __forceinline__ void learned_group(const SceneDev& s, const SearchDev
   float S = group_sum_t<KT>(eval_view<P>(vp, dx, dy, dz), gr.base, gr.K);
   refine<P, KT>(vp, gr, l.iters, l.step0, dx, dy, dz, S);
   const float J = 1.0f - S * kinv;
-  if (pt_ok && gr.slot == 0) {
-    if (valid && J <= l.tau) {
-      write_result(s, i, dx, dy, dz, J);
-    } else {
-      const uint32_t pos = atomicAdd(l.fb_count, 1u);
-      l.fb_list[pos] = (uint32_t)(list_base + j);
+  const bool keep = valid && J <= l.tau;
+  const bool lead = pt_ok && gr.slot == 0;
+  if (lead && keep) write_result(s, i, dx, dy, dz, J);
+  // the same decision in every lane of the wave
+  const int n_pts = __popcll(__ballot(lead));
+  const int n_need = __popcll(__ballot(lead && !keep));
+  if (n_need == 0) return;
+  if (2 * n_need >= n_pts) {
+    float fx, fy, fz, fS;
+    full_search<P, KT>(vp, q, gr, fx, fy, fz, fS);
+    if (lead && !keep) {
+      if (keff == 0)
+        write_result(s, i, 0.0f, 0.0f, 0.0f, INFINITY);
+      else
+        write_result(s, i, fx, fy, fz, 1.0f - fS * kinv);
     }
+    if ((threadIdx.x & (kWave - 1)) == 0) atomicAdd(&l.fb_count[1], (uint32_t)n_need);
+  } else if (lead && !keep) {
+    const uint32_t pos = atomicAdd(&l.fb_count[0], 1u);
+    l.fb_list[pos] = (uint32_t)(list_base + j);
   }
 }
 

@@ -26,11 +26,12 @@ FD_FEATURE_DIM = 112
 
 EXPORTS = (
     "fd_params_init", "fd_context_create", "fd_context_reserve", "fd_context_destroy",
-    "fd_fuse_directions", "fd_last_fallback_count", "fd_fuse_directions_batched",
+    "fd_fuse_directions", "fd_last_fallback_count", "fd_last_fallback_split",
+    "fd_fuse_directions_batched",
     "fd_mlp_create", "fd_mlp_set_params", "fd_mlp_get_params", "fd_mlp_set_calibration",
     "fd_mlp_get_calibration", "fd_mlp_save", "fd_mlp_load", "fd_mlp_forward",
     "fd_mlp_loss_grad", "fd_mlp_train_step", "fd_mlp_destroy", "fd_features", "fd_autotune",
-    "fd_profile_enable", "fd_profile_read", "fd_last_error",
+    "fd_tuned_shape", "fd_profile_enable", "fd_profile_read", "fd_last_error",
 )
 
 FD_STAGE_TILING, FD_STAGE_TOPK, FD_STAGE_FUSE, FD_STAGE_FEATURES, FD_STAGE_MLP, \
@@ -98,6 +99,7 @@ def lib():
         "fd_context_destroy": (None, [P]),
         "fd_fuse_directions": (ctypes.c_int, [P, i64, P, i32, P, P, pp, P, P]),
         "fd_last_fallback_count": (ctypes.c_int, [P, P, ctypes.POINTER(i64)]),
+        "fd_last_fallback_split": (ctypes.c_int, [P, P, ctypes.POINTER(i64), ctypes.POINTER(i64)]),
         "fd_fuse_directions_batched": (ctypes.c_int, [ctypes.POINTER(Scene), i32, pp, P]),
         "fd_mlp_create": (ctypes.c_int, [ctypes.POINTER(P), u64]),
         "fd_mlp_set_params": (ctypes.c_int, [P, P]),
@@ -112,6 +114,7 @@ def lib():
         "fd_mlp_destroy": (None, [P]),
         "fd_features": (ctypes.c_int, [P, i64, P, i32, P, P, pp, P]),
         "fd_autotune": (ctypes.c_int, [P, ctypes.POINTER(Scene), i32, pp, ctypes.c_char_p]),
+        "fd_tuned_shape": (ctypes.c_int, [P, ctypes.POINTER(i32), ctypes.POINTER(i32)]),
         "fd_profile_enable": (ctypes.c_int, [P, ctypes.c_int]),
         "fd_profile_read": (ctypes.c_int, [P, ctypes.c_int, ctypes.POINTER(ctypes.c_double),
                                            ctypes.POINTER(i64)]),
@@ -170,6 +173,19 @@ class Context:
         _check(lib().fd_last_fallback_count(self.handle, _stream_handle(stream),
                                             ctypes.byref(out)))
         return int(out.value)
+
+    def fallback_split(self, stream=None):
+        """(listed, in place) full searches of the last learned call."""
+        a, b = ctypes.c_int64(), ctypes.c_int64()
+        _check(lib().fd_last_fallback_split(self.handle, _stream_handle(stream),
+                                            ctypes.byref(a), ctypes.byref(b)))
+        return int(a.value), int(b.value)
+
+    def tuned(self):
+        """(chunk, grid) of the batched search (fd_tuned_shape)."""
+        c, g = ctypes.c_int32(), ctypes.c_int32()
+        _check(lib().fd_tuned_shape(self.handle, ctypes.byref(c), ctypes.byref(g)))
+        return c.value, g.value
 
     def profile(self, on=True):
         _check(lib().fd_profile_enable(self.handle, int(bool(on))))

@@ -126,7 +126,7 @@ def test_autotuned_shapes_do_not_change_results():
         cache = json.loads(txt)
         assert len(cache) == 1
         (key, val), = cache.items()
-        assert val["chunk"] >= 1 and val["grid"] >= 1
+        assert val["chunk"] >= 1 and (val["grid"] >= 1 or val["grid"] == -1)
         ctx2 = nat.Context(max_points=total, max_scenes=len(scenes))
         nat.autotune(devs, ctx2, cache_path=path, **KW)   # read from the cache
         nat.fuse_batched(devs, ctx2, **KW)

@@ -269,13 +269,16 @@ def test_given_proposal_parity_with_oracle(tau, depth):
                                **extra, **KW)
     torch.cuda.synchronize()
     n_fb = ctx.fallback_count()
+    listed, in_place = ctx.fallback_split()
+    assert listed + in_place == n_fb
     d = d.cpu().numpy()
     c = c.cpu().numpy()
     orc = oracle.Oracle(sc.cams, sc.theta, sc.conf, depth=sc.depth if depth else None, **KW)
     do, co, fb = orc.fuse_learned(sc.points, prop32.astype(np.float64), 2, step0, tau)
     res = compare(orc, sc.points, d, c, do, co)
     print("learned tau", tau, "depth", depth, {k: v for k, v in res.items() if not k.endswith("_idx")},
-          "fallbacks gpu", n_fb, "oracle", int(fb.sum()), flush=True)
+          "fallbacks gpu", n_fb, f"({listed} listed, {in_place} in place)", "oracle",
+          int(fb.sum()), flush=True)
     assert_parity(res, max_fail_frac=5e-3)
     # the fallback decision is a threshold on a float cost: equal up to the
     # points whose refined cost lies within rounding of tau
