@@ -48,10 +48,12 @@ def log(*a):
 _SEARCH_SOURCES = ["fd_search.hpp", "fd_fuse.hip", "fd_device.hpp", "fd_kernels.hpp"]
 _BATCHED_SOURCES = _SEARCH_SOURCES + ["fd_batched.hip"]
 TRAFFIC = {
-    "k_fuse, realistic 500k": {"read": 374.60e6, "write": 37.66e6, "files": _SEARCH_SOURCES,
-                               "src": "39e8c75206e119fe"},
-    "k_fuse, metric workload, per head": {"read": 289.8e6, "write": 19.1e6,
-                                          "files": _SEARCH_SOURCES, "src": "39e8c75206e119fe"},
+    "k_fuse, realistic 500k": {"read": 374.5e6, "write": 37.7e6, "files": _SEARCH_SOURCES,
+                               "src": "aa1735ce806007a0"},
+    "k_fuse, metric workload, per head": {"read": 291.4e6, "write": 19.1e6,
+                                          "files": _SEARCH_SOURCES, "src": "aa1735ce806007a0"},
+    "k_b_learned, metric workload": {"read": 2073.7e6, "write": 160.5e6,
+                                     "files": _BATCHED_SOURCES, "src": "51657d3af78c11f8"},
 }
 
 
@@ -82,7 +84,9 @@ def plain_flop_per_point(patch, n_cand, iters, top_k):
 
 
 def cpu_baseline(sc, kw, seconds, depth=True):
-    """The oracle, untuned, on a bounded stride sample of the same scene."""
+    """The oracle, untuned, on a bounded sample of the same scene: points in
+    stride order (stride 7919, modulo N, wrapping around) until `seconds`
+    have passed."""
     import numpy as np
     import oracle
     threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or (os.cpu_count() or 1)
@@ -93,15 +97,13 @@ def cpu_baseline(sc, kw, seconds, depth=True):
     stride = 7919
     done = 0
     t0 = time.perf_counter()
-    start = 0
-    while time.perf_counter() - t0 < seconds and done < n:
-        idx = (np.arange(start, start + chunk) * stride) % n
+    while time.perf_counter() - t0 < seconds:
+        idx = (np.arange(done, done + chunk) * stride) % n
         orc.fuse(sc.points[idx], n_threads=threads)
         done += chunk
-        start += chunk
     el = time.perf_counter() - t0
     return {"value": done / el, "unit": "points/s", "cores": threads, "kind": "oracle",
-            "sample": f"{done} points (stride {stride} mod N) of the same scene, "
+            "sample": f"{done} points of the same scene ({n} points; stride {stride} modulo N), "
                       f"{el:.1f} s, binary64 oracle, OpenMP over points"}
 
 

@@ -209,9 +209,14 @@ __global__ __launch_bounds__(kBlock) void k_b_fuse(BatchDev b, SearchDev q, cons
   const Group gr = make_group(q.K);
   const int64_t n_items = LIST ? (int64_t)*list_count : b.total;
   const int64_t n_tiles = LIST ? (n_items + gr.G - 1) / gr.G : b.n_tiles;
+  if (n_tiles <= 0) return;  // uniform: nothing to search
   const int home = (int)(blockIdx.x % kQueues);
   for (int r = 0; r < kQueues; ++r) {
     const int qi = (home + r) % kQueues;
+    // a plain read first: an exhausted queue is passed without an atomic
+    if (queue_tile(qi, (int64_t)__builtin_amdgcn_readfirstlane(
+                           __atomic_load_n(&queue[qi], __ATOMIC_RELAXED))) >= n_tiles)
+      continue;
     for (;;) {
       uint32_t v0 = 0;
       if ((threadIdx.x & 63) == 0) v0 = atomicAdd(&queue[qi], (uint32_t)chunk);
