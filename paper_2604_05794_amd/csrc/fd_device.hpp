@@ -12,27 +12,9 @@ namespace fd {
 
 constexpr int kWave = 64;
 
-// Texel of one map as float; outside the image reads 0 (zero border).
-template <typename T>
-__device__ __forceinline__ float tex_load(const T* __restrict__ m, int W, int H,
-                                          int x, int y);
-
-template <>
-__device__ __forceinline__ float tex_load<float>(const float* __restrict__ m,
-                                                 int W, int H, int x, int y) {
-  if ((unsigned)x >= (unsigned)W || (unsigned)y >= (unsigned)H) return 0.0f;
-  return m[(size_t)y * W + x];
-}
-
-template <>
-__device__ __forceinline__ float tex_load<__half>(const __half* __restrict__ m,
-                                                  int W, int H, int x, int y) {
-  if ((unsigned)x >= (unsigned)W || (unsigned)y >= (unsigned)H) return 0.0f;
-  return __half2float(m[(size_t)y * W + x]);
-}
-
-// Same value as tex_load, but the load itself is unconditional (at a clamped
-// address), so a run of them can be issued back to back.
+// Texel (x, y) of one map as float; outside the image reads 0 (zero
+// border).  The load itself is unconditional (at a clamped address), so a
+// run of them can be issued back to back.
 template <typename T>
 __device__ __forceinline__ float tex_load_nb(const T* __restrict__ m, int W, int H, int x,
                                              int y) {
@@ -73,25 +55,6 @@ __device__ __forceinline__ bool project32(const float* __restrict__ cam,
          o.v <= (float)(H - 1);
 }
 
-// Bilinear confidence at the projection, same fixed order:
-//   x0 = floor(u), fx = u - x0, gx = 1 - fx (likewise y)
-//   w00 = gx*gy, w10 = fx*gy, w01 = gx*fy, w11 = fx*fy
-//   C = fma(w11, C11, fma(w01, C01, fma(w10, C10, w00*C00)))
-template <typename T>
-__device__ __forceinline__ float centre_conf32(const T* __restrict__ cm, int W,
-                                               int H, float u, float v) {
-  float x0 = floorf(u), y0 = floorf(v);
-  float fx = u - x0, fy = v - y0;
-  float gx = 1.0f - fx, gy = 1.0f - fy;
-  int ix = (int)x0, iy = (int)y0;
-  float c00 = tex_load_nb<T>(cm, W, H, ix, iy);
-  float c10 = tex_load_nb<T>(cm, W, H, ix + 1, iy);
-  float c01 = tex_load_nb<T>(cm, W, H, ix, iy + 1);
-  float c11 = tex_load_nb<T>(cm, W, H, ix + 1, iy + 1);
-  float w00 = gx * gy, w10 = fx * gy, w01 = gx * fy, w11 = fx * fy;
-  return __builtin_fmaf(w11, c11, __builtin_fmaf(w01, c01, __builtin_fmaf(w10, c10, w00 * c00)));
-}
-
 // Texel at a 32-bit offset from a view's base pointer (the base is the same
 // for the whole wave, so the load takes a scalar base and a vector offset).
 template <typename T>
@@ -105,43 +68,59 @@ __device__ __forceinline__ float ld_texel(const T* __restrict__ base, uint32_t o
     return *(const float*)b;
 }
 
-// Centre confidence of a projection for Eq. (4), or 0 when the view is not
-// eligible (ok false) or, with depth maps, the point is hidden in it.  Same
-// value and operation order as centre_conf32 and visible32; since an eligible
-// projection lies inside the image, only the +1 neighbours need the zero
-// border check.  cb / db: this view's confidence and depth planes (db NULL:
-// no visibility test).  *seen (optional): eligible and visible.
+// View eligibility and centre confidence for Eq. (4), split so that a caller
+// can skip the confidence loads of a view no lane of its wave sees.
+// visible_at: eligible (ok) and, with depth maps, visible (the rule of
+// visible32, nearest texel of the projection).  conf_texels + conf_combine:
+// the bilinear confidence of an eligible projection in the fixed order
+//   x0 = floor(u), fx = u - x0, gx = 1 - fx (likewise y)
+//   w00 = gx*gy, w10 = fx*gy, w01 = gx*fy, w11 = fx*fy
+//   C = fma(w11, C11, fma(w01, C01, fma(w10, C10, w00*C00)))
+// with texels outside the image read as 0; an eligible projection lies inside
+// the image, so only the +1 neighbours need that check.  Texels are read at
+// 32-bit offsets from the view's base pointer.
 template <typename T>
-__device__ __forceinline__ float eligible_conf32(const T* __restrict__ cb,
-                                                 const T* __restrict__ db, int W, int H,
-                                                 bool ok, const Proj& pr, float tau,
-                                                 bool* seen = nullptr) {
+__device__ __forceinline__ bool visible_at(const T* __restrict__ db, int W, bool ok,
+                                           const Proj& pr, float tau) {
+  if (db == nullptr) return ok;
+  const float u = ok ? pr.u : 0.0f, v = ok ? pr.v : 0.0f;
+  const uint32_t xn = (uint32_t)floorf(u + 0.5f), yn = (uint32_t)floorf(v + 0.5f);
+  const float D = ld_texel<T>(db, yn * (uint32_t)W + xn);
+  return ok && fabsf(pr.Z - D) <= tau;
+}
+
+struct ConfTexels {
+  float c00, c10, c01, c11, fx, fy;
+  bool xin, yin;
+};
+
+template <typename T>
+__device__ __forceinline__ ConfTexels conf_texels(const T* __restrict__ cb, int W, int H,
+                                                     bool ok, const Proj& pr) {
+  ConfTexels t;
   const float u = ok ? pr.u : 0.0f, v = ok ? pr.v : 0.0f;
   const float x0 = floorf(u), y0 = floorf(v);
-  const float fx = u - x0, fy = v - y0;
-  const float gx = 1.0f - fx, gy = 1.0f - fy;
+  t.fx = u - x0;
+  t.fy = v - y0;
   const uint32_t ix = (uint32_t)x0, iy = (uint32_t)y0;
   const uint32_t o00 = iy * (uint32_t)W + ix;
-  const bool xin = ix + 1u < (uint32_t)W, yin = iy + 1u < (uint32_t)H;
-  const uint32_t dx = xin ? 1u : 0u, dy = yin ? (uint32_t)W : 0u;
-  float c00 = ld_texel<T>(cb, o00);
-  float c10 = ld_texel<T>(cb, o00 + dx);
-  float c01 = ld_texel<T>(cb, o00 + dy);
-  float c11 = ld_texel<T>(cb, o00 + dx + dy);
-  bool vis = true;
-  if (db != nullptr) {
-    const uint32_t xn = (uint32_t)floorf(u + 0.5f), yn = (uint32_t)floorf(v + 0.5f);
-    const float D = ld_texel<T>(db, yn * (uint32_t)W + xn);
-    vis = fabsf(pr.Z - D) <= tau;
-  }
-  c10 = xin ? c10 : 0.0f;
-  c01 = yin ? c01 : 0.0f;
-  c11 = (xin && yin) ? c11 : 0.0f;
-  const float w00 = gx * gy, w10 = fx * gy, w01 = gx * fy, w11 = fx * fy;
-  const float c =
-      __builtin_fmaf(w11, c11, __builtin_fmaf(w01, c01, __builtin_fmaf(w10, c10, w00 * c00)));
-  if (seen) *seen = ok && vis;  // eligible and visible, whatever the confidence
-  return (ok && vis) ? c : 0.0f;
+  t.xin = ix + 1u < (uint32_t)W;
+  t.yin = iy + 1u < (uint32_t)H;
+  const uint32_t dx = t.xin ? 1u : 0u, dy = t.yin ? (uint32_t)W : 0u;
+  t.c00 = ld_texel<T>(cb, o00);
+  t.c10 = ld_texel<T>(cb, o00 + dx);
+  t.c01 = ld_texel<T>(cb, o00 + dy);
+  t.c11 = ld_texel<T>(cb, o00 + dx + dy);
+  return t;
+}
+
+__device__ __forceinline__ float conf_combine(const ConfTexels& t) {
+  const float c10 = t.xin ? t.c10 : 0.0f;
+  const float c01 = t.yin ? t.c01 : 0.0f;
+  const float c11 = (t.xin && t.yin) ? t.c11 : 0.0f;
+  const float gx = 1.0f - t.fx, gy = 1.0f - t.fy;
+  const float w00 = gx * gy, w10 = t.fx * gy, w01 = gx * t.fy, w11 = t.fx * t.fy;
+  return __builtin_fmaf(w11, c11, __builtin_fmaf(w01, c01, __builtin_fmaf(w10, c10, w00 * t.c00)));
 }
 
 // Visibility of Sec. 3.1.1 (the score V_i^v), decided in binary32: the

@@ -50,15 +50,18 @@ __device__ __forceinline__ float frontal_score32(const float* cam, float px, flo
 }
 
 // Stable insertion of view v with frontal score cs into the descending list
-// (sc, id) of kSlots entries: equal scores keep the lower view index first;
-// a view that does not beat the last entry is skipped.
+// (sc, id) of kSlots entries (empty entries hold -inf): equal scores keep the
+// lower view index first; a view that does not beat the last entry is
+// skipped.  The score of an eligible view is finite (the point lies more
+// than z_near in front of the camera, so its distance to the centre is not
+// zero for any z_near > 0), so it always beats an empty entry.
 __device__ __forceinline__ void frontal_insert(float (&sc)[kSlots], int (&id)[kSlots], float cs,
                                                int cv) {
-  if (!(cs > sc[kSlots - 1]) && id[kSlots - 1] >= 0) return;
+  if (!(cs > sc[kSlots - 1])) return;
   bool ins = false;
 #pragma unroll
   for (int k = 0; k < kSlots; ++k) {
-    const bool take = ins || (cs > sc[k]) || (!ins && id[k] < 0);
+    const bool take = ins || (cs > sc[k]);
     const float ts = sc[k];
     const int tv = id[k];
     sc[k] = take ? cs : ts;
@@ -218,16 +221,36 @@ __device__ __forceinline__ void topk_features_point(const SceneDev& s, const Sea
   const T* conf = (const T*)s.conf;
   const T* depth = (const T*)s.depth;
   const size_t plane = (size_t)s.W * s.H;
-  for (int v = 0; v < s.V; ++v) {
-    Proj pr;
-    const bool ok = project32(s.cams + 16 * v, px, py, pz, s.W, s.H, q.z_near, pr);
-    bool seen;
-    const float c = eligible_conf32<T>(conf + plane * v, depth ? depth + plane * v : nullptr,
-                                       s.W, s.H, ok, pr, s.vis_tau, &seen);
-    if (c > 0.0f) topk_insert<KS>(ck, vk, c, v);
-    // frontal slots: eligible and visible views, whatever their confidence
-    if (seen)
-      frontal_insert(sc, id, frontal_score32(s.cams + 16 * v, px, py, pz, s.hc, nullptr), v);
+  // views in groups of four, as in topk_point: a view no lane of the wave
+  // sees skips its confidence texels and both insertions
+  constexpr int kGroup = 4;
+  for (int v0 = 0; v0 < s.V; v0 += kGroup) {
+    Proj pr[kGroup];
+    bool seen[kGroup];
+#pragma unroll
+    for (int u = 0; u < kGroup; ++u) {
+      const int v = min(v0 + u, s.V - 1);
+      const bool ok = project32(s.cams + 16 * v, px, py, pz, s.W, s.H, q.z_near, pr[u]);
+      seen[u] = visible_at<T>(depth ? depth + plane * v : nullptr, s.W, ok, pr[u], s.vis_tau) &&
+                v0 + u < s.V;
+    }
+    ConfTexels tx[kGroup];
+    bool any[kGroup];
+#pragma unroll
+    for (int u = 0; u < kGroup; ++u) {
+      any[u] = __ballot(seen[u]) != 0;  // wave-uniform
+      if (any[u]) tx[u] = conf_texels<T>(conf + plane * (v0 + u), s.W, s.H, seen[u], pr[u]);
+    }
+#pragma unroll
+    for (int u = 0; u < kGroup; ++u) {
+      if (!any[u]) continue;
+      const int v = v0 + u;
+      const float c = seen[u] ? conf_combine(tx[u]) : 0.0f;
+      if (c > 0.0f) topk_insert<KS>(ck, vk, c, v);
+      // frontal slots: eligible and visible views, whatever their confidence
+      if (seen[u])
+        frontal_insert(sc, id, frontal_score32(s.cams + 16 * v, px, py, pz, s.hc, nullptr), v);
+    }
   }
   int keff = 0;
 #pragma unroll

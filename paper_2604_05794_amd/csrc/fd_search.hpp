@@ -55,23 +55,35 @@ __device__ __forceinline__ void topk_point(const SceneDev& s, const SearchDev& q
   const T* conf = (const T*)s.conf;
   const T* depth = (const T*)s.depth;
   const size_t plane = (size_t)s.W * s.H;
-  // views in groups of four: projections and the texel loads of a group
-  // are independent, so they are issued before the (ordered) insertions
+  // Views in groups of four.  Projections and depth texels of a group are
+  // issued together; a view that no lane of the wave sees (all hidden, behind
+  // or outside, common for the far side of a head) skips its confidence
+  // texels and insertion.  The confidence loads of the seen views are issued
+  // before any of them is used.
   constexpr int kGroup = 4;
   for (int v0 = 0; v0 < s.V; v0 += kGroup) {
-    float cg[kGroup];
+    Proj pr[kGroup];
+    bool seen[kGroup];
 #pragma unroll
     for (int u = 0; u < kGroup; ++u) {
       const int v = min(v0 + u, s.V - 1);
-      Proj pr;
-      const bool ok = project32(s.cams + 16 * v, px, py, pz, s.W, s.H, q.z_near, pr);
-      const float c = eligible_conf32<T>(conf + plane * v, depth ? depth + plane * v : nullptr,
-                                         s.W, s.H, ok, pr, s.vis_tau);
-      cg[u] = (v0 + u < s.V) ? c : 0.0f;
+      const bool ok = project32(s.cams + 16 * v, px, py, pz, s.W, s.H, q.z_near, pr[u]);
+      seen[u] = visible_at<T>(depth ? depth + plane * v : nullptr, s.W, ok, pr[u], s.vis_tau) &&
+                v0 + u < s.V;
+    }
+    ConfTexels tx[kGroup];
+    bool any[kGroup];
+#pragma unroll
+    for (int u = 0; u < kGroup; ++u) {
+      any[u] = __ballot(seen[u]) != 0;  // wave-uniform
+      if (any[u]) tx[u] = conf_texels<T>(conf + plane * (v0 + u), s.W, s.H, seen[u], pr[u]);
     }
 #pragma unroll
-    for (int u = 0; u < kGroup; ++u)
-      if (cg[u] > 0.0f) topk_insert<KS>(sc, id, cg[u], v0 + u);
+    for (int u = 0; u < kGroup; ++u) {
+      if (!any[u]) continue;
+      const float c = seen[u] ? conf_combine(tx[u]) : 0.0f;
+      if (c > 0.0f) topk_insert<KS>(sc, id, c, v0 + u);
+    }
   }
   int keff = 0;
 #pragma unroll
