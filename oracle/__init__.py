@@ -75,6 +75,9 @@ def lib():
             "fdo_fuse_learned": (i32, [P, i64, P, i32, P, P, pp, P, i32, dbl, dbl,
                                        P, P, P, i32]),
             "fdo_features": (i32, [P, i64, P, i32, P, P, pp, P, i32, P, i32]),
+            "fdo_fpmvo": (i32, [P, i64, P, i32, P, P, pp, dbl, i32, dbl, P, P, i32]),
+            "fdo_fpmvo_trace": (i32, [P, P, i32, P, P, pp, dbl, i32, dbl, P, P, P, P, P, P,
+                                      P, P, P, P]),
             "fdo_mlp_n_params": (i64, []),
             "fdo_mlp_forward": (i32, [P, P, i32, i32, P]),
             "fdo_mlp_loss_grad": (dbl, [P, P, P, i32, i32, P]),
@@ -213,6 +216,48 @@ class Oracle:
                                int(learned_iters), float(learned_step0), float(tau),
                                _ptr(dirs), _ptr(costs), _ptr(fb), int(n_threads))
         return dirs, costs, fb
+
+    def fpmvo(self, points, lam=1.0, n_samples=5, delta=5e-3, n_threads=0):
+        """Paper-literal candidates and medoid fusion (needs depth maps):
+        (dirs (N,3), costs (N,))."""
+        if self.depth is None:
+            raise ValueError("fpmvo needs depth maps")
+        pts = _c(points, np.float32).reshape(-1, 3)
+        n = len(pts)
+        d = np.zeros((n, 3))
+        c = np.zeros(n)
+        r = lib().fdo_fpmvo(_ptr(pts), n, _ptr(self.cams), self.V, _ptr(self.theta),
+                            _ptr(self.conf), ctypes.byref(self.prm), float(lam),
+                            int(n_samples), float(delta), _ptr(d), _ptr(c), int(n_threads))
+        if r != 0:
+            raise ValueError("fdo_fpmvo rejected its arguments")
+        return d, c
+
+    def fpmvo_trace(self, p, lam=1.0, n_samples=5, delta=5e-3):
+        if self.depth is None:
+            raise ValueError("fpmvo needs depth maps")
+        p = _c(p, np.float32)
+        S = int(n_samples)
+        views = np.zeros(16, np.int32)
+        cand = np.zeros((16, S, 3))
+        ok = np.zeros((16, S), np.int32)
+        w = np.zeros(16)
+        medoid = np.zeros(S, np.int32)
+        fused = np.zeros((S, 3))
+        J = np.zeros(S)
+        sb = np.zeros(1, np.int32)
+        d = np.zeros(3)
+        cost = np.zeros(1)
+        k = lib().fdo_fpmvo_trace(_ptr(p), _ptr(self.cams), self.V, _ptr(self.theta),
+                                  _ptr(self.conf), ctypes.byref(self.prm), float(lam), S,
+                                  float(delta), _ptr(views), _ptr(cand), _ptr(ok), _ptr(w),
+                                  _ptr(medoid), _ptr(fused), _ptr(J), _ptr(sb), _ptr(d),
+                                  _ptr(cost))
+        if k < 0:
+            raise ValueError("fdo_fpmvo_trace rejected its arguments")
+        return dict(views=views[:k].copy(), cand=cand[:k].copy(), ok=ok[:k].astype(bool),
+                    w=w[:k].copy(), medoid=medoid.copy(), fused=fused, J=J, s_best=int(sb[0]),
+                    dir=d, cost=float(cost[0]))
 
     def features(self, points, head_centre, n_slots=16, n_threads=0):
         pts = _c(points, np.float32).reshape(-1, 3)

@@ -21,6 +21,7 @@
 
 #define FDO_MAX_K 16
 #define FDO_MAX_P 7
+#define FDO_MAX_S 16
 #define FDO_PI 3.14159265358979323846
 
 /* ------------------------------------------------------------------------ */
@@ -205,6 +206,7 @@ void fdo_sample(const void* theta_map, const void* conf_map, int32_t dtype,
 typedef struct {
   int k_eff;
   int views[FDO_MAX_K];
+  double u[FDO_MAX_K][2];    /* binary32 projection of Eq. (4), as double */
   double Xc[FDO_MAX_K][3];   /* camera-space point, binary64 */
   double R[FDO_MAX_K][9];
   double f[FDO_MAX_K][2];
@@ -227,6 +229,8 @@ static void point_setup(const float* p, const float* cams, int n_views,
   st->n_samp = P * P;
   for (int k = 0; k < st->k_eff; ++k) {
     const float* cam = cams + 16 * st->views[k];
+    st->u[k][0] = u[2 * k];
+    st->u[k][1] = u[2 * k + 1];
     for (int i = 0; i < 9; ++i) st->R[k][i] = cam[4 + i];
     st->f[k][0] = cam[0];
     st->f[k][1] = cam[1];
@@ -701,4 +705,172 @@ int fdo_features(const float* points, int64_t n_points, const float* cams,
     }
   }
   return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Paper-literal candidates: multi-view direction sampling (Sec. 3.1.1,
+ * Eqs. 1-3) and medoid-based direction fusion (Sec. 3.1.2, Eqs. 4-7), scored
+ * by the patch consistency of Eqs. 8-12 (the objective above).
+ *
+ * For each view v of Eq. (4) (the visibility test needs prm->depth_maps):
+ *   O_v(u)   unit image orientation (cos t, sin t), t the bilinear
+ *            confidence-weighted doubled-angle mean at the projection u
+ *            (the patch's centre sample); none -> the view gives no
+ *            candidates
+ *   Eq. (1)  u' = u + lambda O_v(u)               (pixels)
+ *   Eq. (2)  z = D_v(nearest texel of u'), z_s = z + delta_s,
+ *            delta_s = -Delta + 2 Delta (s - 1)/(S - 1)  (0 when S = 1);
+ *            u' outside the image or z not finite -> no candidates
+ *   Eq. (3)  p_s = R^T (((u'_x - c_x) z_s / f_x, (u'_y - c_y) z_s / f_y, z_s) - t)
+ *   d_{v,s}  = (p_s - p) / |p_s - p|   (unit; none when z_s <= 0 or p_s = p)
+ * Eqs. (5)-(7), per depth layer s over the views that gave a candidate:
+ *   sigma_i = sum_j w_j |<d_i, d_j>| / sum_j w_j,  w_j = bilinear centre
+ *   confidence of view j; the fused candidate is the d_i of largest sigma_i
+ *   (first of equals in the order of Eq. (4)).
+ * Eq. (12): the fused candidate of lowest J (first of equals); no
+ * refinement.  No candidate in any layer -> direction 0, cost +inf. */
+
+typedef struct {
+  double cand[FDO_MAX_K][FDO_MAX_S][3];
+  int ok[FDO_MAX_K][FDO_MAX_S];
+  double w[FDO_MAX_K];
+  int medoid[FDO_MAX_S];     /* view slot of the fused candidate, -1 = empty */
+  double fused[FDO_MAX_S][3];
+  double J[FDO_MAX_S];
+  int s_best;
+} fpmvo_trace;
+
+static void fpmvo_point(const point_state* st, const float* p, const float* cams,
+                        const fdo_params* prm, double lambda, int S, double delta,
+                        double* dir, double* cost, fpmvo_trace* tr) {
+  const int W = prm->width, H = prm->height, dt = prm->map_dtype;
+  const int P = prm->patch, h = (P - 1) / 2, centre = h * P + h;
+  const int K = st->k_eff;
+  for (int k = 0; k < K; ++k) {
+    tr->w[k] = st->cbar[k][centre];
+    for (int s = 0; s < S; ++s) tr->ok[k][s] = 0;
+    if (!st->valid[k][centre]) continue;
+    const double t = st->tbar[k][centre];
+    const double ux = st->u[k][0] + lambda * cos(t), uy = st->u[k][1] + lambda * sin(t);
+    if (!(ux >= 0.0 && ux <= W - 1 && uy >= 0.0 && uy <= H - 1)) continue;
+    const int ix = (int)floor(ux + 0.5), iy = (int)floor(uy + 0.5);
+    const double z =
+        texel(view_map(prm->depth_maps, dt, W, H, st->views[k]), dt, W, H, ix, iy);
+    if (!isfinite(z)) continue;
+    const float* cam = cams + 16 * st->views[k];
+    for (int s = 0; s < S; ++s) {
+      const double zs = z + (S > 1 ? -delta + 2.0 * delta * s / (S - 1) : 0.0);
+      if (!(zs > 0.0)) continue;
+      const double xc[3] = {(ux - cam[2]) * zs / cam[0] - cam[13],
+                            (uy - cam[3]) * zs / cam[1] - cam[14], zs - cam[15]};
+      double d[3];
+      for (int r = 0; r < 3; ++r)
+        d[r] = st->R[k][r] * xc[0] + st->R[k][3 + r] * xc[1] +
+               st->R[k][6 + r] * xc[2] - (double)p[r];
+      const double n = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+      if (!(n > 0.0)) continue;
+      for (int r = 0; r < 3; ++r) tr->cand[k][s][r] = d[r] / n;
+      tr->ok[k][s] = 1;
+    }
+  }
+  tr->s_best = -1;
+  double Jbest = INFINITY;
+  for (int s = 0; s < S; ++s) {
+    tr->medoid[s] = -1;
+    tr->J[s] = INFINITY;
+    double wsum = 0.0, best = -INFINITY;
+    for (int j = 0; j < K; ++j)
+      if (tr->ok[j][s]) wsum += tr->w[j];
+    for (int i = 0; i < K; ++i) {
+      if (!tr->ok[i][s]) continue;
+      double num = 0.0;
+      for (int j = 0; j < K; ++j)
+        if (tr->ok[j][s])
+          num += tr->w[j] * fabs(tr->cand[i][s][0] * tr->cand[j][s][0] +
+                                 tr->cand[i][s][1] * tr->cand[j][s][1] +
+                                 tr->cand[i][s][2] * tr->cand[j][s][2]);
+      const double sigma = num / wsum;
+      if (sigma > best) {
+        best = sigma;
+        tr->medoid[s] = i;
+      }
+    }
+    if (tr->medoid[s] < 0) continue;
+    for (int r = 0; r < 3; ++r) tr->fused[s][r] = tr->cand[tr->medoid[s]][s][r];
+    tr->J[s] = objective(st, tr->fused[s]);
+    if (tr->J[s] < Jbest) {
+      Jbest = tr->J[s];
+      tr->s_best = s;
+    }
+  }
+  if (tr->s_best < 0) {
+    dir[0] = dir[1] = dir[2] = 0.0;
+    *cost = INFINITY;
+    return;
+  }
+  double d[3] = {tr->fused[tr->s_best][0], tr->fused[tr->s_best][1],
+                 tr->fused[tr->s_best][2]};
+  canonical_sign(d);
+  dir[0] = d[0];
+  dir[1] = d[1];
+  dir[2] = d[2];
+  *cost = Jbest;
+}
+
+int fdo_fpmvo(const float* points, int64_t n_points, const float* cams,
+              int32_t n_views, const void* theta_maps, const void* conf_maps,
+              const fdo_params* prm, double lambda, int32_t n_samples,
+              double delta, double* dirs, double* costs, int32_t n_threads) {
+  if (!prm->depth_maps || n_samples < 1 || n_samples > FDO_MAX_S) return -1;
+#ifdef _OPENMP
+  if (n_threads > 0) omp_set_num_threads(n_threads);
+#pragma omp parallel
+#endif
+  {
+    point_state* st = (point_state*)malloc(sizeof(point_state));
+    fpmvo_trace* tr = (fpmvo_trace*)malloc(sizeof(fpmvo_trace));
+#ifdef _OPENMP
+#pragma omp for schedule(dynamic, 64)
+#endif
+    for (int64_t i = 0; i < n_points; ++i) {
+      point_setup(points + 3 * i, cams, n_views, theta_maps, conf_maps, prm, st);
+      fpmvo_point(st, points + 3 * i, cams, prm, lambda, n_samples, delta,
+                  dirs + 3 * i, costs + i, tr);
+    }
+    free(tr);
+    free(st);
+  }
+  return 0;
+}
+
+int fdo_fpmvo_trace(const float* p, const float* cams, int32_t n_views,
+                    const void* theta_maps, const void* conf_maps,
+                    const fdo_params* prm, double lambda, int32_t n_samples,
+                    double delta, int32_t* views, double* cand, int32_t* ok,
+                    double* w, int32_t* medoid, double* fused, double* J,
+                    int32_t* s_best, double* dir, double* cost) {
+  if (!prm->depth_maps || n_samples < 1 || n_samples > FDO_MAX_S) return -1;
+  point_state* st = (point_state*)malloc(sizeof(point_state));
+  fpmvo_trace* tr = (fpmvo_trace*)malloc(sizeof(fpmvo_trace));
+  point_setup(p, cams, n_views, theta_maps, conf_maps, prm, st);
+  fpmvo_point(st, p, cams, prm, lambda, n_samples, delta, dir, cost, tr);
+  const int K = st->k_eff, S = n_samples;
+  for (int k = 0; k < K; ++k) {
+    views[k] = st->views[k];
+    w[k] = tr->w[k];
+    for (int s = 0; s < S; ++s) {
+      ok[k * S + s] = tr->ok[k][s];
+      for (int r = 0; r < 3; ++r)
+        cand[(k * S + s) * 3 + r] = tr->ok[k][s] ? tr->cand[k][s][r] : 0.0;
+    }
+  }
+  for (int s = 0; s < S; ++s) {
+    medoid[s] = tr->medoid[s];
+    J[s] = tr->J[s];
+    for (int r = 0; r < 3; ++r) fused[3 * s + r] = tr->medoid[s] >= 0 ? tr->fused[s][r] : 0.0;
+  }
+  *s_best = tr->s_best;
+  free(tr);
+  free(st);
+  return K;
 }

@@ -141,6 +141,28 @@ int fdo_features(const float* points, int64_t n_points, const float* cams,
                  const float* head_centre, int32_t n_slots, double* feats,
                  int32_t n_threads);
 
+/* Paper-literal candidates (Sec. 3.1.1-3.1.2, Eqs. 1-7) scored by Eq. (12):
+ * per view of Eq. (4) S depth-layer candidates from the pixel offset
+ * lambda O_v(u) along the observed orientation and the depth map (depth
+ * samples z + delta_s across [-delta, delta]), the confidence-weighted
+ * medoid of each layer, and the layer whose fused candidate has the lowest
+ * J.  Needs prm->depth_maps; 1 <= n_samples <= 16.  Returns 0, or -1 on bad
+ * arguments.  The readings are written out in fdo.c. */
+int fdo_fpmvo(const float* points, int64_t n_points, const float* cams,
+              int32_t n_views, const void* theta_maps, const void* conf_maps,
+              const fdo_params* prm, double lambda, int32_t n_samples,
+              double delta, double* dirs, double* costs, int32_t n_threads);
+
+/* One point, traced: views[K], cand[K][S][3] and ok[K][S] (per view and
+ * layer), w[K], medoid[S] (view slot or -1), fused[S][3], J[S], s_best, and
+ * the output dir / cost.  Returns K_eff (or -1). */
+int fdo_fpmvo_trace(const float* p, const float* cams, int32_t n_views,
+                    const void* theta_maps, const void* conf_maps,
+                    const fdo_params* prm, double lambda, int32_t n_samples,
+                    double delta, int32_t* views, double* cand, int32_t* ok,
+                    double* w, int32_t* medoid, double* fused, double* J,
+                    int32_t* s_best, double* dir, double* cost);
+
 /* ---- direction-proposal MLP: 112 -> 256 -> 256 -> 256 -> 3 ---------------
  * Flat parameter order: W1[112][256], b1[256], W2[256][256], b2[256],
  * W3[256][256], b3[256], W4[256][3], b4[3]  (161283 values; y = x W + b).
