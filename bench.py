@@ -461,7 +461,31 @@ def run_plain(args):
     achieved = flop * sc.n_points / fuse_s / 1e12
     c = costs.cpu().numpy()
     fin = torch.isfinite(costs)
-    err_gt = _axial_deg(dirs[fin], torch.from_numpy(sc.gt).to(dev)[fin])
+    gt = torch.from_numpy(sc.gt).to(dev)
+    err_gt = _axial_deg(dirs[fin], gt[fin])
+    fpmvo = None
+    if dm is not None:
+        # the paper's own candidates (Eqs. 1-7) on the same scene, for comparison
+        fd = torch.empty_like(dirs)
+        fc = torch.empty_like(costs)
+
+        def step_fp():
+            native.fuse_directions(pts, cams, th, cf, dirs=fd, costs=fc, ctx=ctx, stream=stream,
+                                   depth_maps=dm, mode=native.FD_MODE_FPMVO, **kw)
+        el_f, st_f = _timed(step_fp, args, ctx, [("tiling", native.FD_STAGE_TILING),
+                                                 ("topk", native.FD_STAGE_TOPK),
+                                                 ("fuse", native.FD_STAGE_FUSE)])
+        ff = torch.isfinite(fc) & fin
+        fpmvo = {"points_per_s": sc.n_points / (el_f / args.steps),
+                 "ms_per_step": el_f * 1e3 / args.steps, "stages_ms_per_launch": st_f,
+                 "finite_frac": float(torch.isfinite(fc).float().mean()),
+                 "mean_cost": float(fc[ff].mean()), "mean_cost_plain": float(costs[ff].mean()),
+                 "err_vs_gt_deg": {"mean": float(_axial_deg(fd[ff], gt[ff]).mean()),
+                                   "median": float(_axial_deg(fd[ff], gt[ff]).median())},
+                 "mean_err_vs_plain_deg": float(_axial_deg(fd[ff], dirs[ff]).mean())}
+        log(f"fpmvo (paper candidates): {fpmvo['points_per_s'] / 1e6:.1f} M points/s, "
+            f"{json.dumps({k: round(v, 4) for k, v in st_f.items()})}, GT err median "
+            f"{fpmvo['err_vs_gt_deg']['median']:.1f} deg (plain {float(err_gt.median()):.1f})")
     log(f"steps {args.steps}: {ms_step:.3f} ms/step, {value / 1e6:.1f} M points/s; "
         f"stages (ms/launch) {json.dumps({k: round(v, 4) for k, v in stages.items()})}; "
         f"finite costs {np.isfinite(c).mean():.4f}")
@@ -483,6 +507,7 @@ def run_plain(args):
                      "frac_vs_vendor_packed": achieved / PEAK_FP32_VENDOR},
         "stages_ms_per_launch": stages,
         "err_vs_gt_deg": {"mean": float(err_gt.mean()), "median": float(err_gt.median())},
+        "fpmvo_paper_candidates": fpmvo,
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(sc, kw, args.cpu_seconds, depth=not args.no_depth)

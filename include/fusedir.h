@@ -52,7 +52,14 @@ enum {
 };
 
 enum { FD_F32 = 0, FD_F16 = 1 };
-enum { FD_MODE_PLAIN = 0, FD_MODE_LEARNED = 1 };
+/* PLAIN: lattice search + refinement of the objective.  LEARNED: network
+ * proposal, short refinement, plain search as fallback.  FPMVO: the paper's
+ * own candidates (Sec. 3.1.1-3.1.2, Eqs. 1-7: pixel offset along the observed
+ * orientation, depth layers, back-projection, per-layer confidence-weighted
+ * medoid over the top-K views) scored by the same objective (Eq. 12); needs
+ * depth_maps. */
+enum { FD_MODE_PLAIN = 0, FD_MODE_LEARNED = 1, FD_MODE_FPMVO = 2 };
+#define FD_MAX_FPMVO_SAMPLES 16
 /* Source of the learned form's starting direction.  Only FD_PROPOSAL_MLP
  * uses the network; the others replace it for testing (GIVEN reads
  * params->proposal_dirs, NAN makes every proposal invalid). */
@@ -86,7 +93,7 @@ typedef struct fd_params {
   float refine_step0;      /* first stencil angle (rad); <= 0: 0.5 sqrt(2 pi / n_candidates) */
   int32_t top_k;           /* K of Eq. (4), 1..FD_MAX_TOPK */
   float z_near;            /* a view is eligible only if camera-space Z > z_near */
-  int32_t mode;            /* FD_MODE_PLAIN or FD_MODE_LEARNED */
+  int32_t mode;            /* FD_MODE_PLAIN, FD_MODE_LEARNED or FD_MODE_FPMVO */
   const fd_mlp* mlp;       /* network for FD_MODE_LEARNED with FD_PROPOSAL_MLP */
   int32_t learned_iters;   /* refinement iterations after the proposal */
   float learned_step0;     /* their first stencil angle (rad) */
@@ -101,6 +108,9 @@ typedef struct fd_params {
                               features alike) only if the point is visible in it:
                               |Z - D_v(nearest texel of u)| <= vis_tau, decided in
                               binary32 (Sec. 3.1.1, visibility score V_i^v) */
+  float fpmvo_lambda;      /* FPMVO: pixel offset along the observed orientation (Eq. 1), > 0 */
+  int32_t fpmvo_samples;   /* FPMVO: depth layers S (Eq. 2), 1..FD_MAX_FPMVO_SAMPLES */
+  float fpmvo_delta;       /* FPMVO: layers at z + [-delta, delta] (metres, Eq. 2), >= 0 */
   void* stream;            /* hipStream_t */
   fd_context* ctx;         /* workspace; NULL = a per-device default that grows */
 } fd_params;
@@ -108,7 +118,8 @@ typedef struct fd_params {
 /* Defaults: K = 5 (Sec. 3.1.2, Eq. 4), P = 5 (Sec. 4), 128 candidates,
  * 8 refinement iterations, z_near = 1e-3, plain mode, FD_F16 maps,
  * learned_iters = 2, no depth maps, vis_tau = 5e-3 (half the 10 mm depth
- * range of Sec. 3.1.1). */
+ * range of Sec. 3.1.1); FPMVO: lambda = 3 px, S = 5, delta = 5e-3 (the
+ * 2 Delta = 10 mm range of Eq. 2). */
 void fd_params_init(fd_params* params);
 
 /* ---- context: library-owned workspace ------------------------------------
@@ -134,7 +145,11 @@ void fd_context_destroy(fd_context* ctx);
  * dirs        device, n_points x 3 float, written
  * costs       device, n_points float, written
  * Plain mode: tiling of the points by a spatial key, Eq. (4) view selection,
- * patch sampling, lattice argmin of J, pattern-search refinement.  Learned
+ * patch sampling, lattice argmin of J, pattern-search refinement.  FPMVO
+ * mode: the same tiling and view selection, then the paper's candidates and
+ * medoid fusion per depth layer, the fused candidate of lowest J (no
+ * refinement); a point without any candidate gets direction 0 and cost
+ * +inf.  Learned
  * mode: proposal (network or test hook), refinement from it, and the plain
  * search for every point whose refined cost exceeds params->fallback_cost.
  * The learned form needs a context (params->ctx or the default one). */
@@ -162,7 +177,7 @@ int fd_last_fallback_split(fd_context* ctx, void* stream, int64_t* listed, int64
  * launch sequence is captured into a HIP graph on the first call and
  * replayed while the scene array and params are unchanged (a changed array
  * re-captures, which synchronises params->stream).  The learned form takes
- * the network proposal only.  Results equal those of fd_fuse_directions on
+ * the network proposal only; FD_MODE_FPMVO is not batched (FD_E_INVAL).  Results equal those of fd_fuse_directions on
  * each scene alone, bit for bit. */
 typedef struct fd_scene {
   const float* points;

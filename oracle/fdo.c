@@ -783,12 +783,15 @@ static void fpmvo_point(const point_state* st, const float* p, const float* cams
       if (tr->ok[j][s]) wsum += tr->w[j];
     for (int i = 0; i < K; ++i) {
       if (!tr->ok[i][s]) continue;
+      /* G_ii = |<d_i, d_i>| = 1 for a unit direction: taken exactly */
       double num = 0.0;
-      for (int j = 0; j < K; ++j)
-        if (tr->ok[j][s])
-          num += tr->w[j] * fabs(tr->cand[i][s][0] * tr->cand[j][s][0] +
-                                 tr->cand[i][s][1] * tr->cand[j][s][1] +
-                                 tr->cand[i][s][2] * tr->cand[j][s][2]);
+      for (int j = 0; j < K; ++j) {
+        if (!tr->ok[j][s]) continue;
+        num += j == i ? tr->w[j]
+                      : tr->w[j] * fabs(tr->cand[i][s][0] * tr->cand[j][s][0] +
+                                        tr->cand[i][s][1] * tr->cand[j][s][1] +
+                                        tr->cand[i][s][2] * tr->cand[j][s][2]);
+      }
       const double sigma = num / wsum;
       if (sigma > best) {
         best = sigma;

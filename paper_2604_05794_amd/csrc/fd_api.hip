@@ -247,6 +247,9 @@ extern "C" void fd_params_init(fd_params* p) {
   p->proposal_dirs = nullptr;
   p->vis_tau = 5e-3f;
   p->depth_maps = nullptr;
+  p->fpmvo_lambda = 3.0f;
+  p->fpmvo_samples = 5;
+  p->fpmvo_delta = 5e-3f;
   p->stream = nullptr;
   p->ctx = nullptr;
 }
@@ -271,8 +274,17 @@ int fd::check_search_params(const fd_params* p, const char* fn) {
     return set_error(FD_E_INVAL, "%s: z_near must be finite and >= 0", fn);
   if (!(p->vis_tau >= 0.0f) || !std::isfinite(p->vis_tau))
     return set_error(FD_E_INVAL, "%s: vis_tau must be finite and >= 0", fn);
-  if (p->mode != FD_MODE_PLAIN && p->mode != FD_MODE_LEARNED)
+  if (p->mode != FD_MODE_PLAIN && p->mode != FD_MODE_LEARNED && p->mode != FD_MODE_FPMVO)
     return set_error(FD_E_INVAL, "%s: unknown mode %d", fn, p->mode);
+  if (p->mode == FD_MODE_FPMVO) {
+    if (!(p->fpmvo_lambda > 0.0f) || !std::isfinite(p->fpmvo_lambda))
+      return set_error(FD_E_INVAL, "%s: fpmvo_lambda must be finite and > 0", fn);
+    if (p->fpmvo_samples < 1 || p->fpmvo_samples > FD_MAX_FPMVO_SAMPLES)
+      return set_error(FD_E_INVAL, "%s: fpmvo_samples must be in [1, %d]", fn,
+                       FD_MAX_FPMVO_SAMPLES);
+    if (!(p->fpmvo_delta >= 0.0f) || !std::isfinite(p->fpmvo_delta))
+      return set_error(FD_E_INVAL, "%s: fpmvo_delta must be finite and >= 0", fn);
+  }
   if (p->mode == FD_MODE_LEARNED) {
     if (p->learned_iters < 0 || p->learned_iters > FD_MAX_REFINE)
       return set_error(FD_E_INVAL, "%s: learned_iters must be in [0, %d]", fn, FD_MAX_REFINE);
@@ -307,6 +319,8 @@ extern "C" int fd_fuse_directions(const float* points, int64_t n_points, const f
   const char* fn = "fd_fuse_directions";
   int r;
   if ((r = check_search_params(params, fn))) return r;
+  if (params->mode == FD_MODE_FPMVO && !params->depth_maps)
+    return set_error(FD_E_INVAL, "%s: FD_MODE_FPMVO needs depth_maps", fn);
   if (n_points < 0) return set_error(FD_E_INVAL, "%s: n_points < 0", fn);
   if (n_points > (int64_t)UINT32_MAX)
     return set_error(FD_E_INVAL, "%s: n_points exceeds 2^32 - 1", fn);
@@ -396,6 +410,14 @@ int fd::run_scene(fd_context* c, const SceneArgs& a, const fd_params* p, hipStre
     StageTimer t_fuse(c, FD_STAGE_FUSE, st);
     if ((e = launch_fuse(s, q, p->map_dtype, p->patch, nullptr, nullptr, st)) != hipSuccess)
       return hip_error(e, "fusion kernel");
+    t_fuse.stop();
+    return FD_OK;
+  }
+  if (p->mode == FD_MODE_FPMVO) {
+    FpmvoDev f{p->fpmvo_lambda, p->fpmvo_samples, p->fpmvo_delta};
+    StageTimer t_fuse(c, FD_STAGE_FUSE, st);
+    if ((e = launch_fpmvo(s, q, f, p->map_dtype, p->patch, st)) != hipSuccess)
+      return hip_error(e, "candidate fusion kernel");
     t_fuse.stop();
     return FD_OK;
   }

@@ -512,6 +512,8 @@ extern "C" int fd_fuse_directions_batched(const fd_scene* scenes, int32_t n_scen
   if (n_scenes > FD_MAX_BATCH_SCENES)
     return set_error(FD_E_INVAL, "%s: at most %d scenes per call, got %d", fn,
                      FD_MAX_BATCH_SCENES, n_scenes);
+  if (params->mode == FD_MODE_FPMVO)
+    return set_error(FD_E_INVAL, "%s: FD_MODE_FPMVO is not batched", fn);
   if (params->proposal != FD_PROPOSAL_MLP && params->mode == FD_MODE_LEARNED)
     return set_error(FD_E_INVAL, "%s: the batched learned form takes the network proposal", fn);
   int64_t total = 0;

@@ -167,4 +167,48 @@ hipError_t launch_learned_refine(const SceneDev& s, const SearchDev& q, const Le
   return hipGetLastError();
 }
 
+// ---- paper-literal candidates ---------------------------------------------------
+template <typename T, int P, int KT>
+__global__ __launch_bounds__(256) void k_fpmvo(SceneDev s, SearchDev q, FpmvoDev f) {
+  const Group gr = make_group(q.K);
+  const int64_t blk = xcd_tile(gridDim.x);
+  const int64_t wave = blk * (blockDim.x / kWave) + (threadIdx.x / kWave);
+  const int64_t j = wave * gr.G + gr.g;
+  if (wave * gr.G >= s.n) return;  // whole wave idle (uniform exit)
+  const bool pt_ok = gr.lane_ok && j < s.n;
+  fpmvo_group<T, P, KT>(s, q, f, gr, pt_ok, pt_ok ? j : 0);
+}
+
+hipError_t launch_fpmvo(const SceneDev& s, const SearchDev& q, const FpmvoDev& f, int dtype,
+                        int patch, hipStream_t st) {
+  if (s.n <= 0) return hipSuccess;
+  const int G = kWave / q.K;
+  const int64_t nb = (s.n + 4 * (int64_t)G - 1) / (4 * (int64_t)G);
+  dim3 grid((unsigned)nb), block(256);
+#define FD_FPMVO_CASE(T, P)                                                     \
+  if (q.K == 5)                                                                 \
+    hipLaunchKernelGGL((k_fpmvo<T, P, 5>), grid, block, 0, st, s, q, f);        \
+  else                                                                          \
+    hipLaunchKernelGGL((k_fpmvo<T, P, 0>), grid, block, 0, st, s, q, f);
+  if (dtype == 1) {
+    switch (patch) {
+      case 1: FD_FPMVO_CASE(__half, 1) break;
+      case 3: FD_FPMVO_CASE(__half, 3) break;
+      case 5: FD_FPMVO_CASE(__half, 5) break;
+      case 7: FD_FPMVO_CASE(__half, 7) break;
+      default: return hipErrorInvalidValue;
+    }
+  } else {
+    switch (patch) {
+      case 1: FD_FPMVO_CASE(float, 1) break;
+      case 3: FD_FPMVO_CASE(float, 3) break;
+      case 5: FD_FPMVO_CASE(float, 5) break;
+      case 7: FD_FPMVO_CASE(float, 7) break;
+      default: return hipErrorInvalidValue;
+    }
+  }
+#undef FD_FPMVO_CASE
+  return hipGetLastError();
+}
+
 }  // namespace fd

@@ -94,6 +94,13 @@ struct SearchDev {
   float z_near;
 };
 
+// Paper-literal candidate mode.
+struct FpmvoDev {
+  float lambda;   // pixel offset along the observed orientation
+  int samples;    // depth layers S
+  float delta;    // layers span [-delta, delta] around the sampled depth
+};
+
 // Learned form (fd_learned.hip).
 struct LearnedDev {
   const float* proposals;  // n x 3 in point order, or NULL for NaN proposals
@@ -104,6 +111,8 @@ struct LearnedDev {
   uint32_t* fb_count;      // [0] fallback list length, [1] points searched in place
 };
 
+hipError_t launch_fpmvo(const SceneDev& s, const SearchDev& q, const FpmvoDev& f, int dtype,
+                        int patch, hipStream_t st);
 hipError_t launch_tiling(const float* pts, int64_t n, TileWork w, hipStream_t st);
 hipError_t launch_identity_perm(int64_t n, uint32_t* perm, hipStream_t st);
 hipError_t launch_scan_runs(const uint32_t* counts, int n_runs, uint32_t* sums, uint32_t* cursor,

@@ -414,4 +414,120 @@ __device__ __forceinline__ void learned_group(const SceneDev& s, const SearchDev
   }
 }
 
+// ---- paper-literal candidates: Sec. 3.1.1-3.1.2 (Eqs. 1-7), scored by Eq. (12) ----
+// Lane = one view of Eq. (4).  The lane's view gives S candidates: the
+// projection u moved by lambda pixels along the observed orientation (the
+// patch's centre sample), the depth texel nearest to that pixel shifted by
+// delta_s in [-delta, delta], back-projected and taken relative to the point
+// (unit).  Per layer s the group fuses the confidence-weighted medoid of its
+// lanes' candidates (same fixed order in every lane, so every lane takes the
+// same one), and the fused candidate with the largest view sum (lowest J,
+// first of equals) is the result.
+template <typename T, int P, int KT>
+__device__ __forceinline__ void fpmvo_group(const SceneDev& s, const SearchDev& q,
+                                            const FpmvoDev& f, const Group& gr, bool pt_ok,
+                                            int64_t j) {
+  constexpr int HP = (P - 1) / 2, kc = HP * P + HP;
+  const uint32_t i = pt_ok ? s.perm[j] : 0u;
+  const int keff = pt_ok ? (int)s.kcount[j] : 0;
+  const bool slot_ok = pt_ok && gr.slot < keff;
+  const int view = slot_ok ? (int)s.views[FD_TOPK_SLOTS * j + gr.slot] : 0;
+  const float px = s.pts[3 * (size_t)i], py = s.pts[3 * (size_t)i + 1],
+              pz = s.pts[3 * (size_t)i + 2];
+  ViewPatch<P> vp;
+  build_patch<T, P>(s, q, view, slot_ok, px, py, pz, vp);
+  const float kinv = keff > 0 ? 1.0f / (float)keff : 0.0f;
+
+  // Eq. (1): orientation of the centre sample, a = C^2/2, b = a cos 2t,
+  // c = 2 a sin 2t; the unit offset (cos t, sin t) with t in (-pi/2, pi/2]
+  const float* cam = s.cams + 16 * view;
+  Proj pr;
+  const bool in_view = slot_ok && project32(cam, px, py, pz, s.W, s.H, q.z_near, pr);
+  const float a0 = vp.a[kc];
+  bool vok = in_view && a0 > 0.0f;
+  const float ia = vok ? 1.0f / a0 : 0.0f;
+  const float c2 = vp.b[kc] * ia, s2 = 0.5f * vp.c[kc] * ia;
+  const float ct = sqrtf(fmaxf(0.5f * (1.0f + c2), 0.0f));
+  const float st = copysignf(sqrtf(fmaxf(0.5f * (1.0f - c2), 0.0f)), s2);
+  const float w = slot_ok ? sqrtf(2.0f * a0) : 0.0f;  // centre confidence
+  const float ux = (in_view ? pr.u : 0.0f) + f.lambda * ct;
+  const float uy = (in_view ? pr.v : 0.0f) + f.lambda * st;
+  vok = vok && ux >= 0.0f && ux <= (float)(s.W - 1) && uy >= 0.0f && uy <= (float)(s.H - 1);
+  // Eq. (2): depth at the nearest texel of the offset pixel
+  float D = 0.0f;
+  if (vok) {
+    const uint32_t xn = (uint32_t)floorf(ux + 0.5f), yn = (uint32_t)floorf(uy + 0.5f);
+    D = ld_texel<T>((const T*)s.depth + (size_t)s.W * s.H * view, yn * (uint32_t)s.W + xn);
+  }
+  vok = vok && isfinite(D);
+  // Eq. (3): p_s = R^T (X_c - t) with X_c = z_s (bx, by, 1), so
+  // p_s - p = z_s g + h, g = R^T (bx, by, 1), h = -R^T t - p
+  const float* R = cam + 4;
+  const float* tc = cam + 13;
+  const float bx = (ux - cam[2]) / cam[0], by = (uy - cam[3]) / cam[1];
+  const float gx = R[0] * bx + R[3] * by + R[6], gy = R[1] * bx + R[4] * by + R[7],
+              gz = R[2] * bx + R[5] * by + R[8];
+  const float hx = -(R[0] * tc[0] + R[3] * tc[1] + R[6] * tc[2]) - px;
+  const float hy = -(R[1] * tc[0] + R[4] * tc[1] + R[7] * tc[2]) - py;
+  const float hz = -(R[2] * tc[0] + R[5] * tc[1] + R[8] * tc[2]) - pz;
+
+  float Sb = -INFINITY, bxd = 0.0f, byd = 0.0f, bzd = 0.0f;
+  for (int sl = 0; sl < f.samples; ++sl) {
+    const float zs = D + (f.samples > 1 ? -f.delta + 2.0f * f.delta * (float)sl /
+                                                        (float)(f.samples - 1)
+                                        : 0.0f);
+    float dx = __builtin_fmaf(zs, gx, hx), dy = __builtin_fmaf(zs, gy, hy),
+          dz = __builtin_fmaf(zs, gz, hz);
+    const float n = sqrtf(dx * dx + dy * dy + dz * dz);
+    const bool ok = vok && zs > 0.0f && n > 0.0f;
+    // a lane without a candidate shares exact zeros (its depth may be +inf)
+    const float il = ok ? 1.0f / n : 0.0f;
+    dx = ok ? dx * il : 0.0f;
+    dy = ok ? dy * il : 0.0f;
+    dz = ok ? dz * il : 0.0f;
+    // Eqs. (5)-(6): weighted consistency of this lane's candidate with the
+    // group's candidates of the same layer (views in the order of Eq. (4))
+    const float wk = ok ? w : 0.0f;
+    float num = 0.0f, den = 0.0f;
+    const int K = KT > 0 ? KT : gr.K;
+    for (int jj = 0; jj < K; ++jj) {
+      const int src = gr.base + jj;
+      const float xj = __shfl(dx, src, kWave), yj = __shfl(dy, src, kWave),
+                  zj = __shfl(dz, src, kWave), wj = __shfl(wk, src, kWave);
+      // G_ii = 1 exactly for a unit direction
+      num += jj == gr.slot ? wj : wj * fabsf(dx * xj + dy * yj + dz * zj);
+      den += wj;
+    }
+    const float sigma = ok ? num / den : -INFINITY;
+    // Eq. (7): the medoid, first of equals
+    int bj = -1;
+    float bs = -INFINITY;
+    for (int jj = 0; jj < K; ++jj) {
+      const float sj = __shfl(sigma, gr.base + jj, kWave);
+      if (sj > bs) {
+        bs = sj;
+        bj = jj;
+      }
+    }
+    // the same in every lane of the group; the shuffles below run in every lane
+    const int src = gr.base + (bj < 0 ? 0 : bj);
+    const float fx = __shfl(dx, src, kWave), fy = __shfl(dy, src, kWave),
+                fz = __shfl(dz, src, kWave);
+    // Eq. (12): patch consistency of the fused candidate
+    const float Sv = group_sum_t<KT>(eval_view<P>(vp, fx, fy, fz), gr.base, gr.K);
+    if (bj >= 0 && Sv > Sb) {
+      Sb = Sv;
+      bxd = fx;
+      byd = fy;
+      bzd = fz;
+    }
+  }
+  if (pt_ok && gr.slot == 0) {
+    if (keff == 0 || !(Sb > -INFINITY))
+      write_result(s, i, 0.0f, 0.0f, 0.0f, INFINITY);
+    else
+      write_result(s, i, bxd, byd, bzd, 1.0f - Sb * kinv);
+  }
+}
+
 }  // namespace fd

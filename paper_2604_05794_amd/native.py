@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(HERE, "libfusedir.so")
 
 FD_OK, FD_E_INVAL, FD_E_UNSUPPORTED, FD_E_HIP, FD_E_NOMEM = range(5)
 FD_F32, FD_F16 = 0, 1
-FD_MODE_PLAIN, FD_MODE_LEARNED = 0, 1
+FD_MODE_PLAIN, FD_MODE_LEARNED, FD_MODE_FPMVO = 0, 1, 2
 FD_PROPOSAL_MLP, FD_PROPOSAL_GIVEN, FD_PROPOSAL_NAN = 0, 1, 2
 FD_MLP_N_PARAMS = 161283
 FD_FEATURE_DIM = 112
@@ -55,8 +55,9 @@ class Params(ctypes.Structure):
         ("learned_step0", ctypes.c_float), ("fallback_cost", ctypes.c_float),
         ("proposal", ctypes.c_int32), ("proposal_dirs", ctypes.c_void_p),
         ("head_centre", ctypes.c_float * 3), ("vis_tau", ctypes.c_float),
-        ("depth_maps", ctypes.c_void_p), ("stream", ctypes.c_void_p),
-        ("ctx", ctypes.c_void_p),
+        ("depth_maps", ctypes.c_void_p), ("fpmvo_lambda", ctypes.c_float),
+        ("fpmvo_samples", ctypes.c_int32), ("fpmvo_delta", ctypes.c_float),
+        ("stream", ctypes.c_void_p), ("ctx", ctypes.c_void_p),
     ]
 
 
@@ -214,8 +215,8 @@ def make_params(width, height, map_dtype, *, patch=5, n_candidates=128, refine_i
                 refine_step0=0.0, top_k=5, z_near=1e-3, mode=FD_MODE_PLAIN, mlp=None,
                 learned_iters=2, learned_step0=0.0, fallback_cost=math.inf,
                 proposal=FD_PROPOSAL_MLP, proposal_dirs=None, head_centre=(0.0, 0.0, 0.0),
-                depth_maps=None, vis_tau=5e-3, stream=None,
-                ctx: Optional[Context] = None) -> Params:
+                depth_maps=None, vis_tau=5e-3, fpmvo_lambda=3.0, fpmvo_samples=5,
+                fpmvo_delta=5e-3, stream=None, ctx: Optional[Context] = None) -> Params:
     p = Params()
     lib().fd_params_init(ctypes.byref(p))
     p.width, p.height = int(width), int(height)
@@ -237,6 +238,9 @@ def make_params(width, height, map_dtype, *, patch=5, n_candidates=128, refine_i
         p.head_centre[k] = float(head_centre[k])
     p.vis_tau = float(vis_tau)
     p.depth_maps = depth_maps.data_ptr() if depth_maps is not None else None
+    p.fpmvo_lambda = float(fpmvo_lambda)
+    p.fpmvo_samples = int(fpmvo_samples)
+    p.fpmvo_delta = float(fpmvo_delta)
     p.stream = _stream_handle(stream).value
     p.ctx = ctx.handle.value if ctx is not None else None
     return p
