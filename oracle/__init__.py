@@ -4,8 +4,8 @@ TEST INFRASTRUCTURE ONLY.  Only ``tests/``, ``__graft_entry__.smoke()`` and the
 ``cpu_baseline`` leg of ``bench.py`` may import this package.  The product path
 (``paper_2604_05794_amd``) never imports it and shares no code with it.
 
-Thin ctypes marshalling over ``liboracle.so`` (built from ``fdo.c`` and
-``mlp.c`` by :func:`build`); all arithmetic is in the C sources, which cite the
+Thin ctypes marshalling over ``liboracle.so`` (built from ``fdo.c``,
+``mlp.c`` and ``gabor.c`` by :func:`build`); all arithmetic is in the C sources, which cite the
 paper (EfficientMonoHair, Sec. 3.1, Eqs. (4), (8)-(12)).
 """
 from __future__ import annotations
@@ -19,7 +19,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "liboracle.so")
-_SOURCES = ("fdo.c", "mlp.c")
+_SOURCES = ("fdo.c", "mlp.c", "gabor.c")
 
 
 def build() -> str:
@@ -78,6 +78,8 @@ def lib():
             "fdo_fpmvo": (i32, [P, i64, P, i32, P, P, pp, dbl, i32, dbl, P, P, i32]),
             "fdo_fpmvo_trace": (i32, [P, P, i32, P, P, pp, dbl, i32, dbl, P, P, P, P, P, P,
                                       P, P, P, P]),
+            "fdo_gabor_bank": (None, [i32, i32, dbl, dbl, dbl, P]),
+            "fdo_gabor": (dbl, [P, i32, i32, i32, i32, P, P, P, P, P, i32]),
             "fdo_mlp_n_params": (i64, []),
             "fdo_mlp_forward": (i32, [P, P, i32, i32, P]),
             "fdo_mlp_loss_grad": (dbl, [P, P, P, i32, i32, P]),
@@ -356,3 +358,32 @@ def mlp_split(params):
         o += n
         out.append((W, b))
     return out
+
+
+# ---- orientation and confidence maps (gabor.c) ------------------------------
+
+GABOR_DEFAULTS = dict(n_orient=32, radius=8, sigma_along=2.4, sigma_across=1.8, wavelength=4.0)
+
+
+def gabor_bank(n_orient=32, radius=8, sigma_along=2.4, sigma_across=1.8, wavelength=4.0):
+    """(n_orient, 2r+1, 2r+1) zero-mean even Gabor kernels (see gabor.c)."""
+    w = 2 * int(radius) + 1
+    out = np.zeros((int(n_orient), w, w), np.float64)
+    lib().fdo_gabor_bank(int(n_orient), int(radius), float(sigma_along), float(sigma_across),
+                         float(wavelength), _ptr(out))
+    return out
+
+
+def gabor(image, bank, responses=False, n_threads=0):
+    """Orientation (radians, [0, pi)) and confidence ([0, 1]) maps of one
+    (H, W) image: (theta, conf, max raw confidence[, responses (H, W, N)])."""
+    img = _c(image, np.float32)
+    H, W = img.shape
+    N, w, _ = bank.shape
+    bk = _c(bank, np.float64)
+    th = np.zeros((H, W))
+    cf = np.zeros((H, W))
+    rs = np.zeros((H, W, N)) if responses else None
+    m = lib().fdo_gabor(_ptr(img), W, H, N, (w - 1) // 2, _ptr(bk), _ptr(th), _ptr(cf),
+                        _ptr(rs) if responses else None, None, int(n_threads))
+    return (th, cf, m, rs) if responses else (th, cf, m)

@@ -59,7 +59,8 @@ def _raster_lib():
         P = ctypes.c_void_p
         L.scenegen_raster.restype = ctypes.c_int
         L.scenegen_raster.argtypes = [P, P, ctypes.c_int64, P, ctypes.c_int32, ctypes.c_int32,
-                                      ctypes.c_int32, ctypes.c_double, P, P, P, ctypes.c_int32]
+                                      ctypes.c_int32, ctypes.c_double, P, P, P, P,
+                                      ctypes.c_int32]
         L.scenegen_visible_views.restype = ctypes.c_int
         L.scenegen_visible_views.argtypes = [P, ctypes.c_int64, P, ctypes.c_int32, ctypes.c_int32,
                                              ctypes.c_int32, P, ctypes.c_double, P,
@@ -258,7 +259,7 @@ def render_maps(rng_views, verts, offs, cams, width, height, kappa, outlier_frac
     offs = np.ascontiguousarray(offs, np.int64)
     _raster_lib().scenegen_raster(v32.ctypes.data, offs.ctypes.data, len(offs) - 1,
                                   cams.ctypes.data, V, width, height, float(head_radius),
-                                  theta.ctypes.data, depth.ctypes.data, cov.ctypes.data,
+                                  theta.ctypes.data, depth.ctypes.data, cov.ctypes.data, None,
                                   int(n_threads))
     conf = np.zeros((V, height, width), np.float32)
     for v in range(V):
@@ -300,6 +301,60 @@ def visible_views(points, cams, depth, tau=VIS_TAU, n_threads=0):
                                          dep.ctypes.data, float(tau), out.ctypes.data,
                                          int(n_threads))
     return out
+
+
+def render_images(rng, verts, offs, cams, width, height, noise=0.02,
+                  head_radius=SCALP_RADIUS, n_threads=0):
+    """Grey-level frames of the strands (the input of orientation extraction):
+    each strand has its own albedo U(0.35, 1), the scalp 0.15, the background
+    0, plus Gaussian noise of std `noise`; z-buffered like the maps, so the
+    frames and the maps of a scene agree texel for texel."""
+    V = len(cams)
+    v32 = np.ascontiguousarray(verts, np.float32)
+    theta = np.empty((V, height, width), np.float32)
+    depth = np.empty((V, height, width), np.float32)
+    cov = np.empty((V, height, width), np.uint8)
+    sid = np.empty((V, height, width), np.int32)
+    cams = np.ascontiguousarray(cams, np.float32)
+    offs = np.ascontiguousarray(offs, np.int64)
+    _raster_lib().scenegen_raster(v32.ctypes.data, offs.ctypes.data, len(offs) - 1,
+                                  cams.ctypes.data, V, width, height, float(head_radius),
+                                  theta.ctypes.data, depth.ctypes.data, cov.ctypes.data,
+                                  sid.ctypes.data, int(n_threads))
+    albedo = rng.uniform(0.35, 1.0, len(offs) - 1).astype(np.float32)
+    img = np.where(sid >= 0, albedo[np.maximum(sid, 0)], 0.0).astype(np.float32)
+    img[(sid < 0) & np.isfinite(depth)] = 0.15
+    if noise > 0:
+        img += rng.normal(0.0, noise, img.shape).astype(np.float32)
+    return img
+
+
+def make_frames(recipe, seed, n_threads=0):
+    """The strands and cameras of `make_scene(recipe, seed)` as grey-level
+    frames (V, H, W) float32, with the noise-free strand angle of every
+    texel (V, H, W, radians in [0, pi)) and the strand coverage (V, H, W
+    bool) for reference, and the cameras."""
+    if isinstance(recipe, str):
+        recipe = RECIPES[recipe]
+    r = dict(recipe)
+    ss = np.random.SeedSequence(int(seed))
+    s_strands, _, _ = ss.spawn(3)
+    rng_s = np.random.Generator(np.random.PCG64(s_strands))
+    verts, offs = grow_strands(
+        rng_s, r["n_strands"], r["kinds"],
+        helix_r_mm=r.get("helix_r_mm", (5.0, 20.0)), pitch_mm=r.get("pitch_mm", (10.0, 40.0)),
+        wave_amp_mm=r.get("wave_amp_mm", (5.0, 15.0)),
+        wave_len_mm=r.get("wave_len_mm", (20.0, 60.0)),
+        length_mm=r.get("length_mm", (60.0, 150.0)))
+    res = r["res"]
+    cams = orbit_cameras(r["n_views"], res, res, r["arc_deg"])
+    rng_f = np.random.Generator(np.random.PCG64(np.random.SeedSequence([int(seed), 7])))
+    hr = r.get("head_radius", SCALP_RADIUS)
+    frames = render_images(rng_f, verts, offs, cams, res, res, noise=r.get("frame_noise", 0.02),
+                           head_radius=hr, n_threads=n_threads)
+    theta, conf, _ = render_maps([None] * len(cams), verts, offs, cams, res, res, None, 0.0,
+                                 np.float32, head_radius=hr, n_threads=n_threads)
+    return frames, theta, conf > 0, cams
 
 
 # ---- recipes ------------------------------------------------------------------

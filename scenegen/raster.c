@@ -10,7 +10,8 @@
  * stores the angle of the segment's image, in [0, pi), measured from +x
  * towards +y, and the sample's camera-space depth.  A sphere of the given
  * radius at the origin (the scalp) pre-fills the depth buffer, so strands
- * behind the head are hidden; covered_out marks the texels a strand won.
+ * behind the head are hidden; covered_out marks the texels a strand won and
+ * strand_out (optional) holds the winning strand's index (-1: none).
  *
  * Input generation only: this file is shared by nothing but the generator.
  */
@@ -38,7 +39,7 @@ static void proj(const float* cam, const double* x, double* u, double* z) {
 int scenegen_raster(const float* verts, const int64_t* offs, int64_t n_strands,
                     const float* cams, int32_t n_views, int32_t W, int32_t H,
                     double head_radius, float* theta_out, float* depth_out,
-                    uint8_t* covered_out, int32_t n_threads) {
+                    uint8_t* covered_out, int32_t* strand_out, int32_t n_threads) {
   const double z_near = 1e-3;
 #ifdef _OPENMP
   if (n_threads > 0) omp_set_num_threads(n_threads);
@@ -49,6 +50,7 @@ int scenegen_raster(const float* verts, const int64_t* offs, int64_t n_strands,
     float* th = theta_out + (size_t)v * W * H;
     float* dp = depth_out + (size_t)v * W * H;
     uint8_t* cv = covered_out + (size_t)v * W * H;
+    int32_t* sd = strand_out ? strand_out + (size_t)v * W * H : NULL;
     /* camera centre c = -R^T t, for the scalp-sphere depth */
     const float* R = cam + 4;
     const float* t = cam + 13;
@@ -61,6 +63,7 @@ int scenegen_raster(const float* verts, const int64_t* offs, int64_t n_strands,
         th[i] = 0.0f;
         dp[i] = INFINITY;
         cv[i] = 0;
+        if (sd) sd[i] = -1;
         if (head_radius <= 0) continue;
         /* camera ray through the pixel, camera frame then world frame */
         double rc[3] = {(x - cam[2]) / cam[0], (y - cam[3]) / cam[1], 1.0};
@@ -109,6 +112,7 @@ int scenegen_raster(const float* verts, const int64_t* offs, int64_t n_strands,
             dp[i] = (float)z;
             th[i] = (float)ang;
             cv[i] = 1;
+            if (sd) sd[i] = (int32_t)sidx;
           }
         }
       }
