@@ -17,6 +17,9 @@ depth visibility test of Sec. 3.1.1 with the scene's rendered depth maps
              float16 maps, 10% outlier texels, 5x5 patch, 128 candidates +
              8 refinement iterations (fd_fuse_directions, plain mode).
   learned    the same scene, learned form against plain.
+  gabor      orientation and confidence maps from 64 grey frames at 1024^2
+             (the plain workload's views; 32 orientations, radius 8), then
+             the plain search of the plain workload on those maps.
 """
 from __future__ import annotations
 
@@ -515,6 +518,106 @@ def run_plain(args):
     return out
 
 
+def gabor_flop_per_pixel(n_orient, radius):
+    """Algorithmic flop of the filter bank per pixel: one fma (2 flop) per
+    tap and orientation; the argmax and the confidence are not counted."""
+    return 2 * n_orient * (2 * radius + 1) ** 2
+
+
+def run_gabor(args):
+    import numpy as np
+    import torch
+    import oracle
+    import scenegen
+    from paper_2604_05794_amd import native
+
+    name = "realistic"
+    rec = scenegen.RECIPES[name]
+    n_orient, radius = 32, 8
+    t = time.perf_counter()
+    frames, _, _, cams = scenegen.make_frames(name, args.seed)
+    sc = scenegen.make_scene(name, args.seed)
+    assert np.array_equal(cams, sc.cams)
+    V, H, W = frames.shape
+    log(f"generated {V} frames {W}x{H} and {sc.n_points} points in "
+        f"{time.perf_counter() - t:.1f} s")
+    dev = torch.device("cuda:0")
+    fr = torch.from_numpy(frames).to(dev)
+    th = torch.empty((V, H, W), dtype=torch.float16, device=dev)
+    cf = torch.empty_like(th)
+    ctx = native.Context(max_points=sc.n_points)
+    stream = torch.cuda.current_stream()
+
+    def step():
+        native.orientation_maps(fr, n_orient=n_orient, radius=radius, theta=th, conf=cf,
+                                out_dtype=torch.float16, stream=stream, ctx=ctx)
+
+    el, stages = _timed(step, args, ctx, [("gabor", native.FD_STAGE_GABOR),
+                                          ("gabor_norm", native.FD_STAGE_GABOR_NORM)])
+    ms_step = el * 1e3 / args.steps
+    px = V * H * W
+    value = px / (el / args.steps)
+    flop = gabor_flop_per_pixel(n_orient, radius)
+    achieved = flop * px / (stages["gabor"] * 1e-3) / 1e12
+    log(f"maps: {ms_step:.3f} ms/step, {value / 1e9:.2f} G pixels/s, "
+        f"stages {json.dumps({k: round(v, 4) for k, v in stages.items()})}")
+    # the direction search of the plain workload on the extracted maps
+    kw = dict(patch=rec["patch"], n_candidates=rec["n_candidates"],
+              refine_iters=rec["refine_iters"], top_k=5)
+    pts = torch.from_numpy(sc.points).to(dev)
+    cm = torch.from_numpy(sc.cams).to(dev)
+    dm = torch.from_numpy(sc.depth.astype(np.float16)).to(dev)
+    dirs = torch.empty((sc.n_points, 3), dtype=torch.float32, device=dev)
+    costs = torch.empty((sc.n_points,), dtype=torch.float32, device=dev)
+
+    def pipe():
+        step()
+        native.fuse_directions(pts, cm, th, cf, dirs=dirs, costs=costs, ctx=ctx, stream=stream,
+                               depth_maps=dm, **kw)
+
+    el_p, _ = _timed(pipe, args, ctx, [], profile=False)
+    gt = torch.from_numpy(sc.gt).to(dev)
+    fin = torch.isfinite(costs)
+    err = _axial_deg(dirs[fin], gt[fin])
+    pipeline = {"points_per_s": sc.n_points / (el_p / args.steps),
+                "ms_per_step": el_p * 1e3 / args.steps,
+                "finite_frac": float(fin.float().mean()),
+                "err_vs_gt_deg": {"mean": float(err.mean()), "median": float(err.median())}}
+    log(f"frames -> maps -> search: {json.dumps(pipeline)}")
+    out = {
+        "metric": "orientation-map pixels/s (Gabor bank, 32 orientations, radius 8)",
+        "value": value, "unit": "pixels/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"gabor: {V} grey frames {W}x{H} f32 -> f16 maps, "
+                               f"{n_orient} orientations, radius {radius}",
+                   "frames": V, "width": W, "height": H, "n_orient": n_orient,
+                   "radius": radius},
+        "roofline": {"bound": "alu", "kernel": "k_gabor", "achieved": achieved,
+                     "peak": PEAK_FP32_FMA, "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_FMA,
+                     "traffic": traffic_of("k_gabor, 64 frames 1024^2"),
+                     "avg_launch_ms": stages["gabor"], "flop_per_pixel": flop},
+        "stages_ms_per_launch": stages,
+        "pipeline_frames_maps_search": pipeline,
+    }
+    if not args.no_cpu_baseline:
+        bank = oracle.gabor_bank(n_orient=n_orient, radius=radius)
+        threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or (os.cpu_count() or 1)
+        threads = min(threads, os.cpu_count() or threads)
+        done = 0
+        t0 = time.perf_counter()
+        while time.perf_counter() - t0 < args.cpu_seconds:
+            oracle.gabor(frames[done % V], bank, n_threads=threads)
+            done += 1
+        el_c = time.perf_counter() - t0
+        out["cpu_baseline"] = {"value": done * H * W / el_c, "unit": "pixels/s",
+                               "cores": threads, "kind": "oracle",
+                               "sample": f"{done} whole frames of the same set, {el_c:.1f} s, "
+                                         "binary64 oracle, OpenMP over pixels"}
+        log(f"cpu baseline: {out['cpu_baseline']}")
+    return out
+
+
 def run_copy(args):
     """Counter calibration: a plain device-to-device copy of 512 MiB, so the
     FETCH_SIZE / WRITE_SIZE counters can be read against known bytes."""
@@ -540,7 +643,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--workload", default="metric",
-                    choices=["metric", "plain", "learned", "copy"])
+                    choices=["metric", "plain", "learned", "gabor", "copy"])
     ap.add_argument("--heads", type=int, default=8)
     ap.add_argument("--mlp", default=os.path.join(ROOT, "paper_2604_05794_amd", "weights",
                                                   "proposal_mlp.fdmlp"))
@@ -556,7 +659,7 @@ def main():
               "this build runs the one-GPU share.", file=sys.stderr)
         sys.exit(2)
     run = {"metric": run_metric, "plain": run_plain, "learned": run_learned,
-           "copy": run_copy}[args.workload]
+           "gabor": run_gabor, "copy": run_copy}[args.workload]
     out = run(args)
     print(json.dumps(out), flush=True)
 

@@ -246,6 +246,43 @@ int fd_features(const float* points, int64_t n_points, const fd_camera* cams,
                 int32_t n_views, const void* orient_maps,
                 const void* conf_maps, const fd_params* params, void* feats);
 
+/* ---- orientation and confidence maps from frames ---------------------------
+ * The paper extracts its maps O and C with Gabor filters (Sec. 3.1, opening
+ * paragraph) without giving parameters; the reading: n_orient even (cosine)
+ * Gabor kernels of radius r at theta_i = i pi / n_orient (strand direction,
+ * from image +x towards +y), exp(-a^2/(2 s_a^2) - b^2/(2 s_b^2))
+ * cos(2 pi b / lambda) with a along and b across the direction, made zero
+ * mean over the (2r+1)^2 window; response F_i = |correlation| (frame read
+ * as 0 outside); theta = theta_{argmax F_i} (first of equals); confidence
+ * w = sqrt(sum_i d(theta_i, theta)^2 (F_i - F_max)^2) (d: distance between
+ * lines), divided by its maximum over the frame. */
+typedef struct fd_gabor_params {
+  int32_t n_orient;        /* 8, 16 or 32 */
+  int32_t radius;          /* 1..12 */
+  float sigma_along;       /* > 0, pixels */
+  float sigma_across;      /* > 0, pixels */
+  float wavelength;        /* > 0, pixels */
+  int32_t out_dtype;       /* FD_F32 or FD_F16 maps */
+  void* stream;            /* hipStream_t */
+  fd_context* ctx;         /* workspace; NULL = the per-device default */
+} fd_gabor_params;
+
+/* Defaults: 32 orientations, radius 8, s_a = 2.4, s_b = 1.8, lambda = 4,
+ * FD_F16 output. */
+void fd_gabor_params_init(fd_gabor_params* params);
+
+/* frames: device n_frames x H x W float (grey levels, finite), caller-owned;
+ * theta_out, conf_out: device n_frames x H x W of params->out_dtype, written
+ * (theta radians in [0, pi), conf in [0, 1]).  These are the maps
+ * fd_fuse_directions reads.  0 <= n_frames <= FD_MAX_VIEWS,
+ * 1 <= W, H <= 32768, at most 2^34 pixels; otherwise FD_E_INVAL and nothing
+ * is launched.  The bank (rebuilt when its parameters change, after
+ * synchronising the stream), the raw confidences (4 B per pixel) and the
+ * frame maxima live in the context's workspace, grown on demand.
+ * Asynchronous on params->stream. */
+int fd_orientation_maps(const float* frames, int32_t n_frames, int32_t width, int32_t height,
+                        const fd_gabor_params* params, void* theta_out, void* conf_out);
+
 /* ---- tuning ---------------------------------------------------------------
  * Times the batched launch on the sample scenes for each shape of the
  * plain search (persistent: tiles per queue pop and resident grid size; or
@@ -280,7 +317,9 @@ enum {
   FD_STAGE_REFINE = 5,    /* learned: refinement from the proposal, threshold */
   FD_STAGE_FALLBACK = 6,  /* learned: plain search of the fallback list */
   FD_STAGE_BATCHED = 7,   /* persistent batched launch */
-  FD_N_STAGES = 8
+  FD_STAGE_GABOR = 8,     /* orientation maps: filter bank, argmax, raw confidence */
+  FD_STAGE_GABOR_NORM = 9, /* orientation maps: confidence normalisation */
+  FD_N_STAGES = 10
 };
 int fd_profile_enable(fd_context* ctx, int on);
 int fd_profile_read(fd_context* ctx, int stage, double* total_ms, int64_t* count);

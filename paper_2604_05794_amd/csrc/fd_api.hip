@@ -78,6 +78,10 @@ static int grow(T** p, size_t* cap, size_t need, const char* what) {
   return FD_OK;
 }
 
+int fd::ctx_buffer(void** p, size_t* cap_bytes, size_t bytes, const char* what) {
+  return grow((char**)p, cap_bytes, bytes, what);
+}
+
 int fd::context_reserve_points(fd_context* c, int64_t n) {
   int r;
   size_t need = (size_t)(n > 0 ? n : 1);
@@ -133,7 +137,8 @@ extern "C" void fd_context_destroy(fd_context* c) {
   (void)hipDeviceSynchronize();
   void* bufs[] = {c->bbox, c->counts, c->cursor, c->scan_sums, c->lattice, c->fb_count, c->key,
                   c->perm, c->views, c->kcount, c->fb_list, c->prop, c->feats,
-                  c->scene_tab, c->tile_tab, c->tile_queue, c->batch_key, c->batch_perm};
+                  c->scene_tab, c->tile_tab, c->tile_queue, c->batch_key, c->batch_perm,
+                  c->gabor_bank, c->gabor_raw, c->gabor_max};
   for (void* p : bufs)
     if (p) (void)hipFree(p);
   for (auto& p : c->pending) {

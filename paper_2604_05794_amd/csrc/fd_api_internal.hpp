@@ -53,6 +53,15 @@ struct fd_context {
   uint64_t graph_sig = 0;
   uint64_t table_sig = 0;   // scene set whose table is on the device
   hipStream_t cap_stream = nullptr;
+  // orientation-map extraction: the filter bank (tap-major), raw confidence,
+  // per-frame maxima
+  float* gabor_bank = nullptr;
+  size_t cap_gabor_bank = 0;
+  uint64_t gabor_sig = 0;
+  float* gabor_raw = nullptr;
+  size_t cap_gabor_raw = 0;
+  uint32_t* gabor_max = nullptr;
+  size_t cap_gabor_max = 0;
   // tuned shape of the persistent search: tiles per queue pop, resident grid
   int tuned_chunk = 0;
   int tuned_grid = 0;
@@ -91,6 +100,9 @@ int context_reserve_points(fd_context* c, int64_t n);
 int context_reserve_scenes(fd_context* c, int32_t n_scenes, int64_t total_points);
 fd_context* default_context(int dev, int64_t n, int* err);
 int ensure_lattice(fd_context* c, int n, hipStream_t st);
+// Grows a context-owned device buffer to at least `bytes` (no-op if large
+// enough; the old contents are not kept).
+int ctx_buffer(void** p, size_t* cap_bytes, size_t bytes, const char* what);
 int run_scene(fd_context* c, const SceneArgs& a, const fd_params* p, hipStream_t st);
 // Records HIP events around one stage when the context profiles.
 struct StageTimer {

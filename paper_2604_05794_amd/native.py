@@ -31,11 +31,13 @@ EXPORTS = (
     "fd_mlp_create", "fd_mlp_set_params", "fd_mlp_get_params", "fd_mlp_set_calibration",
     "fd_mlp_get_calibration", "fd_mlp_save", "fd_mlp_load", "fd_mlp_forward",
     "fd_mlp_loss_grad", "fd_mlp_train_step", "fd_mlp_destroy", "fd_features", "fd_autotune",
-    "fd_tuned_shape", "fd_profile_enable", "fd_profile_read", "fd_last_error",
+    "fd_tuned_shape", "fd_profile_enable", "fd_profile_read", "fd_gabor_params_init",
+    "fd_orientation_maps", "fd_last_error",
 )
 
 FD_STAGE_TILING, FD_STAGE_TOPK, FD_STAGE_FUSE, FD_STAGE_FEATURES, FD_STAGE_MLP, \
-    FD_STAGE_REFINE, FD_STAGE_FALLBACK, FD_STAGE_BATCHED = range(8)
+    FD_STAGE_REFINE, FD_STAGE_FALLBACK, FD_STAGE_BATCHED, FD_STAGE_GABOR, \
+    FD_STAGE_GABOR_NORM = range(10)
 
 
 class FdError(RuntimeError):
@@ -70,6 +72,15 @@ class Scene(ctypes.Structure):
         ("depth_maps", ctypes.c_void_p),
         ("dirs", ctypes.c_void_p), ("costs", ctypes.c_void_p),
         ("head_centre", ctypes.c_float * 3),
+    ]
+
+
+class GaborParams(ctypes.Structure):
+    _fields_ = [
+        ("n_orient", ctypes.c_int32), ("radius", ctypes.c_int32),
+        ("sigma_along", ctypes.c_float), ("sigma_across", ctypes.c_float),
+        ("wavelength", ctypes.c_float), ("out_dtype", ctypes.c_int32),
+        ("stream", ctypes.c_void_p), ("ctx", ctypes.c_void_p),
     ]
 
 
@@ -119,6 +130,9 @@ def lib():
         "fd_profile_enable": (ctypes.c_int, [P, ctypes.c_int]),
         "fd_profile_read": (ctypes.c_int, [P, ctypes.c_int, ctypes.POINTER(ctypes.c_double),
                                            ctypes.POINTER(i64)]),
+        "fd_gabor_params_init": (None, [ctypes.POINTER(GaborParams)]),
+        "fd_orientation_maps": (ctypes.c_int, [P, i32, i32, i32, ctypes.POINTER(GaborParams),
+                                               P, P]),
         "fd_last_error": (ctypes.c_char_p, []),
     }
     for name, (res, args) in sig.items():
@@ -396,6 +410,38 @@ def features(points, cams, orient_maps, conf_maps, head_centre=(0.0, 0.0, 0.0), 
     _check(lib().fd_features(_ptr(points), n, _ptr(cams), V, _ptr(orient_maps), _ptr(conf_maps),
                              ctypes.byref(p), _ptr(out)))
     return out
+
+
+def orientation_maps(frames, *, n_orient=32, radius=8, sigma_along=2.4, sigma_across=1.8,
+                     wavelength=4.0, out_dtype=torch.float16, theta=None, conf=None,
+                     stream=None, ctx: Optional["Context"] = None):
+    """fd_orientation_maps: (V, H, W) float32 grey frames -> (theta, conf)
+    maps of out_dtype, the inputs of fuse_directions."""
+    _dev_tensor(frames, "frames", torch.float32)
+    if frames.dim() != 3:
+        raise ValueError("frames must be (n_frames, height, width)")
+    V, H, W = frames.shape
+    dt = {torch.float16: FD_F16, torch.float32: FD_F32}.get(out_dtype)
+    if dt is None:
+        raise TypeError("out_dtype must be torch.float16 or torch.float32")
+    if theta is None:
+        theta = torch.empty((V, H, W), dtype=out_dtype, device=frames.device)
+    if conf is None:
+        conf = torch.empty((V, H, W), dtype=out_dtype, device=frames.device)
+    _dev_tensor(theta, "theta", out_dtype)
+    _dev_tensor(conf, "conf", out_dtype)
+    if theta.shape != frames.shape or conf.shape != frames.shape:
+        raise ValueError("theta and conf must have the frames' shape")
+    p = GaborParams()
+    lib().fd_gabor_params_init(ctypes.byref(p))
+    p.n_orient, p.radius = n_orient, radius
+    p.sigma_along, p.sigma_across, p.wavelength = sigma_along, sigma_across, wavelength
+    p.out_dtype = dt
+    p.stream = _stream_handle(stream).value
+    p.ctx = ctx.handle.value if ctx is not None else None
+    _check(lib().fd_orientation_maps(_ptr(frames), V, W, H, ctypes.byref(p), _ptr(theta),
+                                     _ptr(conf)))
+    return theta, conf
 
 
 def _scene_struct(sc):
