@@ -20,6 +20,9 @@ depth visibility test of Sec. 3.1.1 with the scene's rendered depth maps
   gabor      orientation and confidence maps from 64 grey frames at 1024^2
              (the plain workload's views; 32 orientations, radius 8), then
              the plain search of the plain workload on those maps.
+  volume     occupancy / orientation volume of 2M oriented points over the
+             realistic hairstyle's volume (10 deg direction noise, 10%
+             outliers) on a 2 mm grid.
 """
 from __future__ import annotations
 
@@ -618,6 +621,97 @@ def run_gabor(args):
     return out
 
 
+def run_volume(args):
+    import numpy as np
+    import torch
+    import oracle
+    import scenegen
+    from paper_2604_05794_amd import native
+
+    n_pts, voxel = 2_000_000, 0.002
+    t = time.perf_counter()
+    pts, dirs, w, gt = scenegen.make_oriented_points("realistic", args.seed, n_pts)
+    origin, h, dims = scenegen.head_grid(pts, voxel)
+    nv = int(np.prod(dims.astype(np.int64)))
+    log(f"generated {n_pts} oriented points, grid {dims.tolist()} ({nv} voxels) in "
+        f"{time.perf_counter() - t:.1f} s")
+    dev = torch.device("cuda:0")
+    P = torch.from_numpy(pts).to(dev)
+    D = torch.from_numpy(dirs).to(dev)
+    W = torch.from_numpy(w).to(dev)
+    shape = (int(dims[2]), int(dims[1]), int(dims[0]))
+    occ = torch.empty(shape, dtype=torch.int32, device=dev)
+    vd = torch.empty(shape + (3,), dtype=torch.float32, device=dev)
+    vc = torch.empty(shape, dtype=torch.float32, device=dev)
+    ctx = native.Context()
+    stream = torch.cuda.current_stream()
+
+    def step():
+        native.fuse_volume(P, D, origin, h, dims, weights=W, occ=occ, dir_out=vd, coherence=vc,
+                           stream=stream, ctx=ctx)
+
+    stages_list = [("clear", native.FD_STAGE_VOLUME_CLEAR),
+                   ("scatter", native.FD_STAGE_VOLUME_SCATTER),
+                   ("finalize", native.FD_STAGE_VOLUME_FINAL)]
+    el, stages = _timed(step, args, ctx, stages_list)
+    ms_step = el * 1e3 / args.steps
+    value = n_pts / (el / args.steps)
+    busy = int((occ > 0).sum())
+    # algorithmic HBM bytes per launch (each array touched once):
+    # clear writes the sums and counts (52 B/voxel); scatter reads 28 B per
+    # point and read-modify-writes the 52 B of each touched voxel; finalize
+    # reads the counts (4 B/voxel) and the sums of busy voxels (48 B) and
+    # writes orientation and coherence (16 B/voxel)
+    alg = {"clear": 52 * nv, "scatter": 28 * n_pts + 2 * 52 * busy,
+           "finalize": 20 * nv + 48 * busy}
+    gbs = {k: alg[k] / (stages[k] * 1e-3) / 1e9 for k in alg}
+    dom = max(stages, key=lambda k: stages[k])
+    log(f"volume: {ms_step:.3f} ms/step, {value / 1e6:.1f} M points/s, busy voxels {busy}, "
+        f"stages {json.dumps({k: round(v, 4) for k, v in stages.items()})}, "
+        f"GB/s {json.dumps({k: round(v, 1) for k, v in gbs.items()})}")
+    # accuracy of the volume against the ground-truth tangents: the
+    # orientation of each busy voxel vs the mean ground-truth line there
+    gtv = oracle.volume(pts, gt, origin, h, dims)["dir"].reshape(-1, 3)
+    got = vd.reshape(-1, 3).cpu().numpy().astype(np.float64)
+    sel = np.any(gtv != 0, axis=1) & np.any(got != 0, axis=1)
+    ang = np.degrees(np.arctan2(np.linalg.norm(np.cross(gtv[sel], got[sel]), axis=1),
+                                np.abs(np.sum(gtv[sel] * got[sel], 1))))
+    out = {
+        "metric": "oriented points fused into the occupancy / orientation volume per second",
+        "value": value, "unit": "points/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64 (int64 fixed-point sums)",
+        "data": "synthetic",
+        "config": {"workload": f"volume: {n_pts} oriented points of the realistic hairstyle, "
+                               f"2 mm voxels, grid {dims.tolist()}",
+                   "points": n_pts, "voxel_m": float(h), "dims": dims.tolist(),
+                   "voxels": nv, "busy_voxels": busy},
+        "roofline": {"bound": "hbm", "kernel": f"k_vol_{dom}", "achieved": gbs[dom],
+                     "peak": PEAK_HBM, "unit": "GB/s", "frac": gbs[dom] / PEAK_HBM,
+                     "traffic": traffic_of(f"k_vol_{dom}, realistic 2M points 2 mm"),
+                     "avg_launch_ms": stages[dom], "algorithmic_bytes": alg[dom]},
+        "stages_ms_per_launch": stages,
+        "stages_GB_per_s": gbs,
+        "orientation_err_vs_gt_deg": {"mean": float(ang.mean()), "median": float(np.median(ang))},
+    }
+    if not args.no_cpu_baseline:
+        threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or (os.cpu_count() or 1)
+        threads = min(threads, os.cpu_count() or threads)
+        done = 0
+        t0 = time.perf_counter()
+        while time.perf_counter() - t0 < args.cpu_seconds:
+            oracle.volume(pts, dirs, origin, h, dims, weights=w, n_threads=threads)
+            done += 1
+        el_c = time.perf_counter() - t0
+        out["cpu_baseline"] = {"value": done * n_pts / el_c, "unit": "points/s",
+                               "cores": threads, "kind": "oracle",
+                               "sample": f"{done} whole volumes of the same {n_pts} points, "
+                                         f"{el_c:.1f} s, binary64 oracle (sums in one thread, "
+                                         "eigenvectors with OpenMP)"}
+        log(f"cpu baseline: {out['cpu_baseline']}")
+    return out
+
+
 def run_copy(args):
     """Counter calibration: a plain device-to-device copy of 512 MiB, so the
     FETCH_SIZE / WRITE_SIZE counters can be read against known bytes."""
@@ -643,7 +737,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--workload", default="metric",
-                    choices=["metric", "plain", "learned", "gabor", "copy"])
+                    choices=["metric", "plain", "learned", "gabor", "volume", "copy"])
     ap.add_argument("--heads", type=int, default=8)
     ap.add_argument("--mlp", default=os.path.join(ROOT, "paper_2604_05794_amd", "weights",
                                                   "proposal_mlp.fdmlp"))
@@ -659,7 +753,7 @@ def main():
               "this build runs the one-GPU share.", file=sys.stderr)
         sys.exit(2)
     run = {"metric": run_metric, "plain": run_plain, "learned": run_learned,
-           "gabor": run_gabor, "copy": run_copy}[args.workload]
+           "gabor": run_gabor, "volume": run_volume, "copy": run_copy}[args.workload]
     out = run(args)
     print(json.dumps(out), flush=True)
 

@@ -283,6 +283,51 @@ void fd_gabor_params_init(fd_gabor_params* params);
 int fd_orientation_maps(const float* frames, int32_t n_frames, int32_t width, int32_t height,
                         const fd_gabor_params* params, void* theta_out, void* conf_out);
 
+/* ---- occupancy and orientation volume --------------------------------------
+ * The paper fuses the outer points (with the directions found above) and
+ * the inner points into one occupancy / orientation volume before growing
+ * strands (Sec. 3.2, opening paragraph) and gives no rule.  The reading:
+ *   voxel   point p is in voxel (ix, iy, iz), i_a = floor((p_a - o_a) / h)
+ *           with the subtraction and the division in binary32 (IEEE), if
+ *           0 <= i_a < dims_a on every axis; linear index
+ *           (iz * ny + iy) * nx + ix.  Points outside are ignored.
+ *   occupancy  the number of points in the voxel.
+ *   orientation  directions are lines, so they are averaged through the
+ *           structure tensor T = sum w_i d_i d_i^T of the voxel's points;
+ *           the orientation is the unit eigenvector of T's largest
+ *           eigenvalue l1 (sign: z > 0, else y > 0, else x >= 0) and the
+ *           coherence (l1 - l2) / l1 (1: one direction; 0: spread evenly in
+ *           a plane or in space).  A voxel without a weighted direction gets
+ *           orientation 0 and coherence 0.
+ * Each term w d_a d_b is formed in binary64 from the binary32 inputs, kept
+ * in [-1, 1] and rounded to a multiple of 2^-32; the sums are 64-bit
+ * integers, so the volume does not depend on the order of the points
+ * (deterministic), and each sum is within n_v * 2^-33 of the exact one.
+ * The eigenvector is found in binary64 (cyclic Jacobi). */
+#define FD_MAX_VOLUME_DIM 4096
+#define FD_MAX_VOLUME_VOXELS (1LL << 30)
+#define FD_MAX_VOLUME_POINTS ((1LL << 31) - 1)
+
+typedef struct fd_volume_grid {
+  float origin[3];   /* world position of the low corner of voxel (0, 0, 0) */
+  float voxel;       /* voxel edge h (same unit as the points), finite, > 0 */
+  int32_t dims[3];   /* nx, ny, nz in [1, FD_MAX_VOLUME_DIM], product
+                        <= FD_MAX_VOLUME_VOXELS */
+} fd_volume_grid;
+
+/* points, dirs: device n_points x 3 float (dirs unit or 0; a zero direction
+ * counts for the occupancy only); weights: device n_points float in [0, 1]
+ * (the point's reliability; values above 1 are taken as 1, below 0 or NaN
+ * as 0), or NULL for all 1.  Outputs (device, caller-owned, all written):
+ * occ_out nv uint32, dir_out nv x 3 float, coherence_out nv float, and
+ * tensor_out nv x 6 double (xx, yy, zz, xy, xz, yz: the fixed-point sums)
+ * or NULL.  nv = nx * ny * nz.  The sums live in the context's workspace
+ * (48 B per voxel), grown on demand.  FD_E_INVAL for a bad grid, size or
+ * pointer, with nothing launched.  Asynchronous on stream. */
+int fd_fuse_volume(const float* points, const float* dirs, const float* weights,
+                   int64_t n_points, const fd_volume_grid* grid, void* stream, fd_context* ctx,
+                   uint32_t* occ_out, float* dir_out, float* coherence_out, double* tensor_out);
+
 /* ---- tuning ---------------------------------------------------------------
  * Times the batched launch on the sample scenes for each shape of the
  * plain search (persistent: tiles per queue pop and resident grid size; or
@@ -319,7 +364,10 @@ enum {
   FD_STAGE_BATCHED = 7,   /* persistent batched launch */
   FD_STAGE_GABOR = 8,     /* orientation maps: filter bank, argmax, raw confidence */
   FD_STAGE_GABOR_NORM = 9, /* orientation maps: confidence normalisation */
-  FD_N_STAGES = 10
+  FD_STAGE_VOLUME_CLEAR = 10,   /* volume: zero occupancy and sums */
+  FD_STAGE_VOLUME_SCATTER = 11, /* volume: per-point voxel, occupancy, tensor */
+  FD_STAGE_VOLUME_FINAL = 12,   /* volume: per-voxel eigenvector, coherence */
+  FD_N_STAGES = 13
 };
 int fd_profile_enable(fd_context* ctx, int on);
 int fd_profile_read(fd_context* ctx, int stage, double* total_ms, int64_t* count);

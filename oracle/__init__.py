@@ -19,7 +19,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "liboracle.so")
-_SOURCES = ("fdo.c", "mlp.c", "gabor.c")
+_SOURCES = ("fdo.c", "mlp.c", "gabor.c", "volume.c")
 
 
 def build() -> str:
@@ -80,6 +80,10 @@ def lib():
                                       P, P, P, P]),
             "fdo_gabor_bank": (None, [i32, i32, dbl, dbl, dbl, P]),
             "fdo_gabor": (dbl, [P, i32, i32, i32, i32, P, P, P, P, P, i32]),
+            "fdo_voxel_of": (i64, [P, P, flt, P]),
+            "fdo_sym3_eigen": (None, [P, P, P]),
+            "fdo_tensor_orientation": (None, [P, P, P]),
+            "fdo_volume": (i64, [P, P, P, i64, P, flt, P, P, P, P, P, i32]),
             "fdo_mlp_n_params": (i64, []),
             "fdo_mlp_forward": (i32, [P, P, i32, i32, P]),
             "fdo_mlp_loss_grad": (dbl, [P, P, P, i32, i32, P]),
@@ -387,3 +391,50 @@ def gabor(image, bank, responses=False, n_threads=0):
     m = lib().fdo_gabor(_ptr(img), W, H, N, (w - 1) // 2, _ptr(bk), _ptr(th), _ptr(cf),
                         _ptr(rs) if responses else None, None, int(n_threads))
     return (th, cf, m, rs) if responses else (th, cf, m)
+
+
+# ---- occupancy and orientation volume (volume.c) ----------------------------
+
+def voxel_of(p, origin, voxel, dims):
+    """Linear voxel index of one point, or -1 outside the grid."""
+    return int(lib().fdo_voxel_of(_ptr(_c(p, np.float32)), _ptr(_c(origin, np.float32)),
+                                  float(np.float32(voxel)), _ptr(_c(dims, np.int32))))
+
+
+def sym3_eigen(A):
+    """Eigenvalues (descending) and eigenvectors (columns) of a symmetric 3x3."""
+    a = _c(A, np.float64).reshape(3, 3)
+    lam = np.zeros(3)
+    V = np.zeros((3, 3))
+    lib().fdo_sym3_eigen(_ptr(a), _ptr(lam), _ptr(V))
+    return lam, V
+
+
+def tensor_orientation(T6):
+    """(orientation, coherence) of one tensor (xx, yy, zz, xy, xz, yz)."""
+    d = np.zeros(3)
+    c = np.zeros(1)
+    lib().fdo_tensor_orientation(_ptr(_c(T6, np.float64)), _ptr(d), _ptr(c))
+    return d, float(c[0])
+
+
+def volume(points, dirs, origin, voxel, dims, weights=None, n_threads=0):
+    """Occupancy / orientation volume of oriented points: dict with occ
+    (nz, ny, nx) uint32, tensor (nz, ny, nx, 6), dir (nz, ny, nx, 3),
+    coherence (nz, ny, nx) and inside (points counted)."""
+    pts = _c(points, np.float32)
+    drs = _c(dirs, np.float32)
+    n = len(pts)
+    w = None if weights is None else _c(weights, np.float32)
+    dims = np.asarray(dims, np.int32)
+    nx, ny, nz = (int(x) for x in dims)
+    occ = np.zeros((nz, ny, nx), np.uint32)
+    T = np.zeros((nz, ny, nx, 6))
+    D = np.zeros((nz, ny, nx, 3))
+    C = np.zeros((nz, ny, nx))
+    inside = lib().fdo_volume(_ptr(pts), _ptr(drs), _ptr(w) if w is not None else None, n,
+                              _ptr(_c(origin, np.float32)), float(np.float32(voxel)),
+                              _ptr(_c(dims, np.int32)), _ptr(occ), _ptr(T), _ptr(D), _ptr(C),
+                              int(n_threads))
+    return dict(occ=occ, tensor=T, dir=D, coherence=C, inside=int(inside))
+

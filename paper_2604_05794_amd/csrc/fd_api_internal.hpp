@@ -62,6 +62,9 @@ struct fd_context {
   size_t cap_gabor_raw = 0;
   uint32_t* gabor_max = nullptr;
   size_t cap_gabor_max = 0;
+  // orientation volume: fixed-point structure-tensor sums, 6 per voxel
+  long long* vol_acc = nullptr;
+  size_t cap_vol_acc = 0;
   // tuned shape of the persistent search: tiles per queue pop, resident grid
   int tuned_chunk = 0;
   int tuned_grid = 0;

@@ -32,12 +32,15 @@ EXPORTS = (
     "fd_mlp_get_calibration", "fd_mlp_save", "fd_mlp_load", "fd_mlp_forward",
     "fd_mlp_loss_grad", "fd_mlp_train_step", "fd_mlp_destroy", "fd_features", "fd_autotune",
     "fd_tuned_shape", "fd_profile_enable", "fd_profile_read", "fd_gabor_params_init",
-    "fd_orientation_maps", "fd_last_error",
+    "fd_orientation_maps", "fd_fuse_volume", "fd_last_error",
 )
 
 FD_STAGE_TILING, FD_STAGE_TOPK, FD_STAGE_FUSE, FD_STAGE_FEATURES, FD_STAGE_MLP, \
     FD_STAGE_REFINE, FD_STAGE_FALLBACK, FD_STAGE_BATCHED, FD_STAGE_GABOR, \
-    FD_STAGE_GABOR_NORM = range(10)
+    FD_STAGE_GABOR_NORM, FD_STAGE_VOLUME_CLEAR, FD_STAGE_VOLUME_SCATTER, \
+    FD_STAGE_VOLUME_FINAL = range(13)
+FD_MAX_VOLUME_DIM = 4096
+FD_MAX_VOLUME_VOXELS = 1 << 30
 
 
 class FdError(RuntimeError):
@@ -82,6 +85,11 @@ class GaborParams(ctypes.Structure):
         ("wavelength", ctypes.c_float), ("out_dtype", ctypes.c_int32),
         ("stream", ctypes.c_void_p), ("ctx", ctypes.c_void_p),
     ]
+
+
+class VolumeGrid(ctypes.Structure):
+    _fields_ = [("origin", ctypes.c_float * 3), ("voxel", ctypes.c_float),
+                ("dims", ctypes.c_int32 * 3)]
 
 
 class Adam(ctypes.Structure):
@@ -133,6 +141,8 @@ def lib():
         "fd_gabor_params_init": (None, [ctypes.POINTER(GaborParams)]),
         "fd_orientation_maps": (ctypes.c_int, [P, i32, i32, i32, ctypes.POINTER(GaborParams),
                                                P, P]),
+        "fd_fuse_volume": (ctypes.c_int, [P, P, P, i64, ctypes.POINTER(VolumeGrid), P, P, P,
+                                          P, P, P]),
         "fd_last_error": (ctypes.c_char_p, []),
     }
     for name, (res, args) in sig.items():
@@ -442,6 +452,52 @@ def orientation_maps(frames, *, n_orient=32, radius=8, sigma_along=2.4, sigma_ac
     _check(lib().fd_orientation_maps(_ptr(frames), V, W, H, ctypes.byref(p), _ptr(theta),
                                      _ptr(conf)))
     return theta, conf
+
+
+def fuse_volume(points, dirs, origin, voxel, dims, *, weights=None, occ=None, dir_out=None,
+                coherence=None, tensor=False, stream=None, ctx: Optional["Context"] = None):
+    """fd_fuse_volume: occupancy (nz, ny, nx) uint32 (as int32 storage),
+    orientation (nz, ny, nx, 3) float32, coherence (nz, ny, nx) float32 and,
+    with tensor=True, the sums (nz, ny, nx, 6) float64."""
+    _dev_tensor(points, "points", torch.float32, (3,))
+    _dev_tensor(dirs, "dirs", torch.float32, (3,))
+    n = points.shape[0]
+    if dirs.shape[0] != n:
+        raise ValueError("points and dirs must have the same length")
+    if weights is not None:
+        _dev_tensor(weights, "weights", torch.float32)
+        if weights.shape != (n,):
+            raise ValueError("weights must be (n_points,)")
+    nx, ny, nz = (int(x) for x in dims)
+    dev = points.device
+    shape = (nz, ny, nx)
+    g = VolumeGrid()
+    for a in range(3):
+        g.origin[a] = float(origin[a])
+    g.voxel = float(voxel)
+    g.dims[0], g.dims[1], g.dims[2] = nx, ny, nz
+    if not all(1 <= x <= FD_MAX_VOLUME_DIM for x in (nx, ny, nz)) or \
+            nx * ny * nz > FD_MAX_VOLUME_VOXELS:
+        # the library rejects the grid before it looks at any output
+        _check(lib().fd_fuse_volume(_ptr(points), _ptr(dirs), _ptr(weights), n, ctypes.byref(g),
+                                    _stream_handle(stream), None, None, None, None, None))
+    if occ is None:
+        occ = torch.empty(shape, dtype=torch.int32, device=dev)
+    if dir_out is None:
+        dir_out = torch.empty(shape + (3,), dtype=torch.float32, device=dev)
+    if coherence is None:
+        coherence = torch.empty(shape, dtype=torch.float32, device=dev)
+    _dev_tensor(occ, "occ", torch.int32)
+    _dev_tensor(dir_out, "dir_out", torch.float32)
+    _dev_tensor(coherence, "coherence", torch.float32)
+    if occ.numel() != nx * ny * nz or dir_out.numel() != 3 * nx * ny * nz or \
+            coherence.numel() != nx * ny * nz:
+        raise ValueError("output sizes do not match the grid")
+    T = torch.empty(shape + (6,), dtype=torch.float64, device=dev) if tensor else None
+    _check(lib().fd_fuse_volume(_ptr(points), _ptr(dirs), _ptr(weights), n, ctypes.byref(g),
+                                _stream_handle(stream), ctx.handle if ctx is not None else None,
+                                _ptr(occ), _ptr(dir_out), _ptr(coherence), _ptr(T)))
+    return (occ, dir_out, coherence, T) if tensor else (occ, dir_out, coherence)
 
 
 def _scene_struct(sc):

@@ -445,6 +445,52 @@ def make_scene(recipe, seed, scale_points=1.0, n_threads=0) -> Scene:
     return Scene(pts, gt, cams, theta, conf, depth_out, np.zeros(3, np.float32), meta)
 
 
+def make_oriented_points(recipe, seed, n_points, noise_deg=10.0, outliers=0.1):
+    """Oriented points over the whole hair volume of a recipe's strands (the
+    strands of make_scene with the same seed): the stand-in for the fused
+    outer and inferred inner point sets.  Directions are the ground-truth
+    tangents turned by |N(0, noise_deg)| about a random perpendicular axis,
+    with weight U(0.5, 1); an outlier fraction gets a uniform random direction
+    and weight U(0, 0.5).  Returns (points, dirs, weights, gt), float32."""
+    if isinstance(recipe, str):
+        recipe = RECIPES[recipe]
+    r = dict(recipe)
+    ss = np.random.SeedSequence(int(seed))
+    s_strands, _, _, s_dirs = ss.spawn(4)
+    rng_s = np.random.Generator(np.random.PCG64(s_strands))
+    verts, offs = grow_strands(
+        rng_s, r["n_strands"], r["kinds"],
+        helix_r_mm=r.get("helix_r_mm", (5.0, 20.0)), pitch_mm=r.get("pitch_mm", (10.0, 40.0)),
+        wave_amp_mm=r.get("wave_amp_mm", (5.0, 15.0)),
+        wave_len_mm=r.get("wave_len_mm", (20.0, 60.0)),
+        length_mm=r.get("length_mm", (60.0, 150.0)))
+    rng = np.random.Generator(np.random.PCG64(s_dirs))
+    pts, gt = sample_points(rng, verts, offs, int(n_points), r.get("jitter", 2e-3))
+    g = gt.astype(np.float64)
+    a = rng.normal(size=g.shape)
+    a -= np.sum(a * g, axis=1, keepdims=True) * g
+    a /= np.maximum(np.linalg.norm(a, axis=1, keepdims=True), 1e-300)
+    ang = np.abs(rng.normal(0.0, math.radians(noise_deg), len(g)))[:, None]
+    d = np.cos(ang) * g + np.sin(ang) * a
+    w = rng.uniform(0.5, 1.0, len(g))
+    out = rng.uniform(size=len(g)) < outliers
+    d[out] = _unit(rng.normal(size=(int(out.sum()), 3)))
+    w[out] = rng.uniform(0.0, 0.5, int(out.sum()))
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    return (pts.astype(np.float32), d.astype(np.float32), w.astype(np.float32),
+            gt.astype(np.float32))
+
+
+def head_grid(points, voxel):
+    """A voxel grid covering the points with one empty voxel of margin:
+    (origin float32[3], voxel float32, dims int32[3] as nx, ny, nz)."""
+    h = np.float32(voxel)
+    lo = np.floor(points.min(axis=0) / h) * h - h
+    hi = points.max(axis=0)
+    dims = (np.ceil((hi - lo) / h) + 1).astype(np.int32)
+    return lo.astype(np.float32), h, dims
+
+
 def method_params(recipe):
     """Search parameters a recipe is run with (patch, candidates, iterations)."""
     if isinstance(recipe, str):
