@@ -19,7 +19,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "liboracle.so")
-_SOURCES = ("fdo.c", "mlp.c", "gabor.c", "volume.c")
+_SOURCES = ("fdo.c", "mlp.c", "gabor.c", "volume.c", "phg.c")
 
 
 def build() -> str:
@@ -31,6 +31,13 @@ def build() -> str:
     subprocess.run(cmd, check=True)
     os.replace(tmp, _LIB_PATH)
     return _LIB_PATH
+
+
+class TraceParams(ctypes.Structure):
+    _fields_ = [("step", ctypes.c_float), ("max_steps", ctypes.c_int32),
+                ("min_coherence", ctypes.c_float), ("max_bend_cos", ctypes.c_float),
+                ("voxel_cap", ctypes.c_int32), ("batch", ctypes.c_int32),
+                ("seed_mode", ctypes.c_int32), ("centre", ctypes.c_float * 3)]
 
 
 class Params(ctypes.Structure):
@@ -84,6 +91,9 @@ def lib():
             "fdo_sym3_eigen": (None, [P, P, P]),
             "fdo_tensor_orientation": (None, [P, P, P]),
             "fdo_volume": (i64, [P, P, P, i64, P, flt, P, P, P, P, P, i32]),
+            "fdo_grow": (i32, [P, flt, P, P, P, P, P, P, i32, ctypes.POINTER(TraceParams), P, P,
+                               P, P]),
+            "fdo_link": (None, [P, P, P, P, P, i32, flt, flt, P, i32]),
             "fdo_mlp_n_params": (i64, []),
             "fdo_mlp_forward": (i32, [P, P, i32, i32, P]),
             "fdo_mlp_loss_grad": (dbl, [P, P, P, i32, i32, P]),
@@ -437,4 +447,56 @@ def volume(points, dirs, origin, voxel, dims, weights=None, n_threads=0):
                               _ptr(_c(dims, np.int32)), _ptr(occ), _ptr(T), _ptr(D), _ptr(C),
                               int(n_threads))
     return dict(occ=occ, tensor=T, dir=D, coherence=C, inside=int(inside))
+
+
+# ---- parallel hair growing (phg.c) -------------------------------------------
+
+TRACE_DEFAULTS = dict(step=1e-3, max_steps=200, min_coherence=0.2,
+                      max_bend_cos=math.cos(math.radians(30.0)), voxel_cap=8, batch=4096)
+
+
+def grow(volume, grid, seeds, seed_dirs=None, crossings=None, seed_mode=0,
+         centre=(0.0, 0.0, 0.0), **kw):
+    """Traces seeds through an occupancy / orientation volume (dict with occ
+    (nz, ny, nx), dir (.., 3), coherence (..) in binary32); grid = (origin,
+    voxel, dims).  Returns verts (n, max_steps + 1, 3), n_verts, last_dir
+    and the crossing counts (updated copy of `crossings`)."""
+    prm = dict(TRACE_DEFAULTS)
+    prm.update(kw)
+    origin, h, dims = grid
+    dims = np.asarray(dims, np.int32)
+    occ = _c(volume["occ"], np.uint32)
+    vd = _c(volume["dir"], np.float32)
+    coh = _c(volume["coherence"], np.float32)
+    nv = int(np.prod(dims.astype(np.int64)))
+    assert occ.size == nv and vd.size == 3 * nv and coh.size == nv
+    sd = _c(seeds, np.float32).reshape(-1, 3)
+    n = len(sd)
+    dd = _c(seed_dirs, np.float32).reshape(-1, 3) if seed_dirs is not None else None
+    if seed_mode == 0 and dd is None:
+        raise ValueError("seed_mode 0 needs seed_dirs")
+    cr = np.zeros(nv, np.uint32) if crossings is None else _c(crossings, np.uint32).reshape(-1).copy()
+    p = TraceParams(float(prm["step"]), int(prm["max_steps"]), float(prm["min_coherence"]),
+                    float(prm["max_bend_cos"]), int(prm["voxel_cap"]), int(prm["batch"]),
+                    int(seed_mode), (ctypes.c_float * 3)(*[float(c) for c in centre]))
+    S = int(prm["max_steps"]) + 1
+    verts = np.zeros((n, S, 3), np.float32)
+    nvt = np.zeros(n, np.int32)
+    last = np.zeros((n, 3), np.float32)
+    lib().fdo_grow(_ptr(_c(origin, np.float32)), float(np.float32(h)), _ptr(dims), _ptr(occ),
+                   _ptr(vd), _ptr(coh), _ptr(sd), _ptr(dd) if dd is not None else None, n,
+                   ctypes.byref(p), _ptr(cr), _ptr(verts), _ptr(nvt), _ptr(last))
+    return dict(verts=verts, n_verts=nvt, last_dir=last, crossings=cr)
+
+
+def link(starts, start_dirs, ends, end_dirs, flags, max_dist, min_cos, n_threads=0):
+    """Eq. (13) links: succ[i] = the accepted successor piece of i, or -1."""
+    s = _c(starts, np.float32).reshape(-1, 3)
+    n = len(s)
+    succ = np.full(n, -1, np.int32)
+    lib().fdo_link(_ptr(s), _ptr(_c(start_dirs, np.float32)), _ptr(_c(ends, np.float32)),
+                   _ptr(_c(end_dirs, np.float32)), _ptr(_c(flags, np.uint8)), n,
+                   float(np.float32(max_dist)), float(np.float32(min_cos)), _ptr(succ),
+                   int(n_threads))
+    return succ
 
