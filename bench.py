@@ -23,6 +23,10 @@ depth visibility test of Sec. 3.1.1 with the scene's rendered depth maps
   volume     occupancy / orientation volume of 2M oriented points over the
              realistic hairstyle's volume (10 deg direction noise, 10%
              outliers) on a 2 mm grid.
+  phg        parallel hair growing through the volume of 8M such points on
+             a 3 mm grid: 20k guide strands from the scalp roots (batches of
+             4096, deferred occupancy), interior segments from every third
+             voxel traced both ways, and the Eq. 13 linking of all pieces.
 """
 from __future__ import annotations
 
@@ -712,6 +716,143 @@ def run_volume(args):
     return out
 
 
+def run_phg(args):
+    import numpy as np
+    import torch
+    import oracle
+    import scenegen
+    from paper_2604_05794_amd import native
+
+    n_pts, voxel, stride = 8_000_000, 0.003, 3
+    grow_kw = dict(step=1e-3, max_steps=200, min_coherence=0.1,
+                   max_bend_cos=math.cos(math.radians(45.0)), voxel_cap=8)
+    link_kw = dict(max_dist=3e-3, min_cos=math.cos(math.radians(30.0)))
+    t = time.perf_counter()
+    pts, dirs, w, _ = scenegen.make_oriented_points("realistic", args.seed, n_pts)
+    origin, h, dims = scenegen.head_grid(pts, voxel)
+    roots, normals = scenegen.scalp_seeds("realistic", args.seed)
+    lat = scenegen.lattice_seeds(origin, h, dims, stride)
+    nv = int(np.prod(dims.astype(np.int64)))
+    log(f"generated {n_pts} oriented points, grid {dims.tolist()}, {len(roots)} roots, "
+        f"{len(lat)} segment seeds in {time.perf_counter() - t:.1f} s")
+    dev = torch.device("cuda:0")
+    T = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    ctx = native.Context()
+    stream = torch.cuda.current_stream()
+    occ, vd, vc = native.fuse_volume(T(pts), T(dirs), origin, h, dims, weights=T(w), ctx=ctx,
+                                     stream=stream)
+    del pts, dirs, w
+    R, Nr, L = T(roots), T(normals), T(lat)
+    cr = torch.zeros(nv, dtype=torch.int32, device=dev)
+    ng, ns = len(roots), len(lat)
+    ar_g = torch.arange(ng, device=dev)
+    ar_s = torch.arange(ns, device=dev)
+    out = {}
+
+    def step():
+        cr.zero_()
+        g = native.grow_strands(occ, vd, vc, origin, h, dims, R, Nr, crossings=cr, batch=4096,
+                                stream=stream, ctx=ctx, **grow_kw)
+        f = native.grow_strands(occ, vd, vc, origin, h, dims, L, None, crossings=cr,
+                                batch=1 << 20, seed_mode=native.FD_SEED_AWAY, stream=stream,
+                                ctx=ctx, **grow_kw)
+        b = native.grow_strands(occ, vd, vc, origin, h, dims, L, None, crossings=cr,
+                                batch=1 << 20, seed_mode=native.FD_SEED_TOWARDS, stream=stream,
+                                ctx=ctx, **grow_kw)
+        # the piece table: guide strands (no predecessor), then segments
+        # (backward half reversed, then forward half)
+        gn, fn, bn = g[1].long(), f[1].long(), b[1].long()
+        S = torch.cat([R, b[0][ar_s, bn - 1]])
+        SD = torch.cat([Nr, b[2]])
+        E = torch.cat([g[0][ar_g, gn - 1], f[0][ar_s, fn - 1]])
+        ED = torch.cat([g[2], f[2]])
+        F = torch.cat([(gn > 1).to(torch.uint8), ((fn > 1) & (bn > 1)).to(torch.uint8) * 3])
+        succ = native.link_segments(S, SD, E, ED, F, stream=stream, ctx=ctx, **link_kw)
+        out.update(g=g, f=f, b=b, succ=succ, F=F)
+
+    stages_list = [("grow", native.FD_STAGE_GROW), ("crossings", native.FD_STAGE_GROW_CROSS),
+                   ("link", native.FD_STAGE_LINK)]
+    el, stages = _timed(step, args, ctx, stages_list)
+    n_launch = {"grow": math.ceil(ng / 4096) + 2, "crossings": math.ceil(ng / 4096) + 2,
+                "link": 1}
+    per_step = {k: stages[k] * n_launch[k] for k in stages}
+    ms_step = el * 1e3 / args.steps
+    g, f, b, succ, F = out["g"], out["f"], out["b"], out["succ"], out["F"]
+    gsteps = int((g[1] - 1).sum())
+    ssteps = int((f[1] - 1).sum() + (b[1] - 1).sum())
+    links = int((succ >= 0).sum())
+    # algorithmic bytes of the growing kernel per step: the voxel's count,
+    # coherence, crossing count and orientation (24 B) and the new vertex
+    # (12 B); per strand the seed, its direction and the outputs (40 B)
+    alg_grow = 36 * (gsteps + ssteps) + 40 * (ng + 2 * ns)
+    grow_ms = per_step["grow"]
+    achieved = alg_grow / (grow_ms * 1e-3) / 1e9
+    value = ng / (el / args.steps)
+    guide_len = (g[1] - 1).float() * grow_kw["step"] * 1e3
+    log(f"phg: {ms_step:.3f} ms/step; per step (ms) {json.dumps({k: round(v, 4) for k, v in per_step.items()})}; "
+        f"guide steps {gsteps}, segment steps {ssteps}, valid segments "
+        f"{int((F[ng:] == 3).sum())}, links {links}")
+    res = {
+        "metric": "guide strands grown and linked per second (parallel hair growing)",
+        "value": value, "unit": "strands/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"phg: {ng} scalp roots + {ns} interior seeds traced both ways "
+                               f"through the 3 mm volume of {n_pts} oriented points, Eq. 13 "
+                               "linking of all pieces",
+                   "roots": ng, "segment_seeds": ns, "grid": dims.tolist(), "voxel_m": float(h),
+                   **grow_kw, **link_kw, "batch": 4096},
+        "roofline": {"bound": "hbm", "kernel": "k_grow", "achieved": achieved,
+                     "peak": PEAK_HBM, "unit": "GB/s", "frac": achieved / PEAK_HBM,
+                     "traffic": traffic_of("k_grow, phg workload"),
+                     "avg_launch_ms": stages["grow"], "algorithmic_bytes_per_step": alg_grow,
+                     "note": "dependent voxel lookups: latency-bound, not bandwidth-bound"},
+        "stages_ms_per_launch": stages,
+        "stages_ms_per_step": per_step,
+        "result": {"guide_mean_length_mm": float(guide_len.mean()),
+                   "guide_median_length_mm": float(guide_len.median()),
+                   "guide_steps": gsteps, "segment_steps": ssteps,
+                   "valid_segments": int((F[ng:] == 3).sum()), "links": links},
+    }
+    if not args.no_cpu_baseline:
+        threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or (os.cpu_count() or 1)
+        threads = min(threads, os.cpu_count() or threads)
+        host = dict(occ=occ.cpu().numpy().view(np.uint32), dir=vd.cpu().numpy(),
+                    coherence=vc.cpu().numpy())
+        grid = (origin, h, dims)
+        t0 = time.perf_counter()
+        go = oracle.grow(host, grid, roots, normals, batch=4096, **grow_kw)
+        fo = oracle.grow(host, grid, lat, None, crossings=go["crossings"], batch=1 << 20,
+                         seed_mode=1, **grow_kw)
+        bo = oracle.grow(host, grid, lat, None, crossings=fo["crossings"], batch=1 << 20,
+                         seed_mode=2, **grow_kw)
+        t_grow = time.perf_counter() - t0
+        # linking: the pieces of a bounded sample of roots and segments (the
+        # brute-force pair test is quadratic)
+        gn, fn, bn = go["n_verts"], fo["n_verts"], bo["n_verts"]
+        k = min(ns, 12000)
+        S = np.concatenate([roots, bo["verts"][np.arange(k), bn[:k] - 1]])
+        SD = np.concatenate([normals, bo["last_dir"][:k]])
+        E = np.concatenate([go["verts"][np.arange(ng), gn - 1], fo["verts"][np.arange(k), fn[:k] - 1]])
+        ED = np.concatenate([go["last_dir"], fo["last_dir"][:k]])
+        Fo = np.concatenate([np.where(gn > 1, 1, 0), np.where((fn[:k] > 1) & (bn[:k] > 1), 3, 0)]).astype(np.uint8)
+        t1 = time.perf_counter()
+        oracle.link(S, SD, E, ED, Fo, link_kw["max_dist"], link_kw["min_cos"], n_threads=threads)
+        t_link = time.perf_counter() - t1
+        # scale the link time to all pieces by the quadratic pair count
+        n_all = ng + ns
+        t_link_all = t_link * (n_all / len(S)) ** 2
+        res["cpu_baseline"] = {
+            "value": ng / (t_grow + t_link_all), "unit": "strands/s", "cores": threads,
+            "kind": "oracle",
+            "sample": f"oracle growing of all {ng} roots and {ns} segment seeds both ways "
+                      f"({t_grow:.2f} s, one thread) and its brute-force linking of "
+                      f"{len(S)} of the {n_all} pieces ({t_link:.2f} s on {threads} threads), "
+                      f"scaled by the pair count to {t_link_all:.1f} s for all pieces"}
+        log(f"cpu baseline: {res['cpu_baseline']}")
+    return res
+
+
 def run_copy(args):
     """Counter calibration: a plain device-to-device copy of 512 MiB, so the
     FETCH_SIZE / WRITE_SIZE counters can be read against known bytes."""
@@ -737,7 +878,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--workload", default="metric",
-                    choices=["metric", "plain", "learned", "gabor", "volume", "copy"])
+                    choices=["metric", "plain", "learned", "gabor", "volume", "phg", "copy"])
     ap.add_argument("--heads", type=int, default=8)
     ap.add_argument("--mlp", default=os.path.join(ROOT, "paper_2604_05794_amd", "weights",
                                                   "proposal_mlp.fdmlp"))
@@ -753,7 +894,8 @@ def main():
               "this build runs the one-GPU share.", file=sys.stderr)
         sys.exit(2)
     run = {"metric": run_metric, "plain": run_plain, "learned": run_learned,
-           "gabor": run_gabor, "volume": run_volume, "copy": run_copy}[args.workload]
+           "gabor": run_gabor, "volume": run_volume, "phg": run_phg,
+           "copy": run_copy}[args.workload]
     out = run(args)
     print(json.dumps(out), flush=True)
 

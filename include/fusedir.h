@@ -328,6 +328,82 @@ int fd_fuse_volume(const float* points, const float* dirs, const float* weights,
                    int64_t n_points, const fd_volume_grid* grid, void* stream, fd_context* ctx,
                    uint32_t* occ_out, float* dir_out, float* coherence_out, double* tensor_out);
 
+/* ---- parallel hair growing -------------------------------------------------
+ * Strands grow through the volume above from many seeds at once, with the
+ * occupancy bookkeeping deferred to the end of each batch (Sec. 3.2.1), and
+ * short pieces are joined by the proximity and direction test of Eq. (13)
+ * (Sec. 3.2.2).  The paper gives no step, stopping rule, thresholds or
+ * conflict rule; the reading:
+ *   trace   from seed x_0 with reference r (the seed direction, or the
+ *           volume orientation at the seed pointed away from / towards
+ *           `centre`).  Step k reads the voxel v of x_{k-1} and stops if
+ *           x_{k-1} is outside the grid, v is empty, has coherence below
+ *           min_coherence, no orientation, or (voxel_cap > 0) was crossed
+ *           voxel_cap times or more by strands of earlier batches.  The
+ *           direction t is v's orientation, negated if t.r < 0; from the
+ *           second step on the trace also stops if t.r < max_bend_cos (the
+ *           first step may leave the seed direction at any angle: a root's
+ *           reference is the scalp normal).  x_k = x_{k-1} + step t, r = t.
+ *           Binary32 throughout: t.r is a0*b0, then fma(a1, b1, .), then
+ *           fma(a2, b2, .); each coordinate is fma(step, t_a, x_a).
+ *   batches seeds in order, `batch` at a time; a batch sees the crossing
+ *           counts left by the earlier batches (and the caller); after it,
+ *           each of its steps adds 1 to the count of the voxel it read.
+ *   link    piece i may be continued by piece j != i (flags: bit 0 valid,
+ *           bit 1 accepts a predecessor; j needs both) if
+ *           |e_i - s_j|^2 < max_dist^2 (binary32: dx*dx, then fma(dy, dy,
+ *           .), then fma(dz, dz, .), e_i - s_j per coordinate) and
+ *           <u_i, w_j> > min_cos (as t.r above), with e_i, u_i the end point
+ *           and direction of i and s_j, w_j the start point and direction of
+ *           j, both oriented root to tip.  Each i proposes its nearest such
+ *           j (then the lowest j); each j accepts its nearest proposer (then
+ *           the lowest i): succ[i] = j for accepted pairs, else -1. */
+#define FD_MAX_GROW_STEPS 4096
+#define FD_MAX_GROW_SEEDS (1 << 26)
+#define FD_MAX_LINK_PIECES (1 << 26)
+enum { FD_SEED_GIVEN = 0, FD_SEED_AWAY = 1, FD_SEED_TOWARDS = 2 };
+
+typedef struct fd_grow_params {
+  float step;            /* step length (grid unit), finite, > 0 */
+  int32_t max_steps;     /* 1..FD_MAX_GROW_STEPS */
+  float min_coherence;   /* finite */
+  float max_bend_cos;    /* finite; cos of the largest turn between steps */
+  int32_t voxel_cap;     /* >= 0; 0 = crossings never stop a trace */
+  int32_t batch;         /* >= 1 seeds per batch */
+  int32_t seed_mode;     /* FD_SEED_GIVEN (seed_dirs), FD_SEED_AWAY, FD_SEED_TOWARDS */
+  float centre[3];       /* for FD_SEED_AWAY / FD_SEED_TOWARDS */
+  void* stream;          /* hipStream_t */
+  fd_context* ctx;       /* NULL = the per-device default */
+} fd_grow_params;
+
+/* Defaults: step 1 mm, 200 steps, min_coherence 0.2, 30 degrees of bend,
+ * voxel_cap 8, batch 4096, FD_SEED_GIVEN, centre 0. */
+void fd_grow_params_init(fd_grow_params* params);
+
+/* grid, occ, dir, coherence: a volume as fd_fuse_volume writes it (device).
+ * seeds: device n_seeds x 3; seed_dirs: device n_seeds x 3 (FD_SEED_GIVEN
+ * only, else ignored).  crossings: device nv uint32, read and updated
+ * (zero it for a fresh start).  Outputs (device, caller-owned): verts
+ * n_seeds x (max_steps + 1) x 3 (entries past n_verts[i] are not written),
+ * n_verts n_seeds (>= 1: the seed itself), last_dir n_seeds x 3 (the last
+ * step's direction, negated for FD_SEED_TOWARDS so that a backward trace
+ * reports the direction root to tip; 0 without a step).  FD_E_INVAL for a
+ * bad grid, parameter, size or pointer, with nothing launched.
+ * Asynchronous on params->stream (2 launches per batch). */
+int fd_grow_strands(const fd_volume_grid* grid, const uint32_t* occ, const float* dir,
+                    const float* coherence, const float* seeds, const float* seed_dirs,
+                    int32_t n_seeds, const fd_grow_params* params, uint32_t* crossings,
+                    float* verts, int32_t* n_verts, float* last_dir);
+
+/* starts, start_dirs, ends, end_dirs: device n x 3 float (finite); flags:
+ * device n uint8; succ: device n int32 (written).  max_dist finite, > 0;
+ * min_cos finite.  Workspace (2^20 bucket counts and offsets, 28 B per
+ * piece) in the context, grown on demand.  FD_E_INVAL for a bad size,
+ * threshold or pointer.  Asynchronous on stream. */
+int fd_link_segments(const float* starts, const float* start_dirs, const float* ends,
+                     const float* end_dirs, const uint8_t* flags, int32_t n, float max_dist,
+                     float min_cos, void* stream, fd_context* ctx, int32_t* succ);
+
 /* ---- tuning ---------------------------------------------------------------
  * Times the batched launch on the sample scenes for each shape of the
  * plain search (persistent: tiles per queue pop and resident grid size; or
@@ -367,7 +443,10 @@ enum {
   FD_STAGE_VOLUME_CLEAR = 10,   /* volume: zero occupancy and sums */
   FD_STAGE_VOLUME_SCATTER = 11, /* volume: per-point voxel, occupancy, tensor */
   FD_STAGE_VOLUME_FINAL = 12,   /* volume: per-voxel eigenvector, coherence */
-  FD_N_STAGES = 13
+  FD_STAGE_GROW = 13,           /* growing: one batch of traces */
+  FD_STAGE_GROW_CROSS = 14,     /* growing: the batch's deferred crossing counts */
+  FD_STAGE_LINK = 15,           /* segment linking (all its kernels) */
+  FD_N_STAGES = 16
 };
 int fd_profile_enable(fd_context* ctx, int on);
 int fd_profile_read(fd_context* ctx, int stage, double* total_ms, int64_t* count);

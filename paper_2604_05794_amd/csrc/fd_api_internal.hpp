@@ -65,6 +65,21 @@ struct fd_context {
   // orientation volume: fixed-point structure-tensor sums, 6 per voxel
   long long* vol_acc = nullptr;
   size_t cap_vol_acc = 0;
+  // segment linking: start hash (counting sort) and proposals
+  uint32_t* link_counts = nullptr;
+  size_t cap_link_counts = 0;
+  uint32_t* link_cursor = nullptr;
+  size_t cap_link_cursor = 0;
+  uint32_t* link_sums = nullptr;
+  size_t cap_link_sums = 0;
+  uint32_t* link_bucket = nullptr;
+  size_t cap_link_bucket = 0;
+  uint32_t* link_perm = nullptr;
+  size_t cap_link_perm = 0;
+  unsigned long long* link_key = nullptr;
+  size_t cap_link_key = 0;
+  unsigned long long* link_best = nullptr;
+  size_t cap_link_best = 0;
   // tuned shape of the persistent search: tiles per queue pop, resident grid
   int tuned_chunk = 0;
   int tuned_grid = 0;

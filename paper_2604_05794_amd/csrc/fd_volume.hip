@@ -23,6 +23,7 @@
 
 #include "../../include/fusedir.h"
 #include "fd_api_internal.hpp"
+#include "fd_voxel.hpp"
 
 using namespace fd;
 
@@ -30,12 +31,6 @@ namespace {
 
 constexpr double kFix = 4294967296.0;        // 2^32 units per 1.0
 constexpr double kUnfix = 1.0 / 4294967296.0;
-
-struct GridDev {
-  float o[3];
-  float h;
-  int32_t dims[3];
-};
 
 __global__ __launch_bounds__(256) void k_vol_clear(uint4* __restrict__ acc, int64_t n16,
                                                    uint32_t* __restrict__ occ, int64_t nv) {
@@ -45,19 +40,6 @@ __global__ __launch_bounds__(256) void k_vol_clear(uint4* __restrict__ acc, int6
     acc[i] = z;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nv; i += stride)
     occ[i] = 0u;
-}
-
-// binary32 voxel index (subtraction, IEEE division, floor), -1 outside
-__device__ __forceinline__ int64_t voxel_index(const GridDev& g, float x, float y, float z) {
-  const float p[3] = {x, y, z};
-  int32_t ix[3];
-#pragma unroll
-  for (int a = 0; a < 3; ++a) {
-    const float q = (p[a] - g.o[a]) / g.h;
-    if (!(q >= 0.0f) || !(q < (float)g.dims[a])) return -1;
-    ix[a] = (int32_t)q;  // q >= 0: truncation is the floor
-  }
-  return ((int64_t)ix[2] * g.dims[1] + ix[1]) * g.dims[0] + ix[0];
 }
 
 __device__ __forceinline__ unsigned long long fix(double t) {

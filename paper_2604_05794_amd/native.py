@@ -32,13 +32,16 @@ EXPORTS = (
     "fd_mlp_get_calibration", "fd_mlp_save", "fd_mlp_load", "fd_mlp_forward",
     "fd_mlp_loss_grad", "fd_mlp_train_step", "fd_mlp_destroy", "fd_features", "fd_autotune",
     "fd_tuned_shape", "fd_profile_enable", "fd_profile_read", "fd_gabor_params_init",
-    "fd_orientation_maps", "fd_fuse_volume", "fd_last_error",
+    "fd_orientation_maps", "fd_fuse_volume", "fd_grow_params_init", "fd_grow_strands",
+    "fd_link_segments", "fd_last_error",
 )
 
 FD_STAGE_TILING, FD_STAGE_TOPK, FD_STAGE_FUSE, FD_STAGE_FEATURES, FD_STAGE_MLP, \
     FD_STAGE_REFINE, FD_STAGE_FALLBACK, FD_STAGE_BATCHED, FD_STAGE_GABOR, \
     FD_STAGE_GABOR_NORM, FD_STAGE_VOLUME_CLEAR, FD_STAGE_VOLUME_SCATTER, \
-    FD_STAGE_VOLUME_FINAL = range(13)
+    FD_STAGE_VOLUME_FINAL, FD_STAGE_GROW, FD_STAGE_GROW_CROSS, FD_STAGE_LINK = range(16)
+FD_SEED_GIVEN, FD_SEED_AWAY, FD_SEED_TOWARDS = 0, 1, 2
+FD_MAX_GROW_STEPS = 4096
 FD_MAX_VOLUME_DIM = 4096
 FD_MAX_VOLUME_VOXELS = 1 << 30
 
@@ -92,6 +95,16 @@ class VolumeGrid(ctypes.Structure):
                 ("dims", ctypes.c_int32 * 3)]
 
 
+class GrowParams(ctypes.Structure):
+    _fields_ = [
+        ("step", ctypes.c_float), ("max_steps", ctypes.c_int32),
+        ("min_coherence", ctypes.c_float), ("max_bend_cos", ctypes.c_float),
+        ("voxel_cap", ctypes.c_int32), ("batch", ctypes.c_int32),
+        ("seed_mode", ctypes.c_int32), ("centre", ctypes.c_float * 3),
+        ("stream", ctypes.c_void_p), ("ctx", ctypes.c_void_p),
+    ]
+
+
 class Adam(ctypes.Structure):
     _fields_ = [("lr", ctypes.c_float), ("beta1", ctypes.c_float),
                 ("beta2", ctypes.c_float), ("eps", ctypes.c_float)]
@@ -143,6 +156,10 @@ def lib():
                                                P, P]),
         "fd_fuse_volume": (ctypes.c_int, [P, P, P, i64, ctypes.POINTER(VolumeGrid), P, P, P,
                                           P, P, P]),
+        "fd_grow_params_init": (None, [ctypes.POINTER(GrowParams)]),
+        "fd_grow_strands": (ctypes.c_int, [ctypes.POINTER(VolumeGrid), P, P, P, P, P, i32,
+                                           ctypes.POINTER(GrowParams), P, P, P, P]),
+        "fd_link_segments": (ctypes.c_int, [P, P, P, P, P, i32, f32, f32, P, P, P]),
         "fd_last_error": (ctypes.c_char_p, []),
     }
     for name, (res, args) in sig.items():
@@ -498,6 +515,80 @@ def fuse_volume(points, dirs, origin, voxel, dims, *, weights=None, occ=None, di
                                 _stream_handle(stream), ctx.handle if ctx is not None else None,
                                 _ptr(occ), _ptr(dir_out), _ptr(coherence), _ptr(T)))
     return (occ, dir_out, coherence, T) if tensor else (occ, dir_out, coherence)
+
+
+def _grid_struct(origin, voxel, dims):
+    g = VolumeGrid()
+    for a in range(3):
+        g.origin[a] = float(origin[a])
+    g.voxel = float(voxel)
+    g.dims[0], g.dims[1], g.dims[2] = (int(x) for x in dims)
+    return g
+
+
+def grow_strands(occ, dir_vol, coherence, origin, voxel, dims, seeds, seed_dirs=None, *,
+                 crossings, seed_mode=FD_SEED_GIVEN, centre=(0.0, 0.0, 0.0), step=1e-3,
+                 max_steps=200, min_coherence=0.2, max_bend_cos=math.cos(math.radians(30.0)),
+                 voxel_cap=8, batch=4096, stream=None, ctx: Optional["Context"] = None):
+    """fd_grow_strands: traces from seeds through a volume (occ int32/uint32
+    storage, dir (.., 3) float32, coherence float32, as fuse_volume returns
+    them); crossings (nv,) int32 storage is read and updated.  Returns verts
+    (n, max_steps + 1, 3), n_verts (n,), last_dir (n, 3)."""
+    _dev_tensor(occ, "occ", torch.int32)
+    _dev_tensor(dir_vol, "dir", torch.float32)
+    _dev_tensor(coherence, "coherence", torch.float32)
+    _dev_tensor(crossings, "crossings", torch.int32)
+    nv = int(dims[0]) * int(dims[1]) * int(dims[2])
+    if occ.numel() != nv or dir_vol.numel() != 3 * nv or coherence.numel() != nv or \
+            crossings.numel() != nv:
+        raise ValueError("volume arrays do not match the grid")
+    _dev_tensor(seeds, "seeds", torch.float32, (3,))
+    n = seeds.shape[0]
+    if seed_dirs is not None:
+        _dev_tensor(seed_dirs, "seed_dirs", torch.float32, (3,))
+        if seed_dirs.shape[0] != n:
+            raise ValueError("seed_dirs must match seeds")
+    if not 1 <= int(max_steps) <= FD_MAX_GROW_STEPS:
+        raise FdError(FD_E_INVAL, f"max_steps must be in [1, {FD_MAX_GROW_STEPS}]")
+    dev = seeds.device
+    verts = torch.empty((n, int(max_steps) + 1, 3), dtype=torch.float32, device=dev)
+    n_verts = torch.empty((n,), dtype=torch.int32, device=dev)
+    last = torch.empty((n, 3), dtype=torch.float32, device=dev)
+    p = GrowParams()
+    lib().fd_grow_params_init(ctypes.byref(p))
+    p.step, p.max_steps, p.min_coherence = float(step), int(max_steps), float(min_coherence)
+    p.max_bend_cos, p.voxel_cap, p.batch = float(max_bend_cos), int(voxel_cap), int(batch)
+    p.seed_mode = int(seed_mode)
+    for a in range(3):
+        p.centre[a] = float(centre[a])
+    p.stream = _stream_handle(stream).value
+    p.ctx = ctx.handle.value if ctx is not None else None
+    g = _grid_struct(origin, voxel, dims)
+    _check(lib().fd_grow_strands(ctypes.byref(g), _ptr(occ), _ptr(dir_vol), _ptr(coherence),
+                                 _ptr(seeds), _ptr(seed_dirs), n, ctypes.byref(p),
+                                 _ptr(crossings), _ptr(verts), _ptr(n_verts), _ptr(last)))
+    return verts, n_verts, last
+
+
+def link_segments(starts, start_dirs, ends, end_dirs, flags, max_dist, min_cos, *, succ=None,
+                  stream=None, ctx: Optional["Context"] = None):
+    """fd_link_segments (Eq. 13): succ (n,) int32, the accepted successor of
+    each piece or -1."""
+    for t_, nm in ((starts, "starts"), (start_dirs, "start_dirs"), (ends, "ends"),
+                   (end_dirs, "end_dirs")):
+        _dev_tensor(t_, nm, torch.float32, (3,))
+    _dev_tensor(flags, "flags", torch.uint8)
+    n = starts.shape[0]
+    if any(x.shape[0] != n for x in (start_dirs, ends, end_dirs, flags)):
+        raise ValueError("piece arrays must have the same length")
+    if succ is None:
+        succ = torch.empty((n,), dtype=torch.int32, device=starts.device)
+    _dev_tensor(succ, "succ", torch.int32)
+    _check(lib().fd_link_segments(_ptr(starts), _ptr(start_dirs), _ptr(ends), _ptr(end_dirs),
+                                  _ptr(flags), n, float(max_dist), float(min_cos),
+                                  _stream_handle(stream), ctx.handle if ctx is not None else None,
+                                  _ptr(succ)))
+    return succ
 
 
 def _scene_struct(sc):

@@ -481,6 +481,40 @@ def make_oriented_points(recipe, seed, n_points, noise_deg=10.0, outliers=0.1):
             gt.astype(np.float32))
 
 
+def scalp_seeds(recipe, seed):
+    """Roots of a recipe's strands (those of make_scene / make_oriented_points
+    with the same seed) and the outward scalp normals there: the seeds of
+    the guide strands.  float32 (n_strands, 3) each."""
+    if isinstance(recipe, str):
+        recipe = RECIPES[recipe]
+    r = dict(recipe)
+    ss = np.random.SeedSequence(int(seed))
+    s_strands = ss.spawn(1)[0]
+    rng_s = np.random.Generator(np.random.PCG64(s_strands))
+    verts, offs = grow_strands(
+        rng_s, r["n_strands"], r["kinds"],
+        helix_r_mm=r.get("helix_r_mm", (5.0, 20.0)), pitch_mm=r.get("pitch_mm", (10.0, 40.0)),
+        wave_amp_mm=r.get("wave_amp_mm", (5.0, 15.0)),
+        wave_len_mm=r.get("wave_len_mm", (20.0, 60.0)),
+        length_mm=r.get("length_mm", (60.0, 150.0)))
+    roots = verts[offs[:-1]]
+    normals = _unit(roots)
+    return roots.astype(np.float32), normals.astype(np.float32)
+
+
+def lattice_seeds(origin, voxel, dims, stride):
+    """Centres of every stride-th voxel along each axis, x fastest: the
+    seeds of the interior segments.  float32 (n, 3)."""
+    nx, ny, nz = (int(d) for d in dims)
+    ix = np.arange(0, nx, stride)
+    iy = np.arange(0, ny, stride)
+    iz = np.arange(0, nz, stride)
+    Z, Y, X = np.meshgrid(iz, iy, ix, indexing="ij")
+    idx = np.stack([X.ravel(), Y.ravel(), Z.ravel()], 1).astype(np.float64)
+    pts = np.asarray(origin, np.float64) + (idx + 0.5) * float(voxel)
+    return pts.astype(np.float32)
+
+
 def head_grid(points, voxel):
     """A voxel grid covering the points with one empty voxel of margin:
     (origin float32[3], voxel float32, dims int32[3] as nx, ny, nz)."""
