@@ -57,13 +57,25 @@ def log(*a):
 # is a hash of them, and a changed source reports null.
 _SEARCH_SOURCES = ["fd_search.hpp", "fd_fuse.hip", "fd_device.hpp", "fd_kernels.hpp"]
 _BATCHED_SOURCES = _SEARCH_SOURCES + ["fd_batched.hip"]
+_GABOR_SOURCES = ["fd_gabor.hip"]
+_VOLUME_SOURCES = ["fd_volume.hip", "fd_voxel.hpp"]
+_PHG_SOURCES = ["fd_phg.hip", "fd_voxel.hpp"]
 TRAFFIC = {
-    "k_fuse, realistic 500k": {"read": 374.5e6, "write": 37.7e6, "files": _SEARCH_SOURCES,
-                               "src": "aa1735ce806007a0"},
-    "k_fuse, metric workload, per head": {"read": 291.4e6, "write": 19.1e6,
-                                          "files": _SEARCH_SOURCES, "src": "aa1735ce806007a0"},
-    "k_b_learned, metric workload": {"read": 2073.7e6, "write": 160.5e6,
-                                     "files": _BATCHED_SOURCES, "src": "51657d3af78c11f8"},
+    "k_fuse, realistic 500k": {"read": 385.5e6, "write": 37.7e6, "files": _SEARCH_SOURCES,
+                               "src": "320d01ce2a409293"},
+    "k_fuse, metric workload, per head": {"read": 293.6e6, "write": 19.1e6,
+                                          "files": _SEARCH_SOURCES, "src": "320d01ce2a409293"},
+    "k_b_learned, metric workload": {"read": 2080.4e6, "write": 160.6e6,
+                                     "files": _BATCHED_SOURCES, "src": "38a5470b652f7d7a"},
+    "k_gabor, 64 frames 1024^2": {"read": 1058.0e6, "write": 411.0e6, "files": _GABOR_SOURCES,
+                                  "src": "d336fd24608bb426"},
+    # the scatter's writes are its 14M atomics, 32 B each past the L2
+    "k_vol_scatter, realistic 2M points 2 mm": {"read": 56.0e6, "write": 448.0e6,
+                                                "files": _VOLUME_SOURCES,
+                                                "src": "248e93b5391b3f66"},
+    # per pass: the 5 guide batches and the 2 segment launches
+    "k_grow, phg workload": {"read": 202.0e6, "write": 30.7e6, "files": _PHG_SOURCES,
+                             "src": "eacb2ee3e42e0883"},
 }
 
 
