@@ -68,6 +68,44 @@ int main(void) {
     assert lay["sizeof.fd_camera"] == 64 and lay["fd_camera.R"] == 16 and lay["fd_camera.t"] == 52
 
 
+def test_new_struct_layouts_match_the_header():
+    from paper_2604_05794_amd import native
+    code = r"""
+#include <stdio.h>
+#include <stddef.h>
+#include "fusedir.h"
+#define F(s, f) printf("\"%s.%s\": %zu,\n", #s, #f, offsetof(s, f))
+int main(void) {
+  printf("{\n");
+  F(fd_gabor_params, n_orient); F(fd_gabor_params, wavelength); F(fd_gabor_params, out_dtype);
+  F(fd_gabor_params, stream); F(fd_gabor_params, ctx);
+  F(fd_volume_grid, origin); F(fd_volume_grid, voxel); F(fd_volume_grid, dims);
+  F(fd_grow_params, step); F(fd_grow_params, voxel_cap); F(fd_grow_params, seed_mode);
+  F(fd_grow_params, centre); F(fd_grow_params, stream); F(fd_grow_params, ctx);
+  printf("\"sizeof.fd_gabor_params\": %zu, \"sizeof.fd_volume_grid\": %zu,"
+         " \"sizeof.fd_grow_params\": %zu}\n", sizeof(fd_gabor_params),
+         sizeof(fd_volume_grid), sizeof(fd_grow_params));
+  return 0;
+}
+"""
+    with tempfile.TemporaryDirectory() as d:
+        c = os.path.join(d, "l.c")
+        open(c, "w").write(code)
+        exe = os.path.join(d, "l")
+        subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), c, "-o", exe], check=True)
+        lay = json.loads(subprocess.run([exe], capture_output=True, text=True,
+                                        check=True).stdout)
+    for cls, cname, fields in (
+            (native.GaborParams, "fd_gabor_params",
+             ("n_orient", "wavelength", "out_dtype", "stream", "ctx")),
+            (native.VolumeGrid, "fd_volume_grid", ("origin", "voxel", "dims")),
+            (native.GrowParams, "fd_grow_params",
+             ("step", "voxel_cap", "seed_mode", "centre", "stream", "ctx"))):
+        for f in fields:
+            assert getattr(cls, f).offset == lay[f"{cname}.{f}"], (cname, f)
+        assert ctypes.sizeof(cls) == lay[f"sizeof.{cname}"], cname
+
+
 def test_defaults_follow_the_paper():
     from paper_2604_05794_amd import native
     g = json.load(open(os.path.join(ROOT, "tests", "golden", "paper_hyperparameters.json")))
