@@ -69,10 +69,10 @@ TRAFFIC = {
                                      "files": _BATCHED_SOURCES, "src": "38a5470b652f7d7a"},
     "k_gabor, 64 frames 1024^2": {"read": 1058.0e6, "write": 411.0e6, "files": _GABOR_SOURCES,
                                   "src": "d336fd24608bb426"},
-    # the scatter's writes are its 14M atomics, 32 B each past the L2
-    "k_vol_scatter, realistic 2M points 2 mm": {"read": 56.0e6, "write": 448.0e6,
-                                                "files": _VOLUME_SOURCES,
-                                                "src": "248e93b5391b3f66"},
+    # the counting sort: keys and counts, the scan, the placement
+    "volume sort, realistic 2M points 2 mm": {"read": 319.8e6, "write": 237.4e6,
+                                              "files": _VOLUME_SOURCES,
+                                              "src": "b0b5904bb1ae7e7b"},
     # per pass: the 5 guide batches and the 2 segment launches
     "k_grow, phg workload": {"read": 202.0e6, "write": 30.7e6, "files": _PHG_SOURCES,
                              "src": "eacb2ee3e42e0883"},
@@ -667,21 +667,24 @@ def run_volume(args):
                            stream=stream, ctx=ctx)
 
     stages_list = [("clear", native.FD_STAGE_VOLUME_CLEAR),
-                   ("scatter", native.FD_STAGE_VOLUME_SCATTER),
-                   ("finalize", native.FD_STAGE_VOLUME_FINAL)]
+                   ("sort", native.FD_STAGE_VOLUME_SCATTER),
+                   ("reduce", native.FD_STAGE_VOLUME_FINAL)]
     el, stages = _timed(step, args, ctx, stages_list)
     ms_step = el * 1e3 / args.steps
     value = n_pts / (el / args.steps)
     busy = int((occ > 0).sum())
-    # algorithmic HBM bytes per launch (each array touched once):
-    # clear writes the sums and counts (52 B/voxel); scatter reads 28 B per
-    # point and read-modify-writes the 52 B of each touched voxel; finalize
-    # reads the counts (4 B/voxel) and the sums of busy voxels (48 B) and
-    # writes orientation and coherence (16 B/voxel)
-    alg = {"clear": 52 * nv, "scatter": 28 * n_pts + 2 * 52 * busy,
-           "finalize": 20 * nv + 48 * busy}
+    # algorithmic HBM bytes per launch (each array touched once): clear
+    # writes the counts (4 B per voxel); sort reads the points (12 B), writes
+    # voxel and rank (8 B), scans the counts into offsets (8 B read, 4 B
+    # written per voxel) and places each point (voxel and rank 8 B, offset
+    # 4 B, direction and weight 16 B read; 48 B of terms written); reduce
+    # reads count and offset per voxel (8 B) and the terms of each point
+    # (48 B) and writes orientation and coherence (16 B per voxel)
+    alg = {"clear": 4 * nv, "sort": 96 * n_pts + 12 * nv, "reduce": 24 * nv + 48 * n_pts}
     gbs = {k: alg[k] / (stages[k] * 1e-3) / 1e9 for k in alg}
     dom = max(stages, key=lambda k: stages[k])
+    kname = {"clear": "k_fill_u32 (counts)", "sort": "k_vol_key + scan + k_vol_place",
+             "reduce": "k_vol_reduce"}[dom]
     log(f"volume: {ms_step:.3f} ms/step, {value / 1e6:.1f} M points/s, busy voxels {busy}, "
         f"stages {json.dumps({k: round(v, 4) for k, v in stages.items()})}, "
         f"GB/s {json.dumps({k: round(v, 1) for k, v in gbs.items()})}")
@@ -702,9 +705,9 @@ def run_volume(args):
                                f"2 mm voxels, grid {dims.tolist()}",
                    "points": n_pts, "voxel_m": float(h), "dims": dims.tolist(),
                    "voxels": nv, "busy_voxels": busy},
-        "roofline": {"bound": "hbm", "kernel": f"k_vol_{dom}", "achieved": gbs[dom],
+        "roofline": {"bound": "hbm", "kernel": kname, "achieved": gbs[dom],
                      "peak": PEAK_HBM, "unit": "GB/s", "frac": gbs[dom] / PEAK_HBM,
-                     "traffic": traffic_of(f"k_vol_{dom}, realistic 2M points 2 mm"),
+                     "traffic": traffic_of(f"volume {dom}, realistic 2M points 2 mm"),
                      "avg_launch_ms": stages[dom], "algorithmic_bytes": alg[dom]},
         "stages_ms_per_launch": stages,
         "stages_GB_per_s": gbs,

@@ -321,8 +321,9 @@ typedef struct fd_volume_grid {
  * as 0), or NULL for all 1.  Outputs (device, caller-owned, all written):
  * occ_out nv uint32, dir_out nv x 3 float, coherence_out nv float, and
  * tensor_out nv x 6 double (xx, yy, zz, xy, xz, yz: the fixed-point sums)
- * or NULL.  nv = nx * ny * nz.  The sums live in the context's workspace
- * (48 B per voxel), grown on demand.  FD_E_INVAL for a bad grid, size or
+ * or NULL.  nv = nx * ny * nz.  The workspace (a counting sort of the
+ * points by voxel: 56 B per point, 4 B per voxel) lives in the context,
+ * grown on demand.  FD_E_INVAL for a bad grid, size or
  * pointer, with nothing launched.  Asynchronous on stream. */
 int fd_fuse_volume(const float* points, const float* dirs, const float* weights,
                    int64_t n_points, const fd_volume_grid* grid, void* stream, fd_context* ctx,
@@ -440,9 +441,9 @@ enum {
   FD_STAGE_BATCHED = 7,   /* persistent batched launch */
   FD_STAGE_GABOR = 8,     /* orientation maps: filter bank, argmax, raw confidence */
   FD_STAGE_GABOR_NORM = 9, /* orientation maps: confidence normalisation */
-  FD_STAGE_VOLUME_CLEAR = 10,   /* volume: zero occupancy and sums */
-  FD_STAGE_VOLUME_SCATTER = 11, /* volume: per-point voxel, occupancy, tensor */
-  FD_STAGE_VOLUME_FINAL = 12,   /* volume: per-voxel eigenvector, coherence */
+  FD_STAGE_VOLUME_CLEAR = 10,   /* volume: zero the counts */
+  FD_STAGE_VOLUME_SCATTER = 11, /* volume: voxel keys, counts, scan, sort by voxel */
+  FD_STAGE_VOLUME_FINAL = 12,   /* volume: per-voxel sums, eigenvector, coherence */
   FD_STAGE_GROW = 13,           /* growing: one batch of traces */
   FD_STAGE_GROW_CROSS = 14,     /* growing: the batch's deferred crossing counts */
   FD_STAGE_LINK = 15,           /* segment linking (all its kernels) */

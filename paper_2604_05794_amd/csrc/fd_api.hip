@@ -138,7 +138,8 @@ extern "C" void fd_context_destroy(fd_context* c) {
   void* bufs[] = {c->bbox, c->counts, c->cursor, c->scan_sums, c->lattice, c->fb_count, c->key,
                   c->perm, c->views, c->kcount, c->fb_list, c->prop, c->feats,
                   c->scene_tab, c->tile_tab, c->tile_queue, c->batch_key, c->batch_perm,
-                  c->gabor_bank, c->gabor_raw, c->gabor_max, c->vol_acc, c->link_counts,
+                  c->gabor_bank, c->gabor_raw, c->gabor_max, c->vol_key, c->vol_perm,
+                  c->vol_off, c->vol_bsum, c->vol_boff, c->vol_rsum, c->link_counts,
                   c->link_cursor, c->link_sums, c->link_bucket, c->link_perm, c->link_key,
                   c->link_best};
   for (void* p : bufs)

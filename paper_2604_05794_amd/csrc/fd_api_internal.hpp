@@ -62,9 +62,19 @@ struct fd_context {
   size_t cap_gabor_raw = 0;
   uint32_t* gabor_max = nullptr;
   size_t cap_gabor_max = 0;
-  // orientation volume: fixed-point structure-tensor sums, 6 per voxel
-  long long* vol_acc = nullptr;
-  size_t cap_vol_acc = 0;
+  // orientation volume: counting sort of the points by voxel
+  uint32_t* vol_key = nullptr;   // voxel and rank per point
+  size_t cap_vol_key = 0;
+  uint32_t* vol_perm = nullptr;  // sorted fixed-point terms, 48 B per point
+  size_t cap_vol_perm = 0;
+  uint32_t* vol_off = nullptr;   // first slot per voxel
+  size_t cap_vol_off = 0;
+  uint32_t* vol_bsum = nullptr;  // per block of 1024 voxels, padded to 1024 blocks
+  size_t cap_vol_bsum = 0;
+  uint32_t* vol_boff = nullptr;
+  size_t cap_vol_boff = 0;
+  uint32_t* vol_rsum = nullptr;
+  size_t cap_vol_rsum = 0;
   // segment linking: start hash (counting sort) and proposals
   uint32_t* link_counts = nullptr;
   size_t cap_link_counts = 0;
