@@ -85,9 +85,17 @@ __device__ __forceinline__ void write_feature_row(const SceneDev& s, float z_nea
   const T* th = (const T*)s.theta;
   const T* cf = (const T*)s.conf;
   const size_t plane = (size_t)s.W * s.H;
-  uint16_t out[7 * kSlots];
+  // the row in two halves of kSlots / 2 slots (7 x 16 bytes each), so that
+  // only half of it is held in registers at a time
+  constexpr int kHalf = kSlots / 2;
+  static_assert((7 * kHalf * 2) % 16 == 0, "half rows are whole 16-byte chunks");
+  uint4* dst = (uint4*)(feats + (size_t)row * (7 * kSlots));
 #pragma unroll
-  for (int k = 0; k < kSlots; ++k) {
+  for (int h = 0; h < 2; ++h) {
+  uint16_t out[7 * kHalf];
+#pragma unroll
+  for (int kk = 0; kk < kHalf; ++kk) {
+    const int k = h * kHalf + kk;
     float f[7] = {0, 0, 0, 0, 0, 0, 0};
     if (id[k] >= 0) {
       const int v = id[k];
@@ -159,12 +167,12 @@ __device__ __forceinline__ void write_feature_row(const SceneDev& s, float z_nea
       f[6] = 1.0f;
     }
 #pragma unroll
-    for (int e = 0; e < 7; ++e) out[7 * k + e] = feat_bf16(f[e]);
+    for (int e = 0; e < 7; ++e) out[7 * kk + e] = feat_bf16(f[e]);
   }
-  uint4* dst = (uint4*)(feats + (size_t)row * (7 * kSlots));
   const uint4* src = (const uint4*)out;
 #pragma unroll
-  for (int e = 0; e < (7 * kSlots * 2) / 16; ++e) dst[e] = src[e];
+  for (int e = 0; e < (7 * kHalf * 2) / 16; ++e) dst[h * ((7 * kHalf * 2) / 16) + e] = src[e];
+  }
 }
 
 // One lane per point: the kSlots most frontal eligible views, then their
@@ -221,9 +229,10 @@ __device__ __forceinline__ void topk_features_point(const SceneDev& s, const Sea
   const T* conf = (const T*)s.conf;
   const T* depth = (const T*)s.depth;
   const size_t plane = (size_t)s.W * s.H;
-  // views in groups of four, as in topk_point: a view no lane of the wave
-  // sees skips its confidence texels and both insertions
-  constexpr int kGroup = 4;
+  // views in groups of two (four as in topk_point would hold more registers
+  // next to the frontal list): a view no lane of the wave sees skips its
+  // confidence texels and both insertions
+  constexpr int kGroup = 2;
   for (int v0 = 0; v0 < s.V; v0 += kGroup) {
     Proj pr[kGroup];
     bool seen[kGroup];
