@@ -23,6 +23,9 @@ depth visibility test of Sec. 3.1.1 with the scene's rendered depth maps
   volume     occupancy / orientation volume of 2M oriented points over the
              realistic hairstyle's volume (10 deg direction noise, 10%
              outliers) on a 2 mm grid.
+  train      proposal-network training (112 -> 256 -> 256 -> 256 -> 3, BF16
+             MFMA): Adam steps of batch 4096 on the features and plain-search
+             directions of the realistic scene's 500k points.
   phg        parallel hair growing through the volume of 8M such points on
              a 3 mm grid: 20k guide strands from the scalp roots (batches of
              4096, deferred occupancy), interior segments from every third
@@ -868,6 +871,80 @@ def run_phg(args):
     return res
 
 
+PEAK_BF16_MFMA = 2500.0       # TFLOP/s, dense
+
+
+def run_train(args):
+    import numpy as np
+    import torch
+    import scenegen
+    from paper_2604_05794_amd import native
+
+    name = "realistic"
+    rec = scenegen.RECIPES[name]
+    sc = scenegen.make_scene(name, args.seed)
+    dev = torch.device("cuda:0")
+    T = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    pts, cams, th, cf, dm = T(sc.points), T(sc.cams), T(sc.theta), T(sc.conf), T(sc.depth)
+    # the training pairs: proposal features and the plain search's directions
+    feats = native.features(pts, cams, th, cf, head_centre=tuple(sc.head_centre), depth_maps=dm)
+    dirs, costs = native.fuse_directions(pts, cams, th, cf, depth_maps=dm, patch=rec["patch"],
+                                         n_candidates=rec["n_candidates"],
+                                         refine_iters=rec["refine_iters"], top_k=5)
+    ok = torch.isfinite(costs)
+    feats, dirs = feats[ok].contiguous(), dirs[ok].contiguous()
+    B = 4096
+    nb = feats.shape[0] // B
+    net = native.MLP(seed=args.seed)
+    loss = torch.empty(1, dtype=torch.float32, device=dev)
+    stream = torch.cuda.current_stream()
+    k = [0]
+
+    def step():
+        i = k[0] % nb
+        k[0] += 1
+        net.train_step(feats[i * B:(i + 1) * B], dirs[i * B:(i + 1) * B], lr=1e-3, loss=loss,
+                       stream=stream)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    l0 = float(loss)
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    ev0.record(stream)
+    for _ in range(args.steps):
+        step()
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    step_ms = ev0.elapsed_time(ev1) / args.steps
+    # flop per sample: forward 2 x 160,512 MAC; weight gradients the same;
+    # input gradients of layers 2-4 (layer 1's input needs none)
+    mac = 112 * 256 + 256 * 256 + 256 * 256 + 256 * 3
+    flop = 2 * mac * 3 - 2 * 112 * 256
+    achieved = flop * B / (step_ms * 1e-3) / 1e12
+    value = B * args.steps / el
+    log(f"train: {step_ms:.3f} ms/step (batch {B}), {value / 1e6:.2f} M samples/s, "
+        f"{achieved:.1f} TFLOP/s, loss {l0:.4f} -> {float(loss):.4f}")
+    return {
+        "metric": "proposal-network training samples per second (Adam, batch 4096)",
+        "value": value, "unit": "samples/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": el * 1e3 / args.steps, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "bf16 (f32 master, accumulation)",
+        "data": "synthetic",
+        "config": {"workload": "train: 112-256-256-256-3 GELU network, batch 4096, features and "
+                               "plain-search targets of the realistic scene",
+                   "batch": B, "pairs": int(feats.shape[0])},
+        "roofline": {"bound": "mfma", "kernel": "train step (k_gemm_bf16 GEMMs, loss, Adam)",
+                     "achieved": achieved, "peak": PEAK_BF16_MFMA, "unit": "TFLOP/s",
+                     "frac": achieved / PEAK_BF16_MFMA, "traffic": None,
+                     "avg_step_ms": step_ms, "flop_per_sample": flop},
+        "loss": {"after_warmup": l0, "final": float(loss)},
+    }
+
+
 def run_copy(args):
     """Counter calibration: a plain device-to-device copy of 512 MiB, so the
     FETCH_SIZE / WRITE_SIZE counters can be read against known bytes."""
@@ -893,7 +970,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--workload", default="metric",
-                    choices=["metric", "plain", "learned", "gabor", "volume", "phg", "copy"])
+                    choices=["metric", "plain", "learned", "gabor", "volume", "phg", "train",
+                             "copy"])
     ap.add_argument("--heads", type=int, default=8)
     ap.add_argument("--mlp", default=os.path.join(ROOT, "paper_2604_05794_amd", "weights",
                                                   "proposal_mlp.fdmlp"))
@@ -909,7 +987,7 @@ def main():
               "this build runs the one-GPU share.", file=sys.stderr)
         sys.exit(2)
     run = {"metric": run_metric, "plain": run_plain, "learned": run_learned,
-           "gabor": run_gabor, "volume": run_volume, "phg": run_phg,
+           "gabor": run_gabor, "volume": run_volume, "phg": run_phg, "train": run_train,
            "copy": run_copy}[args.workload]
     out = run(args)
     print(json.dumps(out), flush=True)

@@ -242,6 +242,8 @@ struct GemmArgs {
   float* df;     // EPI_GELU_BACK: float gradient out
   uint16_t* hq;  // bf16 out
   int64_t ldh;
+  int ksplit;    // > 1: K in ksplit slices, fp32 partial tiles to part (EPI_STORE only)
+  float* part;   // ksplit x M x N
 };
 
 __global__ __launch_bounds__(64) void k_gemm_bf16(GemmArgs g) {
@@ -250,7 +252,9 @@ __global__ __launch_bounds__(64) void k_gemm_bf16(GemmArgs g) {
   f32x4 acc[4];
 #pragma unroll
   for (int nt = 0; nt < 4; ++nt) acc[nt] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
-  for (int k0 = 0; k0 < g.K; k0 += 32) {
+  const int kslice = g.K / g.ksplit;
+  const int kz0 = blockIdx.z * kslice, kz1 = kz0 + kslice;
+  for (int k0 = kz0; k0 < kz1; k0 += 32) {
     bf16x8 a;
     const int64_t am = (int64_t)(m0 + c16) * g.sam;
 #pragma unroll
@@ -269,6 +273,15 @@ __global__ __launch_bounds__(64) void k_gemm_bf16(GemmArgs g) {
       }
       acc[nt] = mfma(a, b, acc[nt]);
     }
+  }
+  if (g.ksplit > 1) {  // partial tile of this K slice; k_gemm_reduce finishes
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt)
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+        g.part[((size_t)blockIdx.z * g.M + m0 + 4 * gr + r) * g.N + n0 + 16 * nt + c16] =
+            acc[nt][r];
+    return;
   }
 #pragma unroll
   for (int nt = 0; nt < 4; ++nt) {
@@ -291,6 +304,18 @@ __global__ __launch_bounds__(64) void k_gemm_bf16(GemmArgs g) {
       }
     }
   }
+}
+
+// The K slices of a split GEMM summed in slice order (deterministic), stored.
+__global__ void k_gemm_reduce(const float* __restrict__ part, int S, int M, int N, int m_real,
+                              int n_real, float* __restrict__ c, int64_t ldc) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= M * N) return;
+  const int m = i / N, n = i % N;
+  if (m >= m_real || n >= n_real) return;
+  float v = 0.0f;
+  for (int z = 0; z < S; ++z) v += part[((size_t)z * M + m) * N + n];
+  c[m * ldc + n] = v;
 }
 
 // feats (B x 112 bf16) -> X (B x 128 bf16, zero padded)
@@ -332,21 +357,28 @@ __global__ void k_out_loss(const uint16_t* __restrict__ h3, const uint16_t* __re
 }
 
 // Output-layer weight gradient (float): dW4[k][n] = sum_b h3[b][k] dy[b][n],
-// db4[n] = sum_b dy[b][n]; one thread per entry, batch in order.
-__global__ void k_out_wgrad(const uint16_t* __restrict__ h3, const float* __restrict__ dy, int B,
-                            float* __restrict__ grad) {
+// db4[n] = sum_b dy[b][n].  Deterministic two-pass form: thread i of chunk c
+// sums the kRowChunk rows of its chunk in order (k_outw_partial), then each
+// entry sums its chunk partials in a fixed order (k_col_finish).
+constexpr int kRowChunk = 32;
+constexpr int kMaxSplit = 16;  // K slices of a weight-gradient GEMM
+constexpr int kOutGrad = DH * DO + DO;  // dW4 then db4, contiguous in the parameters
+
+__global__ void k_outw_partial(const uint16_t* __restrict__ h3, const float* __restrict__ dy,
+                               int B, float* __restrict__ part) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int c = blockIdx.y;
+  if (i >= kOutGrad) return;
+  const int b0 = c * kRowChunk, b1 = min(B, b0 + kRowChunk);
+  float s = 0.0f;
   if (i < DH * DO) {
     const int k = i / DO, n = i % DO;
-    float s = 0.0f;
-    for (int b = 0; b < B; ++b) s += bf2f(h3[b * DH + k]) * dy[3 * b + n];
-    grad[OFF_W4 + i] = s;
-  } else if (i < DH * DO + DO) {
+    for (int b = b0; b < b1; ++b) s += bf2f(h3[b * DH + k]) * dy[3 * b + n];
+  } else {
     const int n = i - DH * DO;
-    float s = 0.0f;
-    for (int b = 0; b < B; ++b) s += dy[3 * b + n];
-    grad[OFF_B4 + n] = s;
+    for (int b = b0; b < b1; ++b) s += dy[3 * b + n];
   }
+  part[(size_t)c * kOutGrad + i] = s;
 }
 
 // dz3 = (dy W4^T) * gelu'(z3) (W4 as bfloat16 values); float and bfloat16 copies.
@@ -363,13 +395,30 @@ __global__ void k_out_back(const float* __restrict__ dy, const uint16_t* __restr
   dzq[i] = f2bf(d);
 }
 
-// bias gradient: grad[off + n] = sum_b dz[b][n] (float, batch in order)
-__global__ void k_col_sum(const float* __restrict__ dz, int B, int N, float* __restrict__ out) {
+// bias gradient: grad[off + n] = sum_b dz[b][n] (float), as partial sums
+// over chunks of kRowChunk rows in order, then the partials in a fixed order.
+__global__ void k_col_partial(const float* __restrict__ dz, int B, int N,
+                              float* __restrict__ part) {
   const int n = blockIdx.x * blockDim.x + threadIdx.x;
+  const int c = blockIdx.y;
   if (n >= N) return;
+  const int b0 = c * kRowChunk, b1 = min(B, b0 + kRowChunk);
   float s = 0.0f;
-  for (int b = 0; b < B; ++b) s += dz[(size_t)b * N + n];
-  out[n] = s;
+  for (int b = b0; b < b1; ++b) s += dz[(size_t)b * N + n];
+  part[(size_t)c * N + n] = s;
+}
+
+// One wave per entry: lane l sums partials l, l + 64, ... in order, then a
+// fixed shuffle tree (deterministic).
+__global__ void k_col_finish(const float* __restrict__ part, int chunks, int N,
+                             float* __restrict__ out) {
+  const int n = (int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
+  const int lane = (int)(threadIdx.x & 63u);
+  if (n >= N) return;  // wave-uniform
+  float s = 0.0f;
+  for (int c = lane; c < chunks; c += 64) s += part[(size_t)c * N + n];
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+  if (lane == 0) out[n] = s;
 }
 
 __global__ void k_sum_rows(const float* __restrict__ v, int B, float* __restrict__ out) {
@@ -444,6 +493,8 @@ struct fd_mlp {
   float* lrow = nullptr;                 // B
   float* dz = nullptr;                   // B x 256
   uint16_t* dzq = nullptr;               // B x 256
+  float* part = nullptr;                 // chunk partial sums of the gradients
+  float* split = nullptr;                // K-slice partial tiles of the weight gradients
   float* grad = nullptr;                 // N_PARAMS
   float* loss = nullptr;                 // 1
 };
@@ -470,6 +521,8 @@ int ensure_train_ws(fd_mlp* m, int B) {
   fr(m->lrow);
   fr(m->dz);
   fr(m->dzq);
+  fr(m->part);
+  fr(m->split);
   hipError_t e = hipSuccess;
   size_t Bs = (size_t)B;
   e = hipMalloc(&m->x, Bs * D0P * 2);
@@ -481,6 +534,9 @@ int ensure_train_ws(fd_mlp* m, int B) {
   if (e == hipSuccess) e = hipMalloc(&m->lrow, Bs * 4);
   if (e == hipSuccess) e = hipMalloc(&m->dz, Bs * DH * 4);
   if (e == hipSuccess) e = hipMalloc(&m->dzq, Bs * DH * 2);
+  if (e == hipSuccess)
+    e = hipMalloc(&m->part, (Bs / kRowChunk + 1) * (size_t)kOutGrad * 4);
+  if (e == hipSuccess) e = hipMalloc(&m->split, (size_t)kMaxSplit * DH * DH * 4);
   if (e != hipSuccess) {
     m->cap_batch = 0;
     return hip_error(e, "mlp training workspace");
@@ -490,15 +546,27 @@ int ensure_train_ws(fd_mlp* m, int B) {
 }
 
 int launch_gemm(const GemmArgs& g, hipStream_t st) {
-  dim3 grid(g.M / 16, g.N / 64);
+  dim3 grid(g.M / 16, g.N / 64, g.ksplit);
   hipLaunchKernelGGL(k_gemm_bf16, grid, dim3(64), 0, st, g);
+  if (g.ksplit > 1)
+    hipLaunchKernelGGL(k_gemm_reduce, dim3((g.M * g.N + 255) / 256), dim3(256), 0, st, g.part,
+                       g.ksplit, g.M, g.N, g.m_real, g.n_real, g.c, g.ldc);
   hipError_t e = hipGetLastError();
   return e == hipSuccess ? FD_OK : hip_error(e, "mlp gemm");
+}
+
+// K slices for a weight-gradient GEMM over a batch of B rows: up to
+// kMaxSplit, each at least 256 rows and a whole number of 32-row steps.
+int wgrad_split(int B) {
+  int S = 1;
+  while (S < kMaxSplit && B % (64 * S) == 0 && B / (2 * S) >= 256) S *= 2;
+  return S;
 }
 
 GemmArgs gemm_args() {
   GemmArgs g;
   std::memset(&g, 0, sizeof g);
+  g.ksplit = 1;
   return g;
 }
 
@@ -534,14 +602,19 @@ int loss_grad(fd_mlp* m, const uint16_t* feats, const float* tgt, int B, hipStre
   hipLaunchKernelGGL(k_out_loss, dim3((B + 255) / 256), dim3(256), 0, st, m->h[2], m->pk.w4t,
                      m->pk.bias + 3 * DH, tgt, B, m->dy, m->lrow);
   hipLaunchKernelGGL(k_sum_rows, dim3(1), dim3(256), 0, st, m->lrow, B, m->loss);
-  hipLaunchKernelGGL(k_out_wgrad, dim3((DH * DO + DO + 255) / 256), dim3(256), 0, st, m->h[2],
-                     m->dy, B, m->grad);
+  const int chunks = (B + kRowChunk - 1) / kRowChunk;
+  hipLaunchKernelGGL(k_outw_partial, dim3((kOutGrad + 255) / 256, chunks), dim3(256), 0, st,
+                     m->h[2], m->dy, B, m->part);
+  hipLaunchKernelGGL(k_col_finish, dim3((kOutGrad + 3) / 4), dim3(256), 0, st, m->part, chunks,
+                     kOutGrad, m->grad + OFF_W4);
   hipLaunchKernelGGL(k_out_back, dim3((B * DH + 255) / 256), dim3(256), 0, st, m->dy,
                      m->pk.w4t, m->z[2], B, m->dz, m->dzq);
   const int offW[3] = {OFF_W1, OFF_W2, OFF_W3}, offB[3] = {OFF_B1, OFF_B2, OFF_B3};
   for (int l = 2; l >= 0; --l) {
     // bias gradient of layer l from the float dz
-    hipLaunchKernelGGL(k_col_sum, dim3(1), dim3(DH), 0, st, m->dz, B, DH, m->grad + offB[l]);
+    hipLaunchKernelGGL(k_col_partial, dim3(1, chunks), dim3(DH), 0, st, m->dz, B, DH, m->part);
+    hipLaunchKernelGGL(k_col_finish, dim3(DH / 4), dim3(256), 0, st, m->part, chunks, DH,
+                       m->grad + offB[l]);
     // weight gradient: dW_l[k][n] = sum_b h_{l-1}[b][k] dzq[b][n]
     {
       GemmArgs g = gemm_args();
@@ -560,6 +633,8 @@ int loss_grad(fd_mlp* m, const uint16_t* feats, const float* tgt, int B, hipStre
       g.epi = EPI_STORE;
       g.c = m->grad + offW[l];
       g.ldc = DH;
+      g.ksplit = wgrad_split(B);
+      g.part = m->split;
       if ((r = launch_gemm(g, st))) return r;
     }
     if (l == 0) break;
@@ -650,7 +725,7 @@ extern "C" void fd_mlp_destroy(fd_mlp* m) {
   (void)hipDeviceSynchronize();
   void* bufs[] = {m->master, m->adam_m, m->adam_v, m->grad, m->loss, m->pk.w1t, m->pk.w2t,
                   m->pk.w3t, m->pk.w4t, m->pk.bias, m->x, m->dy, m->lrow, m->dz, m->dzq,
-                  m->z[0], m->z[1], m->z[2], m->h[0], m->h[1], m->h[2]};
+                  m->part, m->split, m->z[0], m->z[1], m->z[2], m->h[0], m->h[1], m->h[2]};
   for (void* p : bufs)
     if (p) (void)hipFree(p);
   delete m;

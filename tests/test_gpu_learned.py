@@ -73,12 +73,15 @@ def test_forward_ragged_batches():
         assert torch.equal(part, full[:B]), B
 
 
-def test_gradient_matches_bfloat16_oracle():
+@pytest.mark.parametrize("batch", [64, 352, 1024])
+def test_gradient_matches_bfloat16_oracle(batch):
+    """Whole (64) and ragged (352) chunks of the gradient column sums, and
+    (1024) the weight-gradient products in four K slices."""
     nat = _native()
     p = _rand_params(3)
-    x = _rand_feats(3, 64)
+    x = _rand_feats(3, batch)
     rng = np.random.default_rng(3)
-    t = rng.normal(size=(64, 3))
+    t = rng.normal(size=(batch, 3))
     t = (t / np.linalg.norm(t, axis=1, keepdims=True)).astype(np.float32)
     net = nat.MLP(seed=0)
     net.set_params(p)
