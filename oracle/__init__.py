@@ -94,6 +94,7 @@ def lib():
             "fdo_grow": (i32, [P, flt, P, P, P, P, P, P, i32, ctypes.POINTER(TraceParams), P, P,
                                P, P]),
             "fdo_link": (None, [P, P, P, P, P, i32, flt, flt, P, i32]),
+            "fdo_assemble": (i64, [P, P, i32, i32, P, P, i32, P, P, i32, i32, P, P, P, P]),
             "fdo_mlp_n_params": (i64, []),
             "fdo_mlp_forward": (i32, [P, P, i32, i32, P]),
             "fdo_mlp_loss_grad": (dbl, [P, P, P, i32, i32, P]),
@@ -499,4 +500,30 @@ def link(starts, start_dirs, ends, end_dirs, flags, max_dist, min_cos, n_threads
                    float(np.float32(max_dist)), float(np.float32(min_cos)), _ptr(succ),
                    int(n_threads))
     return succ
+
+
+def assemble(guide, fwd, bwd, succ):
+    """Strands from linked pieces: guide, fwd, bwd are grow() results (guide
+    traces; forward and backward traces of the segment seeds); succ over
+    the guide pieces then the segments.  Returns (offsets (n_guide + 1),
+    verts (total, 3), pieces per strand)."""
+    gv = _c(guide["verts"], np.float32)
+    fv = _c(fwd["verts"], np.float32)
+    bv = _c(bwd["verts"], np.float32)
+    ng, ns = len(gv), len(fv)
+    strides = (gv.shape[1], fv.shape[1], bv.shape[1])
+    gn = _c(guide["n_verts"], np.int32)
+    fn = _c(fwd["n_verts"], np.int32)
+    bn = _c(bwd["n_verts"], np.int32)
+    sc = _c(succ, np.int32)
+    lens = np.zeros(ng, np.int64)
+    pcs = np.zeros(ng, np.int32)
+    args = (_ptr(gv), _ptr(gn), ng, strides[0], _ptr(fv), _ptr(fn), strides[1], _ptr(bv),
+            _ptr(bn), strides[2], ns, _ptr(sc), _ptr(lens), _ptr(pcs))
+    total = lib().fdo_assemble(*args, None)
+    out = np.zeros((max(total, 1), 3), np.float32)
+    lib().fdo_assemble(*args, _ptr(out))
+    off = np.zeros(ng + 1, np.int64)
+    off[1:] = np.cumsum(lens)
+    return off, out[:total], pcs
 

@@ -194,3 +194,45 @@ void fdo_link(const float* starts, const float* start_dirs, const float* ends,
   free(prop);
   free(prop_d);
 }
+
+/* Strands from linked pieces (the output of Sec. 3.2.2): strand g starts
+ * with guide trace g; its successor chain (succ over the n_guide guide
+ * pieces, then the n_seg segments) appends each segment root to tip: the
+ * backward trace reversed without its seed, then the forward trace (seed
+ * included).  A chain ends at -1 or at a guide piece.  Each trace set has
+ * its own stride (max_steps + 1 of its call).  lengths: n_guide vertex
+ * counts; pieces: n_guide piece counts.  With out (3 x the total),
+ * the vertices are written strand after strand; returns the total. */
+int64_t fdo_assemble(const float* guide_v, const int32_t* guide_n, int32_t n_guide,
+                     int32_t g_stride, const float* fwd_v, const int32_t* fwd_n, int32_t f_stride,
+                     const float* bwd_v, const int32_t* bwd_n, int32_t b_stride, int32_t n_seg,
+                     const int32_t* succ, int64_t* lengths, int32_t* pieces, float* out) {
+  int64_t total = 0;
+  for (int32_t g = 0; g < n_guide; ++g) {
+    int64_t len = guide_n[g];
+    int32_t np = 1;
+    if (out)
+      memcpy(out + 3 * total, guide_v + (size_t)g * g_stride * 3,
+             sizeof(float) * 3 * (size_t)guide_n[g]);
+    int64_t pos = total + guide_n[g];
+    int32_t j = succ[g];
+    for (int32_t hop = 0; j >= n_guide && j < n_guide + n_seg && hop < n_guide + n_seg; ++hop) {
+      const int32_t s = j - n_guide;
+      const float* b = bwd_v + (size_t)s * b_stride * 3;
+      const float* f = fwd_v + (size_t)s * f_stride * 3;
+      for (int k = bwd_n[s] - 1; k >= 1; --k) {
+        if (out) memcpy(out + 3 * pos, b + 3 * k, sizeof(float) * 3);
+        ++pos;
+      }
+      if (out) memcpy(out + 3 * pos, f, sizeof(float) * 3 * (size_t)fwd_n[s]);
+      pos += fwd_n[s];
+      len += (bwd_n[s] - 1) + fwd_n[s];
+      ++np;
+      j = succ[j];
+    }
+    lengths[g] = len;
+    pieces[g] = np;
+    total += len;
+  }
+  return total;
+}

@@ -228,3 +228,63 @@ def test_chains_conflicts_and_ties():
     # a piece never continues itself
     assert oracle.link(S[:1], D[:1], S[:1], D[:1], np.array([3], np.uint8), 0.003,
                        COS30).tolist() == [-1]
+
+
+def _trace(points, S):
+    v = np.zeros((S, 3), np.float32)
+    v[:len(points)] = points
+    return v
+
+
+def test_assembly_concatenates_a_chain_root_to_tip():
+    S = 6
+    z = lambda a, b: np.array([[0, 0, t] for t in np.arange(a, b, 0.001)], np.float32)
+    guide = dict(verts=_trace(z(0.0, 0.004), S)[None], n_verts=np.array([4], np.int32))
+    # segment 0 from seed 0.0065: backward to 0.0045, forward to 0.0075;
+    # segment 1 from seed 0.0095: backward 0.0085, forward 0.0105
+    b0 = np.array([[0, 0, 0.0065], [0, 0, 0.0055], [0, 0, 0.0045]], np.float32)
+    f0 = np.array([[0, 0, 0.0065], [0, 0, 0.0075]], np.float32)
+    b1 = np.array([[0, 0, 0.0095], [0, 0, 0.0085]], np.float32)
+    f1 = np.array([[0, 0, 0.0095], [0, 0, 0.0105]], np.float32)
+    fwd = dict(verts=np.stack([_trace(f0, S), _trace(f1, S)]), n_verts=np.array([2, 2], np.int32))
+    bwd = dict(verts=np.stack([_trace(b0, S), _trace(b1, S)]), n_verts=np.array([3, 2], np.int32))
+    off, verts, pieces = oracle.assemble(guide, fwd, bwd, np.array([1, 2, -1], np.int32))
+    want = np.concatenate([z(0.0, 0.004), b0[:0:-1], f0, b1[:0:-1], f1])
+    assert off.tolist() == [0, len(want)] and pieces.tolist() == [3]
+    assert np.array_equal(verts, want)
+    assert np.all(np.diff(verts[:, 2]) > 0)          # root to tip, no repeated seed
+    # an unlinked guide strand is its own trace; a chain stops at a guide piece
+    off, verts, pieces = oracle.assemble(guide, fwd, bwd, np.array([-1, 2, -1], np.int32))
+    assert off.tolist() == [0, 4] and pieces.tolist() == [1]
+    off, verts, pieces = oracle.assemble(guide, fwd, bwd, np.array([1, 0, -1], np.int32))
+    assert pieces.tolist() == [2] and off[-1] == 4 + 2 + 2
+
+
+def test_assembled_strands_are_continuous_on_a_traced_volume():
+    """Grow, link and assemble on a uniform field: inside a piece every step
+    has the step length; at a joint the gap is within the link distance."""
+    dims = (40, 10, 10)
+    grid = _grid(dims, h=0.005)
+    u = np.array([1.0, 0.0, 0.0], np.float32)
+    vol = _uniform(dims, u)
+    roots = np.array([[0.001, 0.025, 0.025]], np.float32)
+    g = oracle.grow(vol, grid, roots, u[None], step=0.004, max_steps=10, voxel_cap=0)
+    seeds = np.array([[0.0495, 0.025, 0.025], [0.0775, 0.025, 0.025]], np.float32)
+    f = oracle.grow(vol, grid, seeds, seed_mode=1, centre=(-1.0, 0.025, 0.025), step=0.004,
+                    max_steps=5, voxel_cap=0)
+    b = oracle.grow(vol, grid, seeds, seed_mode=2, centre=(-1.0, 0.025, 0.025), step=0.004,
+                    max_steps=1, voxel_cap=0)
+    ng = 1
+    S_ = np.concatenate([roots, b["verts"][np.arange(2), b["n_verts"] - 1]])
+    SD = np.concatenate([u[None], b["last_dir"]])
+    E = np.concatenate([g["verts"][np.arange(1), g["n_verts"] - 1],
+                        f["verts"][np.arange(2), f["n_verts"] - 1]])
+    ED = np.concatenate([g["last_dir"], f["last_dir"]])
+    F = np.array([1, 3, 3], np.uint8)
+    succ = oracle.link(S_, SD, E, ED, F, 0.006, COS30)
+    assert succ.tolist() == [1, 2, -1]
+    off, verts, pieces = oracle.assemble(g, f, b, succ)
+    assert pieces.tolist() == [3]
+    d = np.linalg.norm(np.diff(verts.astype(np.float64), axis=0), axis=1)
+    assert np.all((np.abs(d - 0.004) < 1e-6) | (d < 0.006))
+    assert np.all(np.diff(verts[:, 0]) > 0)
