@@ -29,7 +29,8 @@ depth visibility test of Sec. 3.1.1 with the scene's rendered depth maps
   phg        parallel hair growing through the volume of 8M such points on
              a 3 mm grid: 20k guide strands from the scalp roots (batches of
              4096, deferred occupancy), interior segments from every third
-             voxel traced both ways, and the Eq. 13 linking of all pieces.
+             voxel traced both ways, the Eq. 13 linking of all pieces and
+             the assembly of the linked pieces into strands.
 """
 from __future__ import annotations
 
@@ -765,6 +766,9 @@ def run_phg(args):
     ng, ns = len(roots), len(lat)
     ar_g = torch.arange(ng, device=dev)
     ar_s = torch.arange(ns, device=dev)
+    # room for every strand at its longest: all traces at full length
+    S1 = grow_kw["max_steps"] + 1
+    strands = torch.empty((ng * S1 + 2 * ns * S1, 3), dtype=torch.float32, device=dev)
     out = {}
 
     def step():
@@ -786,7 +790,9 @@ def run_phg(args):
         ED = torch.cat([g[2], f[2]])
         F = torch.cat([(gn > 1).to(torch.uint8), ((fn > 1) & (bn > 1)).to(torch.uint8) * 3])
         succ = native.link_segments(S, SD, E, ED, F, stream=stream, ctx=ctx, **link_kw)
-        out.update(g=g, f=f, b=b, succ=succ, F=F)
+        off, _, pieces = native.assemble_strands(g, f, b, succ, out=strands, stream=stream,
+                                                 ctx=ctx)
+        out.update(g=g, f=f, b=b, succ=succ, F=F, off=off, pieces=pieces)
 
     stages_list = [("grow", native.FD_STAGE_GROW), ("crossings", native.FD_STAGE_GROW_CROSS),
                    ("link", native.FD_STAGE_LINK)]
@@ -799,6 +805,8 @@ def run_phg(args):
     gsteps = int((g[1] - 1).sum())
     ssteps = int((f[1] - 1).sum() + (b[1] - 1).sum())
     links = int((succ >= 0).sum())
+    off, pieces = out["off"], out["pieces"]
+    slen = (off[1:] - off[:-1]).float() * grow_kw["step"] * 1e3 - grow_kw["step"] * 1e3
     # algorithmic bytes of the growing kernel per step: the voxel's count,
     # coherence, crossing count and orientation (24 B) and the new vertex
     # (12 B); per strand the seed, its direction and the outputs (40 B)
@@ -827,7 +835,11 @@ def run_phg(args):
                      "note": "dependent voxel lookups: latency-bound, not bandwidth-bound"},
         "stages_ms_per_launch": stages,
         "stages_ms_per_step": per_step,
-        "result": {"guide_mean_length_mm": float(guide_len.mean()),
+        "result": {"strand_mean_length_mm": float(slen.mean()),
+                   "strand_median_length_mm": float(slen.median()),
+                   "strands_with_segments": int((pieces > 1).sum()),
+                   "strand_vertices": int(off[-1]),
+                   "guide_mean_length_mm": float(guide_len.mean()),
                    "guide_median_length_mm": float(guide_len.median()),
                    "guide_steps": gsteps, "segment_steps": ssteps,
                    "valid_segments": int((F[ng:] == 3).sum()), "links": links},

@@ -405,6 +405,31 @@ int fd_link_segments(const float* starts, const float* start_dirs, const float* 
                      const float* end_dirs, const uint8_t* flags, int32_t n, float max_dist,
                      float min_cos, void* stream, fd_context* ctx, int32_t* succ);
 
+/* Strands from linked pieces.  Piece g < n_guide is guide trace g (from
+ * fd_grow_strands with the scalp roots); piece n_guide + s is segment s,
+ * made of backward trace s (FD_SEED_TOWARDS) reversed without its seed,
+ * then forward trace s (FD_SEED_AWAY) from the same seed; succ (n_guide +
+ * n_seg, from fd_link_segments over pieces in that order) chains them.
+ * Strand g is guide trace g followed by its chain of segments, which ends
+ * at -1, at a guide piece, or after n_guide + n_seg links.
+ * fd_strand_offsets: offsets (device, n_guide + 1 int64; offsets[n_guide]
+ * is the total vertex count) and optionally pieces (device, n_guide int32,
+ * pieces per strand).  fd_assemble_strands: out (device, capacity x 3
+ * float) receives strand g's vertices at rows offsets[g] ..
+ * offsets[g + 1] - 1; rows at or beyond capacity are not written.  Vertex
+ * counts must not exceed their stride (max_steps + 1 of the call that
+ * traced them), as fd_grow_strands writes them.  FD_E_INVAL for bad sizes
+ * or pointers.  Asynchronous on stream. */
+int fd_strand_offsets(const int32_t* guide_n, int32_t n_guide, const int32_t* fwd_n,
+                      const int32_t* bwd_n, int32_t n_seg, const int32_t* succ, void* stream,
+                      fd_context* ctx, int64_t* offsets, int32_t* pieces);
+int fd_assemble_strands(const float* guide_v, const int32_t* guide_n, int32_t n_guide,
+                        int32_t g_stride, const float* fwd_v, const int32_t* fwd_n,
+                        int32_t f_stride, const float* bwd_v, const int32_t* bwd_n,
+                        int32_t b_stride, int32_t n_seg, const int32_t* succ,
+                        const int64_t* offsets, int64_t capacity, void* stream, fd_context* ctx,
+                        float* out);
+
 /* ---- tuning ---------------------------------------------------------------
  * Times the batched launch on the sample scenes for each shape of the
  * plain search (persistent: tiles per queue pop and resident grid size; or

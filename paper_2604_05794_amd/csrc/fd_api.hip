@@ -141,7 +141,7 @@ extern "C" void fd_context_destroy(fd_context* c) {
                   c->gabor_bank, c->gabor_raw, c->gabor_max, c->vol_key, c->vol_perm,
                   c->vol_off, c->vol_bsum, c->vol_boff, c->vol_rsum, c->link_counts,
                   c->link_cursor, c->link_sums, c->link_bucket, c->link_perm, c->link_key,
-                  c->link_best};
+                  c->link_best, c->strand_len};
   for (void* p : bufs)
     if (p) (void)hipFree(p);
   for (auto& p : c->pending) {

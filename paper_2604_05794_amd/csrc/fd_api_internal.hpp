@@ -90,6 +90,8 @@ struct fd_context {
   size_t cap_link_key = 0;
   unsigned long long* link_best = nullptr;
   size_t cap_link_best = 0;
+  int64_t* strand_len = nullptr;  // per guide strand, before the scan
+  size_t cap_strand_len = 0;
   // tuned shape of the persistent search: tiles per queue pop, resident grid
   int tuned_chunk = 0;
   int tuned_grid = 0;

@@ -228,6 +228,105 @@ __global__ __launch_bounds__(256) void k_link_accept(int32_t n,
   if (j >= 0 && best[j] != key[i]) succ[i] = -1;
 }
 
+
+// ---- strands from linked pieces ------------------------------------------------
+// Piece g < n_guide is guide trace g; piece n_guide + s is segment s (its
+// backward trace reversed without the seed, then its forward trace).  A
+// chain ends at -1, at a guide piece, or after n_guide + n_seg hops.
+
+struct PiecesDev {
+  const int32_t* gn;
+  const int32_t* fn;
+  const int32_t* bn;
+  const int32_t* succ;
+  int32_t n_guide, n_seg;
+};
+
+__global__ __launch_bounds__(256) void k_strand_len(PiecesDev P, int64_t* __restrict__ len,
+                                                    int32_t* __restrict__ pieces) {
+  const int32_t g = (int32_t)(blockIdx.x * blockDim.x + threadIdx.x);
+  if (g >= P.n_guide) return;
+  int64_t L = P.gn[g];
+  int32_t np = 1;
+  int32_t j = P.succ[g];
+  for (int32_t hop = 0; j >= P.n_guide && j < P.n_guide + P.n_seg && hop < P.n_guide + P.n_seg;
+       ++hop) {
+    const int32_t sg = j - P.n_guide;
+    L += (int64_t)(P.bn[sg] - 1) + P.fn[sg];
+    ++np;
+    j = P.succ[j];
+  }
+  len[g] = L;
+  if (pieces) pieces[g] = np;
+}
+
+// Exclusive scan of n lengths into offsets (n + 1 entries) in one block:
+// thread t owns a contiguous run of entries, summed in order; the run sums
+// are scanned across the block; each thread then writes its run.
+__global__ __launch_bounds__(1024) void k_len_scan(const int64_t* __restrict__ len, int32_t n,
+                                                   int64_t* __restrict__ off) {
+  __shared__ int64_t part[1024];
+  const int t = (int)threadIdx.x;
+  const int32_t per = (n + 1023) / 1024;
+  const int32_t a = t * per, b = min(n, a + per);
+  int64_t s = 0;
+  for (int32_t i = a; i < b; ++i) s += len[i];
+  part[t] = s;
+  __syncthreads();
+  if (t == 0) {
+    int64_t acc = 0;
+    for (int k = 0; k < 1024; ++k) {
+      const int64_t v = part[k];
+      part[k] = acc;
+      acc += v;
+    }
+    off[n] = acc;
+  }
+  __syncthreads();
+  int64_t acc = part[t];
+  for (int32_t i = a; i < b; ++i) {
+    off[i] = acc;
+    acc += len[i];
+  }
+}
+
+__global__ __launch_bounds__(256) void k_assemble(PiecesDev P, const float* __restrict__ gv,
+                                                  int32_t gs, const float* __restrict__ fv,
+                                                  int32_t fs, const float* __restrict__ bv,
+                                                  int32_t bs, const int64_t* __restrict__ off,
+                                                  int64_t cap, float* __restrict__ out) {
+  const int lane = (int)(threadIdx.x & 63u);
+  const int32_t g = (int32_t)((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
+  if (g >= P.n_guide) return;  // wave-uniform
+  int64_t pos = off[g];
+  auto put = [&](int64_t at, const float* src) {
+    if (at < cap) {
+      out[3 * at] = src[0];
+      out[3 * at + 1] = src[1];
+      out[3 * at + 2] = src[2];
+    }
+  };
+  {
+    const float* src = gv + (size_t)g * gs * 3;
+    const int32_t n = min(max(P.gn[g], 0), gs);  // reads stay inside the trace
+    for (int32_t k = lane; k < n; k += 64) put(pos + k, src + 3 * k);
+    pos += n;
+  }
+  int32_t j = P.succ[g];
+  for (int32_t hop = 0; j >= P.n_guide && j < P.n_guide + P.n_seg && hop < P.n_guide + P.n_seg;
+       ++hop) {
+    const int32_t sg = j - P.n_guide;
+    const int32_t nb = min(max(P.bn[sg], 1), bs), nf = min(max(P.fn[sg], 0), fs);
+    const float* b = bv + (size_t)sg * bs * 3;
+    const float* f = fv + (size_t)sg * fs * 3;
+    for (int32_t k = lane; k < nb - 1; k += 64) put(pos + k, b + 3 * (nb - 1 - k));
+    pos += nb - 1;
+    for (int32_t k = lane; k < nf; k += 64) put(pos + k, f + 3 * k);
+    pos += nf;
+    j = P.succ[j];
+  }
+}
+
 int check_grid(const fd_volume_grid* grid, const char* fn, GridDev* g) {
   if (!grid) return set_error(FD_E_INVAL, "%s: grid is NULL", fn);
   if (!(grid->voxel > 0.0f) || !std::isfinite(grid->voxel))
@@ -400,3 +499,66 @@ extern "C" int fd_link_segments(const float* starts, const float* start_dirs, co
   t.stop();
   return FD_OK;
 }
+
+static int check_pieces(const int32_t* gn, int32_t n_guide, const int32_t* fn,
+                        const int32_t* bn, int32_t n_seg, const int32_t* succ, const char* name) {
+  if (n_guide < 0 || n_seg < 0 || n_guide > FD_MAX_GROW_SEEDS || n_seg > FD_MAX_GROW_SEEDS)
+    return set_error(FD_E_INVAL, "%s: piece counts out of range", name);
+  if (n_guide > 0 && (!gn || !succ))
+    return set_error(FD_E_INVAL, "%s: null guide lengths or links", name);
+  if (n_seg > 0 && (!fn || !bn))
+    return set_error(FD_E_INVAL, "%s: null segment lengths", name);
+  return FD_OK;
+}
+
+extern "C" int fd_strand_offsets(const int32_t* guide_n, int32_t n_guide, const int32_t* fwd_n,
+                                 const int32_t* bwd_n, int32_t n_seg, const int32_t* succ,
+                                 void* stream, fd_context* ctx, int64_t* offsets,
+                                 int32_t* pieces) {
+  const char* fn = "fd_strand_offsets";
+  int r;
+  if ((r = check_pieces(guide_n, n_guide, fwd_n, bwd_n, n_seg, succ, fn))) return r;
+  if (!offsets) return set_error(FD_E_INVAL, "%s: offsets is NULL", fn);
+  fd_context* c = context_for(ctx, fn, &r);
+  if (!c) return r;
+  hipStream_t st = (hipStream_t)stream;
+  if ((r = ctx_buffer((void**)&c->strand_len, &c->cap_strand_len,
+                      8 * (size_t)(n_guide > 0 ? n_guide : 1), "strand lengths")))
+    return r;
+  PiecesDev P{guide_n, fwd_n, bwd_n, succ, n_guide, n_seg};
+  if (n_guide > 0)
+    hipLaunchKernelGGL(k_strand_len, dim3((unsigned)((n_guide + 255) / 256)), dim3(256), 0, st,
+                       P, c->strand_len, pieces);
+  hipLaunchKernelGGL(k_len_scan, dim3(1), dim3(1024), 0, st, c->strand_len, n_guide, offsets);
+  hipError_t e = hipGetLastError();
+  return e == hipSuccess ? FD_OK : hip_error(e, "strand offsets");
+}
+
+extern "C" int fd_assemble_strands(const float* guide_v, const int32_t* guide_n, int32_t n_guide,
+                                   int32_t g_stride, const float* fwd_v, const int32_t* fwd_n,
+                                   int32_t f_stride, const float* bwd_v, const int32_t* bwd_n,
+                                   int32_t b_stride, int32_t n_seg, const int32_t* succ,
+                                   const int64_t* offsets, int64_t capacity, void* stream,
+                                   fd_context* ctx, float* out) {
+  const char* fn = "fd_assemble_strands";
+  int r;
+  if ((r = check_pieces(guide_n, n_guide, fwd_n, bwd_n, n_seg, succ, fn))) return r;
+  if (g_stride < 1 || f_stride < 1 || b_stride < 1)
+    return set_error(FD_E_INVAL, "%s: strides must be >= 1", fn);
+  if (capacity < 0) return set_error(FD_E_INVAL, "%s: capacity must be >= 0", fn);
+  if (n_guide > 0 && (!guide_v || !offsets || (capacity > 0 && !out)))
+    return set_error(FD_E_INVAL, "%s: null pointer argument", fn);
+  if (n_seg > 0 && (!fwd_v || !bwd_v))
+    return set_error(FD_E_INVAL, "%s: null segment traces", fn);
+  fd_context* c = context_for(ctx, fn, &r);
+  if (!c) return r;
+  if (n_guide == 0) return FD_OK;
+  hipStream_t st = (hipStream_t)stream;
+  PiecesDev P{guide_n, fwd_n, bwd_n, succ, n_guide, n_seg};
+  hipLaunchKernelGGL(k_assemble, dim3((unsigned)(((int64_t)n_guide * 64 + 255) / 256)), dim3(256),
+                     0, st, P, guide_v, g_stride, fwd_v, f_stride, bwd_v, b_stride, offsets,
+                     capacity, out);
+  hipError_t e = hipGetLastError();
+  return e == hipSuccess ? FD_OK : hip_error(e, "strand assembly");
+}
+

@@ -33,7 +33,7 @@ EXPORTS = (
     "fd_mlp_loss_grad", "fd_mlp_train_step", "fd_mlp_destroy", "fd_features", "fd_autotune",
     "fd_tuned_shape", "fd_profile_enable", "fd_profile_read", "fd_gabor_params_init",
     "fd_orientation_maps", "fd_fuse_volume", "fd_grow_params_init", "fd_grow_strands",
-    "fd_link_segments", "fd_last_error",
+    "fd_link_segments", "fd_strand_offsets", "fd_assemble_strands", "fd_last_error",
 )
 
 FD_STAGE_TILING, FD_STAGE_TOPK, FD_STAGE_FUSE, FD_STAGE_FEATURES, FD_STAGE_MLP, \
@@ -160,6 +160,9 @@ def lib():
         "fd_grow_strands": (ctypes.c_int, [ctypes.POINTER(VolumeGrid), P, P, P, P, P, i32,
                                            ctypes.POINTER(GrowParams), P, P, P, P]),
         "fd_link_segments": (ctypes.c_int, [P, P, P, P, P, i32, f32, f32, P, P, P]),
+        "fd_strand_offsets": (ctypes.c_int, [P, i32, P, P, i32, P, P, P, P, P]),
+        "fd_assemble_strands": (ctypes.c_int, [P, P, i32, i32, P, P, i32, P, P, i32, i32, P, P,
+                                               i64, P, P, P]),
         "fd_last_error": (ctypes.c_char_p, []),
     }
     for name, (res, args) in sig.items():
@@ -589,6 +592,46 @@ def link_segments(starts, start_dirs, ends, end_dirs, flags, max_dist, min_cos, 
                                   _stream_handle(stream), ctx.handle if ctx is not None else None,
                                   _ptr(succ)))
     return succ
+
+
+def assemble_strands(guide, fwd, bwd, succ, *, out=None, stream=None,
+                     ctx: Optional["Context"] = None):
+    """Strands from linked pieces (fd_strand_offsets, then
+    fd_assemble_strands): guide, fwd, bwd are (verts, n_verts, last_dir)
+    as grow_strands returns them; succ over the guide pieces then the
+    segments.  Returns (offsets (n_guide + 1,) int64, verts, pieces
+    (n_guide,) int32).  Without `out` the total is read back to size the
+    output and verts is (total, 3); with `out` ((capacity, 3) float32)
+    nothing is read back, rows past the capacity are not written and verts
+    is `out` itself."""
+    gv, gn = guide[0], guide[1]
+    fv, fn = fwd[0], fwd[1]
+    bv, bn = bwd[0], bwd[1]
+    for t_, nm in ((gv, "guide verts"), (fv, "forward verts"), (bv, "backward verts")):
+        _dev_tensor(t_, nm, torch.float32)
+    for t_, nm in ((gn, "guide n_verts"), (fn, "forward n_verts"), (bn, "backward n_verts"),
+                   (succ, "succ")):
+        _dev_tensor(t_, nm, torch.int32)
+    ng, ns = gn.shape[0], fn.shape[0]
+    if bn.shape[0] != ns or succ.shape[0] != ng + ns:
+        raise ValueError("segment halves and links must match the piece counts")
+    dev = gv.device
+    off = torch.empty(ng + 1, dtype=torch.int64, device=dev)
+    pieces = torch.empty(max(ng, 1), dtype=torch.int32, device=dev)
+    sh = _stream_handle(stream)
+    ch = ctx.handle if ctx is not None else None
+    _check(lib().fd_strand_offsets(_ptr(gn), ng, _ptr(fn), _ptr(bn), ns, _ptr(succ), sh, ch,
+                                   _ptr(off), _ptr(pieces)))
+    if out is None:
+        total = int(off[-1].item())
+        buf = torch.empty((max(total, 1), 3), dtype=torch.float32, device=dev)
+    else:
+        _dev_tensor(out, "out", torch.float32, (3,))
+        buf, total = out, out.shape[0]
+    _check(lib().fd_assemble_strands(_ptr(gv), _ptr(gn), ng, gv.shape[1], _ptr(fv), _ptr(fn),
+                                     fv.shape[1], _ptr(bv), _ptr(bn), bv.shape[1], ns, _ptr(succ),
+                                     _ptr(off), total, sh, ch, _ptr(buf)))
+    return off, (buf[:total] if out is None else buf), pieces[:ng]
 
 
 def _scene_struct(sc):

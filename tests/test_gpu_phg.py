@@ -205,3 +205,53 @@ def test_invalid_arguments():
         with pytest.raises(nat.FdError) as e:
             nat.link_segments(s, s, s, s, f, dmax, cmin)
         assert e.value.code == nat.FD_E_INVAL
+
+
+def test_assembled_strands_match_the_oracle():
+    nat = _native()
+    grid, dev_vol, host_vol = _volume("tiny", 2, 100_000, 0.004)
+    roots, normals = scenegen.scalp_seeds("tiny", 2)
+    nv = int(np.prod(grid[2]))
+    cr = torch.zeros(nv, dtype=torch.int32, device=DEV)
+    origin, h, dims = grid
+    lat = scenegen.lattice_seeds(*grid, 3)
+    prm = dict(T)
+    prm.update(step=2e-3)
+    g = nat.grow_strands(*dev_vol, origin, h, dims, _t(roots), _t(normals), crossings=cr,
+                         batch=64, **prm)
+    prm_s = dict(prm)
+    prm_s.update(max_steps=20)
+    f = nat.grow_strands(*dev_vol, origin, h, dims, _t(lat), None, crossings=cr,
+                         seed_mode=nat.FD_SEED_AWAY, **prm_s)
+    b = nat.grow_strands(*dev_vol, origin, h, dims, _t(lat), None, crossings=cr,
+                         seed_mode=nat.FD_SEED_TOWARDS, **prm_s)
+    host = lambda r: (r[0].cpu().numpy(), r[1].cpu().numpy(), r[2].cpu().numpy())
+    gh, fh, bh = host(g), host(f), host(b)
+    S, SD, E, ED, F = _pieces(gh, fh, bh, roots, normals)
+    succ = nat.link_segments(_t(S), _t(SD), _t(E), _t(ED), _t(F), 0.006, 0.5)
+    off, verts, pieces = nat.assemble_strands(g, f, b, succ)
+    torch.cuda.synchronize()
+    asdict = lambda r: dict(verts=r[0], n_verts=r[1])
+    o_off, o_verts, o_pieces = oracle.assemble(asdict(gh), asdict(fh), asdict(bh),
+                                               succ.cpu().numpy())
+    assert np.array_equal(off.cpu().numpy(), o_off)
+    assert np.array_equal(pieces.cpu().numpy(), o_pieces)
+    assert np.array_equal(verts.cpu().numpy(), o_verts)
+    print("strands", len(roots), "vertices", int(o_off[-1]), "with segments",
+          int((o_pieces > 1).sum()), flush=True)
+    assert (o_pieces > 1).sum() > 5
+    # a short output buffer is filled up to its capacity and no further
+    cap = int(o_off[-1]) // 2
+    out = torch.full((cap + 8, 3), -7.0, dtype=torch.float32, device=DEV)
+    lib = nat.lib()
+    import ctypes
+    rc = lib.fd_assemble_strands(
+        ctypes.c_void_p(g[0].data_ptr()), ctypes.c_void_p(g[1].data_ptr()), len(roots),
+        g[0].shape[1], ctypes.c_void_p(f[0].data_ptr()), ctypes.c_void_p(f[1].data_ptr()),
+        f[0].shape[1], ctypes.c_void_p(b[0].data_ptr()), ctypes.c_void_p(b[1].data_ptr()),
+        b[0].shape[1], len(lat), ctypes.c_void_p(succ.data_ptr()),
+        ctypes.c_void_p(off.data_ptr()), cap, None, None, ctypes.c_void_p(out.data_ptr()))
+    torch.cuda.synchronize()
+    assert rc == 0
+    o = out.cpu().numpy()
+    assert np.array_equal(o[:cap], o_verts[:cap]) and np.all(o[cap:] == -7.0)
