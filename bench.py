@@ -69,7 +69,7 @@ TRAFFIC = {
                                "src": "320d01ce2a409293"},
     "k_fuse, metric workload, per head": {"read": 293.6e6, "write": 19.1e6,
                                           "files": _SEARCH_SOURCES, "src": "320d01ce2a409293"},
-    "k_b_learned, metric workload": {"read": 2080.4e6, "write": 160.6e6,
+    "k_b_learned4, metric workload": {"read": 2080.4e6, "write": 160.6e6,
                                      "files": _BATCHED_SOURCES, "src": "38a5470b652f7d7a"},
     "k_gabor, 64 frames 1024^2": {"read": 1058.0e6, "write": 411.0e6, "files": _GABOR_SOURCES,
                                   "src": "d336fd24608bb426"},
@@ -410,12 +410,12 @@ def run_metric(args):
         "fallback_frac": fb / n, "batched_bitwise_equal": {"plain": same_pb, "learned": same_lb},
         "stages_ms_per_launch_plain": st_p,
         "roofline": {"bound": "alu",
-                     "kernel": "k_b_learned: refinement from the proposal for every point, full "
-                               "search in place for the waves that mostly fall back "
-                               "(learned+batched step)",
+                     "kernel": "k_b_learned4 (k_b_learned at four waves per SIMD): refinement "
+                               "from the proposal for every point, full search in place for "
+                               "the waves that mostly fall back (learned+batched step)",
                      "achieved": achieved, "peak": PEAK_FP32_FMA, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP32_FMA,
-                     "traffic": traffic_of("k_b_learned, metric workload"),
+                     "traffic": traffic_of("k_b_learned4, metric workload"),
                      "avg_launch_ms": st_lb["refine"], "points_per_launch": n,
                      "full_searches_in_place": fb_inplace, "listed_fallbacks": fb_listed,
                      "flop_per_launch": flop_lb, "flop_per_full_search": flop,

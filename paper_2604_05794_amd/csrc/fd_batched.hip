@@ -258,7 +258,8 @@ __global__ __launch_bounds__(kBlock) void k_b_fuse_tiles(BatchDev b, SearchDev q
 
 // One wave per scene-uniform tile, tiles in XCD-aware block order.
 template <typename T, int P, int KT>
-__global__ __launch_bounds__(kBlock) void k_b_learned(BatchDev b, SearchDev q, LearnedDev l) {
+__device__ __forceinline__ void b_learned_body(const BatchDev& b, const SearchDev& q,
+                                               const LearnedDev& l) {
   const Group gr = make_group(q.K);
   const int64_t tile = xcd_tile(gridDim.x) * (blockDim.x / kWave) + (threadIdx.x / kWave);
   if (tile >= b.n_tiles) return;
@@ -270,12 +271,32 @@ __global__ __launch_bounds__(kBlock) void k_b_learned(BatchDev b, SearchDev q, L
 }
 
 template <typename T, int P, int KT>
+__global__ __launch_bounds__(kBlock) void k_b_learned(BatchDev b, SearchDev q, LearnedDev l) {
+  b_learned_body<T, P, KT>(b, q, l);
+}
+
+// The same with at most 128 registers per lane, so that four waves share a
+// SIMD: measured faster for patches up to 5 x 5 (a few registers spill
+// outside the lattice loop); 7 x 7 patches would spill heavily and keep the
+// unbounded form.
+template <typename T, int P, int KT>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) void k_b_learned4(
+    BatchDev b, SearchDev q, LearnedDev l) {
+  b_learned_body<T, P, KT>(b, q, l);
+}
+
+template <typename T, int P, int KT>
 hipError_t launch_b_search(const BatchDev& b, const SearchDev& q, const LearnedDev* l,
                            const uint32_t* list, const uint32_t* count, uint32_t* queue,
                            int chunk, int grid, hipStream_t st) {
   if (l) {
     const int64_t nb = (b.n_tiles + 3) / 4;  // 4 waves per block
-    hipLaunchKernelGGL((k_b_learned<T, P, KT>), dim3((unsigned)nb), dim3(kBlock), 0, st, b, q, *l);
+    if constexpr (P <= 5)
+      hipLaunchKernelGGL((k_b_learned4<T, P, KT>), dim3((unsigned)nb), dim3(kBlock), 0, st, b, q,
+                         *l);
+    else
+      hipLaunchKernelGGL((k_b_learned<T, P, KT>), dim3((unsigned)nb), dim3(kBlock), 0, st, b, q,
+                         *l);
   } else {
     if (list)
       hipLaunchKernelGGL((k_b_fuse<T, P, KT, true>), dim3(grid), dim3(kBlock), 0, st, b, q, list,
