@@ -107,15 +107,23 @@ __global__ void k_mlp_pack(const float* __restrict__ m, Packed p) {
 }
 
 // ---- inference: fused four-layer forward ----------------------------------------------
-// One workgroup (4 waves) = 128 rows.  Activations stay in LDS (128 x 256
+// One workgroup (8 waves) = 128 rows.  Activations stay in LDS (128 x 256
 // bfloat16, rows padded by 16 bytes); wave w produces output columns
-// [64w, 64w + 64) of every hidden layer for all 128 rows.  The product is
+// [32w, 32w + 32) of every hidden layer for all 128 rows.  The product is
 // issued as Z^T = W^T X^T (weights as the A operand, activations as B), so
 // that each lane ends up holding four consecutive output columns of one row
 // and writes them to LDS with one 8-byte store.  Weight fragments come
 // straight from the L2-resident packed weights, one k-step ahead.
 constexpr int FWD_ROWS = 128;
 constexpr int ACT_LD = DH + 8;
+// 8 waves per workgroup, each producing kCols = 32 output columns of every
+// hidden layer (two 16-column MFMA tiles) for all 128 rows; the output
+// layer gives each wave one 16-row tile.
+constexpr int kFwdWaves = 8;
+constexpr int kFwdThreads = 64 * kFwdWaves;
+constexpr int kCols = DH / kFwdWaves;
+constexpr int kNt = kCols / 16;
+static_assert(FWD_ROWS == 16 * kFwdWaves, "one output-layer row tile per wave");
 
 // GELU (tanh form) for the inference forward: 0.5 x (1 + tanh(u)) = x / (1 +
 // e^(-2u)), u = sqrt(2/pi) (x + 0.044715 x^3), with e^(-2u) = 2^(x (A + B x^2))
@@ -128,15 +136,16 @@ __device__ __forceinline__ float gelu_fast(float x) {
   return x * __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(t));
 }
 
-__global__ __launch_bounds__(256, 2) void k_mlp_fwd(const uint16_t* __restrict__ x, int64_t n,
-                                                 Packed p, float* __restrict__ out) {
+__global__ __launch_bounds__(kFwdThreads, 2) void k_mlp_fwd(const uint16_t* __restrict__ x,
+                                                          int64_t n, Packed p,
+                                                          float* __restrict__ out) {
   __shared__ __attribute__((aligned(16))) uint16_t act[FWD_ROWS * ACT_LD];
   __shared__ float yout[FWD_ROWS][4];
   const int t = threadIdx.x, lane = t & 63, w = t >> 6, g = lane >> 4, c16 = lane & 15;
   const int64_t row0 = (int64_t)blockIdx.x * FWD_ROWS;
 
   // input rows -> act[:, 0:128) (k >= 112 and rows >= n zero)
-  for (int e = t; e < FWD_ROWS * (D0P / 8); e += 256) {
+  for (int e = t; e < FWD_ROWS * (D0P / 8); e += kFwdThreads) {
     const int r = e / (D0P / 8), kb = (e % (D0P / 8)) * 8;
     uint4 v = make_uint4(0, 0, 0, 0);
     if (row0 + r < n && kb < D0) v = *(const uint4*)(x + (row0 + r) * D0 + kb);
@@ -148,36 +157,37 @@ __global__ __launch_bounds__(256, 2) void k_mlp_fwd(const uint16_t* __restrict__
   for (int layer = 0; layer < 3; ++layer) {
     const int K = layer == 0 ? D0P : DH;
     const uint16_t* wt = layer == 0 ? p.w1t : (layer == 1 ? p.w2t : p.w3t);
-    // acc[mt][nt]: rows (output columns) 64w + 16nt + 4g + r, column (batch row) 16mt + c16
-    f32x4 acc[8][4];
+    // acc[mt][nt]: rows (output columns) kCols w + 16nt + 4g + r, column
+    // (batch row) 16mt + c16
+    f32x4 acc[8][kNt];
 #pragma unroll
     for (int mt = 0; mt < 8; ++mt)
 #pragma unroll
-      for (int nt = 0; nt < 4; ++nt) acc[mt][nt] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
-    bf16x8 wa[4], wn[4];
+      for (int nt = 0; nt < kNt; ++nt) acc[mt][nt] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+    bf16x8 wa[kNt], wn[kNt];
 #pragma unroll
-    for (int nt = 0; nt < 4; ++nt)
-      wa[nt] = *(const bf16x8*)(wt + (size_t)(64 * w + 16 * nt + c16) * K + 8 * g);
+    for (int nt = 0; nt < kNt; ++nt)
+      wa[nt] = *(const bf16x8*)(wt + (size_t)(kCols * w + 16 * nt + c16) * K + 8 * g);
 #pragma unroll 1
     for (int kc = 0; kc < K; kc += 32) {
       const int kn = kc + 32 < K ? kc + 32 : kc;
 #pragma unroll
-      for (int nt = 0; nt < 4; ++nt)
-        wn[nt] = *(const bf16x8*)(wt + (size_t)(64 * w + 16 * nt + c16) * K + kn + 8 * g);
+      for (int nt = 0; nt < kNt; ++nt)
+        wn[nt] = *(const bf16x8*)(wt + (size_t)(kCols * w + 16 * nt + c16) * K + kn + 8 * g);
 #pragma unroll
       for (int mt = 0; mt < 8; ++mt) {
         const bf16x8 xb = *(const bf16x8*)(act + (16 * mt + c16) * ACT_LD + kc + 8 * g);
 #pragma unroll
-        for (int nt = 0; nt < 4; ++nt) acc[mt][nt] = mfma(wa[nt], xb, acc[mt][nt]);
+        for (int nt = 0; nt < kNt; ++nt) acc[mt][nt] = mfma(wa[nt], xb, acc[mt][nt]);
       }
 #pragma unroll
-      for (int nt = 0; nt < 4; ++nt) wa[nt] = wn[nt];
+      for (int nt = 0; nt < kNt; ++nt) wa[nt] = wn[nt];
     }
     __syncthreads();  // every wave has read this layer's input
     const float* bias = p.bias + layer * DH;
 #pragma unroll
-    for (int nt = 0; nt < 4; ++nt) {
-      const int col = 64 * w + 16 * nt + 4 * g;
+    for (int nt = 0; nt < kNt; ++nt) {
+      const int col = kCols * w + 16 * nt + 4 * g;
       const float4 bb = *(const float4*)(bias + col);
 #pragma unroll
       for (int mt = 0; mt < 8; ++mt) {
@@ -191,22 +201,16 @@ __global__ __launch_bounds__(256, 2) void k_mlp_fwd(const uint16_t* __restrict__
     }
     __syncthreads();
   }
-  // output layer: 256 -> 16 (3 real); wave w takes batch-row tiles 2w, 2w + 1
-  f32x4 o[2] = {f32x4{0.0f, 0.0f, 0.0f, 0.0f}, f32x4{0.0f, 0.0f, 0.0f, 0.0f}};
+  // output layer: 256 -> 16 (3 real); wave w takes batch-row tile w
+  f32x4 o = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
   for (int kc = 0; kc < DH; kc += 32) {
     const bf16x8 b = *(const bf16x8*)(p.w4t + (size_t)c16 * DH + kc + 8 * g);
-#pragma unroll
-    for (int i = 0; i < 2; ++i) {
-      const bf16x8 a = *(const bf16x8*)(act + (16 * (2 * w + i) + c16) * ACT_LD + kc + 8 * g);
-      o[i] = mfma(a, b, o[i]);
-    }
+    const bf16x8 a = *(const bf16x8*)(act + (16 * w + c16) * ACT_LD + kc + 8 * g);
+    o = mfma(a, b, o);
   }
   if (c16 < 3) {
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
-#pragma unroll
-      for (int r = 0; r < 4; ++r)
-        yout[16 * (2 * w + i) + 4 * g + r][c16] = o[i][r] + p.bias[3 * DH + c16];
+    for (int r = 0; r < 4; ++r) yout[16 * w + 4 * g + r][c16] = o[r] + p.bias[3 * DH + c16];
   }
   __syncthreads();
   if (t < FWD_ROWS && row0 + t < n) {
@@ -676,7 +680,8 @@ namespace fd {
 int mlp_forward_dev(const fd_mlp* m, const uint16_t* feats, int64_t n, float* out, hipStream_t st) {
   if (n <= 0) return FD_OK;
   const int64_t nb = (n + FWD_ROWS - 1) / FWD_ROWS;
-  hipLaunchKernelGGL(k_mlp_fwd, dim3((unsigned)nb), dim3(256), 0, st, feats, n, m->pk, out);
+  hipLaunchKernelGGL(k_mlp_fwd, dim3((unsigned)nb), dim3(kFwdThreads), 0, st, feats, n, m->pk,
+                     out);
   hipError_t e = hipGetLastError();
   return e == hipSuccess ? FD_OK : hip_error(e, "mlp forward");
 }
