@@ -26,6 +26,10 @@ depth visibility test of Sec. 3.1.1 with the scene's rendered depth maps
   train      proposal-network training (112 -> 256 -> 256 -> 256 -> 3, BF16
              MFMA): Adam steps of batch 4096 on the features and plain-search
              directions of the realistic scene's 500k points.
+  pipeline   the chain on one GPU: 64 grey frames at 1024^2 -> orientation
+             maps -> plain direction search of the 500k outer points ->
+             volume of those points and 1.5M inner stand-in points (3 mm)
+             -> hair growing, linking and strand assembly.
   phg        parallel hair growing through the volume of 8M such points on
              a 3 mm grid: 20k guide strands from the scalp roots (batches of
              4096, deferred occupancy), interior segments from every third
@@ -47,6 +51,7 @@ sys.path.insert(0, ROOT)
 METRIC = "fused points/s at ≤2° mean angular err; learned+batched vs plain, 1 MI355X"
 PEAK_FP32_FMA = 78.6          # TFLOP/s: 256 CU x 64 lanes x 2 flop x 2.4 GHz, no packed fp32
 PEAK_FP32_VENDOR = 157.3      # TFLOP/s: vendor figure, counts packed dual fp32 issue
+PEAK_FP32_MFMA = 157.3        # TFLOP/s: dense fp32 matrix-core figure (v_mfma_f32_*_f32)
 PEAK_HBM = 8000.0             # GB/s
 
 
@@ -72,7 +77,7 @@ TRAFFIC = {
     # the four-wave form spills a few registers: scratch traffic included
     "k_b_learned4, metric workload": {"read": 2965.7e6, "write": 882.5e6,
                                       "files": _BATCHED_SOURCES, "src": "e1c6962ed9dbe9c5"},
-    "k_gabor, 64 frames 1024^2": {"read": 1058.0e6, "write": 411.0e6, "files": _GABOR_SOURCES,
+    "k_gabor_mfma, 64 frames 1024^2": {"read": 1058.0e6, "write": 411.0e6, "files": _GABOR_SOURCES,
                                   "src": "d336fd24608bb426"},
     # the counting sort: keys and counts, the scan, the placement
     "volume sort, realistic 2M points 2 mm": {"read": 319.8e6, "write": 237.4e6,
@@ -617,9 +622,10 @@ def run_gabor(args):
                                f"{n_orient} orientations, radius {radius}",
                    "frames": V, "width": W, "height": H, "n_orient": n_orient,
                    "radius": radius},
-        "roofline": {"bound": "alu", "kernel": "k_gabor", "achieved": achieved,
-                     "peak": PEAK_FP32_FMA, "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_FMA,
-                     "traffic": traffic_of("k_gabor, 64 frames 1024^2"),
+        "roofline": {"bound": "mfma", "kernel": "k_gabor_mfma", "achieved": achieved,
+                     "peak": PEAK_FP32_MFMA, "unit": "TFLOP/s",
+                     "frac": achieved / PEAK_FP32_MFMA,
+                     "traffic": traffic_of("k_gabor_mfma, 64 frames 1024^2"),
                      "avg_launch_ms": stages["gabor"], "flop_per_pixel": flop},
         "stages_ms_per_launch": stages,
         "pipeline_frames_maps_search": pipeline,
@@ -958,6 +964,126 @@ def run_train(args):
     }
 
 
+def run_pipeline(args):
+    import numpy as np
+    import torch
+    import scenegen
+    from paper_2604_05794_amd import native
+
+    name = "realistic"
+    rec = scenegen.RECIPES[name]
+    t = time.perf_counter()
+    frames, _, _, cams = scenegen.make_frames(name, args.seed)
+    sc = scenegen.make_scene(name, args.seed)
+    assert np.array_equal(cams, sc.cams)
+    pin, din, win, _ = scenegen.make_oriented_points(name, args.seed + 1, 1_500_000)
+    roots, normals = scenegen.scalp_seeds(name, args.seed)
+    origin, h, dims = scenegen.head_grid(np.concatenate([sc.points, pin]), 0.003)
+    lat = scenegen.lattice_seeds(origin, h, dims, 3)
+    log(f"generated frames, {sc.n_points} outer + {len(pin)} inner points, grid "
+        f"{dims.tolist()} in {time.perf_counter() - t:.1f} s")
+    dev = torch.device("cuda:0")
+    T = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    fr, pts, cm, dm = T(frames), T(sc.points), T(sc.cams), T(sc.depth)
+    Pin, Din, Win = T(pin), T(din), T(win)
+    R, Nr, L = T(roots), T(normals), T(lat)
+    V, H, W = frames.shape
+    n_out, ng, ns = sc.n_points, len(roots), len(lat)
+    nv = int(np.prod(dims.astype(np.int64)))
+    th = torch.empty((V, H, W), dtype=torch.float16, device=dev)
+    cf = torch.empty_like(th)
+    dirs = torch.empty((n_out, 3), dtype=torch.float32, device=dev)
+    costs = torch.empty((n_out,), dtype=torch.float32, device=dev)
+    allp = torch.cat([pts, Pin])
+    alld = torch.empty((n_out + len(pin), 3), dtype=torch.float32, device=dev)
+    allw = torch.cat([torch.ones(n_out, dtype=torch.float32, device=dev), Win])
+    shape = (int(dims[2]), int(dims[1]), int(dims[0]))
+    occ = torch.empty(shape, dtype=torch.int32, device=dev)
+    vd = torch.empty(shape + (3,), dtype=torch.float32, device=dev)
+    vc = torch.empty(shape, dtype=torch.float32, device=dev)
+    cr = torch.zeros(nv, dtype=torch.int32, device=dev)
+    gkw = dict(step=1e-3, max_steps=200, min_coherence=0.1,
+               max_bend_cos=math.cos(math.radians(45.0)), voxel_cap=8)
+    S1 = gkw["max_steps"] + 1
+    strands = torch.empty((ng * S1 + 2 * ns * S1, 3), dtype=torch.float32, device=dev)
+    ar_g = torch.arange(ng, device=dev)
+    ar_s = torch.arange(ns, device=dev)
+    ctx = native.Context(max_points=n_out)
+    stream = torch.cuda.current_stream()
+    kw = dict(patch=rec["patch"], n_candidates=rec["n_candidates"],
+              refine_iters=rec["refine_iters"], top_k=5)
+    res = {}
+
+    def step():
+        native.orientation_maps(fr, theta=th, conf=cf, out_dtype=torch.float16, stream=stream,
+                                ctx=ctx)
+        native.fuse_directions(pts, cm, th, cf, dirs=dirs, costs=costs, ctx=ctx, stream=stream,
+                               depth_maps=dm, **kw)
+        alld[:n_out].copy_(dirs)
+        alld[n_out:].copy_(Din)
+        native.fuse_volume(allp, alld, origin, h, dims, weights=allw, occ=occ, dir_out=vd,
+                           coherence=vc, stream=stream, ctx=ctx)
+        cr.zero_()
+        g = native.grow_strands(occ, vd, vc, origin, h, dims, R, Nr, crossings=cr, batch=4096,
+                                stream=stream, ctx=ctx, **gkw)
+        f = native.grow_strands(occ, vd, vc, origin, h, dims, L, None, crossings=cr,
+                                batch=1 << 20, seed_mode=native.FD_SEED_AWAY, stream=stream,
+                                ctx=ctx, **gkw)
+        b = native.grow_strands(occ, vd, vc, origin, h, dims, L, None, crossings=cr,
+                                batch=1 << 20, seed_mode=native.FD_SEED_TOWARDS, stream=stream,
+                                ctx=ctx, **gkw)
+        gn, fn, bn = g[1].long(), f[1].long(), b[1].long()
+        S = torch.cat([R, b[0][ar_s, bn - 1]])
+        SD = torch.cat([Nr, b[2]])
+        E = torch.cat([g[0][ar_g, gn - 1], f[0][ar_s, fn - 1]])
+        ED = torch.cat([g[2], f[2]])
+        F = torch.cat([(gn > 1).to(torch.uint8), ((fn > 1) & (bn > 1)).to(torch.uint8) * 3])
+        succ = native.link_segments(S, SD, E, ED, F, 3e-3, math.cos(math.radians(30.0)),
+                                    stream=stream, ctx=ctx)
+        off, _, pieces = native.assemble_strands(g, f, b, succ, out=strands, stream=stream,
+                                                 ctx=ctx)
+        res.update(off=off, pieces=pieces)
+
+    stages_list = [("gabor", native.FD_STAGE_GABOR), ("gabor_norm", native.FD_STAGE_GABOR_NORM),
+                   ("tiling", native.FD_STAGE_TILING), ("topk", native.FD_STAGE_TOPK),
+                   ("fuse", native.FD_STAGE_FUSE), ("volume_clear", native.FD_STAGE_VOLUME_CLEAR),
+                   ("volume_sort", native.FD_STAGE_VOLUME_SCATTER),
+                   ("volume_reduce", native.FD_STAGE_VOLUME_FINAL),
+                   ("grow", native.FD_STAGE_GROW), ("crossings", native.FD_STAGE_GROW_CROSS),
+                   ("link", native.FD_STAGE_LINK)]
+    el, stages = _timed(step, args, ctx, stages_list)
+    ms_step = el * 1e3 / args.steps
+    n_launch = {"grow": math.ceil(ng / 4096) + 2, "crossings": math.ceil(ng / 4096) + 2}
+    per_step = {k: v * n_launch.get(k, 1) for k, v in stages.items()}
+    flop = gabor_flop_per_pixel(32, 8)
+    px = V * H * W
+    achieved = flop * px / (stages["gabor"] * 1e-3) / 1e12
+    off, pieces = res["off"], res["pieces"]
+    slen = (off[1:] - off[:-1]).float() - 1.0
+    log(f"pipeline: {ms_step:.3f} ms per reconstruction; per step (ms) "
+        f"{json.dumps({k: round(v, 4) for k, v in per_step.items()})}")
+    return {
+        "metric": "hair reconstructions per second on one GPU (frames -> maps -> directions -> "
+                  "volume -> strands)",
+        "value": 1e3 / ms_step, "unit": "reconstructions/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"pipeline: {V} frames {W}x{H} -> maps -> {n_out} outer points "
+                               f"searched -> volume of {n_out + len(pin)} points at 3 mm -> "
+                               f"{ng} roots + {ns} segment seeds -> linked strands",
+                   "frames": V, "outer_points": n_out, "inner_points": len(pin),
+                   "grid": dims.tolist(), "roots": ng, "segment_seeds": ns},
+        "roofline": {"bound": "mfma", "kernel": "k_gabor_mfma (the longest stage)",
+                     "achieved": achieved, "peak": PEAK_FP32_MFMA, "unit": "TFLOP/s",
+                     "frac": achieved / PEAK_FP32_MFMA,
+                     "traffic": traffic_of("k_gabor_mfma, 64 frames 1024^2"),
+                     "avg_launch_ms": stages["gabor"]},
+        "stages_ms_per_step": per_step,
+        "result": {"strand_vertices": int(off[-1]), "strands_with_segments":
+                   int((pieces > 1).sum()), "strand_mean_steps": float(slen.mean())},
+    }
+
+
 def run_copy(args):
     """Counter calibration: a plain device-to-device copy of 512 MiB, so the
     FETCH_SIZE / WRITE_SIZE counters can be read against known bytes."""
@@ -984,7 +1110,7 @@ def main():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--workload", default="metric",
                     choices=["metric", "plain", "learned", "gabor", "volume", "phg", "train",
-                             "copy"])
+                             "pipeline", "copy"])
     ap.add_argument("--heads", type=int, default=8)
     ap.add_argument("--mlp", default=os.path.join(ROOT, "paper_2604_05794_amd", "weights",
                                                   "proposal_mlp.fdmlp"))
@@ -1001,6 +1127,7 @@ def main():
         sys.exit(2)
     run = {"metric": run_metric, "plain": run_plain, "learned": run_learned,
            "gabor": run_gabor, "volume": run_volume, "phg": run_phg, "train": run_train,
+           "pipeline": run_pipeline,
            "copy": run_copy}[args.workload]
     out = run(args)
     print(json.dumps(out), flush=True)

@@ -2,18 +2,18 @@
 // gfx950 (the Gabor-filter extraction the paper names at the start of Sec. 3.1;
 // its reading is documented with fd_orientation_maps in fusedir.h).
 //
-// k_gabor: one thread per pixel, 16 x 16 pixels per workgroup.  The frame
-// tile with its radius-R halo is staged in LDS; the filter bank lives in
-// device memory tap-major (all orientations of one tap together), so every
-// tap's n_orient weights are wave-uniform and come through the scalar cache
-// as operands of the n_orient FMAs the tap costs each pixel.  The epilogue
-// takes the argmax orientation and the raw confidence, and the workgroup's
-// largest raw confidence goes to the frame maximum (an integer atomic on the
-// bits of a non-negative float).  k_gabor_norm divides by that maximum.
+// k_gabor_mfma: the filter bank is a dense contraction over the taps, run on
+// the fp32 matrix cores.  Persistent workgroups of four waves hold the bank
+// in LDS and walk 16 x 32 pixel tiles, each staged in LDS with its radius-R
+// halo; the epilogue takes the argmax orientation and the raw confidence, and
+// the workgroup's largest raw confidence goes to the frame maximum (an
+// integer atomic on the bits of a non-negative float).  k_gabor_norm divides
+// by that maximum.
 #include <hip/hip_fp16.h>
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <vector>
@@ -28,7 +28,6 @@ namespace {
 
 constexpr int kTile = 16;
 constexpr int kMaxRadius = 12;
-constexpr int kTileW = kTile + 2 * kMaxRadius;
 constexpr float kPi = 3.14159265358979323846f;
 
 template <typename TO>
@@ -37,80 +36,6 @@ __device__ __forceinline__ void store_map(void* out, size_t i, float v) {
     ((__half*)out)[i] = __float2half(v);
   else
     ((float*)out)[i] = v;
-}
-
-template <typename TO, int NO>
-__global__ __launch_bounds__(256) void k_gabor(const float* __restrict__ frames, int W, int H,
-                                               int R, const float* __restrict__ bank,
-                                               void* __restrict__ theta_out,
-                                               float* __restrict__ raw,
-                                               uint32_t* __restrict__ frame_max) {
-  __shared__ float tile[kTileW * kTileW];
-  __shared__ float wmax[256 / 64];
-  const int f = blockIdx.z;
-  const int x0 = blockIdx.x * kTile, y0 = blockIdx.y * kTile;
-  const size_t plane = (size_t)W * H;
-  const float* img = frames + plane * f;
-  const int tw = kTile + 2 * R;
-  for (int e = threadIdx.x; e < tw * tw; e += blockDim.x) {
-    const int ty = e / tw, tx = e - ty * tw;
-    const int x = x0 + tx - R, y = y0 + ty - R;
-    tile[ty * tw + tx] = (x >= 0 && x < W && y >= 0 && y < H) ? img[(size_t)y * W + x] : 0.0f;
-  }
-  __syncthreads();
-  const int lx = threadIdx.x % kTile, ly = threadIdx.x / kTile;
-  const int x = x0 + lx, y = y0 + ly;
-  float acc[NO];
-#pragma unroll
-  for (int i = 0; i < NO; ++i) acc[i] = 0.0f;
-  const int w2 = 2 * R + 1;
-  // taps in the oracle's order: dy outer, dx inner
-  for (int dy = 0; dy < w2; ++dy) {
-    const float* row = tile + (ly + dy) * tw + lx;
-    const float* wrow = bank + (size_t)dy * w2 * NO;
-    for (int dx = 0; dx < w2; ++dx) {
-      const float v = row[dx];
-      const float* w = wrow + dx * NO;
-#pragma unroll
-      for (int i = 0; i < NO; ++i) acc[i] = __builtin_fmaf(w[i], v, acc[i]);
-    }
-  }
-  // argmax |F_i| (first of equals) and the spread of the responses around it
-  int best = 0;
-  float fb = fabsf(acc[0]);
-#pragma unroll
-  for (int i = 1; i < NO; ++i) {
-    const float fi = fabsf(acc[i]);
-    if (fi > fb) {
-      fb = fi;
-      best = i;
-    }
-  }
-  float s = 0.0f;
-#pragma unroll
-  for (int i = 0; i < NO; ++i) {
-    const int di = abs(i - best);
-    const float d = (float)min(di, NO - di) * (kPi / NO);
-    const float e = fabsf(acc[i]) - fb;
-    s = __builtin_fmaf(d * d, e * e, s);
-  }
-  const float w = sqrtf(s);
-  const bool inside = x < W && y < H;
-  if (inside) {
-    const size_t i = plane * f + (size_t)y * W + x;
-    store_map<TO>(theta_out, i, (float)best * (kPi / NO));
-    raw[i] = w;
-  }
-  // workgroup maximum of the raw confidence -> frame maximum
-  float m = inside ? w : 0.0f;
-  for (int off = 32; off > 0; off >>= 1) m = fmaxf(m, __shfl_xor(m, off, 64));
-  if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = m;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    float b = wmax[0];
-    for (int k = 1; k < (int)(blockDim.x >> 6); ++k) b = fmaxf(b, wmax[k]);
-    atomicMax(&frame_max[f], __float_as_uint(b));  // b >= 0: bits order as values
-  }
 }
 
 template <typename TO>
@@ -122,6 +47,150 @@ __global__ __launch_bounds__(256) void k_gabor_norm(const float* __restrict__ ra
   if (i >= n) return;
   const float m = __uint_as_float(frame_max[i / plane]);
   store_map<TO>(conf_out, (size_t)i, m > 0.0f ? raw[i] / m : 0.0f);
+}
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+constexpr int kRowsPerWave = 8;
+constexpr int kMfmaRows = 4 * kRowsPerWave;  // tile rows: four waves
+
+// The filter bank as a matrix product on the fp32 matrix cores: for a row
+// of 16 pixels, F[orientation][pixel] = sum_tap G[orientation][tap] I[pixel + tap]
+// in steps of 4 taps (v_mfma_f32_16x16x4f32: A = 16 orientations x 4 bank
+// taps, B = the 4 x 16 image patch gathered from the LDS tile).  Persistent
+// workgroups keep the bank in LDS, zero-padded to whole 4-tap steps and
+// 16-orientation tiles and laid out [tap / 4][orientation tile][tap % 4][16]
+// so that a wave's A operand is 64 consecutive words; they walk pixel tiles
+// 16 wide and 32 high, wave w owning rows 8w .. 8w + 7, so each bank read
+// feeds 8 matrix operations.  A lane's tap offset into the tile advances in
+// registers.  In the result lane (g, c) = (lane / 16, lane % 16) holds
+// orientations 16 nt + 4 g + r (r < 4) of pixel c: the argmax (first of
+// equals) and the confidence sum run over those 4 NT values in the lane, then
+// across the four 16-lane groups.
+template <typename TO, int NT>
+__global__ __launch_bounds__(256) void k_gabor_mfma(const float* __restrict__ frames, int W,
+                                                    int H, int R, int NO,
+                                                    const float* __restrict__ bank,
+                                                    int64_t n_tiles, int tiles_x,
+                                                    int64_t tiles_per_frame,
+                                                    void* __restrict__ theta_out,
+                                                    float* __restrict__ raw,
+                                                    uint32_t* __restrict__ frame_max) {
+  extern __shared__ float lds[];
+  __shared__ float wmax[256 / 64];
+  constexpr int NJ = 16 * NT;
+  const int w2 = 2 * R + 1, taps = w2 * w2, kpad = (taps + 3) & ~3, tw = kTile + 2 * R;
+  const int th = kMfmaRows + 2 * R;  // tile rows with the halo
+  float* sbank = lds;              // kpad x NJ
+  float* tile = lds + kpad * NJ;   // th x tw
+  for (int e = threadIdx.x; e < kpad * NJ; e += blockDim.x) {
+    const int t = e / NJ, j = e - t * NJ;
+    const int dst = (t >> 2) * 4 * NJ + (j >> 4) * 64 + (t & 3) * 16 + (j & 15);
+    sbank[dst] = (t < taps && j < NO) ? bank[(size_t)t * NO + j] : 0.0f;
+  }
+  const int lane = (int)(threadIdx.x & 63u), w = (int)(threadIdx.x >> 6);
+  const int g = lane >> 4, c16 = lane & 15;
+  const size_t plane = (size_t)W * H;
+  for (int64_t tid = blockIdx.x; tid < n_tiles; tid += gridDim.x) {
+    const int64_t f = tid / tiles_per_frame;
+    const int64_t rem = tid - f * tiles_per_frame;
+    const int ty = (int)(rem / tiles_x), tx = (int)(rem - (int64_t)ty * tiles_x);
+    const int x0 = tx * kTile, y0 = ty * kMfmaRows;
+    const float* img = frames + plane * f;
+    __syncthreads();  // the bank is in place; the previous tile is no longer read
+    for (int e = threadIdx.x; e < tw * th; e += blockDim.x) {
+      const int yy = e / tw, xx = e - yy * tw;
+      const int x = x0 + xx - R, y = y0 + yy - R;
+      tile[e] = (x >= 0 && x < W && y >= 0 && y < H) ? img[(size_t)y * W + x] : 0.0f;
+    }
+    __syncthreads();
+    f32x4 acc[kRowsPerWave][NT];
+#pragma unroll
+    for (int p = 0; p < kRowsPerWave; ++p)
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt) acc[p][nt] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+    const float* base = tile + kRowsPerWave * w * tw + c16;
+    const float* bk = sbank + lane;
+    // this lane's tap t = k0 + g as (dy, dx) and its offset dy tw + dx; the
+    // zero bank rows of padded taps (t >= taps) meet the tap at offset 0
+    int dy = g / w2, dx = g - dy * w2;
+    for (int k0 = 0; k0 < kpad; k0 += 4) {
+      const int off = k0 + g < taps ? dy * tw + dx : 0;
+      float a[NT];
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt) a[nt] = bk[k0 * NJ + 64 * nt];
+      const float* src = base + off;
+#pragma unroll
+      for (int p = 0; p < kRowsPerWave; ++p) {
+        const float v = src[p * tw];
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt)
+          acc[p][nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[nt], v, acc[p][nt], 0, 0, 0);
+      }
+      dx += 4;
+      if (dx >= w2) { dx -= w2; ++dy; }
+      if (dx >= w2) { dx -= w2; ++dy; }  // w2 = 3 can wrap twice
+    }
+    // per pixel: argmax |F_j| (first of equals), then the spread of the
+    // responses around it
+    float m = 0.0f;
+#pragma unroll
+    for (int p = 0; p < kRowsPerWave; ++p) {
+      float fv[NT][4];
+      float fb = -1.0f;
+      int jb = 0;
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int j = 16 * nt + 4 * g + r;  // increasing in the lane
+          fv[nt][r] = j < NO ? fabsf(acc[p][nt][r]) : -1.0f;
+          if (fv[nt][r] > fb) {
+            fb = fv[nt][r];
+            jb = j;
+          }
+        }
+#pragma unroll
+      for (int off = 16; off < 64; off <<= 1) {
+        const float of = __shfl_xor(fb, off, 64);
+        const int oj = __shfl_xor(jb, off, 64);
+        if (of > fb || (of == fb && oj < jb)) {
+          fb = of;
+          jb = oj;
+        }
+      }
+      float s = 0.0f;
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int j = 16 * nt + 4 * g + r;
+          if (j < NO) {
+            const int dj = abs(j - jb);
+            const float d = (float)min(dj, NO - dj) * (kPi / NO);
+            const float e = fv[nt][r] - fb;
+            s = __builtin_fmaf(d * d, e * e, s);
+          }
+        }
+      s += __shfl_xor(s, 16, 64);
+      s += __shfl_xor(s, 32, 64);
+      const float wv = sqrtf(s);
+      const int x = x0 + c16, y = y0 + kRowsPerWave * w + p;
+      if (g == 0 && x < W && y < H) {
+        const size_t i = plane * f + (size_t)y * W + x;
+        store_map<TO>(theta_out, i, (float)jb * (kPi / NO));
+        raw[i] = wv;
+        m = fmaxf(m, wv);
+      }
+    }
+    for (int off = 32; off > 0; off >>= 1) m = fmaxf(m, __shfl_xor(m, off, 64));
+    if (lane == 0) wmax[w] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      float bm = wmax[0];
+      for (int k = 1; k < (int)(blockDim.x >> 6); ++k) bm = fmaxf(bm, wmax[k]);
+      atomicMax(&frame_max[f], __float_as_uint(bm));  // bm >= 0: bits order as values
+    }
+  }
 }
 
 uint64_t fnv1(uint64_t h, const void* p, size_t n) {
@@ -158,22 +227,21 @@ std::vector<float> make_bank(const fd_gabor_params* p) {
 template <typename TO>
 hipError_t launch_gabor(const float* frames, int n, int W, int H, int R, int N, const float* bank,
                         void* theta, float* raw, uint32_t* fmax, hipStream_t st) {
-  const dim3 grid((unsigned)((W + kTile - 1) / kTile), (unsigned)((H + kTile - 1) / kTile),
-                  (unsigned)n);
-  switch (N) {
-    case 8:
-      hipLaunchKernelGGL((k_gabor<TO, 8>), grid, dim3(256), 0, st, frames, W, H, R, bank, theta,
-                         raw, fmax);
-      break;
-    case 16:
-      hipLaunchKernelGGL((k_gabor<TO, 16>), grid, dim3(256), 0, st, frames, W, H, R, bank,
-                         theta, raw, fmax);
-      break;
-    default:
-      hipLaunchKernelGGL((k_gabor<TO, 32>), grid, dim3(256), 0, st, frames, W, H, R, bank,
-                         theta, raw, fmax);
-      break;
-  }
+  const int tiles_x = (W + kTile - 1) / kTile, tiles_y = (H + kMfmaRows - 1) / kMfmaRows;
+  const int64_t per_frame = (int64_t)tiles_x * tiles_y, n_tiles = per_frame * n;
+  const int taps = (2 * R + 1) * (2 * R + 1), kpad = (taps + 3) & ~3, tw = kTile + 2 * R;
+  const int th = kMfmaRows + 2 * R;
+  const int nt = N > 16 ? 2 : 1;
+  const size_t lds = sizeof(float) * ((size_t)kpad * 16 * nt + (size_t)tw * th);
+  const auto kern = nt == 2 ? k_gabor_mfma<TO, 2> : k_gabor_mfma<TO, 1>;
+  hipError_t e = hipFuncSetAttribute((const void*)kern,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  // persistent: each workgroup loads the bank once; several resident per CU
+  const int per_cu = (int)std::max<size_t>(1, (160 * 1024) / (lds + 1024));
+  const int64_t grid = std::min<int64_t>(n_tiles, (int64_t)256 * std::min(per_cu, 4));
+  hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(256), lds, st, frames, W, H, R, N, bank,
+                     n_tiles, tiles_x, per_frame, theta, raw, fmax);
   return hipGetLastError();
 }
 
