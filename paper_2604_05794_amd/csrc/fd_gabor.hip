@@ -52,6 +52,7 @@ __global__ __launch_bounds__(256) void k_gabor_norm(const float* __restrict__ ra
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 constexpr int kRowsPerWave = 8;
 constexpr int kMfmaRows = 4 * kRowsPerWave;  // tile rows: four waves
+constexpr int kTw = kTile + 2 * kMaxRadius;  // LDS tile row stride for every radius
 
 // The filter bank as a matrix product on the fp32 matrix cores: for a row
 // of 16 pixels, F[orientation][pixel] = sum_tap G[orientation][tap] I[pixel + tap]
@@ -61,11 +62,16 @@ constexpr int kMfmaRows = 4 * kRowsPerWave;  // tile rows: four waves
 // 16-orientation tiles and laid out [tap / 4][orientation tile][tap % 4][16]
 // so that a wave's A operand is 64 consecutive words; they walk pixel tiles
 // 16 wide and 32 high, wave w owning rows 8w .. 8w + 7, so each bank read
-// feeds 8 matrix operations.  A lane's tap offset into the tile advances in
-// registers.  In the result lane (g, c) = (lane / 16, lane % 16) holds
+// feeds 8 matrix operations.  The tile rows are kTw words apart for every
+// radius: the 8 row reads of a step take immediate offsets and pair up.  The
+// matrix cores only reach their peak when little else is issued beside them,
+// so the per-step bookkeeping is kept small: the position of the step's first
+// tap is wave-uniform (scalar registers) and a lane's tap is at most one row
+// further.  In the result lane (g, c) = (lane / 16, lane % 16) holds
 // orientations 16 nt + 4 g + r (r < 4) of pixel c: the argmax (first of
 // equals) and the confidence sum run over those 4 NT values in the lane, then
-// across the four 16-lane groups.
+// across the four 16-lane groups; the squared bin distances come from a
+// small LDS table.
 template <typename TO, int NT>
 __global__ __launch_bounds__(256) void k_gabor_mfma(const float* __restrict__ frames, int W,
                                                     int H, int R, int NO,
@@ -81,11 +87,22 @@ __global__ __launch_bounds__(256) void k_gabor_mfma(const float* __restrict__ fr
   const int w2 = 2 * R + 1, taps = w2 * w2, kpad = (taps + 3) & ~3, tw = kTile + 2 * R;
   const int th = kMfmaRows + 2 * R;  // tile rows with the halo
   float* sbank = lds;              // kpad x NJ
-  float* tile = lds + kpad * NJ;   // th x tw
+  float* tile = lds + kpad * NJ;   // th x kTw
   for (int e = threadIdx.x; e < kpad * NJ; e += blockDim.x) {
     const int t = e / NJ, j = e - t * NJ;
     const int dst = (t >> 2) * 4 * NJ + (j >> 4) * 64 + (t & 3) * 16 + (j & 15);
     sbank[dst] = (t < taps && j < NO) ? bank[(size_t)t * NO + j] : 0.0f;
+  }
+  // d2tab[NO + k] = squared line distance of two bins k apart (|k| < NO)
+  float* d2tab = tile + kTw * th;  // 64
+  if (threadIdx.x < 64) {
+    const int k = abs((int)threadIdx.x - NO);
+    float v = 0.0f;
+    if (k < NO) {
+      const float dd = (float)min(k, NO - k) * (kPi / NO);
+      v = dd * dd;
+    }
+    d2tab[threadIdx.x] = v;
   }
   const int lane = (int)(threadIdx.x & 63u), w = (int)(threadIdx.x >> 6);
   const int g = lane >> 4, c16 = lane & 15;
@@ -97,10 +114,10 @@ __global__ __launch_bounds__(256) void k_gabor_mfma(const float* __restrict__ fr
     const int x0 = tx * kTile, y0 = ty * kMfmaRows;
     const float* img = frames + plane * f;
     __syncthreads();  // the bank is in place; the previous tile is no longer read
-    for (int e = threadIdx.x; e < tw * th; e += blockDim.x) {
-      const int yy = e / tw, xx = e - yy * tw;
+    for (int e = threadIdx.x; e < kTw * th; e += blockDim.x) {
+      const int yy = e / kTw, xx = e - yy * kTw;
       const int x = x0 + xx - R, y = y0 + yy - R;
-      tile[e] = (x >= 0 && x < W && y >= 0 && y < H) ? img[(size_t)y * W + x] : 0.0f;
+      tile[e] = (xx < tw && x >= 0 && x < W && y >= 0 && y < H) ? img[(size_t)y * W + x] : 0.0f;
     }
     __syncthreads();
     f32x4 acc[kRowsPerWave][NT];
@@ -108,27 +125,33 @@ __global__ __launch_bounds__(256) void k_gabor_mfma(const float* __restrict__ fr
     for (int p = 0; p < kRowsPerWave; ++p)
 #pragma unroll
       for (int nt = 0; nt < NT; ++nt) acc[p][nt] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
-    const float* base = tile + kRowsPerWave * w * tw + c16;
+    const float* base = tile + kRowsPerWave * w * kTw + c16 + g;
     const float* bk = sbank + lane;
-    // this lane's tap t = k0 + g as (dy, dx) and its offset dy tw + dx; the
-    // zero bank rows of padded taps (t >= taps) meet the tap at offset 0
-    int dy = g / w2, dx = g - dy * w2;
+    // wave-uniform (row offset, column) of tap k0; a lane's tap k0 + g is at
+    // most one row further (g < 4 <= w2 + 1 and the column stays < w2)
+    int s_off = 0, s_dx = 0;
     for (int k0 = 0; k0 < kpad; k0 += 4) {
-      const int off = k0 + g < taps ? dy * tw + dx : 0;
+      const int wrap = g >= w2 - s_dx ? kTw - w2 : 0;
+      const int off = k0 + g < taps ? s_off + wrap : -g;
       float a[NT];
 #pragma unroll
       for (int nt = 0; nt < NT; ++nt) a[nt] = bk[k0 * NJ + 64 * nt];
       const float* src = base + off;
 #pragma unroll
       for (int p = 0; p < kRowsPerWave; ++p) {
-        const float v = src[p * tw];
+        const float v = src[p * kTw];
 #pragma unroll
         for (int nt = 0; nt < NT; ++nt)
           acc[p][nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[nt], v, acc[p][nt], 0, 0, 0);
       }
-      dx += 4;
-      if (dx >= w2) { dx -= w2; ++dy; }
-      if (dx >= w2) { dx -= w2; ++dy; }  // w2 = 3 can wrap twice
+      // issue order: the step's LDS reads (the bank, then the row pairs),
+      // then its matrix operations
+      __builtin_amdgcn_sched_group_barrier(0x100, 5, 0);
+      __builtin_amdgcn_sched_group_barrier(0x008, kRowsPerWave * NT, 0);
+      s_dx += 4;
+      s_off += 4;
+      if (s_dx >= w2) { s_dx -= w2; s_off += kTw - w2; }
+      if (s_dx >= w2) { s_dx -= w2; s_off += kTw - w2; }
     }
     // per pixel: argmax |F_j| (first of equals), then the spread of the
     // responses around it
@@ -159,16 +182,15 @@ __global__ __launch_bounds__(256) void k_gabor_mfma(const float* __restrict__ fr
         }
       }
       float s = 0.0f;
+      const float* d2 = d2tab + (NO + 4 * g - jb);
 #pragma unroll
       for (int nt = 0; nt < NT; ++nt)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           const int j = 16 * nt + 4 * g + r;
           if (j < NO) {
-            const int dj = abs(j - jb);
-            const float d = (float)min(dj, NO - dj) * (kPi / NO);
             const float e = fv[nt][r] - fb;
-            s = __builtin_fmaf(d * d, e * e, s);
+            s = __builtin_fmaf(d2[16 * nt + r], e * e, s);
           }
         }
       s += __shfl_xor(s, 16, 64);
@@ -232,7 +254,7 @@ hipError_t launch_gabor(const float* frames, int n, int W, int H, int R, int N, 
   const int taps = (2 * R + 1) * (2 * R + 1), kpad = (taps + 3) & ~3, tw = kTile + 2 * R;
   const int th = kMfmaRows + 2 * R;
   const int nt = N > 16 ? 2 : 1;
-  const size_t lds = sizeof(float) * ((size_t)kpad * 16 * nt + (size_t)tw * th);
+  const size_t lds = sizeof(float) * ((size_t)kpad * 16 * nt + (size_t)kTw * th + 64);
   const auto kern = nt == 2 ? k_gabor_mfma<TO, 2> : k_gabor_mfma<TO, 1>;
   hipError_t e = hipFuncSetAttribute((const void*)kern,
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
