@@ -72,8 +72,11 @@ constexpr int kTw = kTile + 2 * kMaxRadius;  // LDS tile row stride for every ra
 // equals) and the confidence sum run over those 4 NT values in the lane, then
 // across the four 16-lane groups; the squared bin distances come from a
 // small LDS table.
-template <typename TO, int NT>
-__global__ __launch_bounds__(256) void k_gabor_mfma(const float* __restrict__ frames, int W,
+// FULL: n_orient fills the NT orientation tiles (no per-lane validity
+// tests).  Three waves per SIMD is what the LDS allows (three workgroups per
+// CU at radius 8); the register bound keeps the compiler to it.
+template <typename TO, int NT, bool FULL>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_gabor_mfma(const float* __restrict__ frames, int W,
                                                     int H, int R, int NO,
                                                     const float* __restrict__ bank,
                                                     int64_t n_tiles, int tiles_x,
@@ -166,7 +169,7 @@ __global__ __launch_bounds__(256) void k_gabor_mfma(const float* __restrict__ fr
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           const int j = 16 * nt + 4 * g + r;  // increasing in the lane
-          fv[nt][r] = j < NO ? fabsf(acc[p][nt][r]) : -1.0f;
+          fv[nt][r] = (FULL || j < NO) ? fabsf(acc[p][nt][r]) : -1.0f;
           if (fv[nt][r] > fb) {
             fb = fv[nt][r];
             jb = j;
@@ -188,7 +191,7 @@ __global__ __launch_bounds__(256) void k_gabor_mfma(const float* __restrict__ fr
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           const int j = 16 * nt + 4 * g + r;
-          if (j < NO) {
+          if (FULL || j < NO) {
             const float e = fv[nt][r] - fb;
             s = __builtin_fmaf(d2[16 * nt + r], e * e, s);
           }
@@ -255,7 +258,10 @@ hipError_t launch_gabor(const float* frames, int n, int W, int H, int R, int N, 
   const int th = kMfmaRows + 2 * R;
   const int nt = N > 16 ? 2 : 1;
   const size_t lds = sizeof(float) * ((size_t)kpad * 16 * nt + (size_t)kTw * th + 64);
-  const auto kern = nt == 2 ? k_gabor_mfma<TO, 2> : k_gabor_mfma<TO, 1>;
+  // N = 16 and 32 fill their orientation tiles: no per-lane validity tests
+  const auto kern = nt == 2    ? k_gabor_mfma<TO, 2, true>
+                    : N == 16 ? k_gabor_mfma<TO, 1, true>
+                              : k_gabor_mfma<TO, 1, false>;
   hipError_t e = hipFuncSetAttribute((const void*)kern,
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
