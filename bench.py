@@ -77,8 +77,8 @@ TRAFFIC = {
     # the four-wave form spills a few registers: scratch traffic included
     "k_b_learned4, metric workload": {"read": 2965.7e6, "write": 882.5e6,
                                       "files": _BATCHED_SOURCES, "src": "e1c6962ed9dbe9c5"},
-    "k_gabor_mfma, 64 frames 1024^2": {"read": 1149.5e6, "write": 406.8e6,
-                                       "files": _GABOR_SOURCES, "src": "ee6c0ddd10b80a71"},
+    "k_gabor_mfma, 64 frames 1024^2": {"read": 1152.1e6, "write": 406.8e6,
+                                       "files": _GABOR_SOURCES, "src": "e8af559ee6627b21"},
     # the counting sort: keys and counts, the scan, the placement
     "volume sort, realistic 2M points 2 mm": {"read": 319.8e6, "write": 237.4e6,
                                               "files": _VOLUME_SOURCES,

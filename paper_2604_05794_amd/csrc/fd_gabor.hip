@@ -38,15 +38,42 @@ __device__ __forceinline__ void store_map(void* out, size_t i, float v) {
     ((float*)out)[i] = v;
 }
 
+// One frame per grid row (its maximum read once), 8 pixels per thread in
+// 16-byte loads and stores where the plane and the output allow it.
 template <typename TO>
 __global__ __launch_bounds__(256) void k_gabor_norm(const float* __restrict__ raw,
                                                     const uint32_t* __restrict__ frame_max,
-                                                    int64_t plane, int64_t n,
+                                                    int64_t plane, int vec,
                                                     void* __restrict__ conf_out) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const float m = __uint_as_float(frame_max[i / plane]);
-  store_map<TO>(conf_out, (size_t)i, m > 0.0f ? raw[i] / m : 0.0f);
+  const int64_t f = blockIdx.y;
+  const float m = __uint_as_float(frame_max[f]);
+  const float* r = raw + plane * f;
+  TO* out = (TO*)conf_out + plane * f;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  const int64_t t0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (vec) {
+    const int64_t n8 = plane >> 3;
+    for (int64_t i = t0; i < n8; i += stride) {
+      const float4 a = ((const float4*)r)[2 * i], b = ((const float4*)r)[2 * i + 1];
+      const float v[8] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w};
+      float o[8];
+#pragma unroll
+      for (int k = 0; k < 8; ++k) o[k] = m > 0.0f ? v[k] / m : 0.0f;
+      if constexpr (sizeof(TO) == 2) {
+        uint32_t h[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) h[k] = __half_as_ushort(__float2half(o[k]));
+        ((uint4*)out)[i] = make_uint4(h[0] | (h[1] << 16), h[2] | (h[3] << 16),
+                                      h[4] | (h[5] << 16), h[6] | (h[7] << 16));
+      } else {
+        ((float4*)out)[2 * i] = make_float4(o[0], o[1], o[2], o[3]);
+        ((float4*)out)[2 * i + 1] = make_float4(o[4], o[5], o[6], o[7]);
+      }
+    }
+  } else {
+    for (int64_t i = t0; i < plane; i += stride)
+      store_map<TO>(out, (size_t)i, m > 0.0f ? r[i] / m : 0.0f);
+  }
 }
 
 typedef float f32x4 __attribute__((ext_vector_type(4)));
@@ -363,13 +390,17 @@ extern "C" int fd_orientation_maps(const float* frames, int32_t n_frames, int32_
   if (e != hipSuccess) return hip_error(e, "orientation kernel");
   tg.stop();
   StageTimer tn(c, FD_STAGE_GABOR_NORM, st);
-  const int64_t nb = ((int64_t)total + 255) / 256;
+  // raw is a workspace allocation, so only the plane and the caller's output
+  // decide whether whole 16-byte groups line up
+  const int vec = plane % 8 == 0 && (uintptr_t)conf_out % 16 == 0;
+  const int64_t work = vec ? (int64_t)plane / 8 : (int64_t)plane;
+  const dim3 ng((unsigned)std::min<int64_t>((work + 255) / 256, 1 << 20), (unsigned)n_frames);
   if (p->out_dtype == FD_F16)
-    hipLaunchKernelGGL(k_gabor_norm<__half>, dim3((unsigned)nb), dim3(256), 0, st, c->gabor_raw,
-                       c->gabor_max, (int64_t)plane, (int64_t)total, conf_out);
+    hipLaunchKernelGGL(k_gabor_norm<__half>, ng, dim3(256), 0, st, c->gabor_raw, c->gabor_max,
+                       (int64_t)plane, vec, conf_out);
   else
-    hipLaunchKernelGGL(k_gabor_norm<float>, dim3((unsigned)nb), dim3(256), 0, st, c->gabor_raw,
-                       c->gabor_max, (int64_t)plane, (int64_t)total, conf_out);
+    hipLaunchKernelGGL(k_gabor_norm<float>, ng, dim3(256), 0, st, c->gabor_raw, c->gabor_max,
+                       (int64_t)plane, vec, conf_out);
   if ((e = hipGetLastError()) != hipSuccess) return hip_error(e, "confidence kernel");
   tn.stop();
   return FD_OK;
