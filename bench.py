@@ -85,7 +85,7 @@ TRAFFIC = {
                                               "src": "b0b5904bb1ae7e7b"},
     # per pass: the 5 guide batches and the 2 segment launches
     "k_grow, phg workload": {"read": 201.9e6, "write": 30.7e6, "files": _PHG_SOURCES,
-                             "src": "a255c8c4df86e750"},
+                             "src": "4f42252c325b0cf8"},
 }
 
 

@@ -260,34 +260,69 @@ __global__ __launch_bounds__(256) void k_strand_len(PiecesDev P, int64_t* __rest
   if (pieces) pieces[g] = np;
 }
 
-// Exclusive scan of n lengths into offsets (n + 1 entries) in one block:
-// thread t owns a contiguous run of entries, summed in order; the run sums
-// are scanned across the block; each thread then writes its run.
+// Inclusive scan of one value per thread across a block of 1024 threads:
+// within each wave by shuffles, then over the 16 wave totals.  Every thread
+// of the block calls it once.
+__device__ __forceinline__ int64_t block_incl_scan(int64_t x, int64_t* wsum) {
+  const int t = (int)threadIdx.x, lane = t & 63, wv = t >> 6;
+  for (int o = 1; o < 64; o <<= 1) {
+    const int64_t y = __shfl_up(x, o, 64);
+    if (lane >= o) x += y;
+  }
+  if (lane == 63) wsum[wv] = x;
+  __syncthreads();
+  if (wv == 0) {
+    int64_t y = lane < 1024 / 64 ? wsum[lane] : 0;
+    for (int o = 1; o < 1024 / 64; o <<= 1) {
+      const int64_t z = __shfl_up(y, o, 64);
+      if (lane >= o) y += z;
+    }
+    if (lane < 1024 / 64) wsum[lane] = y;
+  }
+  __syncthreads();
+  return x + (wv > 0 ? wsum[wv - 1] : 0);
+}
+
+// Exclusive scan of n entries into off (n + 1 entries, off[n] = the total)
+// in one block: thread t owns a contiguous run, summed in order, and writes
+// it after the block scan of the run sums.  Used on the per-block sums of
+// the lengths (and on an empty list).
 __global__ __launch_bounds__(1024) void k_len_scan(const int64_t* __restrict__ len, int32_t n,
                                                    int64_t* __restrict__ off) {
-  __shared__ int64_t part[1024];
+  __shared__ int64_t wsum[1024 / 64];
   const int t = (int)threadIdx.x;
   const int32_t per = (n + 1023) / 1024;
   const int32_t a = t * per, b = min(n, a + per);
   int64_t s = 0;
   for (int32_t i = a; i < b; ++i) s += len[i];
-  part[t] = s;
-  __syncthreads();
-  if (t == 0) {
-    int64_t acc = 0;
-    for (int k = 0; k < 1024; ++k) {
-      const int64_t v = part[k];
-      part[k] = acc;
-      acc += v;
-    }
-    off[n] = acc;
-  }
-  __syncthreads();
-  int64_t acc = part[t];
+  const int64_t incl = block_incl_scan(s, wsum);
+  if (t == 1023) off[n] = incl;
+  int64_t acc = incl - s;
   for (int32_t i = a; i < b; ++i) {
     off[i] = acc;
     acc += len[i];
   }
+}
+
+// The lengths in blocks of 1024 (coalesced): each block's sum, then, once
+// those are scanned, each entry's offset.
+__global__ __launch_bounds__(1024) void k_len_bsum(const int64_t* __restrict__ len, int32_t n,
+                                                   int64_t* __restrict__ bsum) {
+  __shared__ int64_t wsum[1024 / 64];
+  const int64_t i = (int64_t)blockIdx.x * 1024 + threadIdx.x;
+  const int64_t incl = block_incl_scan(i < n ? len[i] : 0, wsum);
+  if (threadIdx.x == 1023) bsum[blockIdx.x] = incl;
+}
+
+__global__ __launch_bounds__(1024) void k_len_apply(const int64_t* __restrict__ len, int32_t n,
+                                                    const int64_t* __restrict__ boff,
+                                                    int64_t* __restrict__ off) {
+  __shared__ int64_t wsum[1024 / 64];
+  const int64_t i = (int64_t)blockIdx.x * 1024 + threadIdx.x;
+  const int64_t v = i < n ? len[i] : 0;
+  const int64_t incl = block_incl_scan(v, wsum);
+  if (i < n) off[i] = boff[blockIdx.x] + incl - v;
+  if (blockIdx.x == 0 && threadIdx.x == 0) off[n] = boff[gridDim.x];
 }
 
 __global__ __launch_bounds__(256) void k_assemble(PiecesDev P, const float* __restrict__ gv,
@@ -522,14 +557,25 @@ extern "C" int fd_strand_offsets(const int32_t* guide_n, int32_t n_guide, const 
   fd_context* c = context_for(ctx, fn, &r);
   if (!c) return r;
   hipStream_t st = (hipStream_t)stream;
+  // lengths (n_guide), then the block sums (nb) and their offsets (nb + 1)
+  const int32_t nb = (n_guide + 1023) / 1024;
   if ((r = ctx_buffer((void**)&c->strand_len, &c->cap_strand_len,
-                      8 * (size_t)(n_guide > 0 ? n_guide : 1), "strand lengths")))
+                      8 * ((size_t)n_guide + 2 * (size_t)nb + 1), "strand lengths")))
     return r;
   PiecesDev P{guide_n, fwd_n, bwd_n, succ, n_guide, n_seg};
-  if (n_guide > 0)
+  if (n_guide > 0) {
+    int64_t* bsum = c->strand_len + n_guide;
+    int64_t* boff = bsum + nb;
     hipLaunchKernelGGL(k_strand_len, dim3((unsigned)((n_guide + 255) / 256)), dim3(256), 0, st,
                        P, c->strand_len, pieces);
-  hipLaunchKernelGGL(k_len_scan, dim3(1), dim3(1024), 0, st, c->strand_len, n_guide, offsets);
+    hipLaunchKernelGGL(k_len_bsum, dim3((unsigned)nb), dim3(1024), 0, st, c->strand_len,
+                       n_guide, bsum);
+    hipLaunchKernelGGL(k_len_scan, dim3(1), dim3(1024), 0, st, bsum, nb, boff);
+    hipLaunchKernelGGL(k_len_apply, dim3((unsigned)nb), dim3(1024), 0, st, c->strand_len,
+                       n_guide, boff, offsets);
+  } else {
+    hipLaunchKernelGGL(k_len_scan, dim3(1), dim3(1024), 0, st, c->strand_len, 0, offsets);
+  }
   hipError_t e = hipGetLastError();
   return e == hipSuccess ? FD_OK : hip_error(e, "strand offsets");
 }
