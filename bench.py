@@ -70,13 +70,13 @@ _GABOR_SOURCES = ["fd_gabor.hip"]
 _VOLUME_SOURCES = ["fd_volume.hip", "fd_voxel.hpp"]
 _PHG_SOURCES = ["fd_phg.hip", "fd_voxel.hpp"]
 TRAFFIC = {
-    "k_fuse, realistic 500k": {"read": 385.5e6, "write": 37.7e6, "files": _SEARCH_SOURCES,
-                               "src": "320d01ce2a409293"},
-    "k_fuse, metric workload, per head": {"read": 293.6e6, "write": 19.1e6,
-                                          "files": _SEARCH_SOURCES, "src": "320d01ce2a409293"},
+    "k_fuse, realistic 500k": {"read": 377.2e6, "write": 37.7e6, "files": _SEARCH_SOURCES,
+                               "src": "d78225e8409978a0"},
+    "k_fuse, metric workload, per head": {"read": 294.2e6, "write": 19.1e6,
+                                          "files": _SEARCH_SOURCES, "src": "d78225e8409978a0"},
     # the four-wave form spills a few registers: scratch traffic included
-    "k_b_learned4, metric workload": {"read": 2965.7e6, "write": 882.5e6,
-                                      "files": _BATCHED_SOURCES, "src": "e1c6962ed9dbe9c5"},
+    "k_b_learned4, metric workload": {"read": 3039.3e6, "write": 882.0e6,
+                                      "files": _BATCHED_SOURCES, "src": "68f3f75745121fe5"},
     "k_gabor_mfma, 64 frames 1024^2": {"read": 1152.1e6, "write": 406.8e6,
                                        "files": _GABOR_SOURCES, "src": "e8af559ee6627b21"},
     # the counting sort: keys and counts, the scan, the placement

@@ -311,10 +311,26 @@ __device__ __forceinline__ void full_search(const ViewPatch<P>& vp, const Search
                                             float& S) {
   float Sb = -INFINITY;
   int kb = 0;
-#pragma unroll 2
-  for (int k = 0; k < q.n_candidates; ++k) {
-    const float cx = q.lattice[3 * k], cy = q.lattice[3 * k + 1], cz = q.lattice[3 * k + 2];
-    const float Sk = group_sum_t<KT>(eval_view<P>(vp, cx, cy, cz), gr.base, gr.K);
+  // two candidates per pass (by hand: the group sum's cross-lane reads keep
+  // the compiler from unrolling), taken in order so that the first of equals
+  // still wins
+  int k = 0;
+  for (; k + 1 < q.n_candidates; k += 2) {
+    const float* c = q.lattice + 3 * k;
+    const float S0 = group_sum_t<KT>(eval_view<P>(vp, c[0], c[1], c[2]), gr.base, gr.K);
+    const float S1 = group_sum_t<KT>(eval_view<P>(vp, c[3], c[4], c[5]), gr.base, gr.K);
+    if (S0 > Sb) {
+      Sb = S0;
+      kb = k;
+    }
+    if (S1 > Sb) {
+      Sb = S1;
+      kb = k + 1;
+    }
+  }
+  if (k < q.n_candidates) {
+    const float* c = q.lattice + 3 * k;
+    const float Sk = group_sum_t<KT>(eval_view<P>(vp, c[0], c[1], c[2]), gr.base, gr.K);
     if (Sk > Sb) {
       Sb = Sk;
       kb = k;
