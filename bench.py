@@ -78,7 +78,7 @@ TRAFFIC = {
     "k_b_learned4, metric workload": {"read": 3039.3e6, "write": 882.0e6,
                                       "files": _BATCHED_SOURCES, "src": "68f3f75745121fe5"},
     "k_gabor_mfma, 64 frames 1024^2": {"read": 1152.1e6, "write": 406.8e6,
-                                       "files": _GABOR_SOURCES, "src": "e8af559ee6627b21"},
+                                       "files": _GABOR_SOURCES, "src": "21a8f3739c8a0866"},
     # the counting sort: keys and counts, the scan, the placement
     "volume sort, realistic 2M points 2 mm": {"read": 319.8e6, "write": 237.4e6,
                                               "files": _VOLUME_SOURCES,

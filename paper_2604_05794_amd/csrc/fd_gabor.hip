@@ -281,7 +281,7 @@ hipError_t launch_gabor(const float* frames, int n, int W, int H, int R, int N, 
                         void* theta, float* raw, uint32_t* fmax, hipStream_t st) {
   const int tiles_x = (W + kTile - 1) / kTile, tiles_y = (H + kMfmaRows - 1) / kMfmaRows;
   const int64_t per_frame = (int64_t)tiles_x * tiles_y, n_tiles = per_frame * n;
-  const int taps = (2 * R + 1) * (2 * R + 1), kpad = (taps + 3) & ~3, tw = kTile + 2 * R;
+  const int taps = (2 * R + 1) * (2 * R + 1), kpad = (taps + 3) & ~3;
   const int th = kMfmaRows + 2 * R;
   const int nt = N > 16 ? 2 : 1;
   const size_t lds = sizeof(float) * ((size_t)kpad * 16 * nt + (size_t)kTw * th + 64);
