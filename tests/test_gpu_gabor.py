@@ -127,6 +127,25 @@ def test_half_maps_are_the_rounded_float_maps():
     assert np.array_equal(cf16, cf32.astype(np.float16).astype(np.float32))
 
 
+@pytest.mark.parametrize("dt", [torch.float16, torch.float32])
+def test_unaligned_confidence_buffer(dt):
+    """A confidence buffer that is not 16-byte aligned takes the element-wise
+    normalisation and holds the same maps as an aligned one."""
+    nat = _native()
+    frames, _, _, _ = scenegen.make_frames("tiny", 4)
+    fr = torch.from_numpy(np.ascontiguousarray(frames[:3], np.float32)).to(DEV)
+    V, H, W = fr.shape
+    assert (H * W) % 8 == 0  # the aligned call takes the 8-pixel path
+    th0, cf0 = nat.orientation_maps(fr, out_dtype=dt)
+    buf = torch.full((V * H * W + 1,), 7.0, dtype=dt, device=DEV)
+    cf1 = buf[1:].view(V, H, W)
+    assert cf1.data_ptr() % 16 != 0
+    th1, _ = nat.orientation_maps(fr, out_dtype=dt, conf=cf1)
+    torch.cuda.synchronize()
+    assert torch.equal(th0, th1) and torch.equal(cf0, cf1)
+    assert buf[0].item() == 7.0  # nothing written before the buffer
+
+
 def test_frames_are_independent():
     frames, _, _, _ = scenegen.make_frames("tiny", 2)
     th, cf = _gpu(frames[:5])
