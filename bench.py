@@ -76,7 +76,7 @@ TRAFFIC = {
                                           "files": _SEARCH_SOURCES, "src": "d78225e8409978a0"},
     # the four-wave form spills a few registers: scratch traffic included
     "k_b_learned4, metric workload": {"read": 3039.3e6, "write": 882.0e6,
-                                      "files": _BATCHED_SOURCES, "src": "68f3f75745121fe5"},
+                                      "files": _BATCHED_SOURCES, "src": "1578a19317a4d965"},
     "k_gabor_mfma, 64 frames 1024^2": {"read": 1152.1e6, "write": 406.8e6,
                                        "files": _GABOR_SOURCES, "src": "21a8f3739c8a0866"},
     # the counting sort: keys and counts, the scan, the placement
