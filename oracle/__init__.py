@@ -171,7 +171,7 @@ class Oracle:
     def select_views(self, p):
         p = _c(p, np.float32)
         ids = np.zeros(16, np.int32)
-        u = np.zeros(32, np.float32)
+        u = np.zeros(32, np.float64)
         k = lib().fdo_select_views(_ptr(p), _ptr(self.cams), self.V, _ptr(self.conf),
                                    ctypes.byref(self.prm), _ptr(ids), _ptr(u))
         return ids[:k].copy(), u[:2 * k].reshape(k, 2).copy()

@@ -5,8 +5,8 @@
  * at a time, no tiling, no reformulation of the paper's expressions.
  *
  * Build: gcc -O2 -std=c99 -fopenmp -ffp-contract=off -fPIC -shared.
- * Floating-point contraction must stay off so that the binary32 decision
- * arithmetic below is evaluated exactly as written.
+ * Floating-point contraction stays off, so every expression below is
+ * evaluated exactly as written (one rounding per operation).
  */
 #define _POSIX_C_SOURCE 200809L
 #include "fdo.h"
@@ -54,88 +54,78 @@ static const void* view_map(const void* maps, int dtype, int W, int H, int v) {
 }
 
 /* ------------------------------------------------------------------------ */
-/* binary32 decision arithmetic (projection, eligibility, Eq. (4) ranking)   */
+/* projection, eligibility and the Eq. (4) ranking (binary64)                */
 /*
- * View eligibility and the top-K ranking turn floating-point values into a
- * discrete choice, so they are evaluated in binary32 with one fixed order of
- * operations that any implementation can reproduce bit for bit:
- *   X = fma(R0, px, fma(R1, py, fma(R2, pz, t0)))   (likewise Y, Z)
+ * The calibrated pinhole camera of Sec. 3.1 maps a world point p to
+ * X_c = R p + t and to the pixel u = (f_x X/Z + c_x, f_y Y/Z + c_y).
+ * Everything here is evaluated in binary64 from the binary32 inputs (which
+ * convert exactly), so every discrete choice below (in front, inside the
+ * image, visible, confidence above zero, the ranking) is the exact
+ * mathematical choice up to binary64 rounding:
  *   eligible-front  : Z > z_near
- *   iz = 1 / Z (correctly rounded),  u = fma(fx, X * iz, cx),  v = fma(fy, Y * iz, cy)
- *   eligible-inside : 0 <= u <= W-1 and 0 <= v <= H-1
- *   x0 = floor(u), fx = u - x0, gx = 1 - fx (likewise y)
- *   w00 = gx*gy, w10 = fx*gy, w01 = gx*fy, w11 = fx*fy
- *   Cbar = fma(w11, C11, fma(w01, C01, fma(w10, C10, w00*C00)))
- *   eligible : front and inside and Cbar > 0
- *   with depth maps, also visible:
- *     ix = (int)floor(u + 0.5f), iy = (int)floor(v + 0.5f)   (nearest texel)
- *     visible : |Z - D(ix, iy)| <= (float)vis_tau   (Sec. 3.1.1, V_i^v)
- * The pixel position u computed here is also the patch centre (Sec. 3.1.3:
- * the patch is centred on the projection of the point).
+ *   eligible-inside : 0 <= u_x <= W-1 and 0 <= u_y <= H-1
+ *   eligible        : front, inside and the bilinear centre confidence > 0
+ *   with depth maps, also visible (Sec. 3.1.1, the score V_i^v):
+ *     the texel nearest to u, (floor(u_x + 1/2), floor(u_y + 1/2)), holds a
+ *     rendered camera-space depth D with |Z - D| <= vis_tau
+ * The pixel position u is also the centre of the fusion patch (Sec. 3.1.3:
+ * the patch is taken around the projection of the point).
  */
-static int project32(const float* cam, const float* p, int W, int H,
-                     float z_near, float* u, float* z_out) {
+static int project(const float* cam, const float* p, int W, int H,
+                   double z_near, double u[2], double Xc[3]) {
   const float* R = cam + 4;
   const float* t = cam + 13;
-  float X = fmaf(R[0], p[0], fmaf(R[1], p[1], fmaf(R[2], p[2], t[0])));
-  float Y = fmaf(R[3], p[0], fmaf(R[4], p[1], fmaf(R[5], p[2], t[1])));
-  float Z = fmaf(R[6], p[0], fmaf(R[7], p[1], fmaf(R[8], p[2], t[2])));
-  if (!(Z > z_near)) return 0;
-  float iz = 1.0f / Z;
-  float ux = fmaf(cam[0], X * iz, cam[2]);
-  float uy = fmaf(cam[1], Y * iz, cam[3]);
-  if (!(ux >= 0.0f && ux <= (float)(W - 1) && uy >= 0.0f &&
-        uy <= (float)(H - 1)))
-    return 0;
-  u[0] = ux;
-  u[1] = uy;
-  *z_out = Z;
-  return 1;
+  for (int r = 0; r < 3; ++r)
+    Xc[r] = (double)R[3 * r] * p[0] + (double)R[3 * r + 1] * p[1] +
+            (double)R[3 * r + 2] * p[2] + (double)t[r];
+  if (!(Xc[2] > z_near)) return 0;
+  u[0] = (double)cam[0] * (Xc[0] / Xc[2]) + (double)cam[2];
+  u[1] = (double)cam[1] * (Xc[1] / Xc[2]) + (double)cam[3];
+  return u[0] >= 0.0 && u[0] <= (double)(W - 1) && u[1] >= 0.0 &&
+         u[1] <= (double)(H - 1);
 }
 
 /* Sec. 3.1.1 visibility: the point's camera-space depth agrees with the
  * rendered depth at the nearest texel of its projection.  Always true
- * without depth maps. */
-static int visible32(const fdo_params* prm, int v, const float* u, float Z) {
+ * without depth maps; a +inf (nothing rendered) or NaN depth never is. */
+static int visible(const fdo_params* prm, int v, const double* u, double Z) {
   if (!prm->depth_maps) return 1;
   const int W = prm->width, H = prm->height, dt = prm->map_dtype;
-  int ix = (int)floorf(u[0] + 0.5f), iy = (int)floorf(u[1] + 0.5f);
-  float D = texel(view_map(prm->depth_maps, dt, W, H, v), dt, W, H, ix, iy);
-  return fabsf(Z - D) <= (float)prm->vis_tau;
+  int ix = (int)floor(u[0] + 0.5), iy = (int)floor(u[1] + 0.5);
+  double D = texel(view_map(prm->depth_maps, dt, W, H, v), dt, W, H, ix, iy);
+  return fabs(Z - D) <= prm->vis_tau;
 }
 
-static float centre_conf32(const void* cmap, int dtype, int W, int H,
-                           float ux, float uy) {
-  float x0 = floorf(ux), y0 = floorf(uy);
-  float fx = ux - x0, fy = uy - y0;
-  float gx = 1.0f - fx, gy = 1.0f - fy;
+/* Plain bilinear interpolation of a confidence map at (x, y); texels outside
+ * the image read 0. */
+static double bilinear_conf(const void* cmap, int dtype, int W, int H, double x,
+                            double y) {
+  double x0 = floor(x), y0 = floor(y);
+  double fx = x - x0, fy = y - y0;
   int ix = (int)x0, iy = (int)y0;
-  float c00 = texel(cmap, dtype, W, H, ix, iy);
-  float c10 = texel(cmap, dtype, W, H, ix + 1, iy);
-  float c01 = texel(cmap, dtype, W, H, ix, iy + 1);
-  float c11 = texel(cmap, dtype, W, H, ix + 1, iy + 1);
-  float w00 = gx * gy, w10 = fx * gy, w01 = gx * fy, w11 = fx * fy;
-  return fmaf(w11, c11, fmaf(w01, c01, fmaf(w10, c10, w00 * c00)));
+  return (1.0 - fx) * (1.0 - fy) * texel(cmap, dtype, W, H, ix, iy) +
+         fx * (1.0 - fy) * texel(cmap, dtype, W, H, ix + 1, iy) +
+         (1.0 - fx) * fy * texel(cmap, dtype, W, H, ix, iy + 1) +
+         fx * fy * texel(cmap, dtype, W, H, ix + 1, iy + 1);
 }
 
 /* Eq. (4): the K eligible views with the largest centre confidence; equal
  * confidences go to the lower view index. */
 int fdo_select_views(const float* p, const float* cams, int32_t n_views,
                      const void* conf_maps, const fdo_params* prm,
-                     int32_t* views_out, float* u_out) {
+                     int32_t* views_out, double* u_out) {
   const int W = prm->width, H = prm->height, dt = prm->map_dtype;
   int K = prm->top_k;
   if (K > FDO_MAX_K) K = FDO_MAX_K;
   int kept = 0;
   int ids[FDO_MAX_K];
-  float sc[FDO_MAX_K], us[FDO_MAX_K][2];
+  double sc[FDO_MAX_K], us[FDO_MAX_K][2];
   for (int v = 0; v < n_views; ++v) {
-    float u[2], Z;
-    if (!project32(cams + 16 * v, p, W, H, (float)prm->z_near, u, &Z)) continue;
-    if (!visible32(prm, v, u, Z)) continue;
-    float s = centre_conf32(view_map(conf_maps, dt, W, H, v), dt, W, H, u[0],
-                            u[1]);
-    if (!(s > 0.0f)) continue;
+    double u[2], Xc[3];
+    if (!project(cams + 16 * v, p, W, H, prm->z_near, u, Xc)) continue;
+    if (!visible(prm, v, u, Xc[2])) continue;
+    double s = bilinear_conf(view_map(conf_maps, dt, W, H, v), dt, W, H, u[0], u[1]);
+    if (!(s > 0.0)) continue;
     /* insertion into a descending list; a later view must be strictly
        better to move ahead of an earlier one */
     int pos = kept;
@@ -206,7 +196,7 @@ void fdo_sample(const void* theta_map, const void* conf_map, int32_t dtype,
 typedef struct {
   int k_eff;
   int views[FDO_MAX_K];
-  double u[FDO_MAX_K][2];    /* binary32 projection of Eq. (4), as double */
+  double u[FDO_MAX_K][2];    /* projection of the point (patch centre) */
   double Xc[FDO_MAX_K][3];   /* camera-space point, binary64 */
   double R[FDO_MAX_K][9];
   double f[FDO_MAX_K][2];
@@ -224,7 +214,7 @@ static void point_setup(const float* p, const float* cams, int n_views,
                         const fdo_params* prm, point_state* st) {
   const int W = prm->width, H = prm->height, dt = prm->map_dtype;
   const int P = prm->patch, h = (P - 1) / 2;
-  float u[2 * FDO_MAX_K];
+  double u[2 * FDO_MAX_K];
   st->k_eff = fdo_select_views(p, cams, n_views, conf_maps, prm, st->views, u);
   st->n_samp = P * P;
   for (int k = 0; k < st->k_eff; ++k) {
@@ -243,8 +233,7 @@ static void point_setup(const float* p, const float* cams, int n_views,
     for (int b = -h; b <= h; ++b) {
       for (int a = -h; a <= h; ++a, ++s) {
         double o[3];
-        fdo_sample(tm, cm, dt, W, H, (double)u[2 * k] + a,
-                   (double)u[2 * k + 1] + b, o);
+        fdo_sample(tm, cm, dt, W, H, u[2 * k] + a, u[2 * k + 1] + b, o);
         st->cbar[k][s] = o[0];
         st->tbar[k][s] = o[1];
         st->valid[k][s] = (int)o[2];
@@ -567,29 +556,25 @@ int fdo_fuse_learned(const float* points, int64_t n_points, const float* cams,
 /* ------------------------------------------------------------------------ */
 /* proposal-network features                                                 */
 /*
- * Frontal ranking is a discrete choice, decided in binary32:
- *   camera centre  c = -R^T t,  c_x = -fma(R0, t0, fma(R3, t1, R6*t2)),
- *                               c_y = -fma(R1, t0, fma(R4, t1, R7*t2)),
- *                               c_z = -fma(R2, t0, fma(R5, t1, R8*t2))
- *   a = c - p, b = p - o (componentwise binary32 subtraction)
- *   score = fma(a_x, b_x, fma(a_y, b_y, a_z*b_z)) /
- *           sqrt(fma(a_x, a_x, fma(a_y, a_y, a_z*a_z)))
- * eligible views are those that project32() and visible32() accept; the n_slots largest scores are
- * kept, equal scores to the lower view index.  |b| is common to every view of
- * a point and does not change the ranking.
+ * The n_slots most frontal views among the eligible ones (project() and
+ * visible() above), ranked in binary64 by the cosine between the
+ * point -> camera-centre direction a = c - p (camera centre c = -R^T t) and
+ * the outward direction b = p - o:
+ *   score = (a . b) / |a|
+ * |b| is common to every view of a point and does not change the ranking;
+ * equal scores go to the lower view index.
  */
-static float frontal_score32(const float* cam, const float* p,
-                             const float* o) {
+static double frontal_score(const float* cam, const float* p, const float* o) {
   const float* R = cam + 4;
   const float* t = cam + 13;
-  float cx = -fmaf(R[0], t[0], fmaf(R[3], t[1], R[6] * t[2]));
-  float cy = -fmaf(R[1], t[0], fmaf(R[4], t[1], R[7] * t[2]));
-  float cz = -fmaf(R[2], t[0], fmaf(R[5], t[1], R[8] * t[2]));
-  float ax = cx - p[0], ay = cy - p[1], az = cz - p[2];
-  float bx = p[0] - o[0], by = p[1] - o[1], bz = p[2] - o[2];
-  float dot = fmaf(ax, bx, fmaf(ay, by, az * bz));
-  float la = sqrtf(fmaf(ax, ax, fmaf(ay, ay, az * az)));
-  return dot / la;
+  double a[3], b[3];
+  for (int k = 0; k < 3; ++k) {
+    double c = -((double)R[k] * t[0] + (double)R[3 + k] * t[1] + (double)R[6 + k] * t[2]);
+    a[k] = c - (double)p[k];
+    b[k] = (double)p[k] - (double)o[k];
+  }
+  return (a[0] * b[0] + a[1] * b[1] + a[2] * b[2]) /
+         sqrt(a[0] * a[0] + a[1] * a[1] + a[2] * a[2]);
 }
 
 int fdo_features(const float* points, int64_t n_points, const float* cams,
@@ -606,13 +591,13 @@ int fdo_features(const float* points, int64_t n_points, const float* cams,
   for (int64_t i = 0; i < n_points; ++i) {
     const float* p = points + 3 * i;
     int ids[64];
-    float sc[64], us[64][2];
+    double sc[64], us[64][2];
     int kept = 0, S = n_slots > 64 ? 64 : n_slots;
     for (int v = 0; v < n_views; ++v) {
-      float u[2], Z;
-      if (!project32(cams + 16 * v, p, W, H, (float)prm->z_near, u, &Z)) continue;
-      if (!visible32(prm, v, u, Z)) continue;
-      float s = frontal_score32(cams + 16 * v, p, head_centre);
+      double u[2], Xc[3];
+      if (!project(cams + 16 * v, p, W, H, prm->z_near, u, Xc)) continue;
+      if (!visible(prm, v, u, Xc[2])) continue;
+      double s = frontal_score(cams + 16 * v, p, head_centre);
       int pos = kept;
       while (pos > 0 && s > sc[pos - 1]) --pos;
       if (pos >= S) continue;

@@ -48,7 +48,7 @@ typedef struct fdo_params {
   /* Optional visibility test of Sec. 3.1.1 (the score V_i^v): when
    * depth_maps is not NULL (V x H x W, camera-space Z in the map dtype,
    * +inf where nothing was rendered) a view is eligible only if
-   * |Z - D_v(nearest texel of u)| <= vis_tau, decided in binary32. */
+   * |Z - D_v(nearest texel of u)| <= vis_tau. */
   const void* depth_maps;
   double vis_tau;
 } fdo_params;
@@ -56,13 +56,14 @@ typedef struct fdo_params {
 /* binary16 -> binary32, exact. */
 float fdo_half_to_float(uint16_t h);
 
-/* Eq. (4) view selection for one point.  Eligibility and ranking are decided
- * in binary32 with the fixed operation order documented in fdo.c.  Writes up
- * to top_k view ids (best first) and their binary32 pixel positions
- * (u_out[2*k], u_out[2*k+1]); returns K_eff. */
+/* Eq. (4) view selection for one point, in binary64: eligible views (in
+ * front, projecting inside the image, positive bilinear centre confidence
+ * and, with depth maps, visible) ranked by that confidence, equal values to
+ * the lower view index.  Writes up to top_k view ids (best first) and their
+ * pixel positions (u_out[2*k], u_out[2*k+1]; may be NULL); returns K_eff. */
 int fdo_select_views(const float* p, const float* cams, int32_t n_views,
                      const void* conf_maps, const fdo_params* prm,
-                     int32_t* views_out, float* u_out);
+                     int32_t* views_out, double* u_out);
 
 /* Bilinear, confidence-weighted doubled-angle sample at continuous pixel
  * position (x, y) of one view.  out[0] = interpolated confidence,
@@ -127,7 +128,7 @@ int fdo_fuse_learned(const float* points, int64_t n_points, const float* cams,
 
 /* Proposal-network input features: the n_slots most frontal views (ranked by
  * the cosine between the point->camera direction and the outward direction
- * p - head_centre, decided in binary32), each slot
+ * p - head_centre), each slot
  * (q_x, q_y, C, v_x, v_y, v_z, valid): v is the unit point->camera
  * direction, C the bilinear confidence, and (q_x, q_y) = |m| (cos 2psi,
  * sin 2psi) where m is the bilinear confidence-weighted doubled-angle vector
