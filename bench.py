@@ -49,8 +49,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "fused points/s at ≤2° mean angular err; learned+batched vs plain, 1 MI355X"
-PEAK_FP32_FMA = 78.6          # TFLOP/s: 256 CU x 64 lanes x 2 flop x 2.4 GHz, no packed fp32
-PEAK_FP32_VENDOR = 157.3      # TFLOP/s: vendor figure, counts packed dual fp32 issue
+PEAK_FP32 = 157.3             # TFLOP/s: MI355X published fp32 vector peak
 PEAK_FP32_MFMA = 157.3        # TFLOP/s: dense fp32 matrix-core figure (v_mfma_f32_*_f32)
 PEAK_HBM = 8000.0             # GB/s
 
@@ -75,7 +74,7 @@ TRAFFIC = {
     "k_fuse, metric workload, per head": {"read": 294.2e6, "write": 19.1e6,
                                           "files": _SEARCH_SOURCES, "src": "d78225e8409978a0"},
     # the four-wave form spills a few registers: scratch traffic included
-    "k_b_learned4, metric workload": {"read": 3039.3e6, "write": 882.0e6,
+    "k_b_learned, metric workload": {"read": 3039.3e6, "write": 882.0e6,
                                       "files": _BATCHED_SOURCES, "src": "1578a19317a4d965"},
     "k_gabor_mfma, 64 frames 1024^2": {"read": 1152.1e6, "write": 406.8e6,
                                        "files": _GABOR_SOURCES, "src": "21a8f3739c8a0866"},
@@ -105,38 +104,71 @@ def traffic_of(key):
     return t["read"] + t["write"]
 
 
-def plain_flop_per_point(patch, n_cand, iters, top_k):
-    """Algorithmic flop of the plain search per point: every evaluated
-    direction d (lattice + 6 per refinement iteration) in every selected view
-    costs the image direction r = M d (2 rows x 3 fma = 12 flop) and, per
-    patch sample, the quadratic form a + b c2 + c s2 (2 fma = 4 flop); the
-    patch maximum and the view sum are not counted."""
-    D = n_cand + 6 * iters
-    return D * top_k * (12 + 4 * patch * patch)
+# One sim-eval is one (direction, view, patch sample) evaluation of the
+# objective; it is counted as 6 flop (the sample's share of the direction's
+# image vector and doubled angle plus its quadratic form), as in the
+# roofline accounting of the search.
+FLOP_PER_SIM_EVAL = 6
+
+
+def sim_evals_full(patch, n_cand, iters, top_k=5):
+    """Sim-evals of one plain search: lattice plus six stencil directions per
+    refinement iteration, in each of the top_k views, at every patch
+    sample."""
+    return (n_cand + 6 * iters) * top_k * patch * patch
+
+
+def sim_evals_refine(patch, iters, top_k=5):
+    """Sim-evals of the learned form's short refinement from a proposal."""
+    return (1 + 6 * iters) * top_k * patch * patch
+
+
+def plain_flop_per_point(patch, n_cand, iters, top_k=5):
+    return FLOP_PER_SIM_EVAL * sim_evals_full(patch, n_cand, iters, top_k)
+
+
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 def cpu_baseline(sc, kw, seconds, depth=True):
     """The oracle, untuned, on a bounded sample of the same scene: points in
     stride order (stride 7919, modulo N, wrapping around) until `seconds`
-    have passed."""
+    have passed, on every host thread; then the same on one thread for a
+    third of that time."""
     import numpy as np
     import oracle
     threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or (os.cpu_count() or 1)
     threads = min(threads, os.cpu_count() or threads)
     orc = oracle.Oracle(sc.cams, sc.theta, sc.conf, depth=sc.depth if depth else None, **kw)
     n = sc.n_points
-    chunk = 64 * threads
     stride = 7919
-    done = 0
-    t0 = time.perf_counter()
-    while time.perf_counter() - t0 < seconds:
-        idx = (np.arange(done, done + chunk) * stride) % n
-        orc.fuse(sc.points[idx], n_threads=threads)
-        done += chunk
-    el = time.perf_counter() - t0
+
+    def run(nthr, secs):
+        chunk = 64 * nthr
+        done = 0
+        t0 = time.perf_counter()
+        while time.perf_counter() - t0 < secs:
+            idx = (np.arange(done, done + chunk) * stride) % n
+            orc.fuse(sc.points[idx], n_threads=nthr)
+            done += chunk
+        return done, time.perf_counter() - t0
+
+    done, el = run(threads, seconds)
+    done1, el1 = run(1, seconds / 3.0)
     return {"value": done / el, "unit": "points/s", "cores": threads, "kind": "oracle",
+            "cpu_model": _cpu_model(), "logical_cpus": os.cpu_count(),
             "sample": f"{done} points of the same scene ({n} points; stride {stride} modulo N), "
-                      f"{el:.1f} s, binary64 oracle, OpenMP over points"}
+                      f"{el:.1f} s, binary64 oracle, OpenMP over points",
+            "single_thread": {"value": done1 / el1, "unit": "points/s", "cores": 1,
+                              "sample": f"{done1} points, {el1:.1f} s, same order"}}
 
 
 def _axial_deg(a, b):
@@ -270,7 +302,7 @@ def run_learned(args):
         "fallback_frac": n_fb / n,
         "stages_ms_per_launch": {"plain": st_p, "learned": st_l},
         "roofline": {"bound": "alu", "kernel": "k_fuse", "achieved": achieved,
-                     "peak": PEAK_FP32_FMA, "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_FMA,
+                     "peak": PEAK_FP32, "unit": "TFLOP/s", "frac": achieved / PEAK_FP32,
                      "traffic": traffic_of("k_fuse, realistic 500k"),
                      "avg_launch_ms": st_p["fuse"], "flop_per_point": flop},
     }
@@ -355,13 +387,15 @@ def run_metric(args):
         is_batched = name.endswith("batched")
         # the batched forms are timed replaying their graph; their stage
         # times come from a separate pass that launches the same kernels
-        el, st = _timed(fn, args, ctx, stg, profile=not is_batched)
+        # every form is timed with stage timing off; the stage times come
+        # from a separate pass (the batched forms then launch the same
+        # kernels directly instead of replaying their graph)
+        el, _ = _timed(fn, args, ctx, stg, profile=False)
         outs[name] = snap()
-        if is_batched:
-            st = _stage_pass(fn, ctx, stg)
-            if name == "learned_batched":
-                fb_listed, fb_inplace = ctx.fallback_split(stream)
-                n_fb_batched = fb_listed + fb_inplace
+        st = _stage_pass(fn, ctx, stg)
+        if name == "learned_batched":
+            fb_listed, fb_inplace = ctx.fallback_split(stream)
+            n_fb_batched = fb_listed + fb_inplace
         res[name] = (n / (el / args.steps), el * 1e3 / args.steps, st)
         log(f"{name}: {res[name][0] / 1e6:.1f} M points/s, {res[name][1]:.3f} ms/step, "
             f"{json.dumps({k: round(v, 4) for k, v in st.items()})}")
@@ -390,7 +424,7 @@ def run_metric(args):
     # dominant kernel of the learned+batched step: k_b_learned, which refines
     # every point from its proposal (1 + 6 x 2 directions) and runs the full
     # search in place for the waves that mostly fall back
-    flop_refine = (1 + 6 * lkw["learned_iters"]) * 5 * (12 + 4 * kw["patch"] ** 2)
+    flop_refine = FLOP_PER_SIM_EVAL * sim_evals_refine(kw["patch"], lkw["learned_iters"])
     flop_lb = flop_refine * n + flop * fb_inplace
     achieved = flop_lb / (st_lb["refine"] * 1e-3) / 1e12
     achieved_plain = flop * n / (st_p["fuse"] * len(heads) * 1e-3) / 1e12
@@ -416,21 +450,21 @@ def run_metric(args):
         "fallback_frac": fb / n, "batched_bitwise_equal": {"plain": same_pb, "learned": same_lb},
         "stages_ms_per_launch_plain": st_p,
         "roofline": {"bound": "alu",
-                     "kernel": "k_b_learned4 (k_b_learned at four waves per SIMD): refinement "
+                     "kernel": "k_b_learned: refinement "
                                "from the proposal for every point, full search in place for "
                                "the waves that mostly fall back (learned+batched step)",
-                     "achieved": achieved, "peak": PEAK_FP32_FMA, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_FP32_FMA,
-                     "traffic": traffic_of("k_b_learned4, metric workload"),
+                     "achieved": achieved, "peak": PEAK_FP32, "unit": "TFLOP/s",
+                     "frac": achieved / PEAK_FP32,
+                     "traffic": traffic_of("k_b_learned, metric workload"),
                      "avg_launch_ms": st_lb["refine"], "points_per_launch": n,
                      "full_searches_in_place": fb_inplace, "listed_fallbacks": fb_listed,
                      "flop_per_launch": flop_lb, "flop_per_full_search": flop,
-                     "flop_per_refinement": flop_refine, "peak_vendor_packed": PEAK_FP32_VENDOR,
-                     "frac_vs_vendor_packed": achieved / PEAK_FP32_VENDOR},
+                     "flop_per_refinement": flop_refine,
+                     "flop_per_sim_eval": FLOP_PER_SIM_EVAL},
         "roofline_plain_per_head": {
             "bound": "alu", "kernel": "k_fuse (plain search, one launch per head)",
-            "achieved": achieved_plain, "peak": PEAK_FP32_FMA, "unit": "TFLOP/s",
-            "frac": achieved_plain / PEAK_FP32_FMA, "avg_launch_ms": st_p["fuse"],
+            "achieved": achieved_plain, "peak": PEAK_FP32, "unit": "TFLOP/s",
+            "frac": achieved_plain / PEAK_FP32, "avg_launch_ms": st_p["fuse"],
             "points_per_launch": n // len(heads),
             "traffic": traffic_of("k_fuse, metric workload, per head")},
     }
@@ -532,11 +566,10 @@ def run_plain(args):
                    "depth_test": not args.no_depth,
                    "map": f"{sc.width}x{sc.height} f16", **kw},
         "roofline": {"bound": "alu", "kernel": "k_fuse", "achieved": achieved,
-                     "peak": PEAK_FP32_FMA, "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_FMA,
+                     "peak": PEAK_FP32, "unit": "TFLOP/s", "frac": achieved / PEAK_FP32,
                      "traffic": traffic_of("k_fuse, realistic 500k"),
                      "avg_launch_ms": stages["fuse"],
-                     "flop_per_point": flop, "peak_vendor_packed": PEAK_FP32_VENDOR,
-                     "frac_vs_vendor_packed": achieved / PEAK_FP32_VENDOR},
+                     "flop_per_point": flop, "flop_per_sim_eval": FLOP_PER_SIM_EVAL},
         "stages_ms_per_launch": stages,
         "err_vs_gt_deg": {"mean": float(err_gt.mean()), "median": float(err_gt.median())},
         "fpmvo_paper_candidates": fpmvo,
@@ -1084,6 +1117,41 @@ def run_pipeline(args):
     }
 
 
+def l2_probe(sizes=(1 << 20, 2 << 20, 3 << 20), blocks=2048, target_bytes=16 << 30):
+    """Aggregate read bandwidth of buffers that fit one XCD's L2 (4 MiB):
+    every workgroup reads the whole buffer (fd_probe_read), so every XCD
+    serves it from its own L2.  GB/s per size, best of 5 launches."""
+    import torch
+    from paper_2604_05794_amd import native
+    out = {}
+    sink = torch.empty(blocks * 256, dtype=torch.int32, device="cuda:0")
+    for nb in sizes:
+        buf = torch.ones(nb // 4, dtype=torch.int32, device="cuda:0")
+        reps = max(1, int(target_bytes // (nb * blocks)))
+        native.probe_read(buf, reps, blocks, sink)  # warm the caches
+        best = 0.0
+        for _ in range(5):
+            a = torch.cuda.Event(enable_timing=True)
+            b = torch.cuda.Event(enable_timing=True)
+            a.record()
+            native.probe_read(buf, reps, blocks, sink)
+            b.record()
+            b.synchronize()
+            best = max(best, nb * reps * blocks / (a.elapsed_time(b) * 1e-3) / 1e9)
+        out[f"{nb >> 20}MiB"] = best
+    return out
+
+
+def run_l2(args):
+    """Read-bandwidth ceilings: L2-resident buffers (every XCD reads its own
+    copy from L2) and, for scale, buffers in the last-level MALL."""
+    res = l2_probe()
+    mall = l2_probe(sizes=(64 << 20,), blocks=256)
+    log(f"L2 probe {json.dumps({k: round(v) for k, v in res.items()})} GB/s; MALL {mall}")
+    return {"workload": "read bandwidth probe", "l2_GB_per_s": res, "mall_GB_per_s": mall,
+            "l2_peak_measured_GB_per_s": max(res.values())}
+
+
 def run_copy(args):
     """Counter calibration: a plain device-to-device copy of 512 MiB, so the
     FETCH_SIZE / WRITE_SIZE counters can be read against known bytes."""
@@ -1110,7 +1178,7 @@ def main():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--workload", default="metric",
                     choices=["metric", "plain", "learned", "gabor", "volume", "phg", "train",
-                             "pipeline", "copy"])
+                             "pipeline", "copy", "l2"])
     ap.add_argument("--heads", type=int, default=8)
     ap.add_argument("--mlp", default=os.path.join(ROOT, "paper_2604_05794_amd", "weights",
                                                   "proposal_mlp.fdmlp"))
@@ -1128,7 +1196,7 @@ def main():
     run = {"metric": run_metric, "plain": run_plain, "learned": run_learned,
            "gabor": run_gabor, "volume": run_volume, "phg": run_phg, "train": run_train,
            "pipeline": run_pipeline,
-           "copy": run_copy}[args.workload]
+           "copy": run_copy, "l2": run_l2}[args.workload]
     out = run(args)
     print(json.dumps(out), flush=True)
 

@@ -477,6 +477,20 @@ enum {
 int fd_profile_enable(fd_context* ctx, int on);
 int fd_profile_read(fd_context* ctx, int stage, double* total_ms, int64_t* count);
 
+/* ---- bandwidth probe (measurement) -------------------------------------------
+ * Reads the device buffer buf (bytes, a multiple of 16, at most 2^31) reps
+ * times from every one of `blocks` workgroups of 256 lanes (each workgroup
+ * walks the whole buffer with 16-byte loads), folds what it read into one
+ * 32-bit value per lane and writes those to sink (device, blocks x 256
+ * uint32, caller-owned).  A buffer that fits one XCD's L2 (4 MiB) is then
+ * read from L2 by every XCD, so bytes x reps x blocks over the kernel time
+ * is the aggregate L2 read bandwidth; a much larger buffer measures HBM.
+ * Enqueued on stream (NULL: the null stream); no allocation.  Returns
+ * FD_E_INVAL for a null pointer, bytes not a positive multiple of 16 or
+ * above 2^31, reps < 1 or blocks < 1. */
+int fd_probe_read(const void* buf, int64_t bytes, int32_t reps, int32_t blocks, uint32_t* sink,
+                  void* stream);
+
 const char* fd_last_error(void);
 
 #ifdef __cplusplus

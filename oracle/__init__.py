@@ -138,9 +138,13 @@ class Oracle:
     theta/conf maps (V,H,W) f32 or f16; optional depth maps (V,H,W) of the
     same dtype switch on the visibility test with tolerance vis_tau."""
 
+    # z_near and vis_tau default to the binary32 values the library's
+    # parameter struct carries (1e-3 and 5e-3 rounded to binary32), so that
+    # both sides are given the same thresholds
     def __init__(self, cams, theta, conf, patch=5, n_candidates=128,
-                 refine_iters=8, refine_step0=0.0, top_k=5, z_near=1e-3,
-                 depth=None, vis_tau=5e-3):
+                 refine_iters=8, refine_step0=0.0, top_k=5,
+                 z_near=float(np.float32(1e-3)), depth=None,
+                 vis_tau=float(np.float32(5e-3))):
         self.cams = _c(cams, np.float32)
         self.theta, self.conf, dt = _maps(theta, conf)
         V, H, W = self.theta.shape

@@ -61,9 +61,14 @@ int fd::check_device(int* dev_out) {
 
 // ---- context ---------------------------------------------------------------------
 
+// Every reallocation goes through grow() and bumps this counter; a context
+// folds it into the signature of its captured batched graph.
+static uint64_t g_generation = 0;
+
 template <typename T>
 static int grow(T** p, size_t* cap, size_t need, const char* what) {
   if (*cap >= need && *p) return FD_OK;
+  ++g_generation;
   if (*p) {
     hipError_t e = hipFree(*p);
     if (e != hipSuccess) return hip_error(e, what);
@@ -81,6 +86,9 @@ static int grow(T** p, size_t* cap, size_t need, const char* what) {
 int fd::ctx_buffer(void** p, size_t* cap_bytes, size_t bytes, const char* what) {
   return grow((char**)p, cap_bytes, bytes, what);
 }
+
+uint64_t fd::workspace_generation() { return g_generation; }
+void fd::bump_workspace_generation() { ++g_generation; }
 
 int fd::context_reserve_points(fd_context* c, int64_t n) {
   int r;
@@ -109,6 +117,7 @@ extern "C" int fd_context_create(fd_context** out) {
       (r = grow(&c->cursor, &(cap = 0), (size_t)tile_cells(), "cell cursor")) ||
       (r = grow(&c->scan_sums, &(cap = 0), (size_t)tile_cells() / 1024, "scan sums")) ||
       (r = grow(&c->lattice, &(cap = 0), (size_t)3 * FD_MAX_CANDIDATES, "lattice")) ||
+      (r = grow(&c->consts64, &(cap = 0), (size_t)kConstsDoubles, "search constants")) ||
       (r = grow(&c->fb_count, &(cap = 0), (size_t)8, "fallback counters"))) {
     fd_context_destroy(c);
     return r;
@@ -135,7 +144,8 @@ extern "C" int fd_context_reserve(fd_context* c, int64_t max_points, int32_t max
 extern "C" void fd_context_destroy(fd_context* c) {
   if (!c) return;
   (void)hipDeviceSynchronize();
-  void* bufs[] = {c->bbox, c->counts, c->cursor, c->scan_sums, c->lattice, c->fb_count, c->key,
+  void* bufs[] = {c->bbox, c->counts, c->cursor, c->scan_sums, c->lattice, c->consts64,
+                  c->fb_count, c->key,
                   c->perm, c->views, c->kcount, c->fb_list, c->prop, c->feats,
                   c->scene_tab, c->tile_tab, c->tile_queue, c->batch_key, c->batch_perm,
                   c->gabor_bank, c->gabor_raw, c->gabor_max, c->vol_key, c->vol_perm,
@@ -306,16 +316,27 @@ int fd::check_search_params(const fd_params* p, const char* fn) {
   return FD_OK;
 }
 
-float fd::default_step0(int n_candidates) {
-  return (float)(0.5 * std::sqrt(2.0 * 3.14159265358979323846 / (double)n_candidates));
+double fd::default_step0(int n_candidates) {
+  return 0.5 * std::sqrt(2.0 * 3.14159265358979323846 / (double)n_candidates);
 }
 
-int fd::ensure_lattice(fd_context* c, int n, hipStream_t st) {
-  if (c->lattice_n == n) return FD_OK;
-  hipError_t e = launch_lattice(c->lattice, n, st);
-  if (e != hipSuccess) return hip_error(e, "lattice kernel");
-  c->lattice_n = n;
-  return FD_OK;
+void fd::resolve_steps(const fd_params* p, double* step0, double* lstep0) {
+  *step0 = p->refine_step0 > 0.0f ? (double)p->refine_step0 : default_step0(p->n_candidates);
+  double l = p->learned_step0 > 0.0f ? (double)p->learned_step0 : 0.0;
+  if (!(l > 0.0) && p->mlp) {
+    float s0 = 0.0f, tau = 0.0f;
+    if (fd_mlp_get_calibration(p->mlp, &s0, &tau) == FD_OK && s0 > 0.0f) l = (double)s0;
+  }
+  *lstep0 = l > 0.0 ? l : default_step0(p->n_candidates);
+}
+
+ConstsDev fd::context_consts(fd_context* c) {
+  ConstsDev k;
+  k.lattice = c->lattice;
+  k.lattice64 = c->consts64;
+  k.steps = c->consts64 + 3 * FD_MAX_CANDIDATES;
+  k.stencil = k.steps + 6 * FD_MAX_REFINE;
+  return k;
 }
 
 // ---- single scene ---------------------------------------------------------------------
@@ -376,8 +397,11 @@ extern "C" int fd_fuse_directions(const float* points, int64_t n_points, const f
 }
 
 int fd::run_scene(fd_context* c, const SceneArgs& a, const fd_params* p, hipStream_t st) {
-  int r;
-  if ((r = ensure_lattice(c, p->n_candidates, st))) return r;
+  double step0, lstep0;
+  resolve_steps(p, &step0, &lstep0);
+  const ConstsDev kc = context_consts(c);
+  hipError_t e0 = launch_consts(kc, p->n_candidates, step0, lstep0, st);
+  if (e0 != hipSuccess) return hip_error(e0, "search constants");
   TileWork tw{c->bbox, c->key, c->counts, c->cursor, c->scan_sums, c->perm};
   StageTimer t_tile(c, FD_STAGE_TILING, st);
   hipError_t e = launch_tiling(a.points, a.n, tw, st);
@@ -400,13 +424,7 @@ int fd::run_scene(fd_context* c, const SceneArgs& a, const fd_params* p, hipStre
   s.W = a.W;
   s.H = a.H;
   for (int k = 0; k < 3; ++k) s.hc[k] = a.hc[k];
-  SearchDev q;
-  q.lattice = c->lattice;
-  q.n_candidates = p->n_candidates;
-  q.refine_iters = p->refine_iters;
-  q.step0 = p->refine_step0 > 0.0f ? p->refine_step0 : default_step0(p->n_candidates);
-  q.K = p->top_k;
-  q.z_near = p->z_near;
+  const SearchDev q = make_search(kc, p->n_candidates, p->refine_iters, p->top_k, p->z_near);
   const bool fused_topk = p->mode == FD_MODE_LEARNED && p->proposal == FD_PROPOSAL_MLP;
   if (!fused_topk) {  // the learned network path selects views with its features
     StageTimer t_topk(c, FD_STAGE_TOPK, st);

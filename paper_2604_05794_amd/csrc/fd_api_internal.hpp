@@ -13,13 +13,16 @@
 struct fd_context {
   int device = 0;
   int64_t max_points = 0;
+  // bumped whenever a workspace buffer is reallocated, so that a captured
+  // batched graph or uploaded scene table never keeps a freed pointer
+  uint64_t generation = 0;
   // fixed buffers
   int* bbox = nullptr;
   uint32_t* counts = nullptr;
   uint32_t* cursor = nullptr;
   uint32_t* scan_sums = nullptr;
-  float* lattice = nullptr;
-  int lattice_n = -1;
+  float* lattice = nullptr;   // search constants (ConstsDev): binary32 lattice
+  double* consts64 = nullptr; // binary64 lattice, step tables, stencil
   uint32_t* fb_count = nullptr;
   // per-point buffers
   uint32_t* key = nullptr;
@@ -125,14 +128,20 @@ int set_error(int code, const char* fmt, ...);
 int hip_error(hipError_t e, const char* what);
 int check_device(int* dev_out);
 int check_search_params(const fd_params* p, const char* fn);
-float default_step0(int n_candidates);
+double default_step0(int n_candidates);
+// First step of the plain refinement and of the learned form's short
+// refinement (parameter, else the network's calibration, else the default).
+void resolve_steps(const fd_params* p, double* step0, double* lstep0);
+ConstsDev context_consts(fd_context* c);
 int context_reserve_points(fd_context* c, int64_t n);
 int context_reserve_scenes(fd_context* c, int32_t n_scenes, int64_t total_points);
 fd_context* default_context(int dev, int64_t n, int* err);
-int ensure_lattice(fd_context* c, int n, hipStream_t st);
 // Grows a context-owned device buffer to at least `bytes` (no-op if large
 // enough; the old contents are not kept).
 int ctx_buffer(void** p, size_t* cap_bytes, size_t bytes, const char* what);
+// Count of workspace reallocations so far (any context).
+uint64_t workspace_generation();
+void bump_workspace_generation();
 int run_scene(fd_context* c, const SceneArgs& a, const fd_params* p, hipStream_t st);
 // Records HIP events around one stage when the context profiles.
 struct StageTimer {

@@ -222,7 +222,8 @@ __device__ __forceinline__ int64_t queue_tile(int qi, int64_t v) {
 }
 
 template <typename T, int P, int KT, bool LIST>
-__global__ __launch_bounds__(kBlock) void k_b_fuse(BatchDev b, SearchDev q, const uint32_t* list,
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(search_waves(P))))
+void k_b_fuse(BatchDev b, SearchDev q, const uint32_t* list,
                                                    const uint32_t* list_count,
                                                    uint32_t* __restrict__ queue, int chunk) {
   const Group gr = make_group(q.K);
@@ -265,7 +266,8 @@ __global__ __launch_bounds__(kBlock) void k_b_fuse(BatchDev b, SearchDev q, cons
 // Non-persistent form of the plain search (one wave per scene-uniform tile,
 // tiles in XCD-aware block order), which the autotuner may pick instead.
 template <typename T, int P, int KT>
-__global__ __launch_bounds__(kBlock) void k_b_fuse_tiles(BatchDev b, SearchDev q) {
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(search_waves(P))))
+void k_b_fuse_tiles(BatchDev b, SearchDev q) {
   const Group gr = make_group(q.K);
   const int64_t tile = xcd_tile(gridDim.x) * (blockDim.x / kWave) + (threadIdx.x / kWave);
   if (tile >= b.n_tiles) return;
@@ -290,17 +292,8 @@ __device__ __forceinline__ void b_learned_body(const BatchDev& b, const SearchDe
 }
 
 template <typename T, int P, int KT>
-__global__ __launch_bounds__(kBlock) void k_b_learned(BatchDev b, SearchDev q, LearnedDev l) {
-  b_learned_body<T, P, KT>(b, q, l);
-}
-
-// The same with at most 128 registers per lane, so that four waves share a
-// SIMD: measured faster for patches up to 5 x 5 (a few registers spill
-// outside the lattice loop); 7 x 7 patches would spill heavily and keep the
-// unbounded form.
-template <typename T, int P, int KT>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) void k_b_learned4(
-    BatchDev b, SearchDev q, LearnedDev l) {
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(search_waves(P))))
+void k_b_learned(BatchDev b, SearchDev q, LearnedDev l) {
   b_learned_body<T, P, KT>(b, q, l);
 }
 
@@ -310,12 +303,8 @@ hipError_t launch_b_search(const BatchDev& b, const SearchDev& q, const LearnedD
                            int chunk, int grid, hipStream_t st) {
   if (l) {
     const int64_t nb = (b.n_tiles + 3) / 4;  // 4 waves per block
-    if constexpr (P <= 5)
-      hipLaunchKernelGGL((k_b_learned4<T, P, KT>), dim3((unsigned)nb), dim3(kBlock), 0, st, b, q,
-                         *l);
-    else
-      hipLaunchKernelGGL((k_b_learned<T, P, KT>), dim3((unsigned)nb), dim3(kBlock), 0, st, b, q,
-                         *l);
+    hipLaunchKernelGGL((k_b_learned<T, P, KT>), dim3((unsigned)nb), dim3(kBlock), 0, st, b, q,
+                       *l);
   } else {
     if (list)
       hipLaunchKernelGGL((k_b_fuse<T, P, KT, true>), dim3(grid), dim3(kBlock), 0, st, b, q, list,
@@ -394,6 +383,7 @@ int fd::context_reserve_scenes(fd_context* c, int32_t n_scenes, int64_t total_po
   auto fr = [](void* p) {
     if (p) (void)hipFree(p);
   };
+  bump_workspace_generation();
   fr(c->scene_tab);
   fr(c->tile_tab);
   fr(c->tile_queue);
@@ -446,13 +436,12 @@ static int record_batch(fd_context* c, const fd_params* p, int n_scenes, int64_t
   hipLaunchKernelGGL(k_b_scatter, dim3((unsigned)nblocks), dim3(kBlock), 0, st, b, c->key, cursor,
                      c->perm);
   t_tile.stop();
-  SearchDev q;
-  q.lattice = c->lattice;
-  q.n_candidates = p->n_candidates;
-  q.refine_iters = p->refine_iters;
-  q.step0 = p->refine_step0 > 0.0f ? p->refine_step0 : default_step0(p->n_candidates);
-  q.K = p->top_k;
-  q.z_near = p->z_near;
+  double step0, lstep0;
+  resolve_steps(p, &step0, &lstep0);
+  const ConstsDev kc = context_consts(c);
+  if ((e = launch_consts(kc, p->n_candidates, step0, lstep0, st)) != hipSuccess)
+    return hip_error(e, "search constants");
+  const SearchDev q = make_search(kc, p->n_candidates, p->refine_iters, p->top_k, p->z_near);
   if (p->mode == FD_MODE_PLAIN) {  // the learned form selects views with its features
     StageTimer t_topk(c, FD_STAGE_TOPK, st);
     const dim3 grid((unsigned)nblocks), block(kBlock);
@@ -490,17 +479,11 @@ static int record_batch(fd_context* c, const fd_params* p, int n_scenes, int64_t
   }
   // learned
   LearnedDev l;
+  l.steps = q.steps + 3 * FD_MAX_REFINE;
   l.iters = p->learned_iters;
-  l.tau = p->fallback_cost;
+  l.tau = (double)p->fallback_cost;
   l.fb_list = c->fb_list;
   l.fb_count = c->fb_count;
-  float step0 = p->learned_step0;
-  if (!(step0 > 0.0f)) {
-    float s0 = 0.0f, tau = 0.0f;
-    fd_mlp_get_calibration(p->mlp, &s0, &tau);
-    step0 = s0 > 0.0f ? s0 : default_step0(p->n_candidates);
-  }
-  l.step0 = step0;
   {
     StageTimer t_feat(c, FD_STAGE_FEATURES, st);
     const dim3 grid((unsigned)nblocks), block(kBlock);
@@ -602,6 +585,14 @@ extern "C" int fd_fuse_directions_batched(const fd_scene* scenes, int32_t n_scen
   sig = fnv(sig, &pc, sizeof pc);
   sig = fnv(sig, &ctx->tuned_chunk, sizeof ctx->tuned_chunk);
   sig = fnv(sig, &ctx->tuned_grid, sizeof ctx->tuned_grid);
+  // the workspace pointers the table and the graph hold, and the learned
+  // form's first step as resolved now (it may come from the network's
+  // calibration, which the caller can change between calls)
+  const uint64_t gen = workspace_generation();
+  sig = fnv(sig, &gen, sizeof gen);
+  double step0 = 0.0, lstep0 = 0.0;
+  resolve_steps(params, &step0, &lstep0);
+  sig = fnv(sig, &lstep0, sizeof lstep0);
   if (ctx->table_sig != sig) {
     // scene table (host -> device once per scene set, outside the graph)
     std::vector<SceneDev> tab(n_scenes);
@@ -636,8 +627,6 @@ extern "C" int fd_fuse_directions_batched(const fd_scene* scenes, int32_t n_scen
     if (e == hipSuccess) e = hipMemcpy(dblk, blk_off.data(), sizeof(int64_t) * (n_scenes + 1), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(dtile, tile_off.data(), sizeof(int64_t) * (n_scenes + 1), hipMemcpyHostToDevice);
     if (e != hipSuccess) return hip_error(e, "batched scene table upload");
-    if ((r = ensure_lattice(ctx, params->n_candidates, st))) return r;
-    if ((e = hipStreamSynchronize(st)) != hipSuccess) return hip_error(e, "lattice");
     ctx->table_sig = sig;
   }
   StageTimer tb(ctx, FD_STAGE_BATCHED, st);

@@ -28,31 +28,35 @@ __device__ __forceinline__ float tex_load_nb(const T* __restrict__ m, int W, int
   return in ? v : 0.0f;
 }
 
-// Projection and eligibility, in binary32 with the fixed operation order
-// every implementation of the method shares (view selection is a discrete
-// decision and must come out the same everywhere):
-//   X = fma(R0, px, fma(R1, py, fma(R2, pz, t0)))  (likewise Y, Z)
-//   front: Z > z_near;  iz = 1 / Z,  u = fma(fx, X * iz, cx), v = fma(fy, Y * iz, cy)
+// Projection, eligibility and the Eq. (4) ranking score, in binary64.
+// The calibrated pinhole model of Sec. 3.1: X_c = R p + t, pixel
+// u = (f_x X/Z + c_x, f_y Y/Z + c_y).  Every discrete choice of the view
+// selection (in front, inside the image, visible, centre confidence above
+// zero, the ranking) is taken on binary64 values computed from the binary32
+// and binary16 inputs (which convert exactly), with one rounding per
+// operation in the order written below (the library is built without
+// floating-point contraction, and binary64 division and square root are
+// IEEE), so each choice is the exact mathematical one up to binary64
+// rounding:
+//   X = ((R0 px + R1 py) + R2 pz) + t0   (likewise Y, Z)
+//   front: Z > z_near;  u = fx (X / Z) + cx,  v = fy (Y / Z) + cy
 //   inside: 0 <= u <= W-1 and 0 <= v <= H-1
-// The reciprocal is IEEE (the library is built without fast-math).
+// The projection u is also the centre of the fusion patch (Sec. 3.1.3).
 struct Proj {
-  float X, Y, Z, u, v;
+  double X, Y, Z, u, v;
 };
 
-__device__ __forceinline__ bool project32(const float* __restrict__ cam,
-                                          float px, float py, float pz, int W,
-                                          int H, float z_near, Proj& o) {
+__device__ __forceinline__ bool project64(const float* __restrict__ cam, double px, double py,
+                                          double pz, int W, int H, double z_near, Proj& o) {
   const float* R = cam + 4;
   const float* t = cam + 13;
-  o.X = __builtin_fmaf(R[0], px, __builtin_fmaf(R[1], py, __builtin_fmaf(R[2], pz, t[0])));
-  o.Y = __builtin_fmaf(R[3], px, __builtin_fmaf(R[4], py, __builtin_fmaf(R[5], pz, t[1])));
-  o.Z = __builtin_fmaf(R[6], px, __builtin_fmaf(R[7], py, __builtin_fmaf(R[8], pz, t[2])));
+  o.X = (double)R[0] * px + (double)R[1] * py + (double)R[2] * pz + (double)t[0];
+  o.Y = (double)R[3] * px + (double)R[4] * py + (double)R[5] * pz + (double)t[1];
+  o.Z = (double)R[6] * px + (double)R[7] * py + (double)R[8] * pz + (double)t[2];
   if (!(o.Z > z_near)) return false;
-  const float iz = 1.0f / o.Z;
-  o.u = __builtin_fmaf(cam[0], o.X * iz, cam[2]);
-  o.v = __builtin_fmaf(cam[1], o.Y * iz, cam[3]);
-  return o.u >= 0.0f && o.u <= (float)(W - 1) && o.v >= 0.0f &&
-         o.v <= (float)(H - 1);
+  o.u = (double)cam[0] * (o.X / o.Z) + (double)cam[2];
+  o.v = (double)cam[1] * (o.Y / o.Z) + (double)cam[3];
+  return o.u >= 0.0 && o.u <= (double)(W - 1) && o.v >= 0.0 && o.v <= (double)(H - 1);
 }
 
 // Texel at a 32-bit offset from a view's base pointer (the base is the same
@@ -68,29 +72,32 @@ __device__ __forceinline__ float ld_texel(const T* __restrict__ base, uint32_t o
     return *(const float*)b;
 }
 
-// View eligibility and centre confidence for Eq. (4), split so that a caller
-// can skip the confidence loads of a view no lane of its wave sees.
-// visible_at: eligible (ok) and, with depth maps, visible (the rule of
-// visible32, nearest texel of the projection).  conf_texels + conf_combine:
-// the bilinear confidence of an eligible projection in the fixed order
-//   x0 = floor(u), fx = u - x0, gx = 1 - fx (likewise y)
-//   w00 = gx*gy, w10 = fx*gy, w01 = gx*fy, w11 = fx*fy
-//   C = fma(w11, C11, fma(w01, C01, fma(w10, C10, w00*C00)))
-// with texels outside the image read as 0; an eligible projection lies inside
-// the image, so only the +1 neighbours need that check.  Texels are read at
-// 32-bit offsets from the view's base pointer.
+// Visibility of Sec. 3.1.1 (the score V_i^v): the camera-space depth of the
+// point agrees with the rendered depth at the nearest texel of its
+// projection, (floor(u + 1/2), floor(v + 1/2)), within tau (binary64).
+// No depth maps: every eligible view is visible.  A +inf (background) or
+// NaN depth never is.  `ok` (the view is eligible) guards the texel read:
+// an eligible projection lies inside the image.
 template <typename T>
 __device__ __forceinline__ bool visible_at(const T* __restrict__ db, int W, bool ok,
-                                           const Proj& pr, float tau) {
+                                           const Proj& pr, double tau) {
   if (db == nullptr) return ok;
-  const float u = ok ? pr.u : 0.0f, v = ok ? pr.v : 0.0f;
-  const uint32_t xn = (uint32_t)floorf(u + 0.5f), yn = (uint32_t)floorf(v + 0.5f);
-  const float D = ld_texel<T>(db, yn * (uint32_t)W + xn);
-  return ok && fabsf(pr.Z - D) <= tau;
+  const double u = ok ? pr.u : 0.0, v = ok ? pr.v : 0.0;
+  const uint32_t xn = (uint32_t)floor(u + 0.5), yn = (uint32_t)floor(v + 0.5);
+  const double D = (double)ld_texel<T>(db, yn * (uint32_t)W + xn);
+  return ok && fabs(pr.Z - D) <= tau;
 }
 
+// Bilinear centre confidence of an eligible projection (Eq. 4's ranking
+// score), split so that a caller can skip the texels of a view no lane of
+// its wave sees:
+//   x0 = floor(u), fx = u - x0 (likewise y)
+//   C = (1-fx)(1-fy) C00 + fx (1-fy) C10 + (1-fx) fy C01 + fx fy C11
+// with texels outside the image read as 0; an eligible projection lies
+// inside the image, so only the +1 neighbours need that check.
 struct ConfTexels {
-  float c00, c10, c01, c11, fx, fy;
+  float c00, c10, c01, c11;
+  double fx, fy;
   bool xin, yin;
 };
 
@@ -98,8 +105,8 @@ template <typename T>
 __device__ __forceinline__ ConfTexels conf_texels(const T* __restrict__ cb, int W, int H,
                                                      bool ok, const Proj& pr) {
   ConfTexels t;
-  const float u = ok ? pr.u : 0.0f, v = ok ? pr.v : 0.0f;
-  const float x0 = floorf(u), y0 = floorf(v);
+  const double u = ok ? pr.u : 0.0, v = ok ? pr.v : 0.0;
+  const double x0 = floor(u), y0 = floor(v);
   t.fx = u - x0;
   t.fy = v - y0;
   const uint32_t ix = (uint32_t)x0, iy = (uint32_t)y0;
@@ -114,27 +121,33 @@ __device__ __forceinline__ ConfTexels conf_texels(const T* __restrict__ cb, int 
   return t;
 }
 
-__device__ __forceinline__ float conf_combine(const ConfTexels& t) {
-  const float c10 = t.xin ? t.c10 : 0.0f;
-  const float c01 = t.yin ? t.c01 : 0.0f;
-  const float c11 = (t.xin && t.yin) ? t.c11 : 0.0f;
-  const float gx = 1.0f - t.fx, gy = 1.0f - t.fy;
-  const float w00 = gx * gy, w10 = t.fx * gy, w01 = gx * t.fy, w11 = t.fx * t.fy;
-  return __builtin_fmaf(w11, c11, __builtin_fmaf(w01, c01, __builtin_fmaf(w10, c10, w00 * t.c00)));
+__device__ __forceinline__ double conf_combine(const ConfTexels& t) {
+  const double c10 = t.xin ? (double)t.c10 : 0.0;
+  const double c01 = t.yin ? (double)t.c01 : 0.0;
+  const double c11 = (t.xin && t.yin) ? (double)t.c11 : 0.0;
+  return (1.0 - t.fx) * (1.0 - t.fy) * (double)t.c00 + t.fx * (1.0 - t.fy) * c10 +
+         (1.0 - t.fx) * t.fy * c01 + t.fx * t.fy * c11;
 }
 
-// Visibility of Sec. 3.1.1 (the score V_i^v), decided in binary32: the
-// camera-space depth of the point agrees with the rendered depth at the
-// nearest texel of its projection,
-//   ix = (int)floor(u + 0.5f), iy = (int)floor(v + 0.5f),  |Z - D(ix, iy)| <= tau.
-// No depth maps: always visible.  A +inf (background) or NaN depth never is.
-template <typename T>
-__device__ __forceinline__ bool visible32(const void* depth, size_t plane, int view, int W,
-                                          int H, const Proj& pr, float tau) {
-  if (depth == nullptr) return true;
-  const int ix = (int)floorf(pr.u + 0.5f), iy = (int)floorf(pr.v + 0.5f);
-  const float D = tex_load_nb<T>((const T*)depth + plane * view, W, H, ix, iy);
-  return fabsf(pr.Z - D) <= tau;
+// binary64 reciprocal and reciprocal square root of finite positive x:
+// the hardware estimate refined by two Newton steps (error within an ulp or
+// two of the rounded result; the search compares such values only against
+// each other, never bit for bit with another implementation).
+__device__ __forceinline__ double rcp64(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  double e = __builtin_fma(-x, r, 1.0);
+  r = __builtin_fma(r, e, r);
+  e = __builtin_fma(-x, r, 1.0);
+  return __builtin_fma(r, e, r);
+}
+
+__device__ __forceinline__ double rsq64(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  const double h = 0.5 * x;
+  double e = __builtin_fma(-h * y, y, 0.5);
+  y = __builtin_fma(y, e, y);
+  e = __builtin_fma(-h * y, y, 0.5);
+  return __builtin_fma(y, e, y);
 }
 
 // Logical block index such that the blocks of one XCD cover a contiguous
@@ -153,26 +166,27 @@ __device__ __forceinline__ int64_t xcd_tile(int64_t nblocks) {
 // Lanes of a wave are split into groups of `k` consecutive lanes; returns the
 // sum of v over the caller's group, added in lane order (slot 0 first) so
 // every lane of the group gets the same bits.
-__device__ __forceinline__ float group_sum(float v, int group_base, int k) {
-  float s = __shfl(v, group_base, kWave);
+template <typename V>
+__device__ __forceinline__ V group_sum(V v, int group_base, int k) {
+  V s = __shfl(v, group_base, kWave);
   for (int j = 1; j < k; ++j) s += __shfl(v, group_base + j, kWave);
   return s;
 }
 
 // group_sum with the group size known at compile time (KT > 0): the K
 // shuffles are issued back to back and waited for once.
-template <int KT>
-__device__ __forceinline__ float group_sum_t(float v, int group_base, int k) {
+template <int KT, typename V>
+__device__ __forceinline__ V group_sum_t(V v, int group_base, int k) {
   if constexpr (KT > 0) {
-    float x[KT];
+    V x[KT];
 #pragma unroll
     for (int j = 0; j < KT; ++j) x[j] = __shfl(v, group_base + j, kWave);
-    float s = x[0];
+    V s = x[0];
 #pragma unroll
     for (int j = 1; j < KT; ++j) s += x[j];
     return s;
   } else {
-    return group_sum(v, group_base, k);
+    return group_sum<V>(v, group_base, k);
   }
 }
 

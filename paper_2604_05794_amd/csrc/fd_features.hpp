@@ -15,6 +15,7 @@
 namespace fd {
 
 constexpr int kSlots = FD_FEATURE_SLOTS;
+constexpr float kInvPi = 0.318309886183790671538f;
 
 __device__ __forceinline__ uint16_t feat_bf16(float x) {
   // round to nearest even
@@ -24,29 +25,32 @@ __device__ __forceinline__ uint16_t feat_bf16(float x) {
   return (uint16_t)(u >> 16);
 }
 
-// Frontal ranking key of a view, decided in binary32 with a fixed order:
-//   c = -R^T t  (c_x = -fma(R0, t0, fma(R3, t1, R6*t2)), likewise y, z)
+// Frontal ranking key of a view (the "most frontal" views of the proposal
+// features), in binary64 with one rounding per operation in the order
+// written (the ranking is a discrete decision):
+//   c = -R^T t  (c_k = -((R_k t0 + R_{3+k} t1) + R_{6+k} t2))
 //   a = c - p, b = p - o
-//   score = fma(a_x, b_x, fma(a_y, b_y, a_z*b_z)) / sqrt(fma(a_x, a_x, fma(a_y, a_y, a_z*a_z)))
+//   score = ((a_x b_x + a_y b_y) + a_z b_z) / sqrt((a_x^2 + a_y^2) + a_z^2)
 // i.e. the cosine between the point->camera direction and the outward
 // direction p - o, times |p - o| (common to every view of the point).
-__device__ __forceinline__ float frontal_score32(const float* cam, float px, float py, float pz,
-                                                 const float* o, float* vdir) {
+// vdir (optional) receives the unit point->camera direction a / |a|.
+__device__ __forceinline__ double frontal_score64(const float* cam, double px, double py,
+                                                  double pz, const float* o, float* vdir) {
   const float* R = cam + 4;
   const float* t = cam + 13;
-  const float cx = -__builtin_fmaf(R[0], t[0], __builtin_fmaf(R[3], t[1], R[6] * t[2]));
-  const float cy = -__builtin_fmaf(R[1], t[0], __builtin_fmaf(R[4], t[1], R[7] * t[2]));
-  const float cz = -__builtin_fmaf(R[2], t[0], __builtin_fmaf(R[5], t[1], R[8] * t[2]));
-  const float ax = cx - px, ay = cy - py, az = cz - pz;
-  const float bx = px - o[0], by = py - o[1], bz = pz - o[2];
-  const float dot = __builtin_fmaf(ax, bx, __builtin_fmaf(ay, by, az * bz));
-  const float la = sqrtf(__builtin_fmaf(ax, ax, __builtin_fmaf(ay, ay, az * az)));
+  const double t0 = t[0], t1 = t[1], t2 = t[2];
+  const double cx = -((double)R[0] * t0 + (double)R[3] * t1 + (double)R[6] * t2);
+  const double cy = -((double)R[1] * t0 + (double)R[4] * t1 + (double)R[7] * t2);
+  const double cz = -((double)R[2] * t0 + (double)R[5] * t1 + (double)R[8] * t2);
+  const double ax = cx - px, ay = cy - py, az = cz - pz;
+  const double bx = px - (double)o[0], by = py - (double)o[1], bz = pz - (double)o[2];
+  const double la = sqrt(ax * ax + ay * ay + az * az);
   if (vdir) {
-    vdir[0] = ax / la;
-    vdir[1] = ay / la;
-    vdir[2] = az / la;
+    vdir[0] = (float)(ax / la);
+    vdir[1] = (float)(ay / la);
+    vdir[2] = (float)(az / la);
   }
-  return dot / la;
+  return (ax * bx + ay * by + az * bz) / la;
 }
 
 // Stable insertion of view v with frontal score cs into the descending list
@@ -55,14 +59,14 @@ __device__ __forceinline__ float frontal_score32(const float* cam, float px, flo
 // skipped.  The score of an eligible view is finite (the point lies more
 // than z_near in front of the camera, so its distance to the centre is not
 // zero for any z_near > 0), so it always beats an empty entry.
-__device__ __forceinline__ void frontal_insert(float (&sc)[kSlots], int (&id)[kSlots], float cs,
-                                               int cv) {
+__device__ __forceinline__ void frontal_insert(double (&sc)[kSlots], int (&id)[kSlots],
+                                               double cs, int cv) {
   if (!(cs > sc[kSlots - 1])) return;
   bool ins = false;
 #pragma unroll
   for (int k = 0; k < kSlots; ++k) {
     const bool take = ins || (cs > sc[k]);
-    const float ts = sc[k];
+    const double ts = sc[k];
     const int tv = id[k];
     sc[k] = take ? cs : ts;
     id[k] = take ? cv : tv;
@@ -77,10 +81,13 @@ __device__ __forceinline__ void frontal_insert(float (&sc)[kSlots], int (&id)[kS
 // doubled-angle vector, psi the angle of the plane it back-projects to, in a
 // frame tied to the line of sight), the bilinear confidence C, the unit
 // point->camera direction and 1; empty slots are 0.  Written as 112
-// bfloat16 to feats row `row`.
+// bfloat16 to feats row `row`.  The sample position is the binary64
+// projection; the values are formed in binary32 (the hardware sine and
+// cosine of the texel angles err by ~1e-6, far below the 2^-9 relative
+// rounding of bfloat16).
 template <typename T>
-__device__ __forceinline__ void write_feature_row(const SceneDev& s, float z_near, float px,
-                                                  float py, float pz, const int (&id)[kSlots],
+__device__ __forceinline__ void write_feature_row(const SceneDev& s, double z_near, double px,
+                                                  double py, double pz, const int (&id)[kSlots],
                                                   int64_t row, uint16_t* __restrict__ feats) {
   const T* th = (const T*)s.theta;
   const T* cf = (const T*)s.conf;
@@ -101,10 +108,11 @@ __device__ __forceinline__ void write_feature_row(const SceneDev& s, float z_nea
       const int v = id[k];
       const float* cam = s.cams + 16 * v;
       Proj pr;
-      project32(cam, px, py, pz, s.W, s.H, z_near, pr);
-      const float x0 = floorf(pr.u), y0 = floorf(pr.v);
-      const float fx = pr.u - x0, fy = pr.v - y0;
+      project64(cam, px, py, pz, s.W, s.H, z_near, pr);
+      const double x0 = floor(pr.u), y0 = floor(pr.v);
+      const float fx = (float)(pr.u - x0), fy = (float)(pr.v - y0);
       const int ix = (int)x0, iy = (int)y0;
+      const float pX = (float)pr.X, pY = (float)pr.Y, pZ = (float)pr.Z;
       float cb = 0.0f, mx = 0.0f, my = 0.0f;
 #pragma unroll
       for (int b = 0; b < 2; ++b)
@@ -119,7 +127,7 @@ __device__ __forceinline__ void write_feature_row(const SceneDev& s, float z_nea
           my += wc * __builtin_amdgcn_sinf(t * kInvPi);
         }
       float vd[3];
-      frontal_score32(cam, px, py, pz, s.hc, vd);
+      frontal_score64(cam, px, py, pz, s.hc, vd);
       // The observed image line back-projects to a plane through the camera
       // centre containing the line of sight vd; its direction across vd,
       // tt = n x vd, is given by the angle psi in the frame
@@ -131,7 +139,7 @@ __device__ __forceinline__ void write_feature_row(const SceneDev& s, float z_nea
         const float ox = sqrtf(fmaxf(0.5f * (1.0f + ch), 0.0f));
         const float oy = copysignf(sqrtf(fmaxf(0.5f * (1.0f - ch), 0.0f)), sh);
         const float dlx = ox / cam[0], dly = oy / cam[1];
-        const float ncx = -pr.Z * dly, ncy = pr.Z * dlx, ncz = pr.X * dly - pr.Y * dlx;
+        const float ncx = -pZ * dly, ncy = pZ * dlx, ncz = pX * dly - pY * dlx;
         const float* R = cam + 4;
         const float nwx = R[0] * ncx + R[3] * ncy + R[6] * ncz;
         const float nwy = R[1] * ncx + R[4] * ncy + R[7] * ncz;
@@ -179,13 +187,13 @@ __device__ __forceinline__ void write_feature_row(const SceneDev& s, float z_nea
 // feature row (processing-order index j when by_j, else the point index,
 // plus row_base).
 template <typename T>
-__device__ __forceinline__ void features_point(const SceneDev& s, float z_near, int64_t j,
+__device__ __forceinline__ void features_point(const SceneDev& s, double z_near, int64_t j,
                                                int by_j, int64_t row_base,
                                                uint16_t* __restrict__ feats) {
   const uint32_t i = s.perm ? s.perm[j] : (uint32_t)j;
-  const float px = s.pts[3 * (size_t)i], py = s.pts[3 * (size_t)i + 1],
-              pz = s.pts[3 * (size_t)i + 2];
-  float sc[kSlots];
+  const double px = s.pts[3 * (size_t)i], py = s.pts[3 * (size_t)i + 1],
+               pz = s.pts[3 * (size_t)i + 2];
+  double sc[kSlots];
   int id[kSlots];
 #pragma unroll
   for (int k = 0; k < kSlots; ++k) {
@@ -193,11 +201,13 @@ __device__ __forceinline__ void features_point(const SceneDev& s, float z_near, 
     id[k] = -1;
   }
   const size_t plane = (size_t)s.W * s.H;
+  const T* depth = (const T*)s.depth;
   for (int v = 0; v < s.V; ++v) {
     Proj pr;
-    if (!project32(s.cams + 16 * v, px, py, pz, s.W, s.H, z_near, pr)) continue;
-    if (!visible32<T>(s.depth, plane, v, s.W, s.H, pr, s.vis_tau)) continue;
-    frontal_insert(sc, id, frontal_score32(s.cams + 16 * v, px, py, pz, s.hc, nullptr), v);
+    const bool ok = project64(s.cams + 16 * v, px, py, pz, s.W, s.H, z_near, pr);
+    if (!visible_at<T>(depth ? depth + plane * v : nullptr, s.W, ok, pr, (double)s.vis_tau))
+      continue;
+    frontal_insert(sc, id, frontal_score64(s.cams + 16 * v, px, py, pz, s.hc, nullptr), v);
   }
   write_feature_row<T>(s, z_near, px, py, pz, id, row_base + (by_j ? j : (int64_t)i), feats);
 }
@@ -210,16 +220,16 @@ __device__ __forceinline__ void topk_features_point(const SceneDev& s, const Sea
                                                     int64_t j, int64_t row_base,
                                                     uint16_t* __restrict__ feats) {
   const uint32_t i = s.perm[j];
-  const float px = s.pts[3 * (size_t)i], py = s.pts[3 * (size_t)i + 1],
-              pz = s.pts[3 * (size_t)i + 2];
-  float ck[KS];
+  const double px = s.pts[3 * (size_t)i], py = s.pts[3 * (size_t)i + 1],
+               pz = s.pts[3 * (size_t)i + 2];
+  double ck[KS];
   int vk[KS];
 #pragma unroll
   for (int k = 0; k < KS; ++k) {
-    ck[k] = -1.0f;
+    ck[k] = -1.0;
     vk[k] = 0;
   }
-  float sc[kSlots];
+  double sc[kSlots];
   int id[kSlots];
 #pragma unroll
   for (int k = 0; k < kSlots; ++k) {
@@ -229,6 +239,7 @@ __device__ __forceinline__ void topk_features_point(const SceneDev& s, const Sea
   const T* conf = (const T*)s.conf;
   const T* depth = (const T*)s.depth;
   const size_t plane = (size_t)s.W * s.H;
+  const double tau = (double)s.vis_tau;
   // views in groups of two (four as in topk_point would hold more registers
   // next to the frontal list): a view no lane of the wave sees skips its
   // confidence texels and both insertions
@@ -239,8 +250,8 @@ __device__ __forceinline__ void topk_features_point(const SceneDev& s, const Sea
 #pragma unroll
     for (int u = 0; u < kGroup; ++u) {
       const int v = min(v0 + u, s.V - 1);
-      const bool ok = project32(s.cams + 16 * v, px, py, pz, s.W, s.H, q.z_near, pr[u]);
-      seen[u] = visible_at<T>(depth ? depth + plane * v : nullptr, s.W, ok, pr[u], s.vis_tau) &&
+      const bool ok = project64(s.cams + 16 * v, px, py, pz, s.W, s.H, q.z_near, pr[u]);
+      seen[u] = visible_at<T>(depth ? depth + plane * v : nullptr, s.W, ok, pr[u], tau) &&
                 v0 + u < s.V;
     }
     ConfTexels tx[kGroup];
@@ -254,17 +265,17 @@ __device__ __forceinline__ void topk_features_point(const SceneDev& s, const Sea
     for (int u = 0; u < kGroup; ++u) {
       if (!any[u]) continue;
       const int v = v0 + u;
-      const float c = seen[u] ? conf_combine(tx[u]) : 0.0f;
-      if (c > 0.0f) topk_insert<KS>(ck, vk, c, v);
+      const double c = seen[u] ? conf_combine(tx[u]) : 0.0;
+      if (c > 0.0) topk_insert<KS>(ck, vk, c, v);
       // frontal slots: eligible and visible views, whatever their confidence
       if (seen[u])
-        frontal_insert(sc, id, frontal_score32(s.cams + 16 * v, px, py, pz, s.hc, nullptr), v);
+        frontal_insert(sc, id, frontal_score64(s.cams + 16 * v, px, py, pz, s.hc, nullptr), v);
     }
   }
   int keff = 0;
 #pragma unroll
   for (int k = 0; k < KS; ++k) {
-    if (k < q.K && ck[k] > 0.0f) keff = k + 1;
+    if (k < q.K && ck[k] > 0.0) keff = k + 1;
     s.views[FD_TOPK_SLOTS * j + k] = (uint16_t)vk[k];
   }
   s.kcount[j] = (uint8_t)keff;

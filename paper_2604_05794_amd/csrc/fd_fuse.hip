@@ -29,24 +29,61 @@
 
 namespace fd {
 
-// ---- candidate lattice ------------------------------------------------------
+// ---- per-call constants -------------------------------------------------------
 // Hemisphere Fibonacci lattice (Gonzalez 2010): z_k = 1 - (k + 1/2)/n,
-// psi_k = k pi (3 - sqrt 5); evaluated in double, stored as float.
-__global__ void k_lattice(float* __restrict__ out, int n) {
-  int k = blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= n) return;
-  const double golden = 3.14159265358979323846 * (3.0 - sqrt(5.0));
-  double z = 1.0 - ((double)k + 0.5) / (double)n;
-  double rho = sqrt(fmax(0.0, 1.0 - z * z));
-  double psi = golden * (double)k;
-  out[3 * k] = (float)(rho * cos(psi));
-  out[3 * k + 1] = (float)(rho * sin(psi));
-  out[3 * k + 2] = (float)z;
+// psi_k = k pi (3 - sqrt 5), in binary64 and rounded to binary32 for the
+// lattice stage.  Refinement steps alpha_t = step0 / 2^t (exact halvings) with
+// their cosines, sines and cosines minus one, for the plain search and for
+// the learned form's short refinement, and the stencil angles j pi / 3.
+__global__ void k_consts(ConstsDev c, int n, double step0, double lstep0) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < n) {
+    const double golden = 3.14159265358979323846 * (3.0 - sqrt(5.0));
+    const double z = 1.0 - ((double)k + 0.5) / (double)n;
+    const double rho = sqrt(fmax(0.0, 1.0 - z * z));
+    const double psi = golden * (double)k;
+    const double x = rho * cos(psi), y = rho * sin(psi);
+    c.lattice64[3 * k] = x;
+    c.lattice64[3 * k + 1] = y;
+    c.lattice64[3 * k + 2] = z;
+    c.lattice[3 * k] = (float)x;
+    c.lattice[3 * k + 1] = (float)y;
+    c.lattice[3 * k + 2] = (float)z;
+  }
+  if (k < 2 * FD_MAX_REFINE) {
+    const int t = k % FD_MAX_REFINE;
+    const double a = (k < FD_MAX_REFINE ? step0 : lstep0) * ldexp(1.0, -t);
+    double* dst = c.steps + (k < FD_MAX_REFINE ? 0 : 3 * FD_MAX_REFINE);
+    const double h = sin(0.5 * a);
+    dst[t] = cos(a);
+    dst[FD_MAX_REFINE + t] = sin(a);
+    dst[2 * FD_MAX_REFINE + t] = -2.0 * h * h;  // cos a - 1 without cancellation
+  }
+  if (k < 6) {
+    const double a = (double)k * 3.14159265358979323846 / 3.0;
+    c.stencil[k] = cos(a);
+    c.stencil[6 + k] = sin(a);
+  }
 }
 
-hipError_t launch_lattice(float* lattice, int n, hipStream_t st) {
-  hipLaunchKernelGGL(k_lattice, dim3((n + 255) / 256), dim3(256), 0, st, lattice, n);
+hipError_t launch_consts(const ConstsDev& c, int n, double step0, double lstep0, hipStream_t st) {
+  const int m = n > 2 * FD_MAX_REFINE ? n : 2 * FD_MAX_REFINE;
+  hipLaunchKernelGGL(k_consts, dim3((m + 255) / 256), dim3(256), 0, st, c, n, step0, lstep0);
   return hipGetLastError();
+}
+
+SearchDev make_search(const ConstsDev& c, int n_candidates, int refine_iters, int K,
+                      float z_near) {
+  SearchDev q;
+  q.lattice = c.lattice;
+  q.lattice64 = c.lattice64;
+  q.steps = c.steps;
+  q.stencil = c.stencil;
+  q.n_candidates = n_candidates;
+  q.refine_iters = refine_iters;
+  q.K = K;
+  q.z_near = (double)z_near;
+  return q;
 }
 
 template <typename T, int KS>
@@ -78,8 +115,8 @@ hipError_t launch_topk(const SceneDev& s, const SearchDev& q, int dtype, hipStre
 // `list` (optional): processing-order indices to fuse, *list_count of them
 // (read on the device; the grid is sized for the worst case).
 template <typename T, int P, int KT>
-__global__ __launch_bounds__(256) void k_fuse(SceneDev s, SearchDev q, const uint32_t* list,
-                                              const uint32_t* list_count) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(search_waves(P))))
+void k_fuse(SceneDev s, SearchDev q, const uint32_t* list, const uint32_t* list_count) {
   const Group gr = make_group(q.K);
   const int64_t blk = xcd_tile(gridDim.x);
   const int64_t wave = blk * (blockDim.x / kWave) + (threadIdx.x / kWave);
@@ -124,8 +161,8 @@ hipError_t launch_fuse(const SceneDev& s, const SearchDev& q, int dtype, int pat
 }
 
 template <typename T, int P, int KT>
-__global__ __launch_bounds__(256) void k_learned(SceneDev s, SearchDev q, LearnedDev l,
-                                                 int prop_by_j) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(search_waves(P))))
+void k_learned(SceneDev s, SearchDev q, LearnedDev l, int prop_by_j) {
   const Group gr = make_group(q.K);
   const int64_t blk = xcd_tile(gridDim.x);
   const int64_t wave = blk * (blockDim.x / kWave) + (threadIdx.x / kWave);

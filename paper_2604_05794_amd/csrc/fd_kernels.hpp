@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "../../include/fusedir.h"
+
 namespace fd {
 
 // Register slots of the view selection (>= any top_k the API accepts).
@@ -86,12 +88,14 @@ __device__ __forceinline__ SceneDev load_scene(const SceneDev* tab, int s) {
 #undef FD_GLOBAL
 
 struct SearchDev {
-  const float* lattice;  // n_candidates x 3
+  const float* lattice;    // n_candidates x 3, binary32 (lattice stage)
+  const double* lattice64; // the same directions in binary64 (refinement start)
+  const double* steps;     // cos alpha_t, sin alpha_t, cos alpha_t - 1 [FD_MAX_REFINE each]
+  const double* stencil;   // cos(j pi / 3) [6], sin(j pi / 3) [6]
   int n_candidates;
   int refine_iters;
-  float step0;
   int K;
-  float z_near;
+  double z_near;
 };
 
 // Paper-literal candidate mode.
@@ -104,12 +108,23 @@ struct FpmvoDev {
 // Learned form (fd_learned.hip).
 struct LearnedDev {
   const float* proposals;  // n x 3 in point order, or NULL for NaN proposals
+  const double* steps;     // cos / sin of the learned refinement's steps (as SearchDev)
   int iters;
-  float step0;
-  float tau;
+  double tau;
   uint32_t* fb_list;       // processing-order indices that fall back
   uint32_t* fb_count;      // [0] fallback list length, [1] points searched in place
 };
+
+// Per-call constants of the search in device memory (fd_fuse.hip, k_consts):
+// the lattice in binary32 and binary64, the cos/sin tables of the plain and
+// learned refinement steps, and the stencil.
+struct ConstsDev {
+  float* lattice;     // FD_MAX_CANDIDATES x 3
+  double* lattice64;  // FD_MAX_CANDIDATES x 3
+  double* steps;      // 3 x FD_MAX_REFINE (plain), then 3 x FD_MAX_REFINE (learned)
+  double* stencil;    // 12
+};
+constexpr int kConstsDoubles = 3 * FD_MAX_CANDIDATES + 6 * FD_MAX_REFINE + 12;
 
 hipError_t launch_fpmvo(const SceneDev& s, const SearchDev& q, const FpmvoDev& f, int dtype,
                         int patch, hipStream_t st);
@@ -120,7 +135,13 @@ hipError_t launch_scan_runs(const uint32_t* counts, int n_runs, uint32_t* sums, 
 hipError_t launch_fill_u32(uint32_t* p, int64_t n, uint32_t v, hipStream_t st);
 int tile_cells();
 
-hipError_t launch_lattice(float* lattice, int n, hipStream_t st);
+// Fills the per-call constants: lattice of n directions, cos, sin and
+// cos - 1 of the plain steps step0 / 2^t (t < FD_MAX_REFINE) and of the
+// learned steps lstep0 / 2^t, and the stencil.
+hipError_t launch_consts(const ConstsDev& c, int n, double step0, double lstep0, hipStream_t st);
+// Search constants as the kernels read them.
+SearchDev make_search(const ConstsDev& c, int n_candidates, int refine_iters, int K,
+                      float z_near);
 hipError_t launch_topk(const SceneDev& s, const SearchDev& q, int dtype, hipStream_t st);
 hipError_t launch_fuse(const SceneDev& s, const SearchDev& q, int dtype, int patch,
                        const uint32_t* list, const uint32_t* list_count, hipStream_t st);

@@ -55,18 +55,12 @@ int fd::run_learned(fd_context* c, const SceneDev& s, const SearchDev& q, const 
   if ((e = launch_fill_u32(c->fb_count, 2, 0u, st)) != hipSuccess)
     return hip_error(e, "fallback counter reset");
   LearnedDev l;
+  // the learned steps follow the plain ones in the per-call constants
+  l.steps = q.steps + 3 * FD_MAX_REFINE;
   l.iters = p->learned_iters;
-  l.tau = p->fallback_cost;
+  l.tau = (double)p->fallback_cost;
   l.fb_list = c->fb_list;
   l.fb_count = c->fb_count;
-  float step0 = p->learned_step0;
-  if (!(step0 > 0.0f) && p->mlp) {
-    float s0 = 0.0f, tau = 0.0f;
-    fd_mlp_get_calibration(p->mlp, &s0, &tau);
-    step0 = s0;
-  }
-  if (!(step0 > 0.0f)) step0 = default_step0(p->n_candidates);
-  l.step0 = step0;
   int prop_by_j = 0;
   if (p->proposal == FD_PROPOSAL_MLP) {
     // view selection was done together with the features (run_scene skips

@@ -694,6 +694,7 @@ extern "C" int fd_mlp_create(fd_mlp** out, uint64_t seed) {
   fd_mlp* m = new (std::nothrow) fd_mlp();
   if (!m) return set_error(FD_E_NOMEM, "fd_mlp_create: host allocation failed");
   m->device = dev;
+  bump_workspace_generation();  // a captured batched graph holds weight pointers
   hipError_t e = hipMalloc(&m->master, N_PARAMS * 4);
   if (e == hipSuccess) e = hipMalloc(&m->adam_m, N_PARAMS * 4);
   if (e == hipSuccess) e = hipMalloc(&m->adam_v, N_PARAMS * 4);

@@ -3,6 +3,19 @@
 // (fd_batched.hip).  EfficientMonoHair, Sec. 3.1: Eq. (4) view selection,
 // Eqs. (8)-(11) objective, Eq. (12) best candidate, pattern-search
 // refinement.
+//
+// Precision.  View selection is decided in binary64 (fd_device.hpp).  The
+// lattice stage of Eq. (12) scores its candidates in binary32 on binary32
+// patch coefficients (the bulk of the work: the best lattice point is far
+// from the runner-up in all but a vanishing fraction of points).  The
+// refinement compares candidates whose costs differ by as little as the
+// square of its last steps (~1e-6), which binary32 rounding of the cost
+// itself (~1e-7) would decide at random in a few percent of points; it
+// therefore keeps its centre in binary64 and scores each candidate by the
+// change of the cost from the centre, formed from differences so that the
+// rounding is relative to the change (view_delta).  The reported cost is
+// the objective at the result evaluated in binary64 (on the binary32
+// coefficients, whose rounding moves the cost smoothly with the direction).
 #pragma once
 
 #include <hip/hip_fp16.h>
@@ -15,22 +28,20 @@
 
 namespace fd {
 
-constexpr float kInvPi = 0.318309886183790671538f;
-
 // ---- Eq. (4): top-K views by centre confidence ------------------------------
 // One lane per point (processing-order index j).  Stable insertion into a
 // register list of KS >= K slots: a view enters ahead of a listed one only if
 // strictly more confident, so equal confidences keep the lower view index
 // first.  Slots 0..KS-1 of the point's view row are written.
-template <int KS>
-__device__ __forceinline__ void topk_insert(float (&sc)[KS], int (&id)[KS], float c, int v) {
-  float cs = c;
+template <int KS, typename S>
+__device__ __forceinline__ void topk_insert(S (&sc)[KS], int (&id)[KS], S c, int v) {
+  S cs = c;
   int cv = v;
   bool ins = false;
 #pragma unroll
   for (int k = 0; k < KS; ++k) {
     const bool take = ins || (cs > sc[k]);
-    const float ts = sc[k];
+    const S ts = sc[k];
     const int tv = id[k];
     sc[k] = take ? cs : ts;
     id[k] = take ? cv : tv;
@@ -43,19 +54,20 @@ __device__ __forceinline__ void topk_insert(float (&sc)[KS], int (&id)[KS], floa
 template <typename T, int KS>
 __device__ __forceinline__ void topk_point(const SceneDev& s, const SearchDev& q, int64_t j) {
   const uint32_t i = s.perm[j];
-  const float px = s.pts[3 * (size_t)i], py = s.pts[3 * (size_t)i + 1],
-              pz = s.pts[3 * (size_t)i + 2];
-  float sc[KS];
+  const double px = s.pts[3 * (size_t)i], py = s.pts[3 * (size_t)i + 1],
+               pz = s.pts[3 * (size_t)i + 2];
+  double sc[KS];
   int id[KS];
 #pragma unroll
   for (int k = 0; k < KS; ++k) {
-    sc[k] = -1.0f;
+    sc[k] = -1.0;
     id[k] = 0;
   }
   const T* conf = (const T*)s.conf;
   const T* depth = (const T*)s.depth;
   const size_t plane = (size_t)s.W * s.H;
-  // Views in groups of four.  Projections and depth texels of a group are
+  const double tau = (double)s.vis_tau;
+  // Views in groups of kGroup.  Projections and depth texels of a group are
   // issued together; a view that no lane of the wave sees (all hidden, behind
   // or outside, common for the far side of a head) skips its confidence
   // texels and insertion.  The confidence loads of the seen views are issued
@@ -67,8 +79,8 @@ __device__ __forceinline__ void topk_point(const SceneDev& s, const SearchDev& q
 #pragma unroll
     for (int u = 0; u < kGroup; ++u) {
       const int v = min(v0 + u, s.V - 1);
-      const bool ok = project32(s.cams + 16 * v, px, py, pz, s.W, s.H, q.z_near, pr[u]);
-      seen[u] = visible_at<T>(depth ? depth + plane * v : nullptr, s.W, ok, pr[u], s.vis_tau) &&
+      const bool ok = project64(s.cams + 16 * v, px, py, pz, s.W, s.H, q.z_near, pr[u]);
+      seen[u] = visible_at<T>(depth ? depth + plane * v : nullptr, s.W, ok, pr[u], tau) &&
                 v0 + u < s.V;
     }
     ConfTexels tx[kGroup];
@@ -81,14 +93,14 @@ __device__ __forceinline__ void topk_point(const SceneDev& s, const SearchDev& q
 #pragma unroll
     for (int u = 0; u < kGroup; ++u) {
       if (!any[u]) continue;
-      const float c = seen[u] ? conf_combine(tx[u]) : 0.0f;
-      if (c > 0.0f) topk_insert<KS>(sc, id, c, v0 + u);
+      const double c = seen[u] ? conf_combine(tx[u]) : 0.0;
+      if (c > 0.0) topk_insert<KS>(sc, id, c, v0 + u);
     }
   }
   int keff = 0;
 #pragma unroll
   for (int k = 0; k < KS; ++k) {
-    if (k < q.K && sc[k] > 0.0f) keff = k + 1;
+    if (k < q.K && sc[k] > 0.0) keff = k + 1;
     s.views[FD_TOPK_SLOTS * j + k] = (uint16_t)id[k];
   }
   s.kcount[j] = (uint8_t)keff;
@@ -107,9 +119,12 @@ struct ViewPatch {
 // centred on the projection (offsets (a, b) in {-h..h}^2 pixels from the
 // sub-pixel centre, each a bilinear sample of the doubled-angle vector
 // weighted by bilinear weight times confidence, zero outside the image).
+// The projection and the Jacobian are taken in binary64 and rounded once;
+// the texel angles go through an accurate sine/cosine, and the sample's
+// normalisation through IEEE square root and division.
 template <typename T, int P>
 __device__ __forceinline__ void build_patch(const SceneDev& s, const SearchDev& q, int view,
-                                            bool active, float px, float py, float pz,
+                                            bool active, double px, double py, double pz,
                                             ViewPatch<P>& vp) {
   constexpr int P2 = P * P, HP = (P - 1) / 2;
 #pragma unroll
@@ -119,22 +134,23 @@ __device__ __forceinline__ void build_patch(const SceneDev& s, const SearchDev& 
   if (!active) return;
   const float* cam = s.cams + 16 * view;
   Proj pr;
-  project32(cam, px, py, pz, s.W, s.H, q.z_near, pr);
+  project64(cam, px, py, pz, s.W, s.H, q.z_near, pr);
   // r = J_pi d up to the positive factor 1/Z^2:
   //   r_x = fx (Z (R0 . d) - X (R2 . d)),  r_y = fy (Z (R1 . d) - Y (R2 . d))
   const float* R = cam + 4;
-  vp.M[0] = cam[0] * (pr.Z * R[0] - pr.X * R[6]);
-  vp.M[1] = cam[0] * (pr.Z * R[1] - pr.X * R[7]);
-  vp.M[2] = cam[0] * (pr.Z * R[2] - pr.X * R[8]);
-  vp.M[3] = cam[1] * (pr.Z * R[3] - pr.Y * R[6]);
-  vp.M[4] = cam[1] * (pr.Z * R[4] - pr.Y * R[7]);
-  vp.M[5] = cam[1] * (pr.Z * R[5] - pr.Y * R[8]);
+  const double f0 = cam[0], f1 = cam[1];
+  vp.M[0] = (float)(f0 * (pr.Z * R[0] - pr.X * R[6]));
+  vp.M[1] = (float)(f0 * (pr.Z * R[1] - pr.X * R[7]));
+  vp.M[2] = (float)(f0 * (pr.Z * R[2] - pr.X * R[8]));
+  vp.M[3] = (float)(f1 * (pr.Z * R[3] - pr.Y * R[6]));
+  vp.M[4] = (float)(f1 * (pr.Z * R[4] - pr.Y * R[7]));
+  vp.M[5] = (float)(f1 * (pr.Z * R[5] - pr.Y * R[8]));
 
   const size_t plane = (size_t)s.W * s.H;
   const T* th = (const T*)s.theta + plane * view;
   const T* cf = (const T*)s.conf + plane * view;
-  const float x0 = floorf(pr.u), y0 = floorf(pr.v);
-  const float fx = pr.u - x0, fy = pr.v - y0;
+  const double x0 = floor(pr.u), y0 = floor(pr.v);
+  const float fx = (float)(pr.u - x0), fy = (float)(pr.v - y0);
   const float gx = 1.0f - fx, gy = 1.0f - fy;
   const float w00 = gx * gy, w10 = fx * gy, w01 = gx * fy, w11 = fx * fy;
   const int ix = (int)x0 - HP, iy = (int)y0 - HP;
@@ -174,10 +190,11 @@ __device__ __forceinline__ void build_patch(const SceneDev& s, const SearchDev& 
     }
 #pragma unroll
     for (int a = 0; a <= P; ++a) {
-      const float turns = tv[a] * kInvPi;  // 2 theta in revolutions
+      float sn, cs;
+      sincosf(2.0f * tv[a], &sn, &cs);  // 2 theta is exact in binary32
       rc[slot][a] = cv[a];
-      rx[slot][a] = cv[a] * __builtin_amdgcn_cosf(turns);
-      ry[slot][a] = cv[a] * __builtin_amdgcn_sinf(turns);
+      rx[slot][a] = cv[a] * cs;
+      ry[slot][a] = cv[a] * sn;
     }
   };
   load_row(0, iy);
@@ -187,22 +204,107 @@ __device__ __forceinline__ void build_patch(const SceneDev& s, const SearchDev& 
     load_row(r1, iy + b + 1);
 #pragma unroll
     for (int a = 0; a < P; ++a) {
-      float cb = w00 * rc[r0][a] + w10 * rc[r0][a + 1] + w01 * rc[r1][a] + w11 * rc[r1][a + 1];
-      float mx = w00 * rx[r0][a] + w10 * rx[r0][a + 1] + w01 * rx[r1][a] + w11 * rx[r1][a + 1];
-      float my = w00 * ry[r0][a] + w10 * ry[r0][a + 1] + w01 * ry[r1][a] + w11 * ry[r1][a + 1];
-      float n2 = mx * mx + my * my;
-      float al = 0.5f * cb * cb;
-      float inv = n2 > 0.0f ? __builtin_amdgcn_rsqf(n2) : 0.0f;
+      const float cb = w00 * rc[r0][a] + w10 * rc[r0][a + 1] + w01 * rc[r1][a] + w11 * rc[r1][a + 1];
+      const float mx = w00 * rx[r0][a] + w10 * rx[r0][a + 1] + w01 * rx[r1][a] + w11 * rx[r1][a + 1];
+      const float my = w00 * ry[r0][a] + w10 * ry[r0][a + 1] + w01 * ry[r1][a] + w11 * ry[r1][a + 1];
+      const float n2 = mx * mx + my * my;
+      const float al = 0.5f * cb * cb;
+      const bool on = n2 > 0.0f;
+      const float n = on ? sqrtf(n2) : 1.0f;
       const int k = b * P + a;
-      vp.a[k] = n2 > 0.0f ? al : 0.0f;
-      vp.b[k] = al * mx * inv;
-      vp.c[k] = 2.0f * al * my * inv;  // the factor 2 of 2 rx ry folded in
+      vp.a[k] = on ? al : 0.0f;
+      vp.b[k] = on ? al * mx / n : 0.0f;
+      vp.c[k] = on ? 2.0f * al * my / n : 0.0f;  // the factor 2 of 2 rx ry folded in
     }
   }
 }
 
+// The patch in binary64 throughout (texel angles, bilinear weights,
+// normalisation, Jacobian): the paper-literal candidate mode, which scores a
+// handful of candidates per point and compares their costs directly.
+template <int P>
+struct ViewPatch64 {
+  static constexpr int P2 = P * P;
+  double a[P2], b[P2], c[P2];
+  double M[6];
+};
+
+template <typename T, int P>
+__device__ __forceinline__ void build_patch64(const SceneDev& s, const SearchDev& q, int view,
+                                              bool active, double px, double py, double pz,
+                                              ViewPatch64<P>& vp) {
+  constexpr int P2 = P * P, HP = (P - 1) / 2;
+#pragma unroll
+  for (int k = 0; k < P2; ++k) vp.a[k] = vp.b[k] = vp.c[k] = 0.0;
+#pragma unroll
+  for (int k = 0; k < 6; ++k) vp.M[k] = 0.0;
+  if (!active) return;
+  const float* cam = s.cams + 16 * view;
+  Proj pr;
+  project64(cam, px, py, pz, s.W, s.H, q.z_near, pr);
+  const float* R = cam + 4;
+  const double f0 = cam[0], f1 = cam[1];
+  vp.M[0] = f0 * (pr.Z * R[0] - pr.X * R[6]);
+  vp.M[1] = f0 * (pr.Z * R[1] - pr.X * R[7]);
+  vp.M[2] = f0 * (pr.Z * R[2] - pr.X * R[8]);
+  vp.M[3] = f1 * (pr.Z * R[3] - pr.Y * R[6]);
+  vp.M[4] = f1 * (pr.Z * R[4] - pr.Y * R[7]);
+  vp.M[5] = f1 * (pr.Z * R[5] - pr.Y * R[8]);
+  const size_t plane = (size_t)s.W * s.H;
+  const T* th = (const T*)s.theta + plane * view;
+  const T* cf = (const T*)s.conf + plane * view;
+  const double x0 = floor(pr.u), y0 = floor(pr.v);
+  const double fx = pr.u - x0, fy = pr.v - y0;
+  const int ix = (int)x0 - HP, iy = (int)y0 - HP;
+  for (int b = 0; b < P; ++b) {
+#pragma unroll
+    for (int a = 0; a < P; ++a) {
+      double cb = 0.0, mx = 0.0, my = 0.0;
+#pragma unroll
+      for (int jy = 0; jy < 2; ++jy)
+#pragma unroll
+        for (int jx = 0; jx < 2; ++jx) {
+          const double w = (jx ? fx : 1.0 - fx) * (jy ? fy : 1.0 - fy);
+          const double t = tex_load_nb<T>(th, s.W, s.H, ix + a + jx, iy + b + jy);
+          const double c = tex_load_nb<T>(cf, s.W, s.H, ix + a + jx, iy + b + jy);
+          double sn, cs;
+          sincos(2.0 * t, &sn, &cs);
+          cb += w * c;
+          mx += w * c * cs;
+          my += w * c * sn;
+        }
+      const double n = sqrt(mx * mx + my * my);
+      const double al = 0.5 * cb * cb;
+      const int k = b * P + a;
+      vp.a[k] = n > 0.0 ? al : 0.0;
+      vp.b[k] = n > 0.0 ? al * mx / n : 0.0;
+      vp.c[k] = n > 0.0 ? 2.0 * al * my / n : 0.0;
+    }
+  }
+}
+
+template <int P>
+__device__ __forceinline__ double eval_patch64(const ViewPatch64<P>& vp, double dx, double dy,
+                                               double dz) {
+  constexpr int P2 = P * P;
+  const double rx = __builtin_fma(vp.M[0], dx, __builtin_fma(vp.M[1], dy, vp.M[2] * dz));
+  const double ry = __builtin_fma(vp.M[3], dx, __builtin_fma(vp.M[4], dy, vp.M[5] * dz));
+  const double xx = rx * rx;
+  const double n2 = __builtin_fma(ry, ry, xx);
+  const bool on = n2 > 0.0;
+  const double inv = 1.0 / (on ? n2 : 1.0);
+  const double c2 = __builtin_fma(-ry, ry, xx) * inv;
+  const double s2 = (rx * ry) * inv;
+  double m = 0.0;
+#pragma unroll
+  for (int k = 0; k < P2; ++k)
+    m = fmax(m, __builtin_fma(vp.b[k], c2, __builtin_fma(vp.c[k], s2, vp.a[k])));
+  return (on && m > 0.0) ? sqrt(m) : 0.0;
+}
+
 // max_p C_p |cos(phi(d) - theta_p)| for this lane's view (0 if the tangent
-// projects to a point or the lane has no view).  With r = M d, n2 = |r|^2:
+// projects to a point or the lane has no view), binary32: the lattice stage.
+// With r = M d, n2 = |r|^2:
 // C^2 cos^2(phi - theta) = a + b (rx^2 - ry^2)/n2 + c (rx ry)/n2, c = 2 gamma.
 // For n2 = 0 the reciprocal is +inf, every q is NaN, fmaxf keeps the other
 // operand, and the maximum stays 0.
@@ -230,6 +332,52 @@ __device__ __forceinline__ float eval_view(const ViewPatch<P>& vp, float dx, flo
   return __builtin_amdgcn_sqrtf(m);
 }
 
+// The same in binary64 (the refinement): the coefficients are widened
+// exactly, every operation is binary64, and a tangent that projects to a
+// point gives 0.
+template <int P>
+__device__ __forceinline__ double eval_view64(const ViewPatch<P>& vp, double dx, double dy,
+                                              double dz) {
+  constexpr int P2 = P * P;
+  const double rx = __builtin_fma((double)vp.M[0], dx,
+                                  __builtin_fma((double)vp.M[1], dy, (double)vp.M[2] * dz));
+  const double ry = __builtin_fma((double)vp.M[3], dx,
+                                  __builtin_fma((double)vp.M[4], dy, (double)vp.M[5] * dz));
+  const double xx = rx * rx;
+  const double n2 = __builtin_fma(ry, ry, xx);
+  const bool on = n2 > 0.0;
+  const double inv = rcp64(on ? n2 : 1.0);
+  const double c2 = __builtin_fma(-ry, ry, xx) * inv;
+  const double s2 = (rx * ry) * inv;
+  double m = 0.0;
+#pragma unroll
+  for (int k = 0; k < P2; ++k) {
+    const double qk = __builtin_fma((double)vp.b[k], c2,
+                                    __builtin_fma((double)vp.c[k], s2, (double)vp.a[k]));
+    m = fmax(m, qk);
+  }
+  return (on && m > 0.0) ? m * rsq64(m) : 0.0;
+}
+
+// Marks the patch coefficients as rewritten at this point (an empty asm
+// statement on their registers; their values do not change), so that the
+// widening of eval_view64 stays at the evaluation instead of being
+// scheduled early, where 3 P^2 binary64 values would hold twice the
+// registers of the binary32 patch through the whole refinement.
+template <int P>
+__device__ __forceinline__ void pin_patch(ViewPatch<P>& vp) {
+#pragma unroll
+  for (int k = 0; k < P * P; ++k) asm volatile("" : "+v"(vp.a[k]), "+v"(vp.b[k]), "+v"(vp.c[k]));
+}
+
+// Waves per SIMD the search kernels are compiled for: patches up to 5 x 5
+// fit three waves' register share (168) with a few spilled bytes, which
+// measures faster than two waves; 7 x 7 patches keep the compiler's choice.
+#ifndef FD_SEARCH_WAVES
+#define FD_SEARCH_WAVES 3
+#endif
+constexpr int search_waves(int P) { return P <= 5 ? FD_SEARCH_WAVES : 1; }
+
 struct Group {
   int K, G, g, slot, base;
   bool lane_ok;
@@ -247,68 +395,180 @@ __device__ __forceinline__ Group make_group(int K) {
   return gr;
 }
 
-// Pattern search (six directions at angle alpha around d in the basis of
-// Duff et al. 2017, best strictly-better one taken, alpha halves).  Works on
-// the view sum S = sum_v L_v (J = 1 - S / K_eff), larger is better.
+// Change of this lane's view term L_v = sqrt(max_p q_p) from the centre d
+// of a refinement iteration to the candidate d + du (du the exact stencil
+// offset), computed from differences so that binary32 rounding is relative
+// to the change rather than to L_v itself.  With z = rx + i ry the image
+// direction at d and dz = M du, e^{2 i phi} moves by
+//   e^{2 i phi_d} * 2 i Im(eps) / conj(1 + eps),  eps = dz / z,
+// the quadratic form of sample p by b_p dc2 + c_p ds2, and its patch value
+// relative to the centre's maximum Q0 is v_p = g_p + b_p dc2 + c_p ds2 with
+// g_p = q_p(d) - Q0; then L(d + du) - L(d) = V / (sqrt(Q0 + V) + sqrt(Q0)),
+// V = max_p v_p.  A view whose centre direction projects to a point
+// (|z| = 0, L(d) = 0) takes the candidate's own quadratic form instead
+// (g_p = a_p, Q0 = 0); a candidate that projects to a point has L = 0.
+struct ViewCentre {
+  float zx, zy, iz2;  // z and 1 / |z|^2
+  float ec, es;       // cos 2 phi_d, sin 2 phi_d
+  float q0, l0;       // max_p q_p(d) and its square root
+  bool on;            // |z| > 0
+};
+
+template <int P>
+__device__ __forceinline__ ViewCentre view_centre(const ViewPatch<P>& vp, double dx, double dy,
+                                                  double dz, float (&g)[P * P]) {
+  constexpr int P2 = P * P;
+  ViewCentre c;
+  const double rx = __builtin_fma((double)vp.M[0], dx,
+                                  __builtin_fma((double)vp.M[1], dy, (double)vp.M[2] * dz));
+  const double ry = __builtin_fma((double)vp.M[3], dx,
+                                  __builtin_fma((double)vp.M[4], dy, (double)vp.M[5] * dz));
+  const double n2 = rx * rx + ry * ry;
+  c.on = n2 > 0.0;
+  const double i2 = c.on ? rcp64(n2) : 0.0;
+  const float c2 = (float)((rx * rx - ry * ry) * i2), s2 = (float)(rx * ry * i2);
+  c.zx = (float)rx;
+  c.zy = (float)ry;
+  c.iz2 = (float)i2;
+  c.ec = c2;
+  c.es = 2.0f * s2;
+  float m = 0.0f;
+#pragma unroll
+  for (int k = 0; k < P2; ++k) {
+    g[k] = __builtin_fmaf(vp.b[k], c2, __builtin_fmaf(vp.c[k], s2, vp.a[k]));
+    m = __builtin_fmaxf(m, g[k]);
+  }
+  m = c.on ? m : 0.0f;
+#pragma unroll
+  for (int k = 0; k < P2; ++k) g[k] = c.on ? g[k] - m : vp.a[k];
+  c.q0 = m;
+  c.l0 = __builtin_amdgcn_sqrtf(m);
+  return c;
+}
+
+template <int P>
+__device__ __forceinline__ float view_delta(const ViewPatch<P>& vp, const float (&g)[P * P],
+                                            const ViewCentre& c, bool any_off, float ux,
+                                            float uy, float uz) {
+  constexpr int P2 = P * P;
+  const float Dx = __builtin_fmaf(vp.M[0], ux, __builtin_fmaf(vp.M[1], uy, vp.M[2] * uz));
+  const float Dy = __builtin_fmaf(vp.M[3], ux, __builtin_fmaf(vp.M[4], uy, vp.M[5] * uz));
+  // centred form
+  const float er = (Dx * c.zx + Dy * c.zy) * c.iz2, ei = (Dy * c.zx - Dx * c.zy) * c.iz2;
+  const float opr = 1.0f + er;
+  const float D = __builtin_fmaf(opr, opr, ei * ei);
+  const float iD = __builtin_amdgcn_rcpf(D);
+  const float dre = -2.0f * ei * ei * iD, dim = 2.0f * ei * opr * iD;
+  float dc2 = c.ec * dre - c.es * dim;
+  float ds2 = 0.5f * (c.ec * dim + c.es * dre);
+  bool cand_on = D > 0.0f;
+  if (any_off) {  // wave-uniform: some lane's centre direction projects to a point
+    const float xx = Dx * Dx, n2 = __builtin_fmaf(Dy, Dy, xx);
+    const float inv = __builtin_amdgcn_rcpf(n2);
+    dc2 = c.on ? dc2 : __builtin_fmaf(-Dy, Dy, xx) * inv;
+    ds2 = c.on ? ds2 : (Dx * Dy) * inv;
+    cand_on = c.on ? cand_on : n2 > 0.0f;
+  }
+  float V = -INFINITY;
+#pragma unroll
+  for (int k = 0; k + 1 < P2; k += 2) {
+    const float v0 = __builtin_fmaf(vp.b[k], dc2, __builtin_fmaf(vp.c[k], ds2, g[k]));
+    const float v1 = __builtin_fmaf(vp.b[k + 1], dc2, __builtin_fmaf(vp.c[k + 1], ds2, g[k + 1]));
+    V = __builtin_fmaxf(__builtin_fmaxf(V, v0), v1);
+  }
+  if (P2 & 1) {
+    const float v0 = __builtin_fmaf(vp.b[P2 - 1], dc2, __builtin_fmaf(vp.c[P2 - 1], ds2, g[P2 - 1]));
+    V = __builtin_fmaxf(V, v0);
+  }
+  V = __builtin_fmaxf(V, -c.q0);  // q >= 0
+  const float den = __builtin_amdgcn_sqrtf(c.q0 + V) + c.l0;
+  const float dl = den > 0.0f ? V * __builtin_amdgcn_rcpf(den) : 0.0f;
+  return cand_on ? dl : -c.l0;
+}
+
+// Pattern search (six directions at angle alpha_t around d in the
+// orthonormal basis of Duff et al. 2017, stencil angles j pi / 3, the best
+// strictly-better one taken, first of equals; alpha halves every iteration).
+// The centre d and the move are binary64; each candidate is compared with
+// the centre through the change of the view sum (view_delta), so the
+// decisions carry binary32 rounding relative to the cost differences the
+// iteration compares, not to the cost.  cs holds cos alpha_t, sin alpha_t
+// and cos alpha_t - 1 (FD_MAX_REFINE entries each), stencil cos(j pi/3)
+// then sin(j pi/3).
 template <int P, int KT>
 __device__ __forceinline__ void refine(const ViewPatch<P>& vp, const Group& gr, int iters,
-                                       float alpha, float& dx, float& dy, float& dz, float& Sd) {
-  const float cj[6] = {1.0f, 0.5f, -0.5f, -1.0f, -0.5f, 0.5f};
-  const float sj[6] = {0.0f, 0.86602540378443865f, 0.86602540378443865f, 0.0f,
-                       -0.86602540378443865f, -0.86602540378443865f};
+                                       const double* __restrict__ cs,
+                                       const double* __restrict__ stencil, double& dx,
+                                       double& dy, double& dz) {
   for (int t = 0; t < iters; ++t) {
-    const float sg = copysignf(1.0f, dz);
-    const float aa = -1.0f / (sg + dz);
-    const float bb = dx * dy * aa;
-    const float e1x = 1.0f + sg * dx * dx * aa, e1y = sg * bb, e1z = -sg * dx;
-    const float e2x = bb, e2y = sg + dy * dy * aa, e2z = -dy;
-    const float ca = cosf(alpha), sa = sinf(alpha);
-    float bS = -INFINITY, bx = dx, by = dy, bz = dz;
-#pragma unroll
-    for (int j = 0; j < 6; ++j) {
-      float ux = ca * dx + sa * (cj[j] * e1x + sj[j] * e2x);
-      float uy = ca * dy + sa * (cj[j] * e1y + sj[j] * e2y);
-      float uz = ca * dz + sa * (cj[j] * e1z + sj[j] * e2z);
-      const float il = __builtin_amdgcn_rsqf(ux * ux + uy * uy + uz * uz);
-      ux *= il;
-      uy *= il;
-      uz *= il;
-      const float S = group_sum_t<KT>(eval_view<P>(vp, ux, uy, uz), gr.base, gr.K);
-      if (S > bS) {
-        bS = S;
-        bx = ux;
-        by = uy;
-        bz = uz;
+    const double sg = copysign(1.0, dz);
+    const double aa = -1.0 / (sg + dz);
+    const double bb = dx * dy * aa;
+    const double e1x = 1.0 + sg * dx * dx * aa, e1y = sg * bb, e1z = -sg * dx;
+    const double e2x = bb, e2y = sg + dy * dy * aa, e2z = -dy;
+    float g[P * P];
+    const ViewCentre c = view_centre<P>(vp, dx, dy, dz, g);
+    const bool any_off = __ballot(!c.on) != 0;
+    const float sa = (float)cs[FD_MAX_REFINE + t], cm1 = (float)cs[2 * FD_MAX_REFINE + t];
+    const float fdx = (float)dx, fdy = (float)dy, fdz = (float)dz;
+    const float f1x = (float)e1x, f1y = (float)e1y, f1z = (float)e1z;
+    const float f2x = (float)e2x, f2y = (float)e2y, f2z = (float)e2z;
+    float bS = -INFINITY;
+    int bj = 0;
+#pragma unroll 1
+    for (int jj = 0; jj < 6; ++jj) {
+      const float cj = (float)stencil[jj], sj = (float)stencil[6 + jj];
+      const float vx = cj * f1x + sj * f2x;
+      const float vy = cj * f1y + sj * f2y;
+      const float vz = cj * f1z + sj * f2z;
+      const float ux = __builtin_fmaf(cm1, fdx, sa * vx);
+      const float uy = __builtin_fmaf(cm1, fdy, sa * vy);
+      const float uz = __builtin_fmaf(cm1, fdz, sa * vz);
+      const float dS =
+          group_sum_t<KT>(view_delta<P>(vp, g, c, any_off, ux, uy, uz), gr.base, gr.K);
+      if (dS > bS) {
+        bS = dS;
+        bj = jj;
       }
     }
-    if (bS > Sd) {
-      Sd = bS;
-      dx = bx;
-      dy = by;
-      dz = bz;
+    if (bS > 0.0f) {  // the same decision in every lane of the group
+      const double ca = cs[t], sad = cs[FD_MAX_REFINE + t];
+      const double cj = stencil[bj], sj = stencil[6 + bj];
+      double ux = ca * dx + sad * (cj * e1x + sj * e2x);
+      double uy = ca * dy + sad * (cj * e1y + sj * e2y);
+      double uz = ca * dz + sad * (cj * e1z + sj * e2z);
+      const double il = rsq64(ux * ux + uy * uy + uz * uz);
+      dx = ux * il;
+      dy = uy * il;
+      dz = uz * il;
     }
-    alpha *= 0.5f;
   }
 }
 
-__device__ __forceinline__ void write_result(const SceneDev& s, uint32_t i, float dx, float dy,
-                                             float dz, float J) {
-  const bool flip = dz != 0.0f ? dz < 0.0f : (dy != 0.0f ? dy < 0.0f : dx < 0.0f);
-  const float sgn = flip ? -1.0f : 1.0f;
-  s.dirs[3 * (size_t)i] = sgn * dx;
-  s.dirs[3 * (size_t)i + 1] = sgn * dy;
-  s.dirs[3 * (size_t)i + 2] = sgn * dz;
-  s.costs[i] = J;
+// Output: d and -d are the same line; the representative has z > 0, else
+// y > 0, else x >= 0.  cost J = 1 - S / K_eff.
+__device__ __forceinline__ void write_result(const SceneDev& s, uint32_t i, double dx, double dy,
+                                             double dz, double J) {
+  const bool flip = dz != 0.0 ? dz < 0.0 : (dy != 0.0 ? dy < 0.0 : dx < 0.0);
+  const double sgn = flip ? -1.0 : 1.0;
+  s.dirs[3 * (size_t)i] = (float)(sgn * dx);
+  s.dirs[3 * (size_t)i + 1] = (float)(sgn * dy);
+  s.dirs[3 * (size_t)i + 2] = (float)(sgn * dz);
+  s.costs[i] = (float)J;
+}
+
+__device__ __forceinline__ double cost_of(double S, int keff) {
+  return keff > 0 ? 1.0 - S / (double)keff : INFINITY;
 }
 
 // ---- plain search of one point per lane group ---------------------------------
 // Eq. (12) lattice argmin of J (= argmax of the view sum, first of equals),
 // then the pattern-search refinement, on the group's patch registers.
-// Returns the direction in (dx, dy, dz) and the view sum in S.
+// Returns the direction in (dx, dy, dz) and the binary64 view sum in S.
 template <int P, int KT>
-__device__ __forceinline__ void full_search(const ViewPatch<P>& vp, const SearchDev& q,
-                                            const Group& gr, float& dx, float& dy, float& dz,
-                                            float& S) {
+__device__ __forceinline__ void full_search(ViewPatch<P>& vp, const SearchDev& q,
+                                            const Group& gr, double& dx, double& dy, double& dz,
+                                            double& S) {
   float Sb = -INFINITY;
   int kb = 0;
   // two candidates per pass (by hand: the group sum's cross-lane reads keep
@@ -336,11 +596,12 @@ __device__ __forceinline__ void full_search(const ViewPatch<P>& vp, const Search
       kb = k;
     }
   }
-  dx = q.lattice[3 * kb];
-  dy = q.lattice[3 * kb + 1];
-  dz = q.lattice[3 * kb + 2];
-  refine<P, KT>(vp, gr, q.refine_iters, q.step0, dx, dy, dz, Sb);
-  S = Sb;
+  dx = q.lattice64[3 * kb];
+  dy = q.lattice64[3 * kb + 1];
+  dz = q.lattice64[3 * kb + 2];
+  refine<P, KT>(vp, gr, q.refine_iters, q.steps, q.stencil, dx, dy, dz);
+  pin_patch<P>(vp);
+  S = group_sum_t<KT>(eval_view64<P>(vp, dx, dy, dz), gr.base, gr.K);
 }
 
 // The K lanes of the caller's group fuse processing-order point j of scene s
@@ -352,18 +613,17 @@ __device__ __forceinline__ void fuse_group(const SceneDev& s, const SearchDev& q
   const int keff = pt_ok ? (int)s.kcount[j] : 0;
   const bool slot_ok = pt_ok && gr.slot < keff;
   const int view = slot_ok ? (int)s.views[FD_TOPK_SLOTS * j + gr.slot] : 0;
-  const float px = s.pts[3 * (size_t)i], py = s.pts[3 * (size_t)i + 1],
-              pz = s.pts[3 * (size_t)i + 2];
+  const double px = s.pts[3 * (size_t)i], py = s.pts[3 * (size_t)i + 1],
+               pz = s.pts[3 * (size_t)i + 2];
   ViewPatch<P> vp;
   build_patch<T, P>(s, q, view, slot_ok, px, py, pz, vp);
-  const float kinv = keff > 0 ? 1.0f / (float)keff : 0.0f;
-  float dx, dy, dz, S;
+  double dx, dy, dz, S;
   full_search<P, KT>(vp, q, gr, dx, dy, dz, S);
   if (pt_ok && gr.slot == 0) {
     if (keff == 0)
-      write_result(s, i, 0.0f, 0.0f, 0.0f, INFINITY);
+      write_result(s, i, 0.0, 0.0, 0.0, INFINITY);
     else
-      write_result(s, i, dx, dy, dz, 1.0f - S * kinv);
+      write_result(s, i, dx, dy, dz, cost_of(S, keff));
   }
 }
 
@@ -376,7 +636,8 @@ __device__ __forceinline__ void fuse_group(const SceneDev& s, const SearchDev& q
 // already holds (l.fb_count[1] counts those points); otherwise the points
 // that need it are appended as list_base + j to the fallback list
 // (l.fb_count[0] entries) for a later plain-search launch.  Either way a
-// point's result is the plain search's.
+// point's result is the plain search's.  The proposal is normalised, refined
+// and compared with tau in binary64.
 template <typename T, int P, int KT>
 __device__ __forceinline__ void learned_group(const SceneDev& s, const SearchDev& q,
                                               const LearnedDev& l, const Group& gr, bool pt_ok,
@@ -386,27 +647,26 @@ __device__ __forceinline__ void learned_group(const SceneDev& s, const SearchDev
   const int keff = pt_ok ? (int)s.kcount[j] : 0;
   const bool slot_ok = pt_ok && gr.slot < keff;
   const int view = slot_ok ? (int)s.views[FD_TOPK_SLOTS * j + gr.slot] : 0;
-  const float px = s.pts[3 * (size_t)i], py = s.pts[3 * (size_t)i + 1],
-              pz = s.pts[3 * (size_t)i + 2];
+  const double px = s.pts[3 * (size_t)i], py = s.pts[3 * (size_t)i + 1],
+               pz = s.pts[3 * (size_t)i + 2];
   ViewPatch<P> vp;
   build_patch<T, P>(s, q, view, slot_ok, px, py, pz, vp);
-  const float kinv = keff > 0 ? 1.0f / (float)keff : 0.0f;
-  float dx = 0.0f, dy = 0.0f, dz = 0.0f;
+  double dx = 0.0, dy = 0.0, dz = 0.0;
   if (pt_ok && l.proposals) {
     const size_t k = 3 * (size_t)(prop_by_j ? (uint64_t)(prop_base + j) : (uint64_t)i);
     dx = l.proposals[k];
     dy = l.proposals[k + 1];
     dz = l.proposals[k + 2];
   }
-  const float len = sqrtf(dx * dx + dy * dy + dz * dz);
-  const bool valid = keff > 0 && isfinite(len) && len > 0.0f;
-  const float il = valid ? 1.0f / len : 0.0f;
-  dx = valid ? dx * il : 0.0f;
-  dy = valid ? dy * il : 0.0f;
-  dz = valid ? dz * il : 1.0f;
-  float S = group_sum_t<KT>(eval_view<P>(vp, dx, dy, dz), gr.base, gr.K);
-  refine<P, KT>(vp, gr, l.iters, l.step0, dx, dy, dz, S);
-  const float J = 1.0f - S * kinv;
+  const double len = sqrt(dx * dx + dy * dy + dz * dz);
+  const bool valid = keff > 0 && isfinite(len) && len > 0.0;
+  dx = valid ? dx / len : 0.0;
+  dy = valid ? dy / len : 0.0;
+  dz = valid ? dz / len : 1.0;
+  refine<P, KT>(vp, gr, l.iters, l.steps, q.stencil, dx, dy, dz);
+  pin_patch<P>(vp);
+  const double S = group_sum_t<KT>(eval_view64<P>(vp, dx, dy, dz), gr.base, gr.K);
+  const double J = cost_of(S, keff);
   const bool keep = valid && J <= l.tau;
   const bool lead = pt_ok && gr.slot == 0;
   if (lead && keep) write_result(s, i, dx, dy, dz, J);
@@ -415,13 +675,13 @@ __device__ __forceinline__ void learned_group(const SceneDev& s, const SearchDev
   const int n_need = __popcll(__ballot(lead && !keep));
   if (n_need == 0) return;
   if (2 * n_need >= n_pts) {
-    float fx, fy, fz, fS;
+    double fx, fy, fz, fS;
     full_search<P, KT>(vp, q, gr, fx, fy, fz, fS);
     if (lead && !keep) {
       if (keff == 0)
-        write_result(s, i, 0.0f, 0.0f, 0.0f, INFINITY);
+        write_result(s, i, 0.0, 0.0, 0.0, INFINITY);
       else
-        write_result(s, i, fx, fy, fz, 1.0f - fS * kinv);
+        write_result(s, i, fx, fy, fz, cost_of(fS, keff));
     }
     if ((threadIdx.x & (kWave - 1)) == 0) atomicAdd(&l.fb_count[1], (uint32_t)n_need);
   } else if (lead && !keep) {
@@ -438,88 +698,103 @@ __device__ __forceinline__ void learned_group(const SceneDev& s, const SearchDev
 // (unit).  Per layer s the group fuses the confidence-weighted medoid of its
 // lanes' candidates (same fixed order in every lane, so every lane takes the
 // same one), and the fused candidate with the largest view sum (lowest J,
-// first of equals) is the result.
+// first of equals) is the result.  Positions, candidates, the medoid
+// weights, the patch and its score are binary64.
 template <typename T, int P, int KT>
 __device__ __forceinline__ void fpmvo_group(const SceneDev& s, const SearchDev& q,
                                             const FpmvoDev& f, const Group& gr, bool pt_ok,
                                             int64_t j) {
-  constexpr int HP = (P - 1) / 2, kc = HP * P + HP;
   const uint32_t i = pt_ok ? s.perm[j] : 0u;
   const int keff = pt_ok ? (int)s.kcount[j] : 0;
   const bool slot_ok = pt_ok && gr.slot < keff;
   const int view = slot_ok ? (int)s.views[FD_TOPK_SLOTS * j + gr.slot] : 0;
-  const float px = s.pts[3 * (size_t)i], py = s.pts[3 * (size_t)i + 1],
-              pz = s.pts[3 * (size_t)i + 2];
-  ViewPatch<P> vp;
-  build_patch<T, P>(s, q, view, slot_ok, px, py, pz, vp);
-  const float kinv = keff > 0 ? 1.0f / (float)keff : 0.0f;
+  const double px = s.pts[3 * (size_t)i], py = s.pts[3 * (size_t)i + 1],
+               pz = s.pts[3 * (size_t)i + 2];
+  ViewPatch64<P> vp;
+  build_patch64<T, P>(s, q, view, slot_ok, px, py, pz, vp);
 
-  // Eq. (1): orientation of the centre sample, a = C^2/2, b = a cos 2t,
-  // c = 2 a sin 2t; the unit offset (cos t, sin t) with t in (-pi/2, pi/2]
+  // Eq. (1): the orientation t of the centre sample (the bilinear,
+  // confidence-weighted doubled-angle mean at u, recomputed here in binary64:
+  // it places the offset pixel, a discrete choice) and the unit offset
+  // (cos t, sin t), t in (-pi/2, pi/2]; the centre confidence is the medoid
+  // weight of Eq. (6)
   const float* cam = s.cams + 16 * view;
   Proj pr;
-  const bool in_view = slot_ok && project32(cam, px, py, pz, s.W, s.H, q.z_near, pr);
-  const float a0 = vp.a[kc];
-  bool vok = in_view && a0 > 0.0f;
-  const float ia = vok ? 1.0f / a0 : 0.0f;
-  const float c2 = vp.b[kc] * ia, s2 = 0.5f * vp.c[kc] * ia;
-  const float ct = sqrtf(fmaxf(0.5f * (1.0f + c2), 0.0f));
-  const float st = copysignf(sqrtf(fmaxf(0.5f * (1.0f - c2), 0.0f)), s2);
-  const float w = slot_ok ? sqrtf(2.0f * a0) : 0.0f;  // centre confidence
-  const float ux = (in_view ? pr.u : 0.0f) + f.lambda * ct;
-  const float uy = (in_view ? pr.v : 0.0f) + f.lambda * st;
-  vok = vok && ux >= 0.0f && ux <= (float)(s.W - 1) && uy >= 0.0f && uy <= (float)(s.H - 1);
+  const bool in_view = slot_ok && project64(cam, px, py, pz, s.W, s.H, q.z_near, pr);
+  double w = 0.0, ct = 1.0, st = 0.0;
+  bool vok = false;
+  if (in_view) {
+    const size_t plane = (size_t)s.W * s.H;
+    const T* thm = (const T*)s.theta + plane * view;
+    const T* cfm = (const T*)s.conf + plane * view;
+    const double x0 = floor(pr.u), y0 = floor(pr.v);
+    const double fx = pr.u - x0, fy = pr.v - y0;
+    const int ix = (int)x0, iy = (int)y0;
+    double mx = 0.0, my = 0.0;
+    for (int b = 0; b < 2; ++b)
+      for (int a = 0; a < 2; ++a) {
+        const double wt = (a ? fx : 1.0 - fx) * (b ? fy : 1.0 - fy);
+        const double th = tex_load_nb<T>(thm, s.W, s.H, ix + a, iy + b);
+        const double c = tex_load_nb<T>(cfm, s.W, s.H, ix + a, iy + b);
+        w += wt * c;
+        mx += wt * c * cos(2.0 * th);
+        my += wt * c * sin(2.0 * th);
+      }
+    vok = sqrt(mx * mx + my * my) > 0.0;
+    const double t = 0.5 * atan2(my, mx);
+    ct = cos(t);
+    st = sin(t);
+  }
+  const double ux = (in_view ? pr.u : 0.0) + (double)f.lambda * ct;
+  const double uy = (in_view ? pr.v : 0.0) + (double)f.lambda * st;
+  vok = vok && ux >= 0.0 && ux <= (double)(s.W - 1) && uy >= 0.0 && uy <= (double)(s.H - 1);
   // Eq. (2): depth at the nearest texel of the offset pixel
-  float D = 0.0f;
+  double D = 0.0;
   if (vok) {
-    const uint32_t xn = (uint32_t)floorf(ux + 0.5f), yn = (uint32_t)floorf(uy + 0.5f);
+    const uint32_t xn = (uint32_t)floor(ux + 0.5), yn = (uint32_t)floor(uy + 0.5);
     D = ld_texel<T>((const T*)s.depth + (size_t)s.W * s.H * view, yn * (uint32_t)s.W + xn);
   }
   vok = vok && isfinite(D);
-  // Eq. (3): p_s = R^T (X_c - t) with X_c = z_s (bx, by, 1), so
-  // p_s - p = z_s g + h, g = R^T (bx, by, 1), h = -R^T t - p
+  // Eq. (3): p_s = R^T (X_c - t) with X_c = z_s ((ux - cx)/fx, (uy - cy)/fy, 1)
   const float* R = cam + 4;
   const float* tc = cam + 13;
-  const float bx = (ux - cam[2]) / cam[0], by = (uy - cam[3]) / cam[1];
-  const float gx = R[0] * bx + R[3] * by + R[6], gy = R[1] * bx + R[4] * by + R[7],
-              gz = R[2] * bx + R[5] * by + R[8];
-  const float hx = -(R[0] * tc[0] + R[3] * tc[1] + R[6] * tc[2]) - px;
-  const float hy = -(R[1] * tc[0] + R[4] * tc[1] + R[7] * tc[2]) - py;
-  const float hz = -(R[2] * tc[0] + R[5] * tc[1] + R[8] * tc[2]) - pz;
+  const double S1 = f.samples > 1 ? (double)(f.samples - 1) : 1.0;
 
-  float Sb = -INFINITY, bxd = 0.0f, byd = 0.0f, bzd = 0.0f;
+  double Sb = -INFINITY, bxd = 0.0, byd = 0.0, bzd = 0.0;
   for (int sl = 0; sl < f.samples; ++sl) {
-    const float zs = D + (f.samples > 1 ? -f.delta + 2.0f * f.delta * (float)sl /
-                                                        (float)(f.samples - 1)
-                                        : 0.0f);
-    float dx = __builtin_fmaf(zs, gx, hx), dy = __builtin_fmaf(zs, gy, hy),
-          dz = __builtin_fmaf(zs, gz, hz);
-    const float n = sqrtf(dx * dx + dy * dy + dz * dz);
-    const bool ok = vok && zs > 0.0f && n > 0.0f;
+    const double zs =
+        D + (f.samples > 1 ? -(double)f.delta + 2.0 * (double)f.delta * (double)sl / S1 : 0.0);
+    const double xc0 = (ux - (double)cam[2]) * zs / (double)cam[0] - (double)tc[0];
+    const double xc1 = (uy - (double)cam[3]) * zs / (double)cam[1] - (double)tc[1];
+    const double xc2 = zs - (double)tc[2];
+    double dx = (double)R[0] * xc0 + (double)R[3] * xc1 + (double)R[6] * xc2 - px;
+    double dy = (double)R[1] * xc0 + (double)R[4] * xc1 + (double)R[7] * xc2 - py;
+    double dz = (double)R[2] * xc0 + (double)R[5] * xc1 + (double)R[8] * xc2 - pz;
+    const double n = sqrt(dx * dx + dy * dy + dz * dz);
+    const bool ok = vok && zs > 0.0 && n > 0.0;
     // a lane without a candidate shares exact zeros (its depth may be +inf)
-    const float il = ok ? 1.0f / n : 0.0f;
-    dx = ok ? dx * il : 0.0f;
-    dy = ok ? dy * il : 0.0f;
-    dz = ok ? dz * il : 0.0f;
+    dx = ok ? dx / n : 0.0;
+    dy = ok ? dy / n : 0.0;
+    dz = ok ? dz / n : 0.0;
     // Eqs. (5)-(6): weighted consistency of this lane's candidate with the
     // group's candidates of the same layer (views in the order of Eq. (4))
-    const float wk = ok ? w : 0.0f;
-    float num = 0.0f, den = 0.0f;
+    const double wk = ok ? w : 0.0;
+    double num = 0.0, den = 0.0;
     const int K = KT > 0 ? KT : gr.K;
     for (int jj = 0; jj < K; ++jj) {
       const int src = gr.base + jj;
-      const float xj = __shfl(dx, src, kWave), yj = __shfl(dy, src, kWave),
-                  zj = __shfl(dz, src, kWave), wj = __shfl(wk, src, kWave);
+      const double xj = __shfl(dx, src, kWave), yj = __shfl(dy, src, kWave),
+                   zj = __shfl(dz, src, kWave), wj = __shfl(wk, src, kWave);
       // G_ii = 1 exactly for a unit direction
-      num += jj == gr.slot ? wj : wj * fabsf(dx * xj + dy * yj + dz * zj);
+      num += jj == gr.slot ? wj : wj * fabs(dx * xj + dy * yj + dz * zj);
       den += wj;
     }
-    const float sigma = ok ? num / den : -INFINITY;
+    const double sigma = ok ? num / den : -INFINITY;
     // Eq. (7): the medoid, first of equals
     int bj = -1;
-    float bs = -INFINITY;
+    double bs = -INFINITY;
     for (int jj = 0; jj < K; ++jj) {
-      const float sj = __shfl(sigma, gr.base + jj, kWave);
+      const double sj = __shfl(sigma, gr.base + jj, kWave);
       if (sj > bs) {
         bs = sj;
         bj = jj;
@@ -527,10 +802,10 @@ __device__ __forceinline__ void fpmvo_group(const SceneDev& s, const SearchDev& 
     }
     // the same in every lane of the group; the shuffles below run in every lane
     const int src = gr.base + (bj < 0 ? 0 : bj);
-    const float fx = __shfl(dx, src, kWave), fy = __shfl(dy, src, kWave),
-                fz = __shfl(dz, src, kWave);
+    const double fx = __shfl(dx, src, kWave), fy = __shfl(dy, src, kWave),
+                 fz = __shfl(dz, src, kWave);
     // Eq. (12): patch consistency of the fused candidate
-    const float Sv = group_sum_t<KT>(eval_view<P>(vp, fx, fy, fz), gr.base, gr.K);
+    const double Sv = group_sum_t<KT>(eval_patch64<P>(vp, fx, fy, fz), gr.base, gr.K);
     if (bj >= 0 && Sv > Sb) {
       Sb = Sv;
       bxd = fx;
@@ -540,9 +815,9 @@ __device__ __forceinline__ void fpmvo_group(const SceneDev& s, const SearchDev& 
   }
   if (pt_ok && gr.slot == 0) {
     if (keff == 0 || !(Sb > -INFINITY))
-      write_result(s, i, 0.0f, 0.0f, 0.0f, INFINITY);
+      write_result(s, i, 0.0, 0.0, 0.0, INFINITY);
     else
-      write_result(s, i, bxd, byd, bzd, 1.0f - Sb * kinv);
+      write_result(s, i, bxd, byd, bzd, cost_of(Sb, keff));
   }
 }
 

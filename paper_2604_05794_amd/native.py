@@ -33,7 +33,8 @@ EXPORTS = (
     "fd_mlp_loss_grad", "fd_mlp_train_step", "fd_mlp_destroy", "fd_features", "fd_autotune",
     "fd_tuned_shape", "fd_profile_enable", "fd_profile_read", "fd_gabor_params_init",
     "fd_orientation_maps", "fd_fuse_volume", "fd_grow_params_init", "fd_grow_strands",
-    "fd_link_segments", "fd_strand_offsets", "fd_assemble_strands", "fd_last_error",
+    "fd_link_segments", "fd_strand_offsets", "fd_assemble_strands", "fd_probe_read",
+    "fd_last_error",
 )
 
 FD_STAGE_TILING, FD_STAGE_TOPK, FD_STAGE_FUSE, FD_STAGE_FEATURES, FD_STAGE_MLP, \
@@ -163,6 +164,7 @@ def lib():
         "fd_strand_offsets": (ctypes.c_int, [P, i32, P, P, i32, P, P, P, P, P]),
         "fd_assemble_strands": (ctypes.c_int, [P, P, i32, i32, P, P, i32, P, P, i32, i32, P, P,
                                                i64, P, P, P]),
+        "fd_probe_read": (ctypes.c_int, [P, i64, i32, i32, P, P]),
         "fd_last_error": (ctypes.c_char_p, []),
     }
     for name, (res, args) in sig.items():
@@ -690,3 +692,16 @@ def autotune(scenes, ctx: Context, cache_path=None, **kw):
     p = make_params(1, 1, dt, ctx=ctx, **kw)
     _check(lib().fd_autotune(ctx.handle, arr, len(scenes), ctypes.byref(p),
                              os.fsencode(cache_path) if cache_path else None))
+
+
+def probe_read(buf, reps, blocks, sink=None, stream=None):
+    """fd_probe_read: every one of `blocks` workgroups reads the whole device
+    buffer `buf` (a multiple of 16 bytes) `reps` times."""
+    if not buf.is_cuda or not buf.is_contiguous():
+        raise ValueError("buf must be a contiguous device tensor")
+    nbytes = buf.numel() * buf.element_size()
+    if sink is None:
+        sink = torch.empty(int(blocks) * 256, dtype=torch.int32, device=buf.device)
+    _check(lib().fd_probe_read(_ptr(buf), nbytes, int(reps), int(blocks), _ptr(sink),
+                               _stream_handle(stream)))
+    return sink

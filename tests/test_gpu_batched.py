@@ -83,7 +83,7 @@ def test_batched_plain_is_bitwise_per_scene(depth):
     do, co = orc.fuse(sc.points)
     res = compare(orc, sc.points, d["dirs"].cpu().numpy(), d["costs"].cpu().numpy(), do, co)
     print("batched vs oracle", {k: v for k, v in res.items() if not k.endswith("_idx")})
-    assert_parity(res, max_fail_frac=5e-3)
+    assert_parity(res)
 
 
 def test_graph_replay_follows_new_input_values():

@@ -208,13 +208,17 @@ def test_maps_feed_the_direction_search():
     for v in range(frames.shape[0]):
         a, b, _ = oracle.gabor(frames[v], bank)
         th_o[v], cf_o[v] = a, b
+    # the maps: GPU and oracle agree texel by texel up to the binary16
+    # rounding of values on a rounding boundary (the Gabor tests above hold
+    # the exact bar); the search on the GPU's maps is held to the full
+    # parity protocol against the oracle's search on those same maps
+    th_gn, cf_gn = th_g.cpu().numpy(), cf_g.cpu().numpy()
+    assert np.mean(np.abs(cf_gn.astype(np.float32) - cf_o.astype(np.float32)) > 1e-3) < 1e-3
     idx = np.arange(0, sc.n_points, 7)
-    orc = oracle.Oracle(sc.cams, th_o, cf_o, depth=sc.depth.astype(np.float16), patch=3, top_k=5)
+    orc = oracle.Oracle(sc.cams, th_gn, cf_gn, depth=sc.depth.astype(np.float16), patch=3,
+                        top_k=5)
     do, co = orc.fuse(sc.points[idx])
-    res = compare(orc, sc.points[idx], d.cpu().numpy()[idx], c.cpu().numpy()[idx], do, co,
-                  cost_tol=2e-3)
+    res = compare(orc, sc.points[idx], d.cpu().numpy()[idx], c.cpu().numpy()[idx], do, co)
     print("frames->maps->search", {k: v for k, v in res.items() if not k.endswith("_idx")},
           flush=True)
-    # a map texel whose bin or half-rounded confidence differs moves the
-    # objective of every point that samples it: a small share of the points
-    assert_parity(res, max_fail_frac=0.02, max_cost_bad_frac=0.02)
+    assert_parity(res)

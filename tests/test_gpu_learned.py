@@ -282,7 +282,7 @@ def test_given_proposal_parity_with_oracle(tau, depth):
     print("learned tau", tau, "depth", depth, {k: v for k, v in res.items() if not k.endswith("_idx")},
           "fallbacks gpu", n_fb, f"({listed} listed, {in_place} in place)", "oracle",
           int(fb.sum()), flush=True)
-    assert_parity(res, max_fail_frac=5e-3)
+    assert_parity(res)
     # the fallback decision is a threshold on a float cost: equal up to the
     # points whose refined cost lies within rounding of tau
     assert abs(n_fb - int(fb.sum())) <= max(3, 0.002 * sc.n_points)

@@ -99,7 +99,7 @@ def test_parameter_grid(patch, top_k, n_cand, iters):
     do, co = orc.fuse(sc.points)
     res = compare(orc, sc.points, d, c, do, co)
     _log(f"grid P{patch} K{top_k}", res)
-    assert_parity(res, max_fail_frac=5e-3)
+    assert_parity(res)
 
 
 def test_float16_non_square_maps():
@@ -114,7 +114,7 @@ def test_float16_non_square_maps():
     do, co = orc.fuse(sc.points)
     res = compare(orc, sc.points, d, c, do, co)
     _log("f16 non-square", res)
-    assert_parity(res, max_fail_frac=5e-3)
+    assert_parity(res)
 
 
 @pytest.mark.parametrize("n", [1, 2, 11, 12, 13, 47, 48, 49, 61])
