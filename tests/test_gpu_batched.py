@@ -174,3 +174,46 @@ def test_batched_errors():
     assert e.value.code == nat.FD_E_INVAL
     torch.cuda.synchronize()
     assert (devs[0]["dirs"] == 9.0).all()
+
+
+def test_reserve_after_capture_and_a_shared_context():
+    """A captured graph never keeps workspace pointers that a later reserve
+    freed, nor another call's lattice or the learned step it was captured
+    with: after each of these, the batched results still equal the per-scene
+    ones."""
+    nat = _native()
+    scenes = _uneven_scenes()
+    devs = [_dev_scene(s) for s in scenes]
+    total = sum(s.n_points for s in scenes)
+    ctx = nat.Context(max_points=total, max_scenes=len(scenes))
+
+    def check(**kw):
+        for d in devs:
+            d["dirs"].fill_(9.0)
+            d["costs"].fill_(9.0)
+        nat.fuse_batched(devs, ctx, **kw)
+        torch.cuda.synchronize()
+        for d in devs:
+            if d["points"].shape[0] == 0:
+                continue
+            d1, c1 = _single(nat, d, head_centre=d["head_centre"], **kw)
+            torch.cuda.synchronize()
+            assert torch.equal(d1, d["dirs"]) and torch.equal(c1, d["costs"])
+
+    check(**KW)
+    # the per-point buffers move: the next batched call must not replay the
+    # old graph
+    ctx.reserve(4 * total + 1000, max_scenes=len(scenes))
+    check(**KW)
+    # a single-scene call through the same context with another lattice
+    d = devs[2]
+    nat.fuse_directions(d["points"], d["cams"], d["orient_maps"], d["conf_maps"], ctx=ctx,
+                        **dict(KW, n_candidates=128))
+    check(**KW)
+    # the learned form's first step from the network's calibration
+    net = nat.MLP(seed=5)
+    kw = dict(KW, mode=nat.FD_MODE_LEARNED, mlp=net, learned_iters=2, fallback_cost=0.3)
+    net.set_calibration(0.05, 0.3)
+    check(**kw)
+    net.set_calibration(0.2, 0.3)
+    check(**kw)
