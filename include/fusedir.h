@@ -158,6 +158,23 @@ int fd_fuse_directions(const float* points, int64_t n_points,
                        const void* orient_maps, const void* conf_maps,
                        const fd_params* params, float* dirs, float* costs);
 
+/* ---- allocation-free variant ----------------------------------------------
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the plain
+ * mode of fd_fuse_directions, same arguments and results (the same kernels),
+ * with its workspace in a fixed device array that the library holds on each
+ * GPU it runs on until the process ends (under 16 MiB).  It allocates
+ * nothing and ignores params->ctx.  n_points above FD_NOALLOC_MAX_POINTS or a
+ * mode other than FD_MODE_PLAIN returns FD_E_INVAL before anything is
+ * launched.  All calls on one GPU share that array: calls that overlap on
+ * one GPU (several streams or threads) race and must be serialised by the
+ * caller. */
+#define FD_NOALLOC_MAX_POINTS 524288
+int fd_fuse_directions_noalloc(const float* points, int64_t n_points,
+                               const fd_camera* cams, int32_t n_views,
+                               const void* orient_maps, const void* conf_maps,
+                               const fd_params* params, float* dirs, float* costs);
+
 /* Number of points of the last learned call on this context that took the
  * full search (reads a device counter; synchronises params->stream). */
 int fd_last_fallback_count(fd_context* ctx, void* stream, int64_t* out);

@@ -341,11 +341,9 @@ ConstsDev fd::context_consts(fd_context* c) {
 
 // ---- single scene ---------------------------------------------------------------------
 
-extern "C" int fd_fuse_directions(const float* points, int64_t n_points, const fd_camera* cams,
-                                  int32_t n_views, const void* orient_maps,
-                                  const void* conf_maps, const fd_params* params, float* dirs,
-                                  float* costs) {
-  const char* fn = "fd_fuse_directions";
+int fd::check_scene_call(const float* points, int64_t n_points, const fd_camera* cams,
+                         int32_t n_views, const void* orient_maps, const void* conf_maps,
+                         const fd_params* params, float* dirs, float* costs, const char* fn) {
   int r;
   if ((r = check_search_params(params, fn))) return r;
   if (params->mode == FD_MODE_FPMVO && !params->depth_maps)
@@ -364,7 +362,37 @@ extern "C" int fd_fuse_directions(const float* points, int64_t n_points, const f
     return set_error(FD_E_INVAL, "%s: top_k (%d) > n_views (%d)", fn, params->top_k, n_views);
   if (n_points > 0 && (!points || !cams || !orient_maps || !conf_maps || !dirs || !costs))
     return set_error(FD_E_INVAL, "%s: null pointer argument", fn);
-  if ((r = check_device(nullptr))) return r;
+  return check_device(nullptr);
+}
+
+fd::SceneArgs fd::scene_args(const float* points, int64_t n_points, const fd_camera* cams,
+                             int32_t n_views, const void* orient_maps, const void* conf_maps,
+                             const fd_params* params, float* dirs, float* costs) {
+  SceneArgs sa;
+  sa.points = points;
+  sa.n = n_points;
+  sa.cams = (const float*)cams;
+  sa.V = n_views;
+  sa.W = params->width;
+  sa.H = params->height;
+  sa.theta = orient_maps;
+  sa.conf = conf_maps;
+  sa.depth = params->depth_maps;
+  sa.dirs = dirs;
+  sa.costs = costs;
+  for (int k = 0; k < 3; ++k) sa.hc[k] = params->head_centre[k];
+  return sa;
+}
+
+extern "C" int fd_fuse_directions(const float* points, int64_t n_points, const fd_camera* cams,
+                                  int32_t n_views, const void* orient_maps,
+                                  const void* conf_maps, const fd_params* params, float* dirs,
+                                  float* costs) {
+  const char* fn = "fd_fuse_directions";
+  int r;
+  if ((r = check_scene_call(points, n_points, cams, n_views, orient_maps, conf_maps, params,
+                            dirs, costs, fn)))
+    return r;
   if (n_points == 0) return FD_OK;
   int dev = 0;
   (void)hipGetDevice(&dev);
@@ -380,19 +408,8 @@ extern "C" int fd_fuse_directions(const float* points, int64_t n_points, const f
     c = default_context(dev, n_points, &r);
     if (!c) return r;
   }
-  SceneArgs sa;
-  sa.points = points;
-  sa.n = n_points;
-  sa.cams = (const float*)cams;
-  sa.V = n_views;
-  sa.W = params->width;
-  sa.H = params->height;
-  sa.theta = orient_maps;
-  sa.conf = conf_maps;
-  sa.depth = params->depth_maps;
-  sa.dirs = dirs;
-  sa.costs = costs;
-  for (int k = 0; k < 3; ++k) sa.hc[k] = params->head_centre[k];
+  const SceneArgs sa = scene_args(points, n_points, cams, n_views, orient_maps, conf_maps,
+                                  params, dirs, costs);
   return run_scene(c, sa, params, (hipStream_t)params->stream);
 }
 

@@ -143,6 +143,14 @@ int ctx_buffer(void** p, size_t* cap_bytes, size_t bytes, const char* what);
 uint64_t workspace_generation();
 void bump_workspace_generation();
 int run_scene(fd_context* c, const SceneArgs& a, const fd_params* p, hipStream_t st);
+// Argument checks shared by the single-scene entry points (nothing is
+// launched on an error), and the scene they describe.
+int check_scene_call(const float* points, int64_t n_points, const fd_camera* cams,
+                     int32_t n_views, const void* orient_maps, const void* conf_maps,
+                     const fd_params* params, float* dirs, float* costs, const char* fn);
+SceneArgs scene_args(const float* points, int64_t n_points, const fd_camera* cams,
+                     int32_t n_views, const void* orient_maps, const void* conf_maps,
+                     const fd_params* params, float* dirs, float* costs);
 // Records HIP events around one stage when the context profiles.
 struct StageTimer {
   fd_context* c;

@@ -23,10 +23,11 @@ FD_MODE_PLAIN, FD_MODE_LEARNED, FD_MODE_FPMVO = 0, 1, 2
 FD_PROPOSAL_MLP, FD_PROPOSAL_GIVEN, FD_PROPOSAL_NAN = 0, 1, 2
 FD_MLP_N_PARAMS = 161283
 FD_FEATURE_DIM = 112
+FD_NOALLOC_MAX_POINTS = 524288
 
 EXPORTS = (
     "fd_params_init", "fd_context_create", "fd_context_reserve", "fd_context_destroy",
-    "fd_fuse_directions", "fd_last_fallback_count", "fd_last_fallback_split",
+    "fd_fuse_directions", "fd_fuse_directions_noalloc", "fd_last_fallback_count", "fd_last_fallback_split",
     "fd_fuse_directions_batched",
     "fd_mlp_create", "fd_mlp_set_params", "fd_mlp_get_params", "fd_mlp_set_calibration",
     "fd_mlp_get_calibration", "fd_mlp_save", "fd_mlp_load", "fd_mlp_forward",
@@ -132,6 +133,7 @@ def lib():
         "fd_context_reserve": (ctypes.c_int, [P, i64, i32, i32]),
         "fd_context_destroy": (None, [P]),
         "fd_fuse_directions": (ctypes.c_int, [P, i64, P, i32, P, P, pp, P, P]),
+        "fd_fuse_directions_noalloc": (ctypes.c_int, [P, i64, P, i32, P, P, pp, P, P]),
         "fd_last_fallback_count": (ctypes.c_int, [P, P, ctypes.POINTER(i64)]),
         "fd_last_fallback_split": (ctypes.c_int, [P, P, ctypes.POINTER(i64), ctypes.POINTER(i64)]),
         "fd_fuse_directions_batched": (ctypes.c_int, [ctypes.POINTER(Scene), i32, pp, P]),
@@ -309,14 +311,16 @@ def _check_depth(depth, orient_maps):
 
 
 def fuse_directions(points, cams, orient_maps, conf_maps, *, dirs=None, costs=None,
-                    **kw):
+                    noalloc=False, **kw):
     """fd_fuse_directions on torch tensors.
 
     points (N, 3) float32, cams (V, 16) float32, maps (V, H, W) float16 or
     float32 (same dtype), all on the current HIP device.  Keyword arguments
     are the fields of fd_params (see make_params).  Returns (dirs (N, 3),
     costs (N,)) float32, enqueued on `stream` (default: torch's current
-    stream).
+    stream).  noalloc=True calls fd_fuse_directions_noalloc instead (plain
+    mode, at most FD_NOALLOC_MAX_POINTS points; pass dirs and costs to
+    allocate nothing here either).
     """
     _dev_tensor(points, "points", torch.float32, (3,))
     _dev_tensor(cams, "cams", torch.float32, (16,))
@@ -336,8 +340,9 @@ def fuse_directions(points, cams, orient_maps, conf_maps, *, dirs=None, costs=No
     _dev_tensor(costs, "costs", torch.float32)
     _check_depth(kw.get("depth_maps"), orient_maps)
     p = make_params(W, H, map_dtype_of(orient_maps), **kw)
-    _check(lib().fd_fuse_directions(_ptr(points), n, _ptr(cams), V, _ptr(orient_maps),
-                                    _ptr(conf_maps), ctypes.byref(p), _ptr(dirs), _ptr(costs)))
+    fn = lib().fd_fuse_directions_noalloc if noalloc else lib().fd_fuse_directions
+    _check(fn(_ptr(points), n, _ptr(cams), V, _ptr(orient_maps), _ptr(conf_maps),
+              ctypes.byref(p), _ptr(dirs), _ptr(costs)))
     return dirs, costs
 
 
