@@ -344,7 +344,8 @@ def run_metric(args):
             f"({time.perf_counter() - t:.1f} s)")
     n = sum(sc.n_points for sc, _ in heads)
     stream = torch.cuda.current_stream()
-    ctx = native.Context(max_points=n, max_scenes=len(heads))
+    ctx = native.Context(max_points=n, max_views=sum(sc.n_views for sc, _ in heads),
+                         max_scenes=len(heads))
     net = native.MLP(path=args.mlp)
     step0, tau = net.calibration()
     lkw = dict(mode=native.FD_MODE_LEARNED, mlp=net, learned_iters=2, learned_step0=step0,

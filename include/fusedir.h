@@ -123,9 +123,13 @@ typedef struct fd_params {
 void fd_params_init(fd_params* params);
 
 /* ---- context: library-owned workspace ------------------------------------
- * create: allocates the small fixed buffers on the current device.
- * reserve: grows the per-point buffers to max_points points (and the scene
- * table to max_scenes); it is the only call after create that allocates.
+ * create: allocates the small fixed buffers on the current device (and a
+ * camera table for 1024 views).
+ * reserve: grows the per-point buffers to max_points points, the camera
+ * table to max_views views (for one call, or the sum over the scenes of a
+ * batched call) and the scene table to max_scenes; it is the only call
+ * after create that allocates.  A call through a context with more views
+ * than it holds returns FD_E_NOMEM.
  * A context is bound to the device current at create and must be used from
  * one stream at a time.  destroy: frees everything (synchronises the
  * device). */
@@ -164,12 +168,13 @@ int fd_fuse_directions(const float* points, int64_t n_points,
  * mode of fd_fuse_directions, same arguments and results (the same kernels),
  * with its workspace in a fixed device array that the library holds on each
  * GPU it runs on until the process ends (under 16 MiB).  It allocates
- * nothing and ignores params->ctx.  n_points above FD_NOALLOC_MAX_POINTS or a
- * mode other than FD_MODE_PLAIN returns FD_E_INVAL before anything is
- * launched.  All calls on one GPU share that array: calls that overlap on
+ * nothing and ignores params->ctx.  n_points above FD_NOALLOC_MAX_POINTS,
+ * n_views above FD_NOALLOC_MAX_VIEWS or a mode other than FD_MODE_PLAIN
+ * returns FD_E_INVAL before anything is launched.  All calls on one GPU share that array: calls that overlap on
  * one GPU (several streams or threads) race and must be serialised by the
  * caller. */
 #define FD_NOALLOC_MAX_POINTS 524288
+#define FD_NOALLOC_MAX_VIEWS 1024
 int fd_fuse_directions_noalloc(const float* points, int64_t n_points,
                                const fd_camera* cams, int32_t n_views,
                                const void* orient_maps, const void* conf_maps,
@@ -208,6 +213,10 @@ typedef struct fd_scene {
   float* dirs;
   float* costs;
   float head_centre[3];
+  /* learned mode with params->proposal == FD_PROPOSAL_GIVEN: device,
+   * n_points x 3 float proposals in point order (a row that is not a finite
+   * non-zero direction falls back); otherwise ignored (may be NULL) */
+  const float* proposal_dirs;
 } fd_scene;
 
 int fd_fuse_directions_batched(const fd_scene* scenes, int32_t n_scenes,

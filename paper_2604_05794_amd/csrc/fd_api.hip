@@ -104,6 +104,11 @@ int fd::context_reserve_points(fd_context* c, int64_t n) {
   return FD_OK;
 }
 
+int fd::context_reserve_views(fd_context* c, int64_t views) {
+  const size_t need = (size_t)kCam64 * (size_t)(views > 1 ? views : 1);
+  return grow(&c->cams64, &c->cap_cams64, need, "camera table");
+}
+
 extern "C" int fd_context_create(fd_context** out) {
   if (!out) return set_error(FD_E_INVAL, "fd_context_create: out is NULL");
   int dev, r;
@@ -122,7 +127,7 @@ extern "C" int fd_context_create(fd_context** out) {
     fd_context_destroy(c);
     return r;
   }
-  if ((r = context_reserve_points(c, 1))) {
+  if ((r = context_reserve_points(c, 1)) || (r = context_reserve_views(c, 1024))) {
     fd_context_destroy(c);
     return r;
   }
@@ -137,6 +142,7 @@ extern "C" int fd_context_reserve(fd_context* c, int64_t max_points, int32_t max
     return set_error(FD_E_INVAL, "fd_context_reserve: negative size");
   int r;
   if ((r = context_reserve_points(c, max_points))) return r;
+  if ((r = context_reserve_views(c, max_views))) return r;
   if ((r = context_reserve_scenes(c, max_scenes, max_points))) return r;
   return FD_OK;
 }
@@ -145,6 +151,7 @@ extern "C" void fd_context_destroy(fd_context* c) {
   if (!c) return;
   (void)hipDeviceSynchronize();
   void* bufs[] = {c->bbox, c->counts, c->cursor, c->scan_sums, c->lattice, c->consts64,
+                  c->cams64,
                   c->fb_count, c->key,
                   c->perm, c->views, c->kcount, c->fb_list, c->prop, c->feats,
                   c->scene_tab, c->tile_tab, c->tile_queue, c->batch_key, c->batch_perm,
@@ -166,7 +173,7 @@ extern "C" void fd_context_destroy(fd_context* c) {
 
 // Per-device default context, grown on demand (so calls through it may
 // allocate; pass params->ctx for allocation-free calls).
-fd_context* fd::default_context(int dev, int64_t n, int* err) {
+fd_context* fd::default_context(int dev, int64_t n, int* err, int64_t views) {
   static std::mutex mu;
   static std::map<int, fd_context*> ctxs;
   std::lock_guard<std::mutex> lk(mu);
@@ -179,6 +186,9 @@ fd_context* fd::default_context(int dev, int64_t n, int* err) {
   }
   if (c->max_points < n) {
     if ((*err = context_reserve_points(c, n))) return nullptr;
+  }
+  if ((int64_t)(c->cap_cams64 / kCam64) < views) {
+    if ((*err = context_reserve_views(c, views))) return nullptr;
   }
   *err = FD_OK;
   return c;
@@ -272,7 +282,7 @@ extern "C" void fd_params_init(fd_params* p) {
   p->ctx = nullptr;
 }
 
-int fd::check_search_params(const fd_params* p, const char* fn) {
+int fd::check_search_params(const fd_params* p, const char* fn, bool batched) {
   if (!p) return set_error(FD_E_INVAL, "%s: params is NULL", fn);
   if (p->map_dtype != FD_F32 && p->map_dtype != FD_F16)
     return set_error(FD_E_INVAL, "%s: unknown map_dtype %d", fn, p->map_dtype);
@@ -308,7 +318,7 @@ int fd::check_search_params(const fd_params* p, const char* fn) {
       return set_error(FD_E_INVAL, "%s: learned_iters must be in [0, %d]", fn, FD_MAX_REFINE);
     if (p->proposal == FD_PROPOSAL_MLP && !p->mlp)
       return set_error(FD_E_INVAL, "%s: learned mode with the network proposal needs mlp", fn);
-    if (p->proposal == FD_PROPOSAL_GIVEN && !p->proposal_dirs)
+    if (p->proposal == FD_PROPOSAL_GIVEN && !p->proposal_dirs && !batched)
       return set_error(FD_E_INVAL, "%s: FD_PROPOSAL_GIVEN needs proposal_dirs", fn);
     if (p->proposal < FD_PROPOSAL_MLP || p->proposal > FD_PROPOSAL_NAN)
       return set_error(FD_E_INVAL, "%s: unknown proposal %d", fn, p->proposal);
@@ -404,8 +414,12 @@ extern "C" int fd_fuse_directions(const float* points, int64_t n_points, const f
     if (c->max_points < n_points)
       return set_error(FD_E_NOMEM, "%s: context reserved for %lld points, call has %lld", fn,
                        (long long)c->max_points, (long long)n_points);
+    if ((int64_t)(c->cap_cams64 / kCam64) < n_views)
+      return set_error(FD_E_NOMEM, "%s: context reserved for %lld views, call has %d "
+                       "(fd_context_reserve max_views)", fn,
+                       (long long)(c->cap_cams64 / kCam64), n_views);
   } else {
-    c = default_context(dev, n_points, &r);
+    c = default_context(dev, n_points, &r, n_views);
     if (!c) return r;
   }
   const SceneArgs sa = scene_args(points, n_points, cams, n_views, orient_maps, conf_maps,
@@ -425,6 +439,7 @@ int fd::run_scene(fd_context* c, const SceneArgs& a, const fd_params* p, hipStre
   if (e != hipSuccess) return hip_error(e, "tiling kernels");
   t_tile.stop();
   SceneDev s;
+  s.prop = nullptr;
   s.pts = a.points;
   s.cams = a.cams;
   s.theta = a.theta;
@@ -442,6 +457,9 @@ int fd::run_scene(fd_context* c, const SceneArgs& a, const fd_params* p, hipStre
   s.H = a.H;
   for (int k = 0; k < 3; ++k) s.hc[k] = a.hc[k];
   const SearchDev q = make_search(kc, p->n_candidates, p->refine_iters, p->top_k, p->z_near);
+  if ((e = launch_cams64(a.cams, a.V, c->cams64, st)) != hipSuccess)
+    return hip_error(e, "camera table");
+  s.cam64 = c->cams64;
   const bool fused_topk = p->mode == FD_MODE_LEARNED && p->proposal == FD_PROPOSAL_MLP;
   if (!fused_topk) {  // the learned network path selects views with its features
     StageTimer t_topk(c, FD_STAGE_TOPK, st);

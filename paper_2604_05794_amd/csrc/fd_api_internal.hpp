@@ -23,6 +23,8 @@ struct fd_context {
   uint32_t* scan_sums = nullptr;
   float* lattice = nullptr;   // search constants (ConstsDev): binary32 lattice
   double* consts64 = nullptr; // binary64 lattice, step tables, stencil
+  double* cams64 = nullptr;   // binary64 camera table, kCam64 per view
+  size_t cap_cams64 = 0;      // doubles
   uint32_t* fb_count = nullptr;
   // per-point buffers
   uint32_t* key = nullptr;
@@ -127,15 +129,18 @@ struct SceneArgs {
 int set_error(int code, const char* fmt, ...);
 int hip_error(hipError_t e, const char* what);
 int check_device(int* dev_out);
-int check_search_params(const fd_params* p, const char* fn);
+// batched: the proposals of FD_PROPOSAL_GIVEN come with the scenes
+int check_search_params(const fd_params* p, const char* fn, bool batched = false);
 double default_step0(int n_candidates);
 // First step of the plain refinement and of the learned form's short
 // refinement (parameter, else the network's calibration, else the default).
 void resolve_steps(const fd_params* p, double* step0, double* lstep0);
 ConstsDev context_consts(fd_context* c);
 int context_reserve_points(fd_context* c, int64_t n);
+// Grows the binary64 camera table to at least `views` views.
+int context_reserve_views(fd_context* c, int64_t views);
 int context_reserve_scenes(fd_context* c, int32_t n_scenes, int64_t total_points);
-fd_context* default_context(int dev, int64_t n, int* err);
+fd_context* default_context(int dev, int64_t n, int* err, int64_t views = 1);
 // Grows a context-owned device buffer to at least `bytes` (no-op if large
 // enough; the old contents are not kept).
 int ctx_buffer(void** p, size_t* cap_bytes, size_t bytes, const char* what);

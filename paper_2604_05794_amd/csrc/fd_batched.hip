@@ -5,10 +5,11 @@
 // per scene, its per-point workspace pointers offset to the scene's range)
 // lets every kernel find its scene: per-point kernels from a block table
 // (blocks never straddle scenes), the search kernels by a binary search of
-// the point offsets per lane group.  The plain search and the fallback search
-// are persistent: a grid sized to what stays resident pops tiles of points
-// from one atomic queue until it is empty, so uneven scenes balance across
-// the compute units.  The sequence (tiling, view selection, [features,
+// the point offsets per lane group.  The searches (plain, learned, fallback)
+// have a persistent form: a grid sized to what stays resident pops tiles of
+// points from XCD-blocked atomic queues until they are empty, so uneven
+// scenes balance across the compute units; the autotuner picks it or one
+// wave per tile.  The sequence (tiling, view selection, [features,
 // network, refinement,] search) is captured once into a HIP graph and
 // replayed while the scene set and the parameters stay the same.  Every
 // point runs the same per-point code as a single-scene call, so results are
@@ -297,14 +298,53 @@ void k_b_learned(BatchDev b, SearchDev q, LearnedDev l) {
   b_learned_body<T, P, KT>(b, q, l);
 }
 
+// Persistent form of the learned search: the same per-tile work as
+// k_b_learned, tiles popped from the XCD-blocked queues as in k_b_fuse.
+template <typename T, int P, int KT>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(search_waves(P))))
+void k_b_learned_q(BatchDev b, SearchDev q, LearnedDev l, uint32_t* __restrict__ queue,
+                   int chunk) {
+  const Group gr = make_group(q.K);
+  const int64_t n_tiles = b.n_tiles;
+  if (n_tiles <= 0) return;
+  const int home = (int)(blockIdx.x % kQueues);
+  for (int r = 0; r < kQueues; ++r) {
+    const int qi = (home + r) % kQueues;
+    if (queue_tile(qi, (int64_t)__builtin_amdgcn_readfirstlane(
+                           __atomic_load_n(&queue[qi], __ATOMIC_RELAXED))) >= n_tiles)
+      continue;
+    for (;;) {
+      uint32_t v0 = 0;
+      if ((threadIdx.x & 63) == 0) v0 = atomicAdd(&queue[qi], (uint32_t)chunk);
+      v0 = __builtin_amdgcn_readfirstlane(v0);
+      if (queue_tile(qi, v0) >= n_tiles) break;  // tiles of a queue only increase
+      for (int c = 0; c < chunk; ++c) {
+        const int64_t tile = queue_tile(qi, (int64_t)v0 + c);
+        if (tile >= n_tiles) break;  // uniform
+        const int s = find_scene(b.tile_off, b.n_scenes, tile);
+        const SceneDev sc = load_scene(b.tab, s);
+        const int64_t j = (tile - b.tile_off[s]) * gr.G + gr.g;
+        const bool pt_ok = gr.lane_ok && j < sc.n;
+        learned_group<T, P, KT>(sc, q, l, gr, pt_ok, pt_ok ? j : 0, 1, b.pt_off[s],
+                                b.pt_off[s]);
+      }
+    }
+  }
+}
+
 template <typename T, int P, int KT>
 hipError_t launch_b_search(const BatchDev& b, const SearchDev& q, const LearnedDev* l,
                            const uint32_t* list, const uint32_t* count, uint32_t* queue,
                            int chunk, int grid, hipStream_t st) {
   if (l) {
-    const int64_t nb = (b.n_tiles + 3) / 4;  // 4 waves per block
-    hipLaunchKernelGGL((k_b_learned<T, P, KT>), dim3((unsigned)nb), dim3(kBlock), 0, st, b, q,
-                       *l);
+    if (grid > 0) {
+      hipLaunchKernelGGL((k_b_learned_q<T, P, KT>), dim3(grid), dim3(kBlock), 0, st, b, q, *l,
+                         queue, chunk);
+    } else {
+      const int64_t nb = (b.n_tiles + 3) / 4;  // 4 waves per block
+      hipLaunchKernelGGL((k_b_learned<T, P, KT>), dim3((unsigned)nb), dim3(kBlock), 0, st, b,
+                         q, *l);
+    }
   } else {
     if (list)
       hipLaunchKernelGGL((k_b_fuse<T, P, KT, true>), dim3(grid), dim3(kBlock), 0, st, b, q, list,
@@ -410,7 +450,8 @@ int fd::context_reserve_scenes(fd_context* c, int32_t n_scenes, int64_t total_po
 // ---- the batched call --------------------------------------------------------------------
 
 static int record_batch(fd_context* c, const fd_params* p, int n_scenes, int64_t total,
-                        const int64_t* blk_off_host, int64_t n_tiles, hipStream_t st) {
+                        const int64_t* blk_off_host, int64_t n_tiles, const float* const* cams,
+                        const int* views, const int64_t* view_off, hipStream_t st) {
   SceneDev* tab = (SceneDev*)c->scene_tab;
   int64_t* pt_off = (int64_t*)(tab + FD_MAX_BATCH_SCENES);
   int64_t* blk_off = pt_off + (FD_MAX_BATCH_SCENES + 1);
@@ -422,6 +463,11 @@ static int record_batch(fd_context* c, const fd_params* p, int n_scenes, int64_t
   uint32_t* sums = c->batch_perm + FD_MAX_BATCH_SCENES * kBCells;
   int* bbox = (int*)c->tile_tab;
   hipError_t e;
+  // binary64 camera tables of every scene
+  for (int s = 0; s < n_scenes; ++s)
+    if ((e = launch_cams64(cams[s], views[s], c->cams64 + (size_t)kCam64 * view_off[s], st)) !=
+        hipSuccess)
+      return hip_error(e, "camera tables");
   // tiling
   StageTimer t_tile(c, FD_STAGE_TILING, st);
   int* rep = bbox + 6 * FD_MAX_BATCH_SCENES;
@@ -442,7 +488,8 @@ static int record_batch(fd_context* c, const fd_params* p, int n_scenes, int64_t
   if ((e = launch_consts(kc, p->n_candidates, step0, lstep0, st)) != hipSuccess)
     return hip_error(e, "search constants");
   const SearchDev q = make_search(kc, p->n_candidates, p->refine_iters, p->top_k, p->z_near);
-  if (p->mode == FD_MODE_PLAIN) {  // the learned form selects views with its features
+  const bool net = p->mode == FD_MODE_LEARNED && p->proposal == FD_PROPOSAL_MLP;
+  if (!net) {  // the network path selects views together with its features
     StageTimer t_topk(c, FD_STAGE_TOPK, st);
     const dim3 grid((unsigned)nblocks), block(kBlock);
     const bool k5 = q.K <= 5;  // a list of 5 slots holds any top-K with K <= 5
@@ -484,37 +531,46 @@ static int record_batch(fd_context* c, const fd_params* p, int n_scenes, int64_t
   l.tau = (double)p->fallback_cost;
   l.fb_list = c->fb_list;
   l.fb_count = c->fb_count;
-  {
-    StageTimer t_feat(c, FD_STAGE_FEATURES, st);
-    const dim3 grid((unsigned)nblocks), block(kBlock);
-    const bool k5 = q.K <= 5;
-    if (p->map_dtype == FD_F16) {
-      if (k5)
-        hipLaunchKernelGGL((k_b_topk_features<__half, 5>), grid, block, 0, st, b, q, c->feats);
-      else
-        hipLaunchKernelGGL((k_b_topk_features<__half, FD_TOPK_SLOTS>), grid, block, 0, st, b, q,
-                           c->feats);
-    } else {
-      if (k5)
-        hipLaunchKernelGGL((k_b_topk_features<float, 5>), grid, block, 0, st, b, q, c->feats);
-      else
-        hipLaunchKernelGGL((k_b_topk_features<float, FD_TOPK_SLOTS>), grid, block, 0, st, b, q,
-                           c->feats);
+  if (net) {
+    {
+      StageTimer t_feat(c, FD_STAGE_FEATURES, st);
+      const dim3 grid((unsigned)nblocks), block(kBlock);
+      const bool k5 = q.K <= 5;
+      if (p->map_dtype == FD_F16) {
+        if (k5)
+          hipLaunchKernelGGL((k_b_topk_features<__half, 5>), grid, block, 0, st, b, q, c->feats);
+        else
+          hipLaunchKernelGGL((k_b_topk_features<__half, FD_TOPK_SLOTS>), grid, block, 0, st, b,
+                             q, c->feats);
+      } else {
+        if (k5)
+          hipLaunchKernelGGL((k_b_topk_features<float, 5>), grid, block, 0, st, b, q, c->feats);
+        else
+          hipLaunchKernelGGL((k_b_topk_features<float, FD_TOPK_SLOTS>), grid, block, 0, st, b,
+                             q, c->feats);
+      }
+      if ((e = hipGetLastError()) != hipSuccess)
+        return hip_error(e, "batched view selection + features");
+      t_feat.stop();
     }
-    if ((e = hipGetLastError()) != hipSuccess)
-      return hip_error(e, "batched view selection + features");
-    t_feat.stop();
+    StageTimer t_mlp(c, FD_STAGE_MLP, st);
+    int r = mlp_forward_dev(p->mlp, c->feats, total, c->prop, st);
+    if (r) return r;
+    t_mlp.stop();
+    l.proposals = c->prop;
+  } else {
+    // given proposals are read from each scene's own array (SceneDev::prop);
+    // FD_PROPOSAL_NAN leaves that NULL, so every point falls back
+    l.proposals = nullptr;
   }
-  StageTimer t_mlp(c, FD_STAGE_MLP, st);
-  int r = mlp_forward_dev(p->mlp, c->feats, total, c->prop, st);
-  if (r) return r;
-  t_mlp.stop();
-  l.proposals = c->prop;
   if ((e = launch_fill_u32(c->fb_count, 2, 0u, st)) != hipSuccess)
     return hip_error(e, "fallback counter reset");
+  if ((e = launch_fill_u32(queue, kQueues, 0u, st)) != hipSuccess)
+    return hip_error(e, "queue reset");
   StageTimer t_ref(c, FD_STAGE_REFINE, st);
-  if ((e = search(p->map_dtype, p->patch, b, q, &l, nullptr, nullptr, queue, chunk, grid, st)) !=
-      hipSuccess)
+  // tuned_grid < 0: one wave per tile, else the persistent queue
+  if ((e = search(p->map_dtype, p->patch, b, q, &l, nullptr, nullptr, queue, chunk, plain_grid,
+                  st)) != hipSuccess)
     return hip_error(e, "batched learned refinement");
   t_ref.stop();
   if ((e = launch_fill_u32(queue, kQueues, 0u, st)) != hipSuccess)
@@ -531,7 +587,7 @@ extern "C" int fd_fuse_directions_batched(const fd_scene* scenes, int32_t n_scen
                                           const fd_params* params, fd_context* ctx) {
   const char* fn = "fd_fuse_directions_batched";
   int r;
-  if ((r = check_search_params(params, fn))) return r;
+  if ((r = check_search_params(params, fn, true))) return r;
   if (!ctx) return set_error(FD_E_INVAL, "%s: a context is required", fn);
   if (n_scenes < 0 || (n_scenes > 0 && !scenes))
     return set_error(FD_E_INVAL, "%s: bad scene array", fn);
@@ -540,12 +596,17 @@ extern "C" int fd_fuse_directions_batched(const fd_scene* scenes, int32_t n_scen
                      FD_MAX_BATCH_SCENES, n_scenes);
   if (params->mode == FD_MODE_FPMVO)
     return set_error(FD_E_INVAL, "%s: FD_MODE_FPMVO is not batched", fn);
-  if (params->proposal != FD_PROPOSAL_MLP && params->mode == FD_MODE_LEARNED)
-    return set_error(FD_E_INVAL, "%s: the batched learned form takes the network proposal", fn);
+  if (params->mode == FD_MODE_LEARNED && params->proposal == FD_PROPOSAL_GIVEN)
+    for (int s = 0; s < n_scenes; ++s)
+      if (scenes[s].n_points > 0 && !scenes[s].proposal_dirs)
+        return set_error(FD_E_INVAL, "%s: FD_PROPOSAL_GIVEN needs proposal_dirs in scene %d",
+                         fn, s);
   int64_t total = 0;
   const int G = 64 / params->top_k;  // points per search tile (one wave)
   std::vector<int64_t> pt_off(n_scenes + 1, 0), blk_off(n_scenes + 1, 0),
-      tile_off(n_scenes + 1, 0);
+      tile_off(n_scenes + 1, 0), view_off(n_scenes + 1, 0);
+  std::vector<const float*> cam_ptrs(n_scenes);
+  std::vector<int> n_views(n_scenes);
   for (int s = 0; s < n_scenes; ++s) {
     const fd_scene& sc = scenes[s];
     if (sc.n_points < 0) return set_error(FD_E_INVAL, "%s: scene %d has n_points < 0", fn, s);
@@ -562,6 +623,9 @@ extern "C" int fd_fuse_directions_batched(const fd_scene* scenes, int32_t n_scen
     pt_off[s + 1] = total;
     blk_off[s + 1] = blk_off[s] + (sc.n_points + kBlock - 1) / kBlock;
     tile_off[s + 1] = tile_off[s] + (sc.n_points + G - 1) / G;
+    view_off[s + 1] = view_off[s] + sc.n_views;
+    cam_ptrs[s] = (const float*)sc.cams;
+    n_views[s] = sc.n_views;
   }
   if (total > (int64_t)UINT32_MAX) return set_error(FD_E_INVAL, "%s: too many points", fn);
   if ((r = check_device(nullptr))) return r;
@@ -573,6 +637,10 @@ extern "C" int fd_fuse_directions_batched(const fd_scene* scenes, int32_t n_scen
   if (ctx->max_points < total)
     return set_error(FD_E_NOMEM, "%s: context reserved for %lld points, call has %lld", fn,
                      (long long)ctx->max_points, (long long)total);
+  if ((int64_t)(ctx->cap_cams64 / kCam64) < view_off[n_scenes])
+    return set_error(FD_E_NOMEM, "%s: context reserved for %lld views, the scenes have %lld "
+                     "(fd_context_reserve max_views)", fn,
+                     (long long)(ctx->cap_cams64 / kCam64), (long long)view_off[n_scenes]);
   if (ctx->max_scenes < n_scenes || !ctx->scene_tab)
     return set_error(FD_E_NOMEM, "%s: context has no batched workspace (fd_context_reserve "
                      "with max_scenes)", fn);
@@ -604,6 +672,10 @@ extern "C" int fd_fuse_directions_batched(const fd_scene* scenes, int32_t n_scen
       d.theta = sc.orient_maps;
       d.conf = sc.conf_maps;
       d.depth = sc.depth_maps;
+      d.cam64 = ctx->cams64 + (size_t)kCam64 * view_off[s];
+      d.prop = (params->mode == FD_MODE_LEARNED && params->proposal == FD_PROPOSAL_GIVEN)
+                   ? sc.proposal_dirs
+                   : nullptr;
       d.vis_tau = params->vis_tau;
       d.dirs = sc.dirs;
       d.costs = sc.costs;
@@ -633,7 +705,8 @@ extern "C" int fd_fuse_directions_batched(const fd_scene* scenes, int32_t n_scen
   if (ctx->profiling) {
     // stage timing: the same kernels launched directly, with events between
     // the stages (a graph would hold no event records)
-    r = record_batch(ctx, params, n_scenes, total, blk_off.data(), tile_off[n_scenes], st);
+    r = record_batch(ctx, params, n_scenes, total, blk_off.data(), tile_off[n_scenes],
+                     cam_ptrs.data(), n_views.data(), view_off.data(), st);
     if (r) return r;
     tb.stop();
     return FD_OK;
@@ -652,7 +725,7 @@ extern "C" int fd_fuse_directions_batched(const fd_scene* scenes, int32_t n_scen
     e = hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess) return hip_error(e, "hipStreamBeginCapture");
     r = record_batch(ctx, params, n_scenes, total, blk_off.data(), tile_off[n_scenes],
-                     ctx->cap_stream);
+                     cam_ptrs.data(), n_views.data(), view_off.data(), ctx->cap_stream);
     hipGraph_t g = nullptr;
     e = hipStreamEndCapture(ctx->cap_stream, &g);
     if (r) {

@@ -28,16 +28,36 @@ __device__ __forceinline__ float tex_load_nb(const T* __restrict__ m, int W, int
   return in ? v : 0.0f;
 }
 
+// binary64 reciprocal and reciprocal square root of finite positive x:
+// the hardware estimate refined by two Newton steps (error within an ulp or
+// two of the rounded result; the search compares such values only against
+// each other, never bit for bit with another implementation).
+__device__ __forceinline__ double rcp64(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  double e = __builtin_fma(-x, r, 1.0);
+  r = __builtin_fma(r, e, r);
+  e = __builtin_fma(-x, r, 1.0);
+  return __builtin_fma(r, e, r);
+}
+
+__device__ __forceinline__ double rsq64(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  const double h = 0.5 * x;
+  double e = __builtin_fma(-h * y, y, 0.5);
+  y = __builtin_fma(y, e, y);
+  e = __builtin_fma(-h * y, y, 0.5);
+  return __builtin_fma(y, e, y);
+}
+
 // Projection, eligibility and the Eq. (4) ranking score, in binary64.
 // The calibrated pinhole model of Sec. 3.1: X_c = R p + t, pixel
 // u = (f_x X/Z + c_x, f_y Y/Z + c_y).  Every discrete choice of the view
 // selection (in front, inside the image, visible, centre confidence above
 // zero, the ranking) is taken on binary64 values computed from the binary32
-// and binary16 inputs (which convert exactly), with one rounding per
-// operation in the order written below (the library is built without
-// floating-point contraction, and binary64 division and square root are
-// IEEE), so each choice is the exact mathematical one up to binary64
-// rounding:
+// and binary16 inputs (which convert exactly), so each choice is the exact
+// mathematical one up to binary64 rounding.  project64 evaluates, one
+// rounding per operation in the order written (the library is built without
+// floating-point contraction; binary64 division is IEEE):
 //   X = ((R0 px + R1 py) + R2 pz) + t0   (likewise Y, Z)
 //   front: Z > z_near;  u = fx (X / Z) + cx,  v = fy (Y / Z) + cy
 //   inside: 0 <= u <= W-1 and 0 <= v <= H-1
@@ -59,6 +79,27 @@ __device__ __forceinline__ bool project64(const float* __restrict__ cam, double 
   return o.u >= 0.0 && o.u <= (double)(W - 1) && o.v >= 0.0 && o.v <= (double)(H - 1);
 }
 
+// The same projection from the per-call binary64 camera table (kCam64
+// values per view: u = row0 . (p, 1) / Z, v = row1 . (p, 1) / Z with
+// Z = row2 . (p, 1)), for the loops over every view of a point: nine fma
+// and one reciprocal instead of the camera's own rows and two divisions.
+// It agrees with project64 up to binary64 rounding (a few ulp of u).
+struct ProjT {
+  double Z, u, v;
+};
+
+__device__ __forceinline__ bool project_tab(const double* __restrict__ c, double px, double py,
+                                            double pz, int W, int H, double z_near, ProjT& o) {
+  o.Z = __builtin_fma(c[8], px, __builtin_fma(c[9], py, __builtin_fma(c[10], pz, c[11])));
+  const double nu = __builtin_fma(c[0], px, __builtin_fma(c[1], py, __builtin_fma(c[2], pz, c[3])));
+  const double nv = __builtin_fma(c[4], px, __builtin_fma(c[5], py, __builtin_fma(c[6], pz, c[7])));
+  const bool front = o.Z > z_near;
+  const double iz = rcp64(front ? o.Z : 1.0);
+  o.u = nu * iz;
+  o.v = nv * iz;
+  return front && o.u >= 0.0 && o.u <= (double)(W - 1) && o.v >= 0.0 && o.v <= (double)(H - 1);
+}
+
 // Texel at a 32-bit offset from a view's base pointer (the base is the same
 // for the whole wave, so the load takes a scalar base and a vector offset).
 template <typename T>
@@ -78,9 +119,9 @@ __device__ __forceinline__ float ld_texel(const T* __restrict__ base, uint32_t o
 // No depth maps: every eligible view is visible.  A +inf (background) or
 // NaN depth never is.  `ok` (the view is eligible) guards the texel read:
 // an eligible projection lies inside the image.
-template <typename T>
+template <typename T, typename PR>
 __device__ __forceinline__ bool visible_at(const T* __restrict__ db, int W, bool ok,
-                                           const Proj& pr, double tau) {
+                                           const PR& pr, double tau) {
   if (db == nullptr) return ok;
   const double u = ok ? pr.u : 0.0, v = ok ? pr.v : 0.0;
   const uint32_t xn = (uint32_t)floor(u + 0.5), yn = (uint32_t)floor(v + 0.5);
@@ -101,9 +142,9 @@ struct ConfTexels {
   bool xin, yin;
 };
 
-template <typename T>
+template <typename T, typename PR>
 __device__ __forceinline__ ConfTexels conf_texels(const T* __restrict__ cb, int W, int H,
-                                                     bool ok, const Proj& pr) {
+                                                     bool ok, const PR& pr) {
   ConfTexels t;
   const double u = ok ? pr.u : 0.0, v = ok ? pr.v : 0.0;
   const double x0 = floor(u), y0 = floor(v);
@@ -129,25 +170,28 @@ __device__ __forceinline__ double conf_combine(const ConfTexels& t) {
          (1.0 - t.fx) * t.fy * c01 + t.fx * t.fy * c11;
 }
 
-// binary64 reciprocal and reciprocal square root of finite positive x:
-// the hardware estimate refined by two Newton steps (error within an ulp or
-// two of the rounded result; the search compares such values only against
-// each other, never bit for bit with another implementation).
-__device__ __forceinline__ double rcp64(double x) {
-  double r = __builtin_amdgcn_rcp(x);
-  double e = __builtin_fma(-x, r, 1.0);
-  r = __builtin_fma(r, e, r);
-  e = __builtin_fma(-x, r, 1.0);
-  return __builtin_fma(r, e, r);
-}
-
-__device__ __forceinline__ double rsq64(double x) {
-  double y = __builtin_amdgcn_rsq(x);
-  const double h = 0.5 * x;
-  double e = __builtin_fma(-h * y, y, 0.5);
-  y = __builtin_fma(y, e, y);
-  e = __builtin_fma(-h * y, y, 0.5);
-  return __builtin_fma(y, e, y);
+// sin x and cos x in binary32 for |x| <= 1024 (the doubled angle of a map
+// texel): Cody-Waite reduction by pi/2 with the constant split in three
+// parts (each step one fma), then the minimax polynomials on [-pi/4, pi/4]
+// of Moshier's Cephes library (sinf, cosf).  Error within 1.5 ulp of 1
+// (checked over every binary16 angle in [0, pi] and 2e5 random binary32
+// angles against binary64 sin/cos).
+__device__ __forceinline__ void sincos_reduced(float x, float* s, float* c) {
+  const float k = rintf(x * 0.636619772367581343f);
+  float r = __builtin_fmaf(-k, 1.5703125f, x);
+  r = __builtin_fmaf(-k, 4.838267923332751e-4f, r);
+  r = __builtin_fmaf(-k, 2.5632829192545614e-12f, r);
+  const float r2 = r * r;
+  const float ps = __builtin_fmaf(__builtin_fmaf(-1.9515295891e-4f, r2, 8.3321608736e-3f), r2,
+                                  -1.6666654611e-1f);
+  const float pc = __builtin_fmaf(__builtin_fmaf(2.443315711809948e-5f, r2, -1.388731625493765e-3f),
+                                  r2, 4.166664568298827e-2f);
+  const float sp = __builtin_fmaf(r * r2, ps, r);
+  const float cp = __builtin_fmaf(r2 * r2, pc, __builtin_fmaf(-0.5f, r2, 1.0f));
+  const int q = (int)k & 3;
+  const float sv = (q & 1) ? cp : sp, cv = (q & 1) ? sp : cp;
+  *s = (q & 2) ? -sv : sv;
+  *c = ((q + 1) & 2) ? -cv : cv;
 }
 
 // Logical block index such that the blocks of one XCD cover a contiguous

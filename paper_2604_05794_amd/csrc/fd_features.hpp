@@ -26,8 +26,7 @@ __device__ __forceinline__ uint16_t feat_bf16(float x) {
 }
 
 // Frontal ranking key of a view (the "most frontal" views of the proposal
-// features), in binary64 with one rounding per operation in the order
-// written (the ranking is a discrete decision):
+// features), in binary64 (the ranking is a discrete decision):
 //   c = -R^T t  (c_k = -((R_k t0 + R_{3+k} t1) + R_{6+k} t2))
 //   a = c - p, b = p - o
 //   score = ((a_x b_x + a_y b_y) + a_z b_z) / sqrt((a_x^2 + a_y^2) + a_z^2)
@@ -51,6 +50,19 @@ __device__ __forceinline__ double frontal_score64(const float* cam, double px, d
     vdir[2] = (float)(az / la);
   }
   return (ax * bx + ay * by + az * bz) / la;
+}
+
+// The frontal key in the loop over every view of a point, from the camera
+// centre in the binary64 table and b = p - o computed once per point:
+// (a . b) / |a| with a reciprocal square root (agrees with frontal_score64
+// up to binary64 rounding).
+__device__ __forceinline__ double frontal_key(const double* __restrict__ c64, double px,
+                                              double py, double pz, double bx, double by,
+                                              double bz) {
+  const double ax = c64[12] - px, ay = c64[13] - py, az = c64[14] - pz;
+  const double dot = __builtin_fma(ax, bx, __builtin_fma(ay, by, az * bz));
+  const double la2 = __builtin_fma(ax, ax, __builtin_fma(ay, ay, az * az));
+  return dot * rsq64(la2);
 }
 
 // Stable insertion of view v with frontal score cs into the descending list
@@ -202,12 +214,13 @@ __device__ __forceinline__ void features_point(const SceneDev& s, double z_near,
   }
   const size_t plane = (size_t)s.W * s.H;
   const T* depth = (const T*)s.depth;
+  const double bx = px - (double)s.hc[0], by = py - (double)s.hc[1], bz = pz - (double)s.hc[2];
   for (int v = 0; v < s.V; ++v) {
-    Proj pr;
-    const bool ok = project64(s.cams + 16 * v, px, py, pz, s.W, s.H, z_near, pr);
+    ProjT pr;
+    const bool ok = project_tab(s.cam64 + kCam64 * v, px, py, pz, s.W, s.H, z_near, pr);
     if (!visible_at<T>(depth ? depth + plane * v : nullptr, s.W, ok, pr, (double)s.vis_tau))
       continue;
-    frontal_insert(sc, id, frontal_score64(s.cams + 16 * v, px, py, pz, s.hc, nullptr), v);
+    frontal_insert(sc, id, frontal_key(s.cam64 + kCam64 * v, px, py, pz, bx, by, bz), v);
   }
   write_feature_row<T>(s, z_near, px, py, pz, id, row_base + (by_j ? j : (int64_t)i), feats);
 }
@@ -240,17 +253,18 @@ __device__ __forceinline__ void topk_features_point(const SceneDev& s, const Sea
   const T* depth = (const T*)s.depth;
   const size_t plane = (size_t)s.W * s.H;
   const double tau = (double)s.vis_tau;
+  const double bx = px - (double)s.hc[0], by = py - (double)s.hc[1], bz = pz - (double)s.hc[2];
   // views in groups of two (four as in topk_point would hold more registers
   // next to the frontal list): a view no lane of the wave sees skips its
   // confidence texels and both insertions
   constexpr int kGroup = 2;
   for (int v0 = 0; v0 < s.V; v0 += kGroup) {
-    Proj pr[kGroup];
+    ProjT pr[kGroup];
     bool seen[kGroup];
 #pragma unroll
     for (int u = 0; u < kGroup; ++u) {
       const int v = min(v0 + u, s.V - 1);
-      const bool ok = project64(s.cams + 16 * v, px, py, pz, s.W, s.H, q.z_near, pr[u]);
+      const bool ok = project_tab(s.cam64 + kCam64 * v, px, py, pz, s.W, s.H, q.z_near, pr[u]);
       seen[u] = visible_at<T>(depth ? depth + plane * v : nullptr, s.W, ok, pr[u], tau) &&
                 v0 + u < s.V;
     }
@@ -269,7 +283,7 @@ __device__ __forceinline__ void topk_features_point(const SceneDev& s, const Sea
       if (c > 0.0) topk_insert<KS>(ck, vk, c, v);
       // frontal slots: eligible and visible views, whatever their confidence
       if (seen[u])
-        frontal_insert(sc, id, frontal_score64(s.cams + 16 * v, px, py, pz, s.hc, nullptr), v);
+        frontal_insert(sc, id, frontal_key(s.cam64 + kCam64 * v, px, py, pz, bx, by, bz), v);
     }
   }
   int keff = 0;

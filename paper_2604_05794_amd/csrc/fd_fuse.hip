@@ -72,6 +72,34 @@ hipError_t launch_consts(const ConstsDev& c, int n, double step0, double lstep0,
   return hipGetLastError();
 }
 
+// ---- per-call camera table ----------------------------------------------------
+__global__ void k_cams64(const float* __restrict__ cams, int V, double* __restrict__ out) {
+  const int v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= V) return;
+  const float* c = cams + 16 * v;
+  const double fx = c[0], fy = c[1], cx = c[2], cy = c[3];
+  const float* R = c + 4;
+  const float* t = c + 13;
+  double* o = out + (size_t)kCam64 * v;
+  for (int k = 0; k < 3; ++k) {
+    o[k] = fx * (double)R[k] + cx * (double)R[6 + k];
+    o[4 + k] = fy * (double)R[3 + k] + cy * (double)R[6 + k];
+    o[8 + k] = (double)R[6 + k];
+  }
+  o[3] = fx * (double)t[0] + cx * (double)t[2];
+  o[7] = fy * (double)t[1] + cy * (double)t[2];
+  o[11] = (double)t[2];
+  for (int k = 0; k < 3; ++k)
+    o[12 + k] = -((double)R[k] * t[0] + (double)R[3 + k] * t[1] + (double)R[6 + k] * t[2]);
+  o[15] = 0.0;
+}
+
+hipError_t launch_cams64(const float* cams, int V, double* out, hipStream_t st) {
+  if (V <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_cams64, dim3((V + 127) / 128), dim3(128), 0, st, cams, V, out);
+  return hipGetLastError();
+}
+
 SearchDev make_search(const ConstsDev& c, int n_candidates, int refine_iters, int K,
                       float z_near) {
   SearchDev q;

@@ -33,6 +33,8 @@ struct SceneDev {
   uint16_t* views;      // n x 8, selected views (processing order)
   uint8_t* kcount;      // n, K_eff (processing order)
   const void* depth;    // V x H x W camera-space Z, or NULL (no visibility test)
+  const double* cam64;  // V x 16 binary64 projection rows and centre (launch_cams64)
+  const float* prop;    // n x 3 given proposals in point order, or NULL
   int64_t n;
   int V, W, H;
   float hc[3];          // head centre (frontal ranking)
@@ -57,6 +59,8 @@ struct SceneDevGlobal {
   FD_GLOBAL uint16_t* views;
   FD_GLOBAL uint8_t* kcount;
   const FD_GLOBAL void* depth;
+  const FD_GLOBAL double* cam64;
+  const FD_GLOBAL float* prop;
   int64_t n;
   int V, W, H;
   float hc[3];
@@ -77,6 +81,8 @@ __device__ __forceinline__ SceneDev load_scene(const SceneDev* tab, int s) {
   d.views = (uint16_t*)g.views;
   d.kcount = (uint8_t*)g.kcount;
   d.depth = g.depth ? (const void*)g.depth : nullptr;
+  d.cam64 = (const double*)g.cam64;
+  d.prop = g.prop ? (const float*)g.prop : nullptr;
   d.n = g.n;
   d.V = g.V;
   d.W = g.W;
@@ -107,7 +113,7 @@ struct FpmvoDev {
 
 // Learned form (fd_learned.hip).
 struct LearnedDev {
-  const float* proposals;  // n x 3 in point order, or NULL for NaN proposals
+  const float* proposals;  // n x 3 (see learned_group), or NULL: the scene's own (SceneDev::prop)
   const double* steps;     // cos / sin of the learned refinement's steps (as SearchDev)
   int iters;
   double tau;
@@ -139,6 +145,12 @@ int tile_cells();
 // cos - 1 of the plain steps step0 / 2^t (t < FD_MAX_REFINE) and of the
 // learned steps lstep0 / 2^t, and the stencil.
 hipError_t launch_consts(const ConstsDev& c, int n, double step0, double lstep0, hipStream_t st);
+// Per view, kCam64 binary64 values: the projection rows
+// (f_x R_0 + c_x R_2 | f_x t_0 + c_x t_2), (f_y R_1 + c_y R_2 | f_y t_1 + c_y t_2),
+// (R_2 | t_2) (R_i the rows of R), so that u = row0 . (p, 1) / row2 . (p, 1),
+// then the camera centre -R^T t.
+constexpr int kCam64 = 16;
+hipError_t launch_cams64(const float* cams, int V, double* out, hipStream_t st);
 // Search constants as the kernels read them.
 SearchDev make_search(const ConstsDev& c, int n_candidates, int refine_iters, int K,
                       float z_near);

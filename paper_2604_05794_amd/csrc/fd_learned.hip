@@ -150,7 +150,15 @@ extern "C" int fd_features(const float* points, int64_t n_points, const fd_camer
     return set_error(FD_E_INVAL, "%s: vis_tau must be finite and >= 0", fn);
   if ((r = check_device(nullptr))) return r;
   if (n_points == 0) return FD_OK;
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  fd_context* c = default_context(dev, 0, &r, n_views);
+  if (!c) return r;
+  hipError_t e0 = launch_cams64((const float*)cams, n_views, c->cams64,
+                                (hipStream_t)params->stream);
+  if (e0 != hipSuccess) return hip_error(e0, "camera table");
   SceneDev s{};
+  s.cam64 = c->cams64;
   s.pts = points;
   s.cams = (const float*)cams;
   s.theta = orient_maps;

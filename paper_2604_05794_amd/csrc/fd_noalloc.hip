@@ -1,5 +1,6 @@
 // fd_noalloc.hip -- the plain search without any allocation: its workspace
-// (tiling keys and counts, permutation, view lists, search constants) lives
+// (tiling keys and counts, permutation, view lists, search constants, the
+// binary64 camera table) lives
 // in one fixed device array per GPU instead of a context, for callers that
 // cannot allocate (graph capture, tight serving loops).
 #include <hip/hip_runtime.h>
@@ -33,7 +34,9 @@ constexpr size_t kOffKey = align_up(kOffFbCount + sizeof(uint32_t) * 8);
 constexpr size_t kOffPerm = align_up(kOffKey + sizeof(uint32_t) * kMaxPts);
 constexpr size_t kOffViews = align_up(kOffPerm + sizeof(uint32_t) * kMaxPts);
 constexpr size_t kOffKcount = align_up(kOffViews + sizeof(uint16_t) * FD_TOPK_SLOTS * kMaxPts);
-constexpr size_t kScratchBytes = align_up(kOffKcount + sizeof(uint8_t) * kMaxPts);
+constexpr size_t kOffCams = align_up(kOffKcount + sizeof(uint8_t) * kMaxPts);
+constexpr size_t kScratchBytes =
+    align_up(kOffCams + sizeof(double) * kCam64 * (size_t)FD_NOALLOC_MAX_VIEWS);
 static_assert(kScratchBytes <= ((size_t)16 << 20), "scratch stays within 16 MiB");
 
 }  // namespace
@@ -86,6 +89,9 @@ extern "C" int fd_fuse_directions_noalloc(const float* points, int64_t n_points,
   if (n_points > (int64_t)kMaxPts)
     return set_error(FD_E_INVAL, "%s: %lld points exceed the fixed workspace of %lld points",
                      fn, (long long)n_points, (long long)kMaxPts);
+  if (n_views > FD_NOALLOC_MAX_VIEWS)
+    return set_error(FD_E_INVAL, "%s: %d views exceed the fixed workspace of %d views", fn,
+                     n_views, FD_NOALLOC_MAX_VIEWS);
   if ((size_t)tile_cells() > kCellsMax)
     return set_error(FD_E_UNSUPPORTED, "%s: tiling grid larger than the fixed workspace", fn);
   if (n_points == 0) return FD_OK;
@@ -110,6 +116,8 @@ extern "C" int fd_fuse_directions_noalloc(const float* points, int64_t n_points,
   c.perm = (uint32_t*)(base + kOffPerm);
   c.views = (uint16_t*)(base + kOffViews);
   c.kcount = (uint8_t*)(base + kOffKcount);
+  c.cams64 = (double*)(base + kOffCams);
+  c.cap_cams64 = (size_t)kCam64 * FD_NOALLOC_MAX_VIEWS;
   const SceneArgs sa = scene_args(points, n_points, cams, n_views, orient_maps, conf_maps,
                                   params, dirs, costs);
   return run_scene(&c, sa, params, (hipStream_t)params->stream);

@@ -74,12 +74,12 @@ __device__ __forceinline__ void topk_point(const SceneDev& s, const SearchDev& q
   // before any of them is used.
   constexpr int kGroup = 4;
   for (int v0 = 0; v0 < s.V; v0 += kGroup) {
-    Proj pr[kGroup];
+    ProjT pr[kGroup];
     bool seen[kGroup];
 #pragma unroll
     for (int u = 0; u < kGroup; ++u) {
       const int v = min(v0 + u, s.V - 1);
-      const bool ok = project64(s.cams + 16 * v, px, py, pz, s.W, s.H, q.z_near, pr[u]);
+      const bool ok = project_tab(s.cam64 + kCam64 * v, px, py, pz, s.W, s.H, q.z_near, pr[u]);
       seen[u] = visible_at<T>(depth ? depth + plane * v : nullptr, s.W, ok, pr[u], tau) &&
                 v0 + u < s.V;
     }
@@ -120,8 +120,8 @@ struct ViewPatch {
 // sub-pixel centre, each a bilinear sample of the doubled-angle vector
 // weighted by bilinear weight times confidence, zero outside the image).
 // The projection and the Jacobian are taken in binary64 and rounded once;
-// the texel angles go through an accurate sine/cosine, and the sample's
-// normalisation through IEEE square root and division.
+// the texel angles go through an accurate sine/cosine (sincos_reduced), and
+// the sample's normalisation through IEEE square root and division.
 template <typename T, int P>
 __device__ __forceinline__ void build_patch(const SceneDev& s, const SearchDev& q, int view,
                                             bool active, double px, double py, double pz,
@@ -191,7 +191,7 @@ __device__ __forceinline__ void build_patch(const SceneDev& s, const SearchDev& 
 #pragma unroll
     for (int a = 0; a <= P; ++a) {
       float sn, cs;
-      sincosf(2.0f * tv[a], &sn, &cs);  // 2 theta is exact in binary32
+      sincos_reduced(2.0f * tv[a], &sn, &cs);  // 2 theta is exact in binary32
       rc[slot][a] = cv[a];
       rx[slot][a] = cv[a] * cs;
       ry[slot][a] = cv[a] * sn;
@@ -415,21 +415,20 @@ struct ViewCentre {
 };
 
 template <int P>
-__device__ __forceinline__ ViewCentre view_centre(const ViewPatch<P>& vp, double dx, double dy,
-                                                  double dz, float (&g)[P * P]) {
+__device__ __forceinline__ ViewCentre view_centre(const ViewPatch<P>& vp, float dx, float dy,
+                                                  float dz, float (&g)[P * P]) {
   constexpr int P2 = P * P;
   ViewCentre c;
-  const double rx = __builtin_fma((double)vp.M[0], dx,
-                                  __builtin_fma((double)vp.M[1], dy, (double)vp.M[2] * dz));
-  const double ry = __builtin_fma((double)vp.M[3], dx,
-                                  __builtin_fma((double)vp.M[4], dy, (double)vp.M[5] * dz));
-  const double n2 = rx * rx + ry * ry;
-  c.on = n2 > 0.0;
-  const double i2 = c.on ? rcp64(n2) : 0.0;
-  const float c2 = (float)((rx * rx - ry * ry) * i2), s2 = (float)(rx * ry * i2);
-  c.zx = (float)rx;
-  c.zy = (float)ry;
-  c.iz2 = (float)i2;
+  const float rx = __builtin_fmaf(vp.M[0], dx, __builtin_fmaf(vp.M[1], dy, vp.M[2] * dz));
+  const float ry = __builtin_fmaf(vp.M[3], dx, __builtin_fmaf(vp.M[4], dy, vp.M[5] * dz));
+  const float xx = rx * rx;
+  const float n2 = __builtin_fmaf(ry, ry, xx);
+  c.on = n2 > 0.0f;
+  const float i2 = c.on ? __builtin_amdgcn_rcpf(n2) : 0.0f;
+  const float c2 = __builtin_fmaf(-ry, ry, xx) * i2, s2 = (rx * ry) * i2;
+  c.zx = rx;
+  c.zy = ry;
+  c.iz2 = i2;
   c.ec = c2;
   c.es = 2.0f * s2;
   float m = 0.0f;
@@ -489,58 +488,51 @@ __device__ __forceinline__ float view_delta(const ViewPatch<P>& vp, const float 
 // Pattern search (six directions at angle alpha_t around d in the
 // orthonormal basis of Duff et al. 2017, stencil angles j pi / 3, the best
 // strictly-better one taken, first of equals; alpha halves every iteration).
-// The centre d and the move are binary64; each candidate is compared with
-// the centre through the change of the view sum (view_delta), so the
-// decisions carry binary32 rounding relative to the cost differences the
-// iteration compares, not to the cost.  cs holds cos alpha_t, sin alpha_t
-// and cos alpha_t - 1 (FD_MAX_REFINE entries each), stencil cos(j pi/3)
-// then sin(j pi/3).
+// Each candidate d + du (du = (cos alpha - 1) d + sin alpha (cos j e1 +
+// sin j e2), the exact offset of the unit candidate) is compared with the
+// centre through the change of the view sum (view_delta), so the decisions
+// carry binary32 rounding relative to the cost differences the iteration
+// compares, not to the cost; the rounding of the centre and of the basis
+// only moves the stencil by ~1e-7 of its size.  cs holds cos alpha_t,
+// sin alpha_t and cos alpha_t - 1 (FD_MAX_REFINE entries each), stencil
+// cos(j pi/3) then sin(j pi/3).
 template <int P, int KT>
 __device__ __forceinline__ void refine(const ViewPatch<P>& vp, const Group& gr, int iters,
                                        const double* __restrict__ cs,
-                                       const double* __restrict__ stencil, double& dx,
-                                       double& dy, double& dz) {
+                                       const double* __restrict__ stencil, float& dx, float& dy,
+                                       float& dz) {
   for (int t = 0; t < iters; ++t) {
-    const double sg = copysign(1.0, dz);
-    const double aa = -1.0 / (sg + dz);
-    const double bb = dx * dy * aa;
-    const double e1x = 1.0 + sg * dx * dx * aa, e1y = sg * bb, e1z = -sg * dx;
-    const double e2x = bb, e2y = sg + dy * dy * aa, e2z = -dy;
+    const float sg = copysignf(1.0f, dz);
+    const float aa = -1.0f / (sg + dz);
+    const float bb = dx * dy * aa;
+    const float e1x = 1.0f + sg * dx * dx * aa, e1y = sg * bb, e1z = -sg * dx;
+    const float e2x = bb, e2y = sg + dy * dy * aa, e2z = -dy;
     float g[P * P];
     const ViewCentre c = view_centre<P>(vp, dx, dy, dz, g);
     const bool any_off = __ballot(!c.on) != 0;
     const float sa = (float)cs[FD_MAX_REFINE + t], cm1 = (float)cs[2 * FD_MAX_REFINE + t];
-    const float fdx = (float)dx, fdy = (float)dy, fdz = (float)dz;
-    const float f1x = (float)e1x, f1y = (float)e1y, f1z = (float)e1z;
-    const float f2x = (float)e2x, f2y = (float)e2y, f2z = (float)e2z;
-    float bS = -INFINITY;
-    int bj = 0;
+    float bS = -INFINITY, bux = 0.0f, buy = 0.0f, buz = 0.0f;
 #pragma unroll 1
     for (int jj = 0; jj < 6; ++jj) {
       const float cj = (float)stencil[jj], sj = (float)stencil[6 + jj];
-      const float vx = cj * f1x + sj * f2x;
-      const float vy = cj * f1y + sj * f2y;
-      const float vz = cj * f1z + sj * f2z;
-      const float ux = __builtin_fmaf(cm1, fdx, sa * vx);
-      const float uy = __builtin_fmaf(cm1, fdy, sa * vy);
-      const float uz = __builtin_fmaf(cm1, fdz, sa * vz);
+      const float ux = __builtin_fmaf(cm1, dx, sa * (cj * e1x + sj * e2x));
+      const float uy = __builtin_fmaf(cm1, dy, sa * (cj * e1y + sj * e2y));
+      const float uz = __builtin_fmaf(cm1, dz, sa * (cj * e1z + sj * e2z));
       const float dS =
           group_sum_t<KT>(view_delta<P>(vp, g, c, any_off, ux, uy, uz), gr.base, gr.K);
       if (dS > bS) {
         bS = dS;
-        bj = jj;
+        bux = ux;
+        buy = uy;
+        buz = uz;
       }
     }
     if (bS > 0.0f) {  // the same decision in every lane of the group
-      const double ca = cs[t], sad = cs[FD_MAX_REFINE + t];
-      const double cj = stencil[bj], sj = stencil[6 + bj];
-      double ux = ca * dx + sad * (cj * e1x + sj * e2x);
-      double uy = ca * dy + sad * (cj * e1y + sj * e2y);
-      double uz = ca * dz + sad * (cj * e1z + sj * e2z);
-      const double il = rsq64(ux * ux + uy * uy + uz * uz);
-      dx = ux * il;
-      dy = uy * il;
-      dz = uz * il;
+      const float nx = dx + bux, ny = dy + buy, nz = dz + buz;
+      const float il = __builtin_amdgcn_rsqf(__builtin_fmaf(nx, nx, __builtin_fmaf(ny, ny, nz * nz)));
+      dx = nx * il;
+      dy = ny * il;
+      dz = nz * il;
     }
   }
 }
@@ -596,10 +588,11 @@ __device__ __forceinline__ void full_search(ViewPatch<P>& vp, const SearchDev& q
       kb = k;
     }
   }
-  dx = q.lattice64[3 * kb];
-  dy = q.lattice64[3 * kb + 1];
-  dz = q.lattice64[3 * kb + 2];
-  refine<P, KT>(vp, gr, q.refine_iters, q.steps, q.stencil, dx, dy, dz);
+  float fx = q.lattice[3 * kb], fy = q.lattice[3 * kb + 1], fz = q.lattice[3 * kb + 2];
+  refine<P, KT>(vp, gr, q.refine_iters, q.steps, q.stencil, fx, fy, fz);
+  dx = fx;
+  dy = fy;
+  dz = fz;
   pin_patch<P>(vp);
   S = group_sum_t<KT>(eval_view64<P>(vp, dx, dy, dz), gr.base, gr.K);
 }
@@ -628,8 +621,9 @@ __device__ __forceinline__ void fuse_group(const SceneDev& s, const SearchDev& q
 }
 
 // ---- learned form: refinement from a proposal, threshold, fallback -------------
-// prop: proposals (x, y, z); row prop_base + j when prop_by_j, else the point
-// index i; NULL = every proposal invalid.  A point is kept when its proposal
+// Proposals (x, y, z): l.proposals row prop_base + j when prop_by_j, else
+// row i (the point index); without l.proposals, the scene's own s.prop row
+// i; with neither, every proposal is invalid.  A point is kept when its proposal
 // is a finite non-zero direction and the refined cost satisfies J <= tau;
 // otherwise it takes the plain search.  A wave in which at least half of its
 // points need the plain search runs it at once on the patch registers it
@@ -652,18 +646,27 @@ __device__ __forceinline__ void learned_group(const SceneDev& s, const SearchDev
   ViewPatch<P> vp;
   build_patch<T, P>(s, q, view, slot_ok, px, py, pz, vp);
   double dx = 0.0, dy = 0.0, dz = 0.0;
-  if (pt_ok && l.proposals) {
-    const size_t k = 3 * (size_t)(prop_by_j ? (uint64_t)(prop_base + j) : (uint64_t)i);
-    dx = l.proposals[k];
-    dy = l.proposals[k + 1];
-    dz = l.proposals[k + 2];
+  const float* pp = nullptr;
+  if (pt_ok) {
+    if (l.proposals)
+      pp = l.proposals + 3 * (size_t)(prop_by_j ? (uint64_t)(prop_base + j) : (uint64_t)i);
+    else if (s.prop)
+      pp = s.prop + 3 * (size_t)i;
+  }
+  if (pp) {
+    dx = pp[0];
+    dy = pp[1];
+    dz = pp[2];
   }
   const double len = sqrt(dx * dx + dy * dy + dz * dz);
   const bool valid = keff > 0 && isfinite(len) && len > 0.0;
-  dx = valid ? dx / len : 0.0;
-  dy = valid ? dy / len : 0.0;
-  dz = valid ? dz / len : 1.0;
-  refine<P, KT>(vp, gr, l.iters, l.steps, q.stencil, dx, dy, dz);
+  float fx = valid ? (float)(dx / len) : 0.0f;
+  float fy = valid ? (float)(dy / len) : 0.0f;
+  float fz = valid ? (float)(dz / len) : 1.0f;
+  refine<P, KT>(vp, gr, l.iters, l.steps, q.stencil, fx, fy, fz);
+  dx = fx;
+  dy = fy;
+  dz = fz;
   pin_patch<P>(vp);
   const double S = group_sum_t<KT>(eval_view64<P>(vp, dx, dy, dz), gr.base, gr.K);
   const double J = cost_of(S, keff);

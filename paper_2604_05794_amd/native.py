@@ -80,6 +80,7 @@ class Scene(ctypes.Structure):
         ("depth_maps", ctypes.c_void_p),
         ("dirs", ctypes.c_void_p), ("costs", ctypes.c_void_p),
         ("head_centre", ctypes.c_float * 3),
+        ("proposal_dirs", ctypes.c_void_p),
     ]
 
 
@@ -668,6 +669,12 @@ def _scene_struct(sc):
     hc = sc.get("head_centre", (0.0, 0.0, 0.0))
     for k in range(3):
         s.head_centre[k] = float(hc[k])
+    prop = sc.get("proposal_dirs")
+    if prop is not None:
+        _dev_tensor(prop, "proposal_dirs", torch.float32, (3,))
+        if prop.shape[0] != pts.shape[0]:
+            raise ValueError("proposal_dirs must have one row per point")
+    s.proposal_dirs = prop.data_ptr() if prop is not None else None
     return s, map_dtype_of(th)
 
 
