@@ -69,13 +69,12 @@ _GABOR_SOURCES = ["fd_gabor.hip"]
 _VOLUME_SOURCES = ["fd_volume.hip", "fd_voxel.hpp"]
 _PHG_SOURCES = ["fd_phg.hip", "fd_voxel.hpp"]
 TRAFFIC = {
-    "k_fuse, realistic 500k": {"read": 377.2e6, "write": 37.7e6, "files": _SEARCH_SOURCES,
-                               "src": "d78225e8409978a0"},
-    "k_fuse, metric workload, per head": {"read": 294.2e6, "write": 19.1e6,
-                                          "files": _SEARCH_SOURCES, "src": "d78225e8409978a0"},
-    # the four-wave form spills a few registers: scratch traffic included
-    "k_b_learned, metric workload": {"read": 3039.3e6, "write": 882.0e6,
-                                      "files": _BATCHED_SOURCES, "src": "1578a19317a4d965"},
+    "k_fuse, realistic 500k": {"read": 396.0e6, "write": 37.7e6, "files": _SEARCH_SOURCES,
+                               "src": "e2ac0430697ad175"},
+    "k_fuse, metric workload, per head": {"read": 135.1e6, "write": 8.5e6,
+                                          "files": _SEARCH_SOURCES, "src": "e2ac0430697ad175"},
+    "k_b_learned, metric workload": {"read": 2149.6e6, "write": 160.6e6,
+                                     "files": _BATCHED_SOURCES, "src": "6e26eb6ec8a0700d"},
     "k_gabor_mfma, 64 frames 1024^2": {"read": 1152.1e6, "write": 406.8e6,
                                        "files": _GABOR_SOURCES, "src": "21a8f3739c8a0866"},
     # the counting sort: keys and counts, the scan, the placement
@@ -372,10 +371,15 @@ def run_metric(args):
             native.fuse_batched(scenes, ctx, stream=stream, **kw, **extra)
         return step
 
-    # tile shapes of the batched search, picked by the autotuner (untimed)
-    t = time.perf_counter()
-    native.autotune([d for _, d in heads], ctx, stream=stream, **kw)
-    log(f"autotune: {time.perf_counter() - t:.1f} s, chunk {ctx.tuned()[0]}, grid {ctx.tuned()[1]}")
+    # tile shapes of each batched form, picked by the autotuner (untimed):
+    # persistent tile queues or one wave per tile
+    tuned = {}
+    for name, extra in (("plain_batched", {}), ("learned_batched", lkw)):
+        t = time.perf_counter()
+        native.autotune([d for _, d in heads], ctx, stream=stream, **kw, **extra)
+        tuned[name] = ctx.tuned()
+        log(f"autotune {name}: {time.perf_counter() - t:.1f} s, chunk {tuned[name][0]}, "
+            f"grid {tuned[name][1]}")
 
     def snap():
         return (torch.cat([d["dirs"] for _, d in heads]).clone(),
@@ -386,8 +390,8 @@ def run_metric(args):
     for name, fn in (("plain", per_head({})), ("plain_batched", batched({})),
                      ("learned", per_head(lkw)), ("learned_batched", batched(lkw))):
         is_batched = name.endswith("batched")
-        # the batched forms are timed replaying their graph; their stage
-        # times come from a separate pass that launches the same kernels
+        if is_batched:
+            ctx.set_tuned(*tuned[name])
         # every form is timed with stage timing off; the stage times come
         # from a separate pass (the batched forms then launch the same
         # kernels directly instead of replaying their graph)
@@ -442,7 +446,8 @@ def run_metric(args):
                    "mode": "learned+batched", "points": n, "heads": len(heads), "views": 128,
                    "depth_test": not args.no_depth,
                    "learned_step0": step0, "fallback_cost": tau,
-                   "batched_shape": dict(zip(("chunk", "grid"), ctx.tuned())), **kw},
+                   "batched_shape": {k: dict(zip(("chunk", "grid"), v)) for k, v in tuned.items()},
+                   **kw},
         "plain_points_per_s": v_p, "speedup_vs_plain": v_lb / v_p,
         "points_per_s": {k: v[0] for k, v in res.items()},
         "ms_per_step_by_form": {k: v[1] for k, v in res.items()},
@@ -1118,6 +1123,119 @@ def run_pipeline(args):
     }
 
 
+def run_gains(args):
+    """What the network gains over the method without it, and what the
+    threshold trades.  On the realistic scene and one tight-curl head:
+    the learned form with the network proposal against the learned form with
+    a proposal from a small Fibonacci lattice (N' directions, no refinement:
+    the plain search with n_candidates = N', refine_iters = 0), both refined
+    by the same 2 iterations from the same calibrated step and held to the
+    same threshold tau (equal sim-eval budget after the proposal); N' runs
+    over a range and the one whose proposal takes the network's measured
+    time (features + forward) is marked.  Then a sweep of tau for the
+    network form.  Each row: points/s of the whole learned call (proposal
+    included), fallback fraction, mean and 95th-percentile angle to the plain
+    result."""
+    import numpy as np
+    import torch
+    import scenegen
+    from paper_2604_05794_amd import native
+
+    dev = torch.device("cuda:0")
+    net = native.MLP(path=args.mlp)
+    step0, tau0 = net.calibration()
+    stream = torch.cuda.current_stream()
+    out = {"workload": "network proposal vs Fibonacci proposal at equal refinement budget; "
+                       "threshold sweep", "learned_step0": step0, "tau_calibrated": tau0,
+           "scenes": {}}
+
+    def timed(fn):
+        for _ in range(args.warmup):
+            fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / args.steps
+
+    for name in ("realistic", "curls"):
+        rec = scenegen.RECIPES[name]
+        kw = dict(patch=rec["patch"], n_candidates=rec["n_candidates"],
+                  refine_iters=rec["refine_iters"], top_k=5)
+        sc = scenegen.make_scene(name, args.seed)
+        n = sc.n_points
+        pts, cams = torch.from_numpy(sc.points).to(dev), torch.from_numpy(sc.cams).to(dev)
+        th, cf = torch.from_numpy(sc.theta).to(dev), torch.from_numpy(sc.conf).to(dev)
+        kw["depth_maps"] = torch.from_numpy(sc.depth).to(dev)
+        ctx = native.Context(max_points=n, max_views=sc.n_views)
+        dp, cp = (torch.empty((n, 3), device=dev), torch.empty((n,), device=dev))
+        dl, cl = torch.empty_like(dp), torch.empty_like(cp)
+        dq, cq = torch.empty_like(dp), torch.empty_like(cp)
+
+        def plain():
+            native.fuse_directions(pts, cams, th, cf, dirs=dp, costs=cp, ctx=ctx, stream=stream,
+                                   **kw)
+        t_plain = timed(plain)
+        fin = torch.isfinite(cp)
+
+        def row(t, d):
+            a = _axial_deg(d[fin], dp[fin])
+            return {"points_per_s": n / t, "ms": t * 1e3, "fallback": ctx.fallback_count() / n,
+                    "mean_err_vs_plain_deg": float(a.mean()),
+                    "p95_err_vs_plain_deg": float(torch.quantile(a, 0.95))}
+
+        def learned_net(tau):
+            def fn():
+                native.fuse_directions(pts, cams, th, cf, dirs=dl, costs=cl, ctx=ctx,
+                                       stream=stream, mode=native.FD_MODE_LEARNED, mlp=net,
+                                       learned_iters=2, learned_step0=step0, fallback_cost=tau,
+                                       head_centre=sc.head_centre, **kw)
+            return fn
+        t_net = timed(learned_net(tau0))
+        res = {"plain": {"points_per_s": n / t_plain, "ms": t_plain * 1e3},
+               "network": row(t_net, dl)}
+        st = _stage_pass(learned_net(tau0), ctx, [("features", native.FD_STAGE_FEATURES),
+                                                 ("mlp", native.FD_STAGE_MLP)])
+        t_prop_net = (st.get("features", 0.0) + st.get("mlp", 0.0)) * 1e-3
+        res["network"]["proposal_ms"] = t_prop_net * 1e3
+        fib = {}
+        for nprime in (4, 8, 12, 16, 24, 32, 48, 64):
+            pkw = dict(kw, n_candidates=nprime, refine_iters=0)
+
+            def prop():
+                native.fuse_directions(pts, cams, th, cf, dirs=dq, costs=cq, ctx=ctx,
+                                       stream=stream, **pkw)
+
+            def fn():
+                prop()
+                native.fuse_directions(pts, cams, th, cf, dirs=dl, costs=cl, ctx=ctx,
+                                       stream=stream, mode=native.FD_MODE_LEARNED,
+                                       proposal=native.FD_PROPOSAL_GIVEN, proposal_dirs=dq,
+                                       learned_iters=2, learned_step0=step0, fallback_cost=tau0,
+                                       **kw)
+            t_prop = timed(prop)
+            t_all = timed(fn)
+            r = row(t_all, dl)
+            r["proposal_ms"] = t_prop * 1e3
+            fib[nprime] = r
+        res["fibonacci"] = fib
+        match = min(fib, key=lambda k: abs(fib[k]["proposal_ms"] - t_prop_net * 1e3))
+        res["fibonacci_matched_n"] = match
+        sweep = {}
+        for tau in sorted({0.5 * tau0, tau0, 1.5 * tau0, 2 * tau0, 3 * tau0, 0.1, 0.2, 0.3}):
+            t = timed(learned_net(tau))
+            sweep[f"{tau:.4f}"] = row(t, dl)
+        t = timed(learned_net(float("inf")))
+        sweep["inf"] = row(t, dl)
+        res["tau_sweep"] = sweep
+        out["scenes"][name] = res
+        log(f"{name}: plain {n / t_plain / 1e6:.1f} M points/s; network "
+            f"{json.dumps({k: round(v, 4) for k, v in res['network'].items()})}; fibonacci "
+            f"N'={match} {json.dumps({k: round(v, 4) for k, v in fib[match].items()})}")
+    return out
+
+
 def l2_probe(sizes=(1 << 20, 2 << 20, 3 << 20), blocks=2048, target_bytes=16 << 30):
     """Aggregate read bandwidth of buffers that fit one XCD's L2 (4 MiB):
     every workgroup reads the whole buffer (fd_probe_read), so every XCD
@@ -1179,7 +1297,7 @@ def main():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--workload", default="metric",
                     choices=["metric", "plain", "learned", "gabor", "volume", "phg", "train",
-                             "pipeline", "copy", "l2"])
+                             "pipeline", "copy", "l2", "gains"])
     ap.add_argument("--heads", type=int, default=8)
     ap.add_argument("--mlp", default=os.path.join(ROOT, "paper_2604_05794_amd", "weights",
                                                   "proposal_mlp.fdmlp"))
@@ -1197,7 +1315,7 @@ def main():
     run = {"metric": run_metric, "plain": run_plain, "learned": run_learned,
            "gabor": run_gabor, "volume": run_volume, "phg": run_phg, "train": run_train,
            "pipeline": run_pipeline,
-           "copy": run_copy, "l2": run_l2}[args.workload]
+           "copy": run_copy, "l2": run_l2, "gains": run_gains}[args.workload]
     out = run(args)
     print(json.dumps(out), flush=True)
 

@@ -472,6 +472,10 @@ int fd_autotune(fd_context* ctx, const fd_scene* sample, int32_t n_scenes,
  * queue pop and *grid workgroups (0: the full resident grid, -1: one wave
  * per tile instead of the persistent queue). */
 int fd_tuned_shape(const fd_context* ctx, int32_t* chunk, int32_t* grid);
+/* Sets that shape directly (a shape fd_autotune returned for another form,
+ * say): chunk >= 1, grid >= 0 (0: the full resident grid) or -1; results
+ * do not depend on it.  Returns FD_E_INVAL for other values. */
+int fd_set_tuned_shape(fd_context* ctx, int32_t chunk, int32_t grid);
 
 /* ---- stage timing -----------------------------------------------------------
  * While enabled on a context, every call through it records a pair of HIP

@@ -868,3 +868,12 @@ extern "C" int fd_tuned_shape(const fd_context* ctx, int32_t* chunk, int32_t* gr
   *grid = ctx->tuned_grid;
   return FD_OK;
 }
+
+extern "C" int fd_set_tuned_shape(fd_context* ctx, int32_t chunk, int32_t grid) {
+  if (!ctx) return set_error(FD_E_INVAL, "fd_set_tuned_shape: ctx is NULL");
+  if (chunk < 1 || grid < -1)
+    return set_error(FD_E_INVAL, "fd_set_tuned_shape: chunk >= 1 and grid >= -1 required");
+  ctx->tuned_chunk = chunk;
+  ctx->tuned_grid = grid;
+  return FD_OK;
+}

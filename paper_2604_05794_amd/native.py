@@ -32,7 +32,7 @@ EXPORTS = (
     "fd_mlp_create", "fd_mlp_set_params", "fd_mlp_get_params", "fd_mlp_set_calibration",
     "fd_mlp_get_calibration", "fd_mlp_save", "fd_mlp_load", "fd_mlp_forward",
     "fd_mlp_loss_grad", "fd_mlp_train_step", "fd_mlp_destroy", "fd_features", "fd_autotune",
-    "fd_tuned_shape", "fd_profile_enable", "fd_profile_read", "fd_gabor_params_init",
+    "fd_tuned_shape", "fd_set_tuned_shape", "fd_profile_enable", "fd_profile_read", "fd_gabor_params_init",
     "fd_orientation_maps", "fd_fuse_volume", "fd_grow_params_init", "fd_grow_strands",
     "fd_link_segments", "fd_strand_offsets", "fd_assemble_strands", "fd_probe_read",
     "fd_last_error",
@@ -152,6 +152,7 @@ def lib():
         "fd_features": (ctypes.c_int, [P, i64, P, i32, P, P, pp, P]),
         "fd_autotune": (ctypes.c_int, [P, ctypes.POINTER(Scene), i32, pp, ctypes.c_char_p]),
         "fd_tuned_shape": (ctypes.c_int, [P, ctypes.POINTER(i32), ctypes.POINTER(i32)]),
+        "fd_set_tuned_shape": (ctypes.c_int, [P, i32, i32]),
         "fd_profile_enable": (ctypes.c_int, [P, ctypes.c_int]),
         "fd_profile_read": (ctypes.c_int, [P, ctypes.c_int, ctypes.POINTER(ctypes.c_double),
                                            ctypes.POINTER(i64)]),
@@ -236,6 +237,10 @@ class Context:
         c, g = ctypes.c_int32(), ctypes.c_int32()
         _check(lib().fd_tuned_shape(self.handle, ctypes.byref(c), ctypes.byref(g)))
         return c.value, g.value
+
+    def set_tuned(self, chunk, grid):
+        """fd_set_tuned_shape."""
+        _check(lib().fd_set_tuned_shape(self.handle, int(chunk), int(grid)))
 
     def profile(self, on=True):
         _check(lib().fd_profile_enable(self.handle, int(bool(on))))
