@@ -17,6 +17,9 @@ depth visibility test of Sec. 3.1.1 with the scene's rendered depth maps
              float16 maps, 10% outlier texels, 5x5 patch, 128 candidates +
              8 refinement iterations (fd_fuse_directions, plain mode).
   learned    the same scene, learned form against plain.
+  batched    16 uneven hairstyles (50k-800k points, 32-128 views, 512-1024
+             px float16 maps): plain search of all in one captured batched
+             launch against one call per scene.
   gabor      orientation and confidence maps from 64 grey frames at 1024^2
              (the plain workload's views; 32 orientations, radius 8), then
              the plain search of the plain workload on those maps.
@@ -478,6 +481,108 @@ def run_metric(args):
         out["cpu_baseline"] = cpu_baseline(heads[0][0], kw, args.cpu_seconds,
                                            depth=not args.no_depth)
         log(f"cpu baseline: {out['cpu_baseline']}")
+    return out
+
+
+def run_batched(args):
+    """The uneven 16-hairstyle set (scene i: round(50k 16^(i/15)) points,
+    32 + 32 (5i mod 4) views, [512, 768, 1024][7i mod 3] px float16 maps,
+    the realistic recipe otherwise), plain search of all 16 scenes in one
+    captured batched launch with the autotuned tile shape (value), against
+    one fd_fuse_directions call per scene."""
+    import torch
+    import scenegen
+    from paper_2604_05794_amd import native
+
+    rec = scenegen.RECIPES["realistic"]
+    kw = dict(patch=rec["patch"], n_candidates=rec["n_candidates"],
+              refine_iters=rec["refine_iters"], top_k=5)
+    dev = torch.device("cuda:0")
+    scenes = []
+    t = time.perf_counter()
+    for i, r in enumerate(scenegen.batched_recipes(16)):
+        sc = scenegen.make_scene(r, args.seed + i)
+        d = dict(points=torch.from_numpy(sc.points).to(dev),
+                 cams=torch.from_numpy(sc.cams).to(dev),
+                 orient_maps=torch.from_numpy(sc.theta).to(dev),
+                 conf_maps=torch.from_numpy(sc.conf).to(dev),
+                 dirs=torch.empty((sc.n_points, 3), dtype=torch.float32, device=dev),
+                 costs=torch.empty((sc.n_points,), dtype=torch.float32, device=dev))
+        if not args.no_depth:
+            d["depth_maps"] = torch.from_numpy(sc.depth).to(dev)
+        scenes.append((sc, d))
+        log(f"scene {i}: {sc.n_points} points, {sc.n_views} views {sc.width}^2 "
+            f"({time.perf_counter() - t:.1f} s)")
+    n = sum(sc.n_points for sc, _ in scenes)
+    stream = torch.cuda.current_stream()
+    ctx = native.Context(max_points=n, max_views=sum(sc.n_views for sc, _ in scenes),
+                         max_scenes=len(scenes))
+    devs = [d for _, d in scenes]
+    stg = [("tiling", native.FD_STAGE_TILING), ("topk", native.FD_STAGE_TOPK),
+           ("fuse", native.FD_STAGE_FUSE), ("batched", native.FD_STAGE_BATCHED)]
+
+    def per_scene():
+        for sc, d in scenes:
+            native.fuse_directions(d["points"], d["cams"], d["orient_maps"], d["conf_maps"],
+                                   dirs=d["dirs"], costs=d["costs"], ctx=ctx, stream=stream,
+                                   depth_maps=d.get("depth_maps"), **kw)
+
+    def batched():
+        native.fuse_batched(devs, ctx, stream=stream, **kw)
+
+    t = time.perf_counter()
+    native.autotune(devs, ctx, stream=stream, **kw)
+    tuned = ctx.tuned()
+    log(f"autotune: {time.perf_counter() - t:.1f} s, chunk {tuned[0]}, grid {tuned[1]}")
+
+    def snap():
+        return (torch.cat([d["dirs"] for d in devs]).clone(),
+                torch.cat([d["costs"] for d in devs]).clone())
+
+    el_p, _ = _timed(per_scene, args, ctx, stg, profile=False)
+    out_p = snap()
+    st_p = _stage_pass(per_scene, ctx, stg)
+    ctx.set_tuned(*tuned)
+    el_b, _ = _timed(batched, args, ctx, stg, profile=False)
+    out_b = snap()
+    st_b = _stage_pass(batched, ctx, stg)
+    same = bool(torch.equal(out_p[0], out_b[0]) and torch.equal(out_p[1], out_b[1]))
+    v_b = n / (el_b / args.steps)
+    v_p = n / (el_p / args.steps)
+    log(f"batched: {v_b / 1e6:.1f} M points/s ({el_b * 1e3 / args.steps:.3f} ms/step) "
+        f"{json.dumps({k: round(v, 4) for k, v in st_b.items()})}; per scene: "
+        f"{v_p / 1e6:.1f} M points/s {json.dumps({k: round(v, 4) for k, v in st_p.items()})}; "
+        f"bitwise equal {same}")
+    flop = plain_flop_per_point(kw["patch"], kw["n_candidates"], kw["refine_iters"], 5)
+    achieved = flop * n / (st_b["fuse"] * 1e-3) / 1e12
+    kern = "k_b_fuse_tiles (persistent tile queue)" if tuned[1] > 0 else \
+        "k_b_fuse (one wave per tile)"
+    out = {
+        "metric": METRIC, "value": v_b, "unit": "points/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": el_b * 1e3 / args.steps,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"batched plain: 16 uneven hairstyles, {n} points in all "
+                               "(50k-800k per scene), 32-128 views, 512-1024 px f16 maps, "
+                               "realistic recipe, P=5, 128 candidates + 8 refinement "
+                               "iterations, one captured batched launch",
+                   "mode": "plain+batched", "points": n,
+                   "scenes": [[sc.n_points, sc.n_views, sc.width] for sc, _ in scenes],
+                   "depth_test": not args.no_depth,
+                   "batched_shape": dict(zip(("chunk", "grid"), tuned)), **kw},
+        "per_scene_points_per_s": v_p, "speedup_vs_per_scene": v_b / v_p,
+        "ms_per_step_per_scene": el_p * 1e3 / args.steps,
+        "batched_bitwise_equal_per_scene": same,
+        "stages_ms_per_launch": st_b, "stages_ms_per_launch_per_scene": st_p,
+        "roofline": {"bound": "alu", "kernel": kern, "achieved": achieved,
+                     "peak": PEAK_FP32, "unit": "TFLOP/s", "frac": achieved / PEAK_FP32,
+                     "traffic": None, "avg_launch_ms": st_b["fuse"], "points_per_launch": n,
+                     "flop_per_point": flop, "flop_per_sim_eval": FLOP_PER_SIM_EVAL},
+    }
+    if not args.no_cpu_baseline:
+        sc = scenes[len(scenes) // 2][0]
+        out["cpu_baseline"] = cpu_baseline(sc, kw, args.cpu_seconds, depth=not args.no_depth)
+        out["cpu_baseline"]["sample"] += f" (scene {len(scenes) // 2} of the set)"
     return out
 
 
@@ -1297,7 +1402,7 @@ def main():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--workload", default="metric",
                     choices=["metric", "plain", "learned", "gabor", "volume", "phg", "train",
-                             "pipeline", "copy", "l2", "gains"])
+                             "pipeline", "copy", "l2", "gains", "batched"])
     ap.add_argument("--heads", type=int, default=8)
     ap.add_argument("--mlp", default=os.path.join(ROOT, "paper_2604_05794_amd", "weights",
                                                   "proposal_mlp.fdmlp"))
@@ -1315,7 +1420,8 @@ def main():
     run = {"metric": run_metric, "plain": run_plain, "learned": run_learned,
            "gabor": run_gabor, "volume": run_volume, "phg": run_phg, "train": run_train,
            "pipeline": run_pipeline,
-           "copy": run_copy, "l2": run_l2, "gains": run_gains}[args.workload]
+           "copy": run_copy, "l2": run_l2, "gains": run_gains,
+           "batched": run_batched}[args.workload]
     out = run(args)
     print(json.dumps(out), flush=True)
 
