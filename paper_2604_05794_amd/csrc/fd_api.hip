@@ -345,7 +345,6 @@ ConstsDev fd::context_consts(fd_context* c) {
   k.lattice = c->lattice;
   k.lattice64 = c->consts64;
   k.steps = c->consts64 + 3 * FD_MAX_CANDIDATES;
-  k.stencil = k.steps + 6 * FD_MAX_REFINE;
   return k;
 }
 

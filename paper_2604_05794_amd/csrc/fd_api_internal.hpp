@@ -22,7 +22,7 @@ struct fd_context {
   uint32_t* cursor = nullptr;
   uint32_t* scan_sums = nullptr;
   float* lattice = nullptr;   // search constants (ConstsDev): binary32 lattice
-  double* consts64 = nullptr; // binary64 lattice, step tables, stencil
+  double* consts64 = nullptr; // binary64 lattice, step tables
   double* cams64 = nullptr;   // binary64 camera table, kCam64 per view
   size_t cap_cams64 = 0;      // doubles
   uint32_t* fb_count = nullptr;

@@ -227,7 +227,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(search_w
 void k_b_fuse(BatchDev b, SearchDev q, const uint32_t* list,
                                                    const uint32_t* list_count,
                                                    uint32_t* __restrict__ queue, int chunk) {
-  const Group gr = make_group(q.K);
+  const Group gr = make_group<KT>(q.K);
   const int64_t n_items = LIST ? (int64_t)*list_count : b.total;
   const int64_t n_tiles = LIST ? (n_items + gr.G - 1) / gr.G : b.n_tiles;
   if (n_tiles <= 0) return;  // uniform: nothing to search
@@ -269,7 +269,7 @@ void k_b_fuse(BatchDev b, SearchDev q, const uint32_t* list,
 template <typename T, int P, int KT>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(search_waves(P))))
 void k_b_fuse_tiles(BatchDev b, SearchDev q) {
-  const Group gr = make_group(q.K);
+  const Group gr = make_group<KT>(q.K);
   const int64_t tile = xcd_tile(gridDim.x) * (blockDim.x / kWave) + (threadIdx.x / kWave);
   if (tile >= b.n_tiles) return;
   const int s = find_scene(b.tile_off, b.n_scenes, tile);
@@ -282,7 +282,7 @@ void k_b_fuse_tiles(BatchDev b, SearchDev q) {
 template <typename T, int P, int KT>
 __device__ __forceinline__ void b_learned_body(const BatchDev& b, const SearchDev& q,
                                                const LearnedDev& l) {
-  const Group gr = make_group(q.K);
+  const Group gr = make_group<KT>(q.K);
   const int64_t tile = xcd_tile(gridDim.x) * (blockDim.x / kWave) + (threadIdx.x / kWave);
   if (tile >= b.n_tiles) return;
   const int s = find_scene(b.tile_off, b.n_scenes, tile);
@@ -304,7 +304,7 @@ template <typename T, int P, int KT>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(search_waves(P))))
 void k_b_learned_q(BatchDev b, SearchDev q, LearnedDev l, uint32_t* __restrict__ queue,
                    int chunk) {
-  const Group gr = make_group(q.K);
+  const Group gr = make_group<KT>(q.K);
   const int64_t n_tiles = b.n_tiles;
   if (n_tiles <= 0) return;
   const int home = (int)(blockIdx.x % kQueues);

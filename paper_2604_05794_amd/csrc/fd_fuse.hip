@@ -34,7 +34,7 @@ namespace fd {
 // psi_k = k pi (3 - sqrt 5), in binary64 and rounded to binary32 for the
 // lattice stage.  Refinement steps alpha_t = step0 / 2^t (exact halvings) with
 // their cosines, sines and cosines minus one, for the plain search and for
-// the learned form's short refinement, and the stencil angles j pi / 3.
+// the learned form's short refinement.
 __global__ void k_consts(ConstsDev c, int n, double step0, double lstep0) {
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k < n) {
@@ -58,11 +58,6 @@ __global__ void k_consts(ConstsDev c, int n, double step0, double lstep0) {
     dst[t] = cos(a);
     dst[FD_MAX_REFINE + t] = sin(a);
     dst[2 * FD_MAX_REFINE + t] = -2.0 * h * h;  // cos a - 1 without cancellation
-  }
-  if (k < 6) {
-    const double a = (double)k * 3.14159265358979323846 / 3.0;
-    c.stencil[k] = cos(a);
-    c.stencil[6 + k] = sin(a);
   }
 }
 
@@ -106,7 +101,6 @@ SearchDev make_search(const ConstsDev& c, int n_candidates, int refine_iters, in
   q.lattice = c.lattice;
   q.lattice64 = c.lattice64;
   q.steps = c.steps;
-  q.stencil = c.stencil;
   q.n_candidates = n_candidates;
   q.refine_iters = refine_iters;
   q.K = K;
@@ -145,7 +139,7 @@ hipError_t launch_topk(const SceneDev& s, const SearchDev& q, int dtype, hipStre
 template <typename T, int P, int KT>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(search_waves(P))))
 void k_fuse(SceneDev s, SearchDev q, const uint32_t* list, const uint32_t* list_count) {
-  const Group gr = make_group(q.K);
+  const Group gr = make_group<KT>(q.K);
   const int64_t blk = xcd_tile(gridDim.x);
   const int64_t wave = blk * (blockDim.x / kWave) + (threadIdx.x / kWave);
   const int64_t t = wave * gr.G + gr.g;
@@ -191,7 +185,7 @@ hipError_t launch_fuse(const SceneDev& s, const SearchDev& q, int dtype, int pat
 template <typename T, int P, int KT>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(search_waves(P))))
 void k_learned(SceneDev s, SearchDev q, LearnedDev l, int prop_by_j) {
-  const Group gr = make_group(q.K);
+  const Group gr = make_group<KT>(q.K);
   const int64_t blk = xcd_tile(gridDim.x);
   const int64_t wave = blk * (blockDim.x / kWave) + (threadIdx.x / kWave);
   const int64_t j = wave * gr.G + gr.g;
@@ -235,7 +229,7 @@ hipError_t launch_learned_refine(const SceneDev& s, const SearchDev& q, const Le
 // ---- paper-literal candidates ---------------------------------------------------
 template <typename T, int P, int KT>
 __global__ __launch_bounds__(256) void k_fpmvo(SceneDev s, SearchDev q, FpmvoDev f) {
-  const Group gr = make_group(q.K);
+  const Group gr = make_group<KT>(q.K);
   const int64_t blk = xcd_tile(gridDim.x);
   const int64_t wave = blk * (blockDim.x / kWave) + (threadIdx.x / kWave);
   const int64_t j = wave * gr.G + gr.g;

@@ -97,7 +97,6 @@ struct SearchDev {
   const float* lattice;    // n_candidates x 3, binary32 (lattice stage)
   const double* lattice64; // the same directions in binary64 (refinement start)
   const double* steps;     // cos alpha_t, sin alpha_t, cos alpha_t - 1 [FD_MAX_REFINE each]
-  const double* stencil;   // cos(j pi / 3) [6], sin(j pi / 3) [6]
   int n_candidates;
   int refine_iters;
   int K;
@@ -122,15 +121,14 @@ struct LearnedDev {
 };
 
 // Per-call constants of the search in device memory (fd_fuse.hip, k_consts):
-// the lattice in binary32 and binary64, the cos/sin tables of the plain and
-// learned refinement steps, and the stencil.
+// the lattice in binary32 and binary64 and the cos/sin tables of the plain
+// and learned refinement steps.
 struct ConstsDev {
   float* lattice;     // FD_MAX_CANDIDATES x 3
   double* lattice64;  // FD_MAX_CANDIDATES x 3
   double* steps;      // 3 x FD_MAX_REFINE (plain), then 3 x FD_MAX_REFINE (learned)
-  double* stencil;    // 12
 };
-constexpr int kConstsDoubles = 3 * FD_MAX_CANDIDATES + 6 * FD_MAX_REFINE + 12;
+constexpr int kConstsDoubles = 3 * FD_MAX_CANDIDATES + 6 * FD_MAX_REFINE;
 
 hipError_t launch_fpmvo(const SceneDev& s, const SearchDev& q, const FpmvoDev& f, int dtype,
                         int patch, hipStream_t st);
@@ -143,7 +141,7 @@ int tile_cells();
 
 // Fills the per-call constants: lattice of n directions, cos, sin and
 // cos - 1 of the plain steps step0 / 2^t (t < FD_MAX_REFINE) and of the
-// learned steps lstep0 / 2^t, and the stencil.
+// learned steps lstep0 / 2^t.
 hipError_t launch_consts(const ConstsDev& c, int n, double step0, double lstep0, hipStream_t st);
 // Per view, kCam64 binary64 values: the projection rows
 // (f_x R_0 + c_x R_2 | f_x t_0 + c_x t_2), (f_y R_1 + c_y R_2 | f_y t_1 + c_y t_2),

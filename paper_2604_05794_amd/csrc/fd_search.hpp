@@ -378,21 +378,81 @@ __device__ __forceinline__ void pin_patch(ViewPatch<P>& vp) {
 #endif
 constexpr int search_waves(int P) { return P <= 5 ? FD_SEARCH_WAVES : 1; }
 
+// Lane groups: the K lanes of one point.  With K known at compile time
+// (KT > 0) the groups lie inside the wave's 16-lane rows (16 / K groups per
+// row, the rest of the row idle: for K = 5 the same 12 groups per wave as
+// packing them end to end), so that a group's view sum can be formed with
+// row shifts (group_lead_sum); otherwise the groups are packed end to end.
+// Idle lanes belong to no point (lane_ok false) but take part in the
+// cross-lane operations of the last group of their row or wave.
 struct Group {
   int K, G, g, slot, base;
   bool lane_ok;
 };
 
+template <int KT>
 __device__ __forceinline__ Group make_group(int K) {
   Group gr;
   const int lane = threadIdx.x & (kWave - 1);
   gr.K = K;
-  gr.G = kWave / K;
-  gr.g = lane / K;
-  gr.slot = lane - gr.g * K;
-  gr.lane_ok = gr.g < gr.G;
-  gr.base = (gr.lane_ok ? gr.g : gr.G - 1) * K;
+  if constexpr (KT > 0) {
+    constexpr int R = 16 / KT;
+    static_assert(4 * R == kWave / KT, "as many groups per wave as the host's 64 / K");
+    const int row = lane >> 4, r = lane & 15;
+    const int gi = r / KT;
+    gr.G = 4 * R;
+    gr.lane_ok = gi < R;
+    const int gc = gr.lane_ok ? gi : R - 1;
+    gr.g = row * R + gc;
+    gr.slot = r - gc * KT;
+    gr.base = row * 16 + gc * KT;
+  } else {
+    gr.G = kWave / K;
+    gr.g = lane / K;
+    gr.slot = lane - gr.g * K;
+    gr.lane_ok = gr.g < gr.G;
+    gr.base = (gr.lane_ok ? gr.g : gr.G - 1) * K;
+  }
   return gr;
+}
+
+// The group's sum of v, added in slot order (slot 0 first), exact only in
+// the group's slot-0 lane: with row-aligned groups (KT > 0) that lane reads
+// slot j through a row shift by j, which never leaves the row; otherwise
+// every lane gets the sum.  A decision taken on it is passed to the rest of
+// the group with lead_value.
+// v of lane + J within the 16-lane row (DPP row_shl:J; 0 past the row's end).
+template <int J>
+__device__ __forceinline__ float row_shl(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x100 + J, 0xf, 0xf,
+                                                    false));
+}
+
+template <int KT, int J>
+__device__ __forceinline__ float lead_sum_from(float s, float v) {
+  if constexpr (J < KT)
+    return lead_sum_from<KT, J + 1>(s + row_shl<J>(v), v);
+  else
+    return s;
+}
+
+template <int KT>
+__device__ __forceinline__ float group_lead_sum(float v, int base, int k) {
+  if constexpr (KT > 0) {
+    static_assert(KT <= 16, "a group fits in a row");
+    return lead_sum_from<KT, 1>(v, v);
+  } else {
+    return group_sum<float>(v, base, k);
+  }
+}
+
+// The value x of the group's slot-0 lane, in every lane of the group.
+template <int KT>
+__device__ __forceinline__ int lead_value(int x, int base) {
+  if constexpr (KT > 0)
+    return __shfl(x, base, kWave);
+  else
+    return x;
 }
 
 // Change of this lane's view term L_v = sqrt(max_p q_p) from the centre d
@@ -425,6 +485,8 @@ __device__ __forceinline__ ViewCentre view_centre(const ViewPatch<P>& vp, float 
   const float n2 = __builtin_fmaf(ry, ry, xx);
   c.on = n2 > 0.0f;
   const float i2 = c.on ? __builtin_amdgcn_rcpf(n2) : 0.0f;
+  // off (rx = ry = 0): c2 = s2 = 0, so q_p = a_p and, with m = 0 below,
+  // g_p = a_p as the off case requires
   const float c2 = __builtin_fmaf(-ry, ry, xx) * i2, s2 = (rx * ry) * i2;
   c.zx = rx;
   c.zy = ry;
@@ -439,21 +501,51 @@ __device__ __forceinline__ ViewCentre view_centre(const ViewPatch<P>& vp, float 
   }
   m = c.on ? m : 0.0f;
 #pragma unroll
-  for (int k = 0; k < P2; ++k) g[k] = c.on ? g[k] - m : vp.a[k];
+  for (int k = 0; k < P2; ++k) g[k] -= m;
   c.q0 = m;
   c.l0 = __builtin_amdgcn_sqrtf(m);
   return c;
 }
 
+// The stencil's image offsets relative to the centre: with e1, e2 the
+// basis and z = M d, a candidate's dz = M du = (cos a - 1) z + sin a
+// (cos j M e1 + sin j M e2), so eps = dz / z = (cos a - 1) + sin a (cos j
+// A1 + sin j A2) + i sin a (cos j B1 + sin j B2) with A_k + i B_k =
+// M e_k / z, formed once per iteration.
+struct StencilFrame {
+  float a1, a2, b1, b2;  // sin a times A_k and B_k
+  float m1x, m1y, m2x, m2y;  // sin a times M e_k (off-centre views)
+};
+
+template <int P>
+__device__ __forceinline__ StencilFrame stencil_frame(const ViewPatch<P>& vp, const ViewCentre& c,
+                                                      float sa, float e1x, float e1y, float e1z,
+                                                      float e2x, float e2y, float e2z) {
+  StencilFrame f;
+  const float p1x = __builtin_fmaf(vp.M[0], e1x, __builtin_fmaf(vp.M[1], e1y, vp.M[2] * e1z));
+  const float p1y = __builtin_fmaf(vp.M[3], e1x, __builtin_fmaf(vp.M[4], e1y, vp.M[5] * e1z));
+  const float p2x = __builtin_fmaf(vp.M[0], e2x, __builtin_fmaf(vp.M[1], e2y, vp.M[2] * e2z));
+  const float p2y = __builtin_fmaf(vp.M[3], e2x, __builtin_fmaf(vp.M[4], e2y, vp.M[5] * e2z));
+  f.m1x = sa * p1x;
+  f.m1y = sa * p1y;
+  f.m2x = sa * p2x;
+  f.m2y = sa * p2y;
+  const float si = sa * c.iz2;
+  f.a1 = (p1x * c.zx + p1y * c.zy) * si;
+  f.b1 = (p1y * c.zx - p1x * c.zy) * si;
+  f.a2 = (p2x * c.zx + p2y * c.zy) * si;
+  f.b2 = (p2y * c.zx - p2x * c.zy) * si;
+  return f;
+}
+
 template <int P>
 __device__ __forceinline__ float view_delta(const ViewPatch<P>& vp, const float (&g)[P * P],
-                                            const ViewCentre& c, bool any_off, float ux,
-                                            float uy, float uz) {
+                                            const ViewCentre& c, const StencilFrame& f,
+                                            bool any_off, float cm1, float cj, float sj) {
   constexpr int P2 = P * P;
-  const float Dx = __builtin_fmaf(vp.M[0], ux, __builtin_fmaf(vp.M[1], uy, vp.M[2] * uz));
-  const float Dy = __builtin_fmaf(vp.M[3], ux, __builtin_fmaf(vp.M[4], uy, vp.M[5] * uz));
-  // centred form
-  const float er = (Dx * c.zx + Dy * c.zy) * c.iz2, ei = (Dy * c.zx - Dx * c.zy) * c.iz2;
+  // centred form: eps = er + i ei
+  const float er = __builtin_fmaf(cj, f.a1, __builtin_fmaf(sj, f.a2, cm1));
+  const float ei = __builtin_fmaf(cj, f.b1, sj * f.b2);
   const float opr = 1.0f + er;
   const float D = __builtin_fmaf(opr, opr, ei * ei);
   const float iD = __builtin_amdgcn_rcpf(D);
@@ -462,6 +554,9 @@ __device__ __forceinline__ float view_delta(const ViewPatch<P>& vp, const float 
   float ds2 = 0.5f * (c.ec * dim + c.es * dre);
   bool cand_on = D > 0.0f;
   if (any_off) {  // wave-uniform: some lane's centre direction projects to a point
+    // (z = 0 there, so dz is the stencil part alone)
+    const float Dx = __builtin_fmaf(cj, f.m1x, sj * f.m2x);
+    const float Dy = __builtin_fmaf(cj, f.m1y, sj * f.m2y);
     const float xx = Dx * Dx, n2 = __builtin_fmaf(Dy, Dy, xx);
     const float inv = __builtin_amdgcn_rcpf(n2);
     dc2 = c.on ? dc2 : __builtin_fmaf(-Dy, Dy, xx) * inv;
@@ -494,16 +589,24 @@ __device__ __forceinline__ float view_delta(const ViewPatch<P>& vp, const float 
 // carry binary32 rounding relative to the cost differences the iteration
 // compares, not to the cost; the rounding of the centre and of the basis
 // only moves the stencil by ~1e-7 of its size.  cs holds cos alpha_t,
-// sin alpha_t and cos alpha_t - 1 (FD_MAX_REFINE entries each), stencil
-// cos(j pi/3) then sin(j pi/3).
+// sin alpha_t and cos alpha_t - 1 (FD_MAX_REFINE entries each).  The six
+// changes of an iteration are formed first and then summed over the group,
+// so that their cross-lane reads are in flight together.
+//
+// Stencil cosines and sines: the binary32 roundings of the binary64 values
+// of cos(j pi / 3) and sin(j pi / 3) (sin pi rounds to 1.2246468e-16, not 0).
+constexpr float kStencilC[6] = {1.0f, 0.5f, -0.5f, -1.0f, -0.5f, 0.5f};
+constexpr float kStencilS[6] = {0.0f, 0.866025403784438597f, 0.866025403784438597f,
+                                1.22464679914735321e-16f, -0.866025403784438597f,
+                                -0.866025403784438597f};
+
 template <int P, int KT>
 __device__ __forceinline__ void refine(const ViewPatch<P>& vp, const Group& gr, int iters,
-                                       const double* __restrict__ cs,
-                                       const double* __restrict__ stencil, float& dx, float& dy,
+                                       const double* __restrict__ cs, float& dx, float& dy,
                                        float& dz) {
   for (int t = 0; t < iters; ++t) {
     const float sg = copysignf(1.0f, dz);
-    const float aa = -1.0f / (sg + dz);
+    const float aa = -__builtin_amdgcn_rcpf(sg + dz);  // |sg + dz| >= 1
     const float bb = dx * dy * aa;
     const float e1x = 1.0f + sg * dx * dx * aa, e1y = sg * bb, e1z = -sg * dx;
     const float e2x = bb, e2y = sg + dy * dy * aa, e2z = -dy;
@@ -511,24 +614,34 @@ __device__ __forceinline__ void refine(const ViewPatch<P>& vp, const Group& gr, 
     const ViewCentre c = view_centre<P>(vp, dx, dy, dz, g);
     const bool any_off = __ballot(!c.on) != 0;
     const float sa = (float)cs[FD_MAX_REFINE + t], cm1 = (float)cs[2 * FD_MAX_REFINE + t];
-    float bS = -INFINITY, bux = 0.0f, buy = 0.0f, buz = 0.0f;
-#pragma unroll 1
+    const StencilFrame f = stencil_frame<P>(vp, c, sa, e1x, e1y, e1z, e2x, e2y, e2z);
+    float dl[6];
+#pragma unroll
+    for (int jj = 0; jj < 6; ++jj)
+      dl[jj] = view_delta<P>(vp, g, c, f, any_off, cm1, kStencilC[jj], kStencilS[jj]);
+    float bS = -INFINITY;
+    int bj = 0;
+#pragma unroll
     for (int jj = 0; jj < 6; ++jj) {
-      const float cj = (float)stencil[jj], sj = (float)stencil[6 + jj];
+      const float dS = group_lead_sum<KT>(dl[jj], gr.base, gr.K);
+      if (dS > bS) {
+        bS = dS;
+        bj = jj;
+      }
+    }
+    // the slot-0 lane's decision, in every lane of the group
+    bj = lead_value<KT>(bS > 0.0f ? bj : -1, gr.base);
+    if (bj >= 0) {
+      float cj = kStencilC[0], sj = kStencilS[0];
+#pragma unroll
+      for (int jj = 1; jj < 6; ++jj) {
+        cj = bj == jj ? kStencilC[jj] : cj;
+        sj = bj == jj ? kStencilS[jj] : sj;
+      }
       const float ux = __builtin_fmaf(cm1, dx, sa * (cj * e1x + sj * e2x));
       const float uy = __builtin_fmaf(cm1, dy, sa * (cj * e1y + sj * e2y));
       const float uz = __builtin_fmaf(cm1, dz, sa * (cj * e1z + sj * e2z));
-      const float dS =
-          group_sum_t<KT>(view_delta<P>(vp, g, c, any_off, ux, uy, uz), gr.base, gr.K);
-      if (dS > bS) {
-        bS = dS;
-        bux = ux;
-        buy = uy;
-        buz = uz;
-      }
-    }
-    if (bS > 0.0f) {  // the same decision in every lane of the group
-      const float nx = dx + bux, ny = dy + buy, nz = dz + buz;
+      const float nx = dx + ux, ny = dy + uy, nz = dz + uz;
       const float il = __builtin_amdgcn_rsqf(__builtin_fmaf(nx, nx, __builtin_fmaf(ny, ny, nz * nz)));
       dx = nx * il;
       dy = ny * il;
@@ -569,8 +682,8 @@ __device__ __forceinline__ void full_search(ViewPatch<P>& vp, const SearchDev& q
   int k = 0;
   for (; k + 1 < q.n_candidates; k += 2) {
     const float* c = q.lattice + 3 * k;
-    const float S0 = group_sum_t<KT>(eval_view<P>(vp, c[0], c[1], c[2]), gr.base, gr.K);
-    const float S1 = group_sum_t<KT>(eval_view<P>(vp, c[3], c[4], c[5]), gr.base, gr.K);
+    const float S0 = group_lead_sum<KT>(eval_view<P>(vp, c[0], c[1], c[2]), gr.base, gr.K);
+    const float S1 = group_lead_sum<KT>(eval_view<P>(vp, c[3], c[4], c[5]), gr.base, gr.K);
     if (S0 > Sb) {
       Sb = S0;
       kb = k;
@@ -582,14 +695,15 @@ __device__ __forceinline__ void full_search(ViewPatch<P>& vp, const SearchDev& q
   }
   if (k < q.n_candidates) {
     const float* c = q.lattice + 3 * k;
-    const float Sk = group_sum_t<KT>(eval_view<P>(vp, c[0], c[1], c[2]), gr.base, gr.K);
+    const float Sk = group_lead_sum<KT>(eval_view<P>(vp, c[0], c[1], c[2]), gr.base, gr.K);
     if (Sk > Sb) {
       Sb = Sk;
       kb = k;
     }
   }
+  kb = lead_value<KT>(kb, gr.base);
   float fx = q.lattice[3 * kb], fy = q.lattice[3 * kb + 1], fz = q.lattice[3 * kb + 2];
-  refine<P, KT>(vp, gr, q.refine_iters, q.steps, q.stencil, fx, fy, fz);
+  refine<P, KT>(vp, gr, q.refine_iters, q.steps, fx, fy, fz);
   dx = fx;
   dy = fy;
   dz = fz;
@@ -663,7 +777,7 @@ __device__ __forceinline__ void learned_group(const SceneDev& s, const SearchDev
   float fx = valid ? (float)(dx / len) : 0.0f;
   float fy = valid ? (float)(dy / len) : 0.0f;
   float fz = valid ? (float)(dz / len) : 1.0f;
-  refine<P, KT>(vp, gr, l.iters, l.steps, q.stencil, fx, fy, fz);
+  refine<P, KT>(vp, gr, l.iters, l.steps, fx, fy, fz);
   dx = fx;
   dy = fy;
   dz = fz;
