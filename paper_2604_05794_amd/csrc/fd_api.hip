@@ -455,6 +455,7 @@ int fd::run_scene(fd_context* c, const SceneArgs& a, const fd_params* p, hipStre
   s.W = a.W;
   s.H = a.H;
   for (int k = 0; k < 3; ++k) s.hc[k] = a.hc[k];
+  s.pairs = scene_pairs(p->map_dtype, a.W, a.theta, a.conf, a.depth);
   const SearchDev q = make_search(kc, p->n_candidates, p->refine_iters, p->top_k, p->z_near);
   if ((e = launch_cams64(a.cams, a.V, c->cams64, st)) != hipSuccess)
     return hip_error(e, "camera table");

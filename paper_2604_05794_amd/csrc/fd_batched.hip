@@ -37,7 +37,7 @@ int mlp_forward_dev(const fd_mlp* m, const uint16_t* feats, int64_t n, float* ou
 
 namespace {
 
-constexpr int kBCellBits = 5;  // per axis: 32^3 cells per scene
+constexpr int kBCellBits = 6;  // per axis: 64^3 cells per scene (as one scene's tiling)
 constexpr int kBCells = 1 << (3 * kBCellBits);
 constexpr int kBlock = 256;
 
@@ -202,6 +202,17 @@ __global__ __launch_bounds__(kBlock) void k_b_topk_features(BatchDev b, SearchDe
   if (j < 0) return;
   const SceneDev sc = load_scene(b.tab, s);
   topk_features_point<T, KS>(sc, q, j, b.pt_off[s], feats);
+}
+
+// The same for batches whose scenes have at most kMaskViews views.
+template <typename T, int KS>
+__global__ __launch_bounds__(kBlock) void k_b_topk_features_m(BatchDev b, SearchDev q,
+                                                              uint16_t* __restrict__ feats) {
+  int s;
+  const int64_t j = block_point(b, &s, xcd_tile(gridDim.x));
+  if (j < 0) return;
+  const SceneDev sc = load_scene(b.tab, s);
+  topk_features_point_masked<T, KS, kMaskViews / 32>(sc, q, j, b.pt_off[s], feats);
 }
 
 // Persistent search.  Without a list, the items are the scenes' points in
@@ -437,7 +448,9 @@ int fd::context_reserve_scenes(fd_context* c, int32_t n_scenes, int64_t total_po
   if (e == hipSuccess) e = hipMalloc(&c->tile_tab, S * 6 * (1 + kBboxRep) * sizeof(int));
   if (e == hipSuccess) e = hipMalloc((void**)&c->tile_queue, kQueues * sizeof(uint32_t));
   if (e == hipSuccess) e = hipMalloc((void**)&c->batch_key, S * kBCells * sizeof(uint32_t));
-  if (e == hipSuccess) e = hipMalloc((void**)&c->batch_perm, (S * kBCells + 1024) * sizeof(uint32_t));
+  // cell cursors, then the scan's run sums
+  if (e == hipSuccess)
+    e = hipMalloc((void**)&c->batch_perm, (S * kBCells + S * (kBCells / 1024)) * sizeof(uint32_t));
   if (e != hipSuccess) {
     c->max_scenes = 0;
     return hip_error(e, "batched workspace");
@@ -536,19 +549,28 @@ static int record_batch(fd_context* c, const fd_params* p, int n_scenes, int64_t
       StageTimer t_feat(c, FD_STAGE_FEATURES, st);
       const dim3 grid((unsigned)nblocks), block(kBlock);
       const bool k5 = q.K <= 5;
+      int max_views = 0;
+      for (int s = 0; s < n_scenes; ++s) max_views = views[s] > max_views ? views[s] : max_views;
+      const bool m = max_views <= kMaskViews;
+#define FD_B_TOPK_FEATURES(T, KS)                                                           \
+  do {                                                                                      \
+    if (m)                                                                                  \
+      hipLaunchKernelGGL((k_b_topk_features_m<T, KS>), grid, block, 0, st, b, q, c->feats); \
+    else                                                                                    \
+      hipLaunchKernelGGL((k_b_topk_features<T, KS>), grid, block, 0, st, b, q, c->feats);   \
+  } while (0)
       if (p->map_dtype == FD_F16) {
         if (k5)
-          hipLaunchKernelGGL((k_b_topk_features<__half, 5>), grid, block, 0, st, b, q, c->feats);
+          FD_B_TOPK_FEATURES(__half, 5);
         else
-          hipLaunchKernelGGL((k_b_topk_features<__half, FD_TOPK_SLOTS>), grid, block, 0, st, b,
-                             q, c->feats);
+          FD_B_TOPK_FEATURES(__half, FD_TOPK_SLOTS);
       } else {
         if (k5)
-          hipLaunchKernelGGL((k_b_topk_features<float, 5>), grid, block, 0, st, b, q, c->feats);
+          FD_B_TOPK_FEATURES(float, 5);
         else
-          hipLaunchKernelGGL((k_b_topk_features<float, FD_TOPK_SLOTS>), grid, block, 0, st, b,
-                             q, c->feats);
+          FD_B_TOPK_FEATURES(float, FD_TOPK_SLOTS);
       }
+#undef FD_B_TOPK_FEATURES
       if ((e = hipGetLastError()) != hipSuccess)
         return hip_error(e, "batched view selection + features");
       t_feat.stop();
@@ -687,6 +709,8 @@ extern "C" int fd_fuse_directions_batched(const fd_scene* scenes, int32_t n_scen
       d.W = sc.width;
       d.H = sc.height;
       for (int k = 0; k < 3; ++k) d.hc[k] = sc.head_centre[k];
+      d.pairs = scene_pairs(params->map_dtype, sc.width, sc.orient_maps, sc.conf_maps,
+                            sc.depth_maps);
       tab[s] = d;
     }
     SceneDev* dtab = (SceneDev*)ctx->scene_tab;

@@ -142,9 +142,29 @@ struct ConfTexels {
   bool xin, yin;
 };
 
+// The two binary16 texels (x, x + 1) of a row, from one 8-byte load of the
+// aligned texel pair that holds x and the next pair: `row` is the row's
+// offset in texels, x & ~1 <= W - 4, W even and the map 4-byte aligned (so
+// the load stays in the row and is dword aligned).
+__device__ __forceinline__ void ld_pair_h(const void* __restrict__ base, uint32_t row,
+                                          uint32_t x, float& lo, float& hi) {
+  const uint32_t a = x & ~1u;
+  const uint2 w = *(const uint2*)((const char*)base + (uint32_t)((row + a) * 2u));
+  const uint32_t p = __builtin_amdgcn_alignbit(w.y, w.x, (x & 1u) * 16u);
+  lo = __half2float(__ushort_as_half((unsigned short)(p & 0xffffu)));
+  hi = __half2float(__ushort_as_half((unsigned short)(p >> 16)));
+}
+
+// pair loads apply: the scene allows them (binary16, even width, 4-byte
+// aligned maps) and the pair at x & ~1 and the next one lie inside the row
+template <typename T>
+__device__ __forceinline__ bool pair_ok(bool pairs, int W, uint32_t x) {
+  return sizeof(T) == 2 && pairs && (x & ~1u) + 3u < (uint32_t)W;
+}
+
 template <typename T, typename PR>
 __device__ __forceinline__ ConfTexels conf_texels(const T* __restrict__ cb, int W, int H,
-                                                     bool ok, const PR& pr) {
+                                                     bool ok, const PR& pr, bool pairs) {
   ConfTexels t;
   const double u = ok ? pr.u : 0.0, v = ok ? pr.v : 0.0;
   const double x0 = floor(u), y0 = floor(v);
@@ -155,10 +175,15 @@ __device__ __forceinline__ ConfTexels conf_texels(const T* __restrict__ cb, int 
   t.xin = ix + 1u < (uint32_t)W;
   t.yin = iy + 1u < (uint32_t)H;
   const uint32_t dx = t.xin ? 1u : 0u, dy = t.yin ? (uint32_t)W : 0u;
-  t.c00 = ld_texel<T>(cb, o00);
-  t.c10 = ld_texel<T>(cb, o00 + dx);
-  t.c01 = ld_texel<T>(cb, o00 + dy);
-  t.c11 = ld_texel<T>(cb, o00 + dx + dy);
+  if (pair_ok<T>(pairs, W, ix)) {  // x + 1 is inside the row here
+    ld_pair_h(cb, iy * (uint32_t)W, ix, t.c00, t.c10);
+    ld_pair_h(cb, iy * (uint32_t)W + dy, ix, t.c01, t.c11);
+  } else {
+    t.c00 = ld_texel<T>(cb, o00);
+    t.c10 = ld_texel<T>(cb, o00 + dx);
+    t.c01 = ld_texel<T>(cb, o00 + dy);
+    t.c11 = ld_texel<T>(cb, o00 + dx + dy);
+  }
   return t;
 }
 

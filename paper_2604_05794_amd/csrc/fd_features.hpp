@@ -15,47 +15,29 @@
 namespace fd {
 
 constexpr int kSlots = FD_FEATURE_SLOTS;
+// Scenes with at most this many views take the three-pass form
+// (topk_features_point_masked), with their visibility bits in registers.
+constexpr int kMaskViews = 128;
 constexpr float kInvPi = 0.318309886183790671538f;
 
-__device__ __forceinline__ uint16_t feat_bf16(float x) {
-  // round to nearest even
-  uint32_t u = __float_as_uint(x);
-  if ((u & 0x7f800000u) == 0x7f800000u) return (uint16_t)((u >> 16) | ((u & 0xffffu) ? 0x40u : 0u));
-  u += 0x7fffu + ((u >> 16) & 1u);
-  return (uint16_t)(u >> 16);
+typedef float feat_f32x2 __attribute__((ext_vector_type(2)));
+typedef __bf16 feat_bf16x2_t __attribute__((ext_vector_type(2)));
+
+// (a, b) rounded to bfloat16 (nearest even; the packed conversion
+// instruction), a in the low half.
+__device__ __forceinline__ uint32_t feat_bf16x2(float a, float b) {
+  const feat_bf16x2_t v = __builtin_convertvector((feat_f32x2){a, b}, feat_bf16x2_t);
+  return __builtin_bit_cast(uint32_t, v);
 }
 
 // Frontal ranking key of a view (the "most frontal" views of the proposal
-// features), in binary64 (the ranking is a discrete decision):
-//   c = -R^T t  (c_k = -((R_k t0 + R_{3+k} t1) + R_{6+k} t2))
-//   a = c - p, b = p - o
-//   score = ((a_x b_x + a_y b_y) + a_z b_z) / sqrt((a_x^2 + a_y^2) + a_z^2)
-// i.e. the cosine between the point->camera direction and the outward
-// direction p - o, times |p - o| (common to every view of the point).
-// vdir (optional) receives the unit point->camera direction a / |a|.
-__device__ __forceinline__ double frontal_score64(const float* cam, double px, double py,
-                                                  double pz, const float* o, float* vdir) {
-  const float* R = cam + 4;
-  const float* t = cam + 13;
-  const double t0 = t[0], t1 = t[1], t2 = t[2];
-  const double cx = -((double)R[0] * t0 + (double)R[3] * t1 + (double)R[6] * t2);
-  const double cy = -((double)R[1] * t0 + (double)R[4] * t1 + (double)R[7] * t2);
-  const double cz = -((double)R[2] * t0 + (double)R[5] * t1 + (double)R[8] * t2);
-  const double ax = cx - px, ay = cy - py, az = cz - pz;
-  const double bx = px - (double)o[0], by = py - (double)o[1], bz = pz - (double)o[2];
-  const double la = sqrt(ax * ax + ay * ay + az * az);
-  if (vdir) {
-    vdir[0] = (float)(ax / la);
-    vdir[1] = (float)(ay / la);
-    vdir[2] = (float)(az / la);
-  }
-  return (ax * bx + ay * by + az * bz) / la;
-}
-
-// The frontal key in the loop over every view of a point, from the camera
-// centre in the binary64 table and b = p - o computed once per point:
-// (a . b) / |a| with a reciprocal square root (agrees with frontal_score64
-// up to binary64 rounding).
+// features), in binary64 (the ranking is a discrete decision): with the
+// camera centre c = -R^T t from the binary64 table, a = c - p and
+// b = p - o (o the head centre, b formed once per point),
+//   key = (a . b) / |a|,
+// the cosine between the point->camera direction and the outward direction
+// p - o, times |p - o| (common to every view of the point); the reciprocal
+// square root is the refined hardware estimate.
 __device__ __forceinline__ double frontal_key(const double* __restrict__ c64, double px,
                                               double py, double pz, double bx, double by,
                                               double bz) {
@@ -93,69 +75,122 @@ __device__ __forceinline__ void frontal_insert(double (&sc)[kSlots], int (&id)[k
 // doubled-angle vector, psi the angle of the plane it back-projects to, in a
 // frame tied to the line of sight), the bilinear confidence C, the unit
 // point->camera direction and 1; empty slots are 0.  Written as 112
-// bfloat16 to feats row `row`.  The sample position is the binary64
-// projection; the values are formed in binary32 (the hardware sine and
-// cosine of the texel angles err by ~1e-6, far below the 2^-9 relative
-// rounding of bfloat16).
+// bfloat16 to feats row `row`.  These are values, not decisions (the slot
+// views are chosen in binary64 beforehand), and they are rounded to
+// bfloat16 (relative step 2^-8), so apart from the sample position
+// (binary64) they are formed in binary32 with the hardware reciprocal,
+// square root and sine / cosine (errors ~1e-6 relative).
 template <typename T>
-__device__ __forceinline__ void write_feature_row(const SceneDev& s, double z_near, double px,
-                                                  double py, double pz, const int (&id)[kSlots],
+__device__ __forceinline__ void write_feature_row(const SceneDev& s, double px, double py,
+                                                  double pz, const int (&id)[kSlots],
                                                   int64_t row, uint16_t* __restrict__ feats) {
   const T* th = (const T*)s.theta;
   const T* cf = (const T*)s.conf;
   const size_t plane = (size_t)s.W * s.H;
+  const float qx0 = (float)px, qy0 = (float)py, qz0 = (float)pz;
   // the row in two halves of kSlots / 2 slots (7 x 16 bytes each), so that
-  // only half of it is held in registers at a time
+  // only half of it is held in registers at a time; slots in pairs, whose
+  // 14 values convert to 7 packed bfloat16 pairs
   constexpr int kHalf = kSlots / 2;
   static_assert((7 * kHalf * 2) % 16 == 0, "half rows are whole 16-byte chunks");
+  static_assert(kHalf % 2 == 0, "slots are converted in pairs");
   uint4* dst = (uint4*)(feats + (size_t)row * (7 * kSlots));
 #pragma unroll
   for (int h = 0; h < 2; ++h) {
-  uint16_t out[7 * kHalf];
+  uint32_t out[7 * kHalf / 2];
 #pragma unroll
-  for (int kk = 0; kk < kHalf; ++kk) {
-    const int k = h * kHalf + kk;
-    float f[7] = {0, 0, 0, 0, 0, 0, 0};
+  for (int kp = 0; kp < kHalf; kp += 2) {
+  float f2[14];
+#pragma unroll
+  for (int s2 = 0; s2 < 2; ++s2) {
+    const int k = h * kHalf + kp + s2;
+    float* f = f2 + 7 * s2;
+#pragma unroll
+    for (int e = 0; e < 7; ++e) f[e] = 0.0f;
     if (id[k] >= 0) {
       const int v = id[k];
-      const float* cam = s.cams + 16 * v;
-      Proj pr;
-      project64(cam, px, py, pz, s.W, s.H, z_near, pr);
-      const double x0 = floor(pr.u), y0 = floor(pr.v);
-      const float fx = (float)(pr.u - x0), fy = (float)(pr.v - y0);
+      const float4* c4 = (const float4*)(s.cam64 + kCam64 * v + kCam32Off);
+      const float4 q0 = c4[0], q1 = c4[1], q2 = c4[2], q3 = c4[3];
+      // fx fy cx cy | R0 R1 R2 R3 | R4 R5 R6 R7 | R8 t0 t1 t2
+      // the sample position in binary64 from the same record (binary32
+      // would move the bilinear weights by ~5e-5 and flip the bfloat16
+      // rounding of many more values)
+      const double dX = __builtin_fma((double)q1.x, px, __builtin_fma((double)q1.y, py,
+                                      __builtin_fma((double)q1.z, pz, (double)q3.y)));
+      const double dY = __builtin_fma((double)q1.w, px, __builtin_fma((double)q2.x, py,
+                                      __builtin_fma((double)q2.y, pz, (double)q3.z)));
+      const double dZ = __builtin_fma((double)q2.z, px, __builtin_fma((double)q2.w, py,
+                                      __builtin_fma((double)q3.x, pz, (double)q3.w)));
+      const double idz = rcp64(dZ);  // the slot's view sees the point: dZ > z_near > 0
+      const double su = __builtin_fma((double)q0.x, dX * idz, (double)q0.z);
+      const double sv = __builtin_fma((double)q0.y, dY * idz, (double)q0.w);
+      const float pX = (float)dX, pY = (float)dY, pZ = (float)dZ;
+      const double x0 = floor(su), y0 = floor(sv);
+      const float fx = (float)(su - x0), fy = (float)(sv - y0);
       const int ix = (int)x0, iy = (int)y0;
-      const float pX = (float)pr.X, pY = (float)pr.Y, pZ = (float)pr.Z;
       float cb = 0.0f, mx = 0.0f, my = 0.0f;
+      // the 2 x 2 texels (zero outside the image); binary16 rows away from
+      // the right edge take one pair load per row and map
+      float tq[2][2], cq[2][2];
+      if (pair_ok<T>(s.pairs, s.W, (uint32_t)ix) && ix >= 0 && iy >= 0 && iy < s.H) {
+        const uint32_t r0 = (uint32_t)iy * (uint32_t)s.W;
+        const bool yin = iy + 1 < s.H;
+        const uint32_t r1 = r0 + (yin ? (uint32_t)s.W : 0u);
+        ld_pair_h(th + plane * v, r0, (uint32_t)ix, tq[0][0], tq[0][1]);
+        ld_pair_h(cf + plane * v, r0, (uint32_t)ix, cq[0][0], cq[0][1]);
+        ld_pair_h(th + plane * v, r1, (uint32_t)ix, tq[1][0], tq[1][1]);
+        ld_pair_h(cf + plane * v, r1, (uint32_t)ix, cq[1][0], cq[1][1]);
+        if (!yin) tq[1][0] = tq[1][1] = cq[1][0] = cq[1][1] = 0.0f;
+      } else {
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+          for (int a = 0; a < 2; ++a) {
+            tq[b][a] = tex_load_nb<T>(th + plane * v, s.W, s.H, ix + a, iy + b);
+            cq[b][a] = tex_load_nb<T>(cf + plane * v, s.W, s.H, ix + a, iy + b);
+          }
+      }
 #pragma unroll
       for (int b = 0; b < 2; ++b)
 #pragma unroll
         for (int a = 0; a < 2; ++a) {
           const float w = (a ? fx : 1.0f - fx) * (b ? fy : 1.0f - fy);
-          const float t = tex_load_nb<T>(th + plane * v, s.W, s.H, ix + a, iy + b);
-          const float c = tex_load_nb<T>(cf + plane * v, s.W, s.H, ix + a, iy + b);
+          const float t = tq[b][a];
+          const float c = cq[b][a];
           const float wc = w * c;
           cb += wc;
-          mx += wc * __builtin_amdgcn_cosf(t * kInvPi);
-          my += wc * __builtin_amdgcn_sinf(t * kInvPi);
+          mx = __builtin_fmaf(wc, __builtin_amdgcn_cosf(t * kInvPi), mx);
+          my = __builtin_fmaf(wc, __builtin_amdgcn_sinf(t * kInvPi), my);
         }
-      float vd[3];
-      frontal_score64(cam, px, py, pz, s.hc, vd);
+      // unit point -> camera direction vd: centre c = -R^T t
+      const float ccx = -__builtin_fmaf(q1.x, q3.y, __builtin_fmaf(q1.w, q3.z, q2.z * q3.w));
+      const float ccy = -__builtin_fmaf(q1.y, q3.y, __builtin_fmaf(q2.x, q3.z, q2.w * q3.w));
+      const float ccz = -__builtin_fmaf(q1.z, q3.y, __builtin_fmaf(q2.y, q3.z, q3.x * q3.w));
+      float vd[3] = {ccx - qx0, ccy - qy0, ccz - qz0};
+      {
+        const float il = __builtin_amdgcn_rsqf(
+            __builtin_fmaf(vd[0], vd[0], __builtin_fmaf(vd[1], vd[1], vd[2] * vd[2])));
+        vd[0] *= il;
+        vd[1] *= il;
+        vd[2] *= il;
+      }
       // The observed image line back-projects to a plane through the camera
       // centre containing the line of sight vd; its direction across vd,
       // tt = n x vd, is given by the angle psi in the frame
       // e1 = normalize(z x vd), e2 = vd x e1, carried as |m| (cos 2psi, sin 2psi).
       float qx = 0.0f, qy = 0.0f;
-      const float mag = sqrtf(mx * mx + my * my);
-      if (mag > 0.0f) {
-        const float ch = mx / mag, sh = my / mag;  // cos, sin of 2 theta
-        const float ox = sqrtf(fmaxf(0.5f * (1.0f + ch), 0.0f));
-        const float oy = copysignf(sqrtf(fmaxf(0.5f * (1.0f - ch), 0.0f)), sh);
-        const float dlx = ox / cam[0], dly = oy / cam[1];
+      const float m2 = __builtin_fmaf(mx, mx, my * my);
+      if (m2 > 0.0f) {
+        const float imag = __builtin_amdgcn_rsqf(m2);
+        const float mag = m2 * imag;
+        const float ch = mx * imag, sh = my * imag;  // cos, sin of 2 theta
+        const float ox = __builtin_amdgcn_sqrtf(fmaxf(0.5f * (1.0f + ch), 0.0f));
+        const float oy = copysignf(__builtin_amdgcn_sqrtf(fmaxf(0.5f * (1.0f - ch), 0.0f)), sh);
+        const float dlx = ox * __builtin_amdgcn_rcpf(q0.x), dly = oy * __builtin_amdgcn_rcpf(q0.y);
         const float ncx = -pZ * dly, ncy = pZ * dlx, ncz = pX * dly - pY * dlx;
-        const float* R = cam + 4;
-        const float nwx = R[0] * ncx + R[3] * ncy + R[6] * ncz;
-        const float nwy = R[1] * ncx + R[4] * ncy + R[7] * ncz;
-        const float nwz = R[2] * ncx + R[5] * ncy + R[8] * ncz;
+        const float nwx = __builtin_fmaf(q1.x, ncx, __builtin_fmaf(q1.w, ncy, q2.z * ncz));
+        const float nwy = __builtin_fmaf(q1.y, ncx, __builtin_fmaf(q2.x, ncy, q2.w * ncz));
+        const float nwz = __builtin_fmaf(q1.z, ncx, __builtin_fmaf(q2.y, ncy, q3.x * ncz));
         const float tx = nwy * vd[2] - nwz * vd[1];
         const float ty = nwz * vd[0] - nwx * vd[2];
         const float tz = nwx * vd[1] - nwy * vd[0];
@@ -163,19 +198,21 @@ __device__ __forceinline__ void write_feature_row(const SceneDev& s, double z_ne
         const float ux = vert ? 1.0f : 0.0f, uz = vert ? 0.0f : 1.0f;
         // e1 = up x vd, up = (ux, 0, uz)
         float e1x = -uz * vd[1], e1y = uz * vd[0] - ux * vd[2], e1z = ux * vd[1];
-        const float il = 1.0f / sqrtf(e1x * e1x + e1y * e1y + e1z * e1z);
+        const float il = __builtin_amdgcn_rsqf(
+            __builtin_fmaf(e1x, e1x, __builtin_fmaf(e1y, e1y, e1z * e1z)));
         e1x *= il;
         e1y *= il;
         e1z *= il;
         const float e2x = vd[1] * e1z - vd[2] * e1y;
         const float e2y = vd[2] * e1x - vd[0] * e1z;
         const float e2z = vd[0] * e1y - vd[1] * e1x;
-        const float t1 = tx * e1x + ty * e1y + tz * e1z;
-        const float t2 = tx * e2x + ty * e2y + tz * e2z;
-        const float tn = t1 * t1 + t2 * t2;
+        const float t1 = __builtin_fmaf(tx, e1x, __builtin_fmaf(ty, e1y, tz * e1z));
+        const float t2 = __builtin_fmaf(tx, e2x, __builtin_fmaf(ty, e2y, tz * e2z));
+        const float tn = __builtin_fmaf(t1, t1, t2 * t2);
         if (tn > 0.0f) {
-          qx = mag * (t1 * t1 - t2 * t2) / tn;
-          qy = mag * 2.0f * t1 * t2 / tn;
+          const float r = mag * __builtin_amdgcn_rcpf(tn);
+          qx = r * __builtin_fmaf(t1, t1, -t2 * t2);
+          qy = r * 2.0f * t1 * t2;
         }
       }
       f[0] = qx;
@@ -186,8 +223,9 @@ __device__ __forceinline__ void write_feature_row(const SceneDev& s, double z_ne
       f[5] = vd[2];
       f[6] = 1.0f;
     }
+  }
 #pragma unroll
-    for (int e = 0; e < 7; ++e) out[7 * kk + e] = feat_bf16(f[e]);
+  for (int e = 0; e < 7; ++e) out[7 * (kp / 2) + e] = feat_bf16x2(f2[2 * e], f2[2 * e + 1]);
   }
   const uint4* src = (const uint4*)out;
 #pragma unroll
@@ -222,7 +260,7 @@ __device__ __forceinline__ void features_point(const SceneDev& s, double z_near,
       continue;
     frontal_insert(sc, id, frontal_key(s.cam64 + kCam64 * v, px, py, pz, bx, by, bz), v);
   }
-  write_feature_row<T>(s, z_near, px, py, pz, id, row_base + (by_j ? j : (int64_t)i), feats);
+  write_feature_row<T>(s, px, py, pz, id, row_base + (by_j ? j : (int64_t)i), feats);
 }
 
 // Eq. (4) view selection and the proposal features in one pass over the
@@ -273,7 +311,7 @@ __device__ __forceinline__ void topk_features_point(const SceneDev& s, const Sea
 #pragma unroll
     for (int u = 0; u < kGroup; ++u) {
       any[u] = __ballot(seen[u]) != 0;  // wave-uniform
-      if (any[u]) tx[u] = conf_texels<T>(conf + plane * (v0 + u), s.W, s.H, seen[u], pr[u]);
+      if (any[u]) tx[u] = conf_texels<T>(conf + plane * (v0 + u), s.W, s.H, seen[u], pr[u], s.pairs);
     }
 #pragma unroll
     for (int u = 0; u < kGroup; ++u) {
@@ -293,7 +331,103 @@ __device__ __forceinline__ void topk_features_point(const SceneDev& s, const Sea
     s.views[FD_TOPK_SLOTS * j + k] = (uint16_t)vk[k];
   }
   s.kcount[j] = (uint8_t)keff;
-  write_feature_row<T>(s, q.z_near, px, py, pz, id, row_base + j, feats);
+  write_feature_row<T>(s, px, py, pz, id, row_base + j, feats);
+}
+
+// Bitwise OR of m over the wave, in a scalar register.
+// The same for a scene of at most 32 MW views, in three passes over the
+// views that hold less state at a time: the Eq. (4) selection (four views
+// at a time, as topk_point), which also keeps each view's visibility as a
+// bit in MW registers; the frontal ranking from those bits (projections and
+// depth texels are not read again; the views are taken in increasing order,
+// so the list is the same as the one-pass form's); the feature row.
+__device__ __forceinline__ uint32_t wave_or32(uint32_t m) {
+#pragma unroll
+  for (int off = 1; off < kWave; off <<= 1) m |= (uint32_t)__shfl_xor((int)m, off, kWave);
+  return __builtin_amdgcn_readfirstlane(m);
+}
+
+template <typename T, int KS, int MW>
+__device__ __forceinline__ void topk_features_point_masked(const SceneDev& s, const SearchDev& q,
+                                                           int64_t j, int64_t row_base,
+                                                           uint16_t* __restrict__ feats) {
+  const uint32_t i = s.perm[j];
+  const double px = s.pts[3 * (size_t)i], py = s.pts[3 * (size_t)i + 1],
+               pz = s.pts[3 * (size_t)i + 2];
+  const T* conf = (const T*)s.conf;
+  const T* depth = (const T*)s.depth;
+  const size_t plane = (size_t)s.W * s.H;
+  const double tau = (double)s.vis_tau;
+  uint32_t mask[MW];
+  {
+    double ck[KS];
+    int vk[KS];
+#pragma unroll
+    for (int k = 0; k < KS; ++k) {
+      ck[k] = -1.0;
+      vk[k] = 0;
+    }
+    constexpr int kGroup = 4;
+#pragma unroll
+    for (int w = 0; w < MW; ++w) {
+      uint32_t bits = 0;
+      const int vend = min(s.V, 32 * (w + 1));
+      for (int v0 = 32 * w; v0 < vend; v0 += kGroup) {
+        ProjT pr[kGroup];
+        bool seen[kGroup];
+#pragma unroll
+        for (int u = 0; u < kGroup; ++u) {
+          const int v = min(v0 + u, s.V - 1);
+          const bool ok =
+              project_tab(s.cam64 + kCam64 * v, px, py, pz, s.W, s.H, q.z_near, pr[u]);
+          seen[u] = visible_at<T>(depth ? depth + plane * v : nullptr, s.W, ok, pr[u], tau) &&
+                    v0 + u < s.V;
+          bits |= (seen[u] ? 1u : 0u) << (v0 + u - 32 * w);
+        }
+        ConfTexels tx[kGroup];
+        bool any[kGroup];
+#pragma unroll
+        for (int u = 0; u < kGroup; ++u) {
+          any[u] = __ballot(seen[u]) != 0;  // wave-uniform
+          if (any[u]) tx[u] = conf_texels<T>(conf + plane * (v0 + u), s.W, s.H, seen[u], pr[u], s.pairs);
+        }
+#pragma unroll
+        for (int u = 0; u < kGroup; ++u) {
+          if (!any[u]) continue;
+          const double c = seen[u] ? conf_combine(tx[u]) : 0.0;
+          if (c > 0.0) topk_insert<KS>(ck, vk, c, v0 + u);
+        }
+      }
+      mask[w] = bits;
+    }
+    int keff = 0;
+#pragma unroll
+    for (int k = 0; k < KS; ++k) {
+      if (k < q.K && ck[k] > 0.0) keff = k + 1;
+      s.views[FD_TOPK_SLOTS * j + k] = (uint16_t)vk[k];
+    }
+    s.kcount[j] = (uint8_t)keff;
+  }
+  double sc[kSlots];
+  int id[kSlots];
+#pragma unroll
+  for (int k = 0; k < kSlots; ++k) {
+    sc[k] = -INFINITY;
+    id[k] = -1;
+  }
+  const double bx = px - (double)s.hc[0], by = py - (double)s.hc[1], bz = pz - (double)s.hc[2];
+#pragma unroll
+  for (int w = 0; w < MW; ++w) {
+    uint32_t um = wave_or32(mask[w]);  // views some lane of the wave sees
+    while (um) {
+      const int b = __builtin_ctz(um);
+      um &= um - 1u;
+      const int v = 32 * w + b;
+      if ((mask[w] >> b) & 1u)
+        frontal_insert(sc, id, frontal_key(s.cam64 + kCam64 * v, px, py, pz, bx, by, bz), v);
+    }
+  }
+  write_feature_row<T>(s, px, py, pz, id, row_base + j, feats);
 }
 
 }  // namespace fd

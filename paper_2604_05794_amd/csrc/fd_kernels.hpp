@@ -39,7 +39,16 @@ struct SceneDev {
   int V, W, H;
   float hc[3];          // head centre (frontal ranking)
   float vis_tau;        // visibility tolerance on |Z - D|
+  int pairs;            // texel pairs may be read with 4-byte loads (scene_pairs)
 };
+
+// Texel pairs of a row may be read with dword-aligned loads: binary16 maps
+// of even width whose base addresses are 4-byte aligned.
+inline int scene_pairs(int map_dtype, int W, const void* theta, const void* conf,
+                       const void* depth) {
+  const uintptr_t a = (uintptr_t)theta | (uintptr_t)conf | (uintptr_t)depth;
+  return map_dtype == FD_F16 && (W & 1) == 0 && (a & 3u) == 0;
+}
 
 // A scene record read from device memory (the batched scene table) would
 // hold generic pointers, which the compiler addresses with flat
@@ -65,6 +74,7 @@ struct SceneDevGlobal {
   int V, W, H;
   float hc[3];
   float vis_tau;
+  int pairs;
 };
 static_assert(sizeof(SceneDevGlobal) == sizeof(SceneDev), "scene record views differ");
 
@@ -143,11 +153,13 @@ int tile_cells();
 // cos - 1 of the plain steps step0 / 2^t (t < FD_MAX_REFINE) and of the
 // learned steps lstep0 / 2^t.
 hipError_t launch_consts(const ConstsDev& c, int n, double step0, double lstep0, hipStream_t st);
-// Per view, kCam64 binary64 values: the projection rows
+// Per view, kCam64 binary64 slots: the projection rows
 // (f_x R_0 + c_x R_2 | f_x t_0 + c_x t_2), (f_y R_1 + c_y R_2 | f_y t_1 + c_y t_2),
 // (R_2 | t_2) (R_i the rows of R), so that u = row0 . (p, 1) / row2 . (p, 1),
-// then the camera centre -R^T t.
-constexpr int kCam64 = 16;
+// then the camera centre -R^T t and a zero; then (slots 16-23, 16-byte
+// aligned) the camera record itself, 16 binary32 values, for vector loads.
+constexpr int kCam64 = 24;
+constexpr int kCam32Off = 16;  // first slot of the binary32 record
 hipError_t launch_cams64(const float* cams, int V, double* out, hipStream_t st);
 // Search constants as the kernels read them.
 SearchDev make_search(const ConstsDev& c, int n_candidates, int refine_iters, int K,

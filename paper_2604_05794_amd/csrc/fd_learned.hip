@@ -36,6 +36,14 @@ __global__ __launch_bounds__(256) void k_topk_features(SceneDev s, SearchDev q,
   topk_features_point<T, KS>(s, q, j, 0, feats);
 }
 
+template <typename T, int KS>
+__global__ __launch_bounds__(256) void k_topk_features_m(SceneDev s, SearchDev q,
+                                                         uint16_t* __restrict__ feats) {
+  const int64_t j = xcd_tile(gridDim.x) * blockDim.x + threadIdx.x;
+  if (j >= s.n) return;
+  topk_features_point_masked<T, KS, kMaskViews / 32>(s, q, j, 0, feats);
+}
+
 }  // namespace
 
 static hipError_t launch_features_rows(const SceneDev& s, int dtype, float z_near, int by_j,
@@ -68,19 +76,26 @@ int fd::run_learned(fd_context* c, const SceneDev& s, const SearchDev& q, const 
     StageTimer tf(c, FD_STAGE_FEATURES, st);
     dim3 grid((unsigned)((s.n + 255) / 256));
     const bool k5 = q.K <= 5;  // a list of 5 slots holds any top-K with K <= 5
+    const bool m = s.V <= kMaskViews;
+#define FD_TOPK_FEATURES(T, KS)                                                            \
+  do {                                                                                     \
+    if (m)                                                                                 \
+      hipLaunchKernelGGL((k_topk_features_m<T, KS>), grid, dim3(256), 0, st, s, q, c->feats); \
+    else                                                                                   \
+      hipLaunchKernelGGL((k_topk_features<T, KS>), grid, dim3(256), 0, st, s, q, c->feats);   \
+  } while (0)
     if (p->map_dtype == FD_F16) {
       if (k5)
-        hipLaunchKernelGGL((k_topk_features<__half, 5>), grid, dim3(256), 0, st, s, q, c->feats);
+        FD_TOPK_FEATURES(__half, 5);
       else
-        hipLaunchKernelGGL((k_topk_features<__half, FD_TOPK_SLOTS>), grid, dim3(256), 0, st, s,
-                           q, c->feats);
+        FD_TOPK_FEATURES(__half, FD_TOPK_SLOTS);
     } else {
       if (k5)
-        hipLaunchKernelGGL((k_topk_features<float, 5>), grid, dim3(256), 0, st, s, q, c->feats);
+        FD_TOPK_FEATURES(float, 5);
       else
-        hipLaunchKernelGGL((k_topk_features<float, FD_TOPK_SLOTS>), grid, dim3(256), 0, st, s,
-                           q, c->feats);
+        FD_TOPK_FEATURES(float, FD_TOPK_SLOTS);
     }
+#undef FD_TOPK_FEATURES
     if ((e = hipGetLastError()) != hipSuccess) return hip_error(e, "view selection + features");
     tf.stop();
     StageTimer tm(c, FD_STAGE_MLP, st);
@@ -171,6 +186,7 @@ extern "C" int fd_features(const float* points, int64_t n_points, const fd_camer
   s.W = params->width;
   s.H = params->height;
   for (int k = 0; k < 3; ++k) s.hc[k] = params->head_centre[k];
+  s.pairs = scene_pairs(params->map_dtype, s.W, orient_maps, conf_maps, params->depth_maps);
   hipError_t e = launch_features_rows(s, params->map_dtype, params->z_near, 0, (uint16_t*)feats,
                                       (hipStream_t)params->stream);
   return e == hipSuccess ? FD_OK : hip_error(e, "feature kernel");

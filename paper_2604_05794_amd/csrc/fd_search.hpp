@@ -88,7 +88,7 @@ __device__ __forceinline__ void topk_point(const SceneDev& s, const SearchDev& q
 #pragma unroll
     for (int u = 0; u < kGroup; ++u) {
       any[u] = __ballot(seen[u]) != 0;  // wave-uniform
-      if (any[u]) tx[u] = conf_texels<T>(conf + plane * (v0 + u), s.W, s.H, seen[u], pr[u]);
+      if (any[u]) tx[u] = conf_texels<T>(conf + plane * (v0 + u), s.W, s.H, seen[u], pr[u], s.pairs);
     }
 #pragma unroll
     for (int u = 0; u < kGroup; ++u) {
@@ -156,9 +156,9 @@ __device__ __forceinline__ void build_patch(const SceneDev& s, const SearchDev& 
   const int ix = (int)x0 - HP, iy = (int)y0 - HP;
   // texel rows of the (P+1)^2 footprint: C, C cos 2theta, C sin 2theta
   float rc[2][P + 1], rx[2][P + 1], ry[2][P + 1];
-  // binary16 rows away from the right edge of an even-width map: one 16-byte
-  // load per map covers texels [ix & ~1, (ix & ~1) + 7] of the row
-  const bool wide_ok = sizeof(T) == 2 && P <= 5 && (s.W & 1) == 0;
+  // binary16 rows away from the right edge of an even-width, 4-byte aligned
+  // map: one 16-byte load per map covers texels [ix & ~1, (ix & ~1) + 7]
+  const bool wide_ok = sizeof(T) == 2 && P <= 5 && s.pairs;
   auto load_row = [&](int slot, int y) {
     float tv[P + 1], cv[P + 1];
     const int a0 = ix & ~1;
@@ -425,7 +425,7 @@ __device__ __forceinline__ Group make_group(int K) {
 template <int J>
 __device__ __forceinline__ float row_shl(float v) {
   return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x100 + J, 0xf, 0xf,
-                                                    false));
+                                                    true));
 }
 
 template <int KT, int J>

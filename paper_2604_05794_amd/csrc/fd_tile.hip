@@ -195,12 +195,47 @@ hipError_t launch_tiling(const float* pts, int64_t n, TileWork w, hipStream_t st
   return hipGetLastError();
 }
 
-// Exclusive scan of n_runs x 1024 counts (n_runs <= 1024) into cursor.
+// Exclusive scan in place of the n run sums (one block; each thread scans
+// a chunk of at most kMaxRunsPerThread consecutive sums).
+constexpr int kMaxRunsPerThread = 16;
+__global__ __launch_bounds__(1024) void k_run_scan(uint32_t* __restrict__ sums, int n) {
+  __shared__ uint32_t wsum[16];
+  const int per = (n + kScanRun - 1) / kScanRun;
+  const int r0 = threadIdx.x * per;
+  uint32_t loc = 0;
+  for (int k = 0; k < per; ++k)
+    if (r0 + k < n) loc += sums[r0 + k];
+  uint32_t run = block_incl_scan(loc, wsum) - loc;
+  for (int k = 0; k < per; ++k)
+    if (r0 + k < n) {
+      const uint32_t v = sums[r0 + k];
+      sums[r0 + k] = run;
+      run += v;
+    }
+}
+
+// Run r's cell starts: its exclusive prefix (sums[r]) plus the scan within
+// the run.
+__global__ __launch_bounds__(1024) void k_cell_scan_from(const uint32_t* __restrict__ counts,
+                                                         const uint32_t* __restrict__ sums,
+                                                         uint32_t* __restrict__ cursor) {
+  __shared__ uint32_t wsum[16];
+  const uint32_t b = sums[blockIdx.x];
+  const uint32_t v = counts[(size_t)blockIdx.x * kScanRun + threadIdx.x];
+  const uint32_t incl = block_incl_scan(v, wsum);
+  cursor[(size_t)blockIdx.x * kScanRun + threadIdx.x] = b + incl - v;
+}
+
+// Exclusive scan of n_runs x 1024 counts (n_runs <= 16384) into cursor, in
+// three passes: run sums, their scan, the runs; `sums` (n_runs entries)
+// ends up holding each run's exclusive prefix.
 hipError_t launch_scan_runs(const uint32_t* counts, int n_runs, uint32_t* sums, uint32_t* cursor,
                             hipStream_t st) {
-  if (n_runs < 1 || n_runs > 1024) return hipErrorInvalidValue;
+  if (n_runs < 1 || n_runs > kScanRun * kMaxRunsPerThread) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_cell_block_sums, dim3(n_runs), dim3(kScanRun), 0, st, counts, sums);
-  hipLaunchKernelGGL(k_cell_scan, dim3(n_runs), dim3(kScanRun), 0, st, counts, sums, cursor);
+  hipLaunchKernelGGL(k_run_scan, dim3(1), dim3(kScanRun), 0, st, sums, n_runs);
+  hipLaunchKernelGGL(k_cell_scan_from, dim3(n_runs), dim3(kScanRun), 0, st, counts, sums,
+                     cursor);
   return hipGetLastError();
 }
 

@@ -117,6 +117,39 @@ def test_float16_non_square_maps():
     assert_parity(res)
 
 
+def _misaligned(t):
+    """A copy of t whose data starts 2 bytes past a 4-byte boundary."""
+    flat = torch.empty(t.numel() + 1, dtype=t.dtype, device=t.device)
+    v = flat[1:].view(t.shape)
+    v.copy_(t)
+    assert v.data_ptr() % 4 == 2
+    return v
+
+
+def test_maps_not_4_byte_aligned_take_single_texel_loads():
+    """Binary16 maps whose base is only 2-byte aligned (or of odd width)
+    cannot take the paired texel loads; the results are bitwise those of
+    the aligned maps, in the plain search and the proposal features."""
+    nat = _native()
+    rec = dict(scenegen.RECIPES["realistic"])
+    rec["n_points"] = 3000
+    rec["n_views"] = 16
+    rec["res"] = 256
+    sc = scenegen.make_scene(rec, 21)
+    pts, cams, th, cf = _dev(sc)
+    dm = torch.from_numpy(sc.depth).to(th.device)
+    kw = dict(patch=5, n_candidates=64, refine_iters=6, top_k=5, depth_maps=dm)
+    d0, c0 = nat.fuse_directions(pts, cams, th, cf, **kw)
+    f0 = nat.features(pts, cams, th, cf, head_centre=sc.head_centre, depth_maps=dm)
+    kw["depth_maps"] = _misaligned(dm)
+    d1, c1 = nat.fuse_directions(pts, cams, _misaligned(th), _misaligned(cf), **kw)
+    f1 = nat.features(pts, cams, _misaligned(th), _misaligned(cf), head_centre=sc.head_centre,
+                      depth_maps=kw["depth_maps"])
+    torch.cuda.synchronize()
+    assert torch.equal(d0, d1) and torch.equal(c0, c1)
+    assert torch.equal(f0, f1)
+
+
 @pytest.mark.parametrize("n", [1, 2, 11, 12, 13, 47, 48, 49, 61])
 def test_ragged_sizes(n):
     sc = _scene("tiny")
