@@ -205,14 +205,19 @@ __global__ __launch_bounds__(kBlock) void k_b_topk_features(BatchDev b, SearchDe
 }
 
 // The same for batches whose scenes have at most kMaskViews views.
+// (a workgroup's points belong to one scene, whose camera table it copies
+// to LDS first).
 template <typename T, int KS>
 __global__ __launch_bounds__(kBlock) void k_b_topk_features_m(BatchDev b, SearchDev q,
                                                               uint16_t* __restrict__ feats) {
+  __shared__ double ctab[kMaskViews * kCam64];
   int s;
   const int64_t j = block_point(b, &s, xcd_tile(gridDim.x));
-  if (j < 0) return;
   const SceneDev sc = load_scene(b.tab, s);
-  topk_features_point_masked<T, KS, kMaskViews / 32>(sc, q, j, b.pt_off[s], feats);
+  for (int e = threadIdx.x; e < sc.V * kCam64; e += kBlock) ctab[e] = sc.cam64[e];
+  __syncthreads();
+  if (j < 0) return;
+  topk_features_point_masked<T, KS, kMaskViews / 32>(sc, q, ctab, j, b.pt_off[s], feats);
 }
 
 // Persistent search.  Without a list, the items are the scenes' points in

@@ -87,8 +87,8 @@ __global__ void k_cams64(const float* __restrict__ cams, int V, double* __restri
   for (int k = 0; k < 3; ++k)
     o[12 + k] = -((double)R[k] * t[0] + (double)R[3 + k] * t[1] + (double)R[6 + k] * t[2]);
   o[15] = 0.0;
-  float* o32 = (float*)(o + kCam32Off);
-  for (int k = 0; k < 16; ++k) o32[k] = c[k];
+  for (int k = 0; k < 8; ++k)
+    o[kCam32Off + k] = __builtin_bit_cast(double, make_float2(c[2 * k], c[2 * k + 1]));
 }
 
 hipError_t launch_cams64(const float* cams, int V, double* out, hipStream_t st) {

@@ -43,11 +43,11 @@ struct SceneDev {
 };
 
 // Texel pairs of a row may be read with dword-aligned loads: binary16 maps
-// of even width whose base addresses are 4-byte aligned.
+// of even width (at least 4) whose base addresses are 4-byte aligned.
 inline int scene_pairs(int map_dtype, int W, const void* theta, const void* conf,
                        const void* depth) {
   const uintptr_t a = (uintptr_t)theta | (uintptr_t)conf | (uintptr_t)depth;
-  return map_dtype == FD_F16 && (W & 1) == 0 && (a & 3u) == 0;
+  return map_dtype == FD_F16 && (W & 1) == 0 && W >= 4 && (a & 3u) == 0;
 }
 
 // A scene record read from device memory (the batched scene table) would
@@ -99,6 +99,7 @@ __device__ __forceinline__ SceneDev load_scene(const SceneDev* tab, int s) {
   d.H = g.H;
   for (int k = 0; k < 3; ++k) d.hc[k] = g.hc[k];
   d.vis_tau = g.vis_tau;
+  d.pairs = g.pairs;
   return d;
 }
 #undef FD_GLOBAL

@@ -39,9 +39,12 @@ __global__ __launch_bounds__(256) void k_topk_features(SceneDev s, SearchDev q,
 template <typename T, int KS>
 __global__ __launch_bounds__(256) void k_topk_features_m(SceneDev s, SearchDev q,
                                                          uint16_t* __restrict__ feats) {
+  __shared__ double ctab[kMaskViews * kCam64];
+  for (int e = threadIdx.x; e < s.V * kCam64; e += blockDim.x) ctab[e] = s.cam64[e];
+  __syncthreads();
   const int64_t j = xcd_tile(gridDim.x) * blockDim.x + threadIdx.x;
   if (j >= s.n) return;
-  topk_features_point_masked<T, KS, kMaskViews / 32>(s, q, j, 0, feats);
+  topk_features_point_masked<T, KS, kMaskViews / 32>(s, q, ctab, j, 0, feats);
 }
 
 }  // namespace
