@@ -18,19 +18,25 @@ import subprocess
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+# FD_ORACLE_LIB selects another build of the same sources (the sanitizer test)
+_LIB_PATH = os.environ.get("FD_ORACLE_LIB") or os.path.join(_HERE, "liboracle.so")
 _SOURCES = ("fdo.c", "mlp.c", "gabor.c", "volume.c", "phg.c")
 
 
-def build() -> str:
-    """Compile liboracle.so with gcc (binary64, OpenMP, no FP contraction)."""
+def build(out=None, sanitize=False) -> str:
+    """Compile liboracle.so with gcc (binary64, OpenMP, no FP contraction);
+    sanitize=True adds AddressSanitizer and UndefinedBehaviorSanitizer
+    (aborting on the first report) for a build at `out`."""
+    out = out or _LIB_PATH
     srcs = [os.path.join(_HERE, s) for s in _SOURCES]
-    tmp = _LIB_PATH + ".tmp"
-    cmd = ["gcc", "-O2", "-std=c99", "-fopenmp", "-ffp-contract=off",
-           "-fno-fast-math", "-fPIC", "-shared", "-Wall", "-o", tmp] + srcs + ["-lm"]
+    tmp = out + ".tmp"
+    san = (["-fsanitize=address,undefined", "-fno-sanitize-recover=all",
+            "-fno-omit-frame-pointer", "-g"] if sanitize else [])
+    cmd = (["gcc", "-O2", "-std=c99", "-fopenmp", "-ffp-contract=off", "-fno-fast-math",
+            "-fPIC", "-shared", "-Wall"] + san + ["-o", tmp] + srcs + ["-lm"])
     subprocess.run(cmd, check=True)
-    os.replace(tmp, _LIB_PATH)
-    return _LIB_PATH
+    os.replace(tmp, out)
+    return out
 
 
 class TraceParams(ctypes.Structure):
