@@ -225,12 +225,15 @@ __global__ __launch_bounds__(kFwdThreads, 2) void k_mlp_fwd(const uint16_t* __re
 
 // ---- training: generic bfloat16 matrix product and elementwise kernels -------------
 // C[m][n] = sum_k A(m, k) B(k, n), A(m, k) = a[m * sam + k * sak],
-// B(k, n) = b[k * sbk + n * sbn]; M % 16 == 0, N % 64 == 0 (columns >= N_real
-// are not stored), K % 32 == 0.  One wave per 16 x 64 output block, k in
-// ascending order: deterministic.  Epilogue:
-//   EPI_STORE      c[m * ldc + n] = acc                        (n < n_real, m < m_real)
+// B(k, n) = b[k * sbk + n * sbn], each operand contiguous along k (sak = 1,
+// sbk = 1) or along m / n (sam = 1, sbn = 1); N % 64 == 0, K % 32 == 0 (per
+// K slice), rows m >= M read as zero.  Columns >= n_real and rows >=
+// m_real are not stored.  k in ascending order per slice: deterministic.
+// Epilogue:
+//   EPI_STORE      c[m * ldc + n] = acc
 //   EPI_BIAS_GELU  z = acc + bias[n]; zf[m*ldc+n] = z; h[m*ldh+n] = bf16(gelu(z))
-//   EPI_GELU_BACK  d = acc * gelu'(zf[m*ldc+n]); df[..] = d; dq[m*ldh+n] = bf16(d)
+//   EPI_GELU_BACK  d = acc * gelu'(zf[m*ldc+n]); dq[m*ldh+n] = bf16(d); df[tile][n] =
+//                  sum of d over the tile's rows (the next bias gradient's partials)
 enum { EPI_STORE = 0, EPI_BIAS_GELU = 1, EPI_GELU_BACK = 2 };
 
 struct GemmArgs {
@@ -243,58 +246,131 @@ struct GemmArgs {
   float* c;  // EPI_STORE: output; EPI_BIAS_GELU: z out; EPI_GELU_BACK: z in
   int64_t ldc;
   const float* bias;
-  float* df;     // EPI_GELU_BACK: float gradient out
+  float* df;     // EPI_GELU_BACK: per 64-row tile column sums of the gradient (tiles x N)
   uint16_t* hq;  // bf16 out
   int64_t ldh;
   int ksplit;    // > 1: K in ksplit slices, fp32 partial tiles to part (EPI_STORE only)
   float* part;   // ksplit x M x N
 };
 
-__global__ __launch_bounds__(64) void k_gemm_bf16(GemmArgs g) {
-  const int lane = threadIdx.x, gr = lane >> 4, c16 = lane & 15;
-  const int m0 = blockIdx.x * 16, n0 = blockIdx.y * 64;
+// Workgroup tile 64 x 64 (four waves; wave w takes output columns
+// [16w, 16w + 16) of all 64 rows: four 16 x 16 MFMA tiles).  K is taken in
+// stages of up to kGemmKS: every global load of a stage is issued first
+// (16 bytes per thread and 32-k step), then stored to LDS with k contiguous
+// (rows padded by 8 elements) — a k-contiguous operand as it is, an m- or
+// n-contiguous one transposed with 2-byte stores — and after one barrier
+// the products of the whole stage run from LDS.
+constexpr int kGemmT = 64, kGemmK = 32, kGemmKS = 256, kGemmLd = kGemmKS + 8;
+
+template <bool AK, bool BK>
+__device__ __forceinline__ void gemm_load_step(const GemmArgs& g, int m0, int n0, int k0, int t,
+                                               uint4& va, uint4& vb) {
+  if (AK) {  // thread t: row t / 4, k 8 (t % 4) .. + 7
+    const int r = t >> 2, kq = (t & 3) * 8;
+    va = m0 + r < g.M ? *(const uint4*)(g.a + (int64_t)(m0 + r) * g.sam + k0 + kq)
+                      : make_uint4(0, 0, 0, 0);
+  } else {   // thread t: k t / 8, rows 8 (t % 8) .. + 7 (M is a multiple of 64 here)
+    const int k = t >> 3, mq = (t & 7) * 8;
+    va = *(const uint4*)(g.a + (int64_t)(k0 + k) * g.sak + m0 + mq);
+  }
+  if (BK) {
+    const int r = t >> 2, kq = (t & 3) * 8;
+    vb = *(const uint4*)(g.b + (int64_t)(n0 + r) * g.sbn + k0 + kq);
+  } else {
+    const int k = t >> 3, nq = (t & 7) * 8;
+    vb = *(const uint4*)(g.b + (int64_t)(k0 + k) * g.sbk + n0 + nq);
+  }
+}
+
+template <bool AK, bool BK>
+__device__ __forceinline__ void gemm_store_step(uint16_t (*As)[kGemmLd], uint16_t (*Bs)[kGemmLd],
+                                                int kk, int t, const uint4& va, const uint4& vb) {
+  if (AK) {
+    *(uint4*)&As[t >> 2][kk + (t & 3) * 8] = va;
+  } else {
+    const int k = t >> 3, mq = (t & 7) * 8;
+    const uint32_t w[4] = {va.x, va.y, va.z, va.w};
+#pragma unroll
+    for (int j = 0; j < 8; ++j) As[mq + j][kk + k] = (uint16_t)(w[j >> 1] >> (16 * (j & 1)));
+  }
+  if (BK) {
+    *(uint4*)&Bs[t >> 2][kk + (t & 3) * 8] = vb;
+  } else {
+    const int k = t >> 3, nq = (t & 7) * 8;
+    const uint32_t w[4] = {vb.x, vb.y, vb.z, vb.w};
+#pragma unroll
+    for (int j = 0; j < 8; ++j) Bs[nq + j][kk + k] = (uint16_t)(w[j >> 1] >> (16 * (j & 1)));
+  }
+}
+
+// Column sums over the tile's 64 rows of the values v[mt][r] (row
+// 16 mt + 4 gr + r, column c16 of the wave's 16): rows in order within a
+// lane, then the four row groups gr in order (the same for every tile).
+__device__ __forceinline__ float gemm_colsum(const float (&v)[4][4], int lane) {
+  float s = 0.0f;
+#pragma unroll
+  for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) s += v[mt][r];
+  // lanes c16, c16 + 16, c16 + 32, c16 + 48 hold row groups 0..3
+  const float s1 = __shfl(s, (lane & 15) + 16, 64), s2 = __shfl(s, (lane & 15) + 32, 64),
+              s3 = __shfl(s, (lane & 15) + 48, 64), s0 = __shfl(s, lane & 15, 64);
+  return ((s0 + s1) + s2) + s3;
+}
+
+template <bool AK, bool BK>
+__global__ __launch_bounds__(256) void k_gemm_bf16(GemmArgs g) {
+  __shared__ __attribute__((aligned(16))) uint16_t As[kGemmT][kGemmLd];
+  __shared__ __attribute__((aligned(16))) uint16_t Bs[kGemmT][kGemmLd];
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6, gr = lane >> 4, c16 = lane & 15;
+  const int m0 = blockIdx.x * kGemmT, n0 = blockIdx.y * kGemmT;
   f32x4 acc[4];
 #pragma unroll
-  for (int nt = 0; nt < 4; ++nt) acc[nt] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+  for (int mt = 0; mt < 4; ++mt) acc[mt] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
   const int kslice = g.K / g.ksplit;
   const int kz0 = blockIdx.z * kslice, kz1 = kz0 + kslice;
-  for (int k0 = kz0; k0 < kz1; k0 += 32) {
-    bf16x8 a;
-    const int64_t am = (int64_t)(m0 + c16) * g.sam;
+  for (int ks = kz0; ks < kz1; ks += kGemmKS) {
+    const int kn = min(kGemmKS, kz1 - ks);  // a multiple of 32
+    uint4 va[kGemmKS / kGemmK], vb[kGemmKS / kGemmK];
 #pragma unroll
-    for (int j = 0; j < 8; ++j) {
-      const int64_t k = k0 + 8 * gr + j;
-      a[j] = __ushort_as_bfloat16(g.a[am + k * g.sak]);
-    }
+    for (int q = 0; q < kGemmKS / kGemmK; ++q)
+      if (q * kGemmK < kn) gemm_load_step<AK, BK>(g, m0, n0, ks + q * kGemmK, t, va[q], vb[q]);
+    if (ks > kz0) __syncthreads();  // the previous stage's products are done
 #pragma unroll
-    for (int nt = 0; nt < 4; ++nt) {
-      bf16x8 b;
-      const int64_t bn = (int64_t)(n0 + 16 * nt + c16) * g.sbn;
+    for (int q = 0; q < kGemmKS / kGemmK; ++q)
+      if (q * kGemmK < kn) gemm_store_step<AK, BK>(As, Bs, q * kGemmK, t, va[q], vb[q]);
+    __syncthreads();
+#pragma unroll 2
+    for (int kk = 0; kk < kn; kk += kGemmK) {
+      const bf16x8 b = *(const bf16x8*)&Bs[16 * w + c16][kk + 8 * gr];
 #pragma unroll
-      for (int j = 0; j < 8; ++j) {
-        const int64_t k = k0 + 8 * gr + j;
-        b[j] = __ushort_as_bfloat16(g.b[k * g.sbk + bn]);
+      for (int mt = 0; mt < 4; ++mt) {
+        const bf16x8 a = *(const bf16x8*)&As[16 * mt + c16][kk + 8 * gr];
+        acc[mt] = mfma(a, b, acc[mt]);
       }
-      acc[nt] = mfma(a, b, acc[nt]);
     }
   }
+  // acc[mt] holds D[4 gr + r][c16] of the tile (rows 16 mt + ..., columns 16 w + ...)
+  const int n = n0 + 16 * w + c16;
   if (g.ksplit > 1) {  // partial tile of this K slice; k_gemm_reduce finishes
 #pragma unroll
-    for (int nt = 0; nt < 4; ++nt)
+    for (int mt = 0; mt < 4; ++mt)
 #pragma unroll
-      for (int r = 0; r < 4; ++r)
-        g.part[((size_t)blockIdx.z * g.M + m0 + 4 * gr + r) * g.N + n0 + 16 * nt + c16] =
-            acc[nt][r];
+      for (int r = 0; r < 4; ++r) {
+        const int m = m0 + 16 * mt + 4 * gr + r;
+        if (m < g.M) g.part[((size_t)blockIdx.z * g.M + m) * g.N + n] = acc[mt][r];
+      }
     return;
   }
+  float dsum[4][4];
 #pragma unroll
-  for (int nt = 0; nt < 4; ++nt) {
-    const int n = n0 + 16 * nt + c16;
+  for (int mt = 0; mt < 4; ++mt) {
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      const int m = m0 + 4 * gr + r;
-      if (m >= g.m_real || n >= g.n_real) continue;
-      const float v = acc[nt][r];
+      const int m = m0 + 16 * mt + 4 * gr + r;
+      dsum[mt][r] = 0.0f;
+      if (m >= g.m_real || m >= g.M || n >= g.n_real) continue;
+      const float v = acc[mt][r];
       if (g.epi == EPI_STORE) {
         g.c[m * g.ldc + n] = v;
       } else if (g.epi == EPI_BIAS_GELU) {
@@ -303,10 +379,16 @@ __global__ __launch_bounds__(64) void k_gemm_bf16(GemmArgs g) {
         g.hq[m * g.ldh + n] = f2bf(gelu(z));
       } else {
         const float d = v * gelu_grad(g.c[m * g.ldc + n]);
-        g.df[m * g.ldc + n] = d;
+        dsum[mt][r] = d;
         g.hq[m * g.ldh + n] = f2bf(d);
       }
     }
+  }
+  if (g.epi == EPI_GELU_BACK) {
+    // the bias gradient's partial over this tile's rows (float d), for
+    // k_col_finish to sum over the row tiles in order
+    const float cs = gemm_colsum(dsum, lane);
+    if (gr == 0) g.df[(size_t)blockIdx.x * g.N + n] = cs;
   }
 }
 
@@ -330,20 +412,47 @@ __global__ void k_pad_input(const uint16_t* __restrict__ f, int B, uint16_t* __r
   x[i] = k < D0 ? f[r * D0 + k] : 0;
 }
 
-// Output layer forward + loss + its gradient, one row per thread:
+// Output layer forward + loss + its gradient, eight lanes per row (lane j
+// takes k in [32 j, 32 j + 32) in order; the eight partial sums are added
+// by a fixed shuffle tree):
 // y = h3 W4 + b4 (float, W4 as bfloat16 values), u = y/|y|, loss_b = 1 - (u.t)^2,
 // dL/dy = (g - u (u.g)) / |y| with g = -2 (u.t) t / B.
-__global__ void k_out_loss(const uint16_t* __restrict__ h3, const uint16_t* __restrict__ w4t,
-                           const float* __restrict__ bias4, const float* __restrict__ tgt, int B,
-                           float* __restrict__ dy, float* __restrict__ loss_row) {
-  const int b = blockIdx.x * blockDim.x + threadIdx.x;
-  if (b >= B) return;
-  float y[3];
-  for (int n = 0; n < 3; ++n) {
-    float s = 0.0f;
-    for (int k = 0; k < DH; ++k) s += bf2f(h3[b * DH + k]) * bf2f(w4t[n * DH + k]);
-    y[n] = s + bias4[n];
+constexpr int kOutLanes = 8;
+__global__ __launch_bounds__(256) void k_out_loss(const uint16_t* __restrict__ h3,
+                                                  const uint16_t* __restrict__ w4t,
+                                                  const float* __restrict__ bias4,
+                                                  const float* __restrict__ tgt, int B,
+                                                  float* __restrict__ dy,
+                                                  float* __restrict__ loss_row) {
+  const int b = (int)((blockIdx.x * blockDim.x + threadIdx.x) / kOutLanes);
+  const int j = (int)(threadIdx.x % kOutLanes);
+  const int bb = b < B ? b : B - 1;  // every lane takes part in the shuffles
+  float part[3] = {0.0f, 0.0f, 0.0f};
+  const int k0 = j * (DH / kOutLanes);
+#pragma unroll
+  for (int q = 0; q < DH / kOutLanes; q += 8) {
+    const uint4 hv = *(const uint4*)(h3 + (size_t)bb * DH + k0 + q);
+    const uint32_t hw[4] = {hv.x, hv.y, hv.z, hv.w};
+#pragma unroll
+    for (int n = 0; n < 3; ++n) {
+      const uint4 wv = *(const uint4*)(w4t + n * DH + k0 + q);
+      const uint32_t ww[4] = {wv.x, wv.y, wv.z, wv.w};
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const uint16_t he = (uint16_t)(hw[e >> 1] >> (16 * (e & 1)));
+        const uint16_t we = (uint16_t)(ww[e >> 1] >> (16 * (e & 1)));
+        part[n] += bf2f(he) * bf2f(we);
+      }
+    }
   }
+#pragma unroll
+  for (int n = 0; n < 3; ++n)
+#pragma unroll
+    for (int off = 1; off < kOutLanes; off <<= 1) part[n] += __shfl_xor(part[n], off, 64);
+  if (j != 0 || b >= B) return;
+  float y[3];
+#pragma unroll
+  for (int n = 0; n < 3; ++n) y[n] = part[n] + bias4[n];
   const float nrm = sqrtf(y[0] * y[0] + y[1] * y[1] + y[2] * y[2]);
   float u[3], t[3], ut = 0.0f;
   for (int n = 0; n < 3; ++n) {
@@ -539,7 +648,7 @@ int ensure_train_ws(fd_mlp* m, int B) {
   if (e == hipSuccess) e = hipMalloc(&m->dz, Bs * DH * 4);
   if (e == hipSuccess) e = hipMalloc(&m->dzq, Bs * DH * 2);
   if (e == hipSuccess)
-    e = hipMalloc(&m->part, (Bs / kRowChunk + 1) * (size_t)kOutGrad * 4);
+    e = hipMalloc(&m->part, (Bs / kRowChunk + 1) * (size_t)kOutGrad * 4);  // >= tiles x DH
   if (e == hipSuccess) e = hipMalloc(&m->split, (size_t)kMaxSplit * DH * DH * 4);
   if (e != hipSuccess) {
     m->cap_batch = 0;
@@ -550,8 +659,19 @@ int ensure_train_ws(fd_mlp* m, int B) {
 }
 
 int launch_gemm(const GemmArgs& g, hipStream_t st) {
-  dim3 grid(g.M / 16, g.N / 64, g.ksplit);
-  hipLaunchKernelGGL(k_gemm_bf16, grid, dim3(64), 0, st, g);
+  const bool ak = g.sak == 1, bk = g.sbk == 1;
+  if ((!ak && g.sam != 1) || (!bk && g.sbn != 1) || g.N % kGemmT || (!ak && g.M % kGemmT) ||
+      (g.K / g.ksplit) % kGemmK)
+    return set_error(FD_E_INVAL, "mlp gemm: unsupported operand layout or shape");
+  dim3 grid((g.M + kGemmT - 1) / kGemmT, g.N / kGemmT, g.ksplit);
+  if (ak && bk)
+    hipLaunchKernelGGL((k_gemm_bf16<true, true>), grid, dim3(256), 0, st, g);
+  else if (ak)
+    hipLaunchKernelGGL((k_gemm_bf16<true, false>), grid, dim3(256), 0, st, g);
+  else if (bk)
+    hipLaunchKernelGGL((k_gemm_bf16<false, true>), grid, dim3(256), 0, st, g);
+  else
+    hipLaunchKernelGGL((k_gemm_bf16<false, false>), grid, dim3(256), 0, st, g);
   if (g.ksplit > 1)
     hipLaunchKernelGGL(k_gemm_reduce, dim3((g.M * g.N + 255) / 256), dim3(256), 0, st, g.part,
                        g.ksplit, g.M, g.N, g.m_real, g.n_real, g.c, g.ldc);
@@ -603,8 +723,8 @@ int loss_grad(fd_mlp* m, const uint16_t* feats, const float* tgt, int B, hipStre
     g.ldh = DH;
     if ((r = launch_gemm(g, st))) return r;
   }
-  hipLaunchKernelGGL(k_out_loss, dim3((B + 255) / 256), dim3(256), 0, st, m->h[2], m->pk.w4t,
-                     m->pk.bias + 3 * DH, tgt, B, m->dy, m->lrow);
+  hipLaunchKernelGGL(k_out_loss, dim3((B * kOutLanes + 255) / 256), dim3(256), 0, st, m->h[2],
+                     m->pk.w4t, m->pk.bias + 3 * DH, tgt, B, m->dy, m->lrow);
   hipLaunchKernelGGL(k_sum_rows, dim3(1), dim3(256), 0, st, m->lrow, B, m->loss);
   const int chunks = (B + kRowChunk - 1) / kRowChunk;
   hipLaunchKernelGGL(k_outw_partial, dim3((kOutGrad + 255) / 256, chunks), dim3(256), 0, st,
@@ -614,11 +734,15 @@ int loss_grad(fd_mlp* m, const uint16_t* feats, const float* tgt, int B, hipStre
   hipLaunchKernelGGL(k_out_back, dim3((B * DH + 255) / 256), dim3(256), 0, st, m->dy,
                      m->pk.w4t, m->z[2], B, m->dz, m->dzq);
   const int offW[3] = {OFF_W1, OFF_W2, OFF_W3}, offB[3] = {OFF_B1, OFF_B2, OFF_B3};
+  const int tiles = (B + kGemmT - 1) / kGemmT;
   for (int l = 2; l >= 0; --l) {
-    // bias gradient of layer l from the float dz
-    hipLaunchKernelGGL(k_col_partial, dim3(1, chunks), dim3(DH), 0, st, m->dz, B, DH, m->part);
-    hipLaunchKernelGGL(k_col_finish, dim3(DH / 4), dim3(256), 0, st, m->part, chunks, DH,
-                       m->grad + offB[l]);
+    // bias gradient of layer l: sums of the float dz over the batch, as row
+    // chunk partials (k_out_back's dz for the last hidden layer, the
+    // previous input-gradient product's tile partials for the others)
+    if (l == 2)
+      hipLaunchKernelGGL(k_col_partial, dim3(1, chunks), dim3(DH), 0, st, m->dz, B, DH, m->part);
+    hipLaunchKernelGGL(k_col_finish, dim3(DH / 4), dim3(256), 0, st, m->part,
+                       l == 2 ? chunks : tiles, DH, m->grad + offB[l]);
     // weight gradient: dW_l[k][n] = sum_b h_{l-1}[b][k] dzq[b][n]
     {
       GemmArgs g = gemm_args();
@@ -660,14 +784,13 @@ int loss_grad(fd_mlp* m, const uint16_t* feats, const float* tgt, int B, hipStre
       g.epi = EPI_GELU_BACK;
       g.c = m->z[l - 1];
       g.ldc = DH;
-      // the new gradient goes to the buffers of layer l (z[l], h[l] are no
-      // longer needed: gelu'(z[l]) and h[l]'s weight gradient are done)
-      g.df = m->z[l];
+      // the new bfloat16 gradient goes to h[l] (no longer needed: h[l]'s
+      // weight gradient is done), its bias-gradient partials to part
+      g.df = m->part;
       g.hq = m->h[l];
       g.ldh = DH;
       if ((r = launch_gemm(g, st))) return r;
     }
-    std::swap(m->dz, m->z[l]);
     std::swap(m->dzq, m->h[l]);
   }
   hipError_t e = hipGetLastError();
