@@ -107,23 +107,29 @@ __global__ void k_mlp_pack(const float* __restrict__ m, Packed p) {
 }
 
 // ---- inference: fused four-layer forward ----------------------------------------------
-// One workgroup (8 waves) = 128 rows.  Activations stay in LDS (128 x 256
-// bfloat16, rows padded by 16 bytes); wave w produces output columns
-// [32w, 32w + 32) of every hidden layer for all 128 rows.  The product is
+// One workgroup = 128 rows.  Activations stay in LDS (128 x 256 bfloat16,
+// rows padded by 16 bytes); wave w produces output columns
+// [kCols w, kCols (w + 1)) of every hidden layer for all 128 rows.  The product is
 // issued as Z^T = W^T X^T (weights as the A operand, activations as B), so
 // that each lane ends up holding four consecutive output columns of one row
 // and writes them to LDS with one 8-byte store.  Weight fragments come
 // straight from the L2-resident packed weights, one k-step ahead.
 constexpr int FWD_ROWS = 128;
 constexpr int ACT_LD = DH + 8;
-// 8 waves per workgroup, each producing kCols = 32 output columns of every
-// hidden layer (two 16-column MFMA tiles) for all 128 rows; the output
-// layer gives each wave one 16-row tile.
-constexpr int kFwdWaves = 8;
+// FD_MLP_FWD_WAVES waves per workgroup, each producing kCols output columns
+// of every hidden layer (kNt 16-column MFMA tiles) for all 128 rows; the
+// output layer gives each wave 128 / (16 kFwdWaves) 16-row tiles.  Eight
+// waves (two column tiles each) measure faster than four (four each, half
+// the LDS reads per product): 0.49 against 0.53 ms per 1M rows.
+#ifndef FD_MLP_FWD_WAVES
+#define FD_MLP_FWD_WAVES 8
+#endif
+constexpr int kFwdWaves = FD_MLP_FWD_WAVES;
 constexpr int kFwdThreads = 64 * kFwdWaves;
 constexpr int kCols = DH / kFwdWaves;
 constexpr int kNt = kCols / 16;
-static_assert(FWD_ROWS == 16 * kFwdWaves, "one output-layer row tile per wave");
+constexpr int kOutTiles = FWD_ROWS / (16 * kFwdWaves);
+static_assert(FWD_ROWS % (16 * kFwdWaves) == 0, "whole output-layer row tiles per wave");
 
 // GELU (tanh form) for the inference forward: 0.5 x (1 + tanh(u)) = x / (1 +
 // e^(-2u)), u = sqrt(2/pi) (x + 0.044715 x^3), with e^(-2u) = 2^(x (A + B x^2))
@@ -201,16 +207,21 @@ __global__ __launch_bounds__(kFwdThreads, 2) void k_mlp_fwd(const uint16_t* __re
     }
     __syncthreads();
   }
-  // output layer: 256 -> 16 (3 real); wave w takes batch-row tile w
-  f32x4 o = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
-  for (int kc = 0; kc < DH; kc += 32) {
-    const bf16x8 b = *(const bf16x8*)(p.w4t + (size_t)c16 * DH + kc + 8 * g);
-    const bf16x8 a = *(const bf16x8*)(act + (16 * w + c16) * ACT_LD + kc + 8 * g);
-    o = mfma(a, b, o);
-  }
-  if (c16 < 3) {
+  // output layer: 256 -> 16 (3 real); wave w takes batch-row tiles
+  // w, w + kFwdWaves, ...
 #pragma unroll
-    for (int r = 0; r < 4; ++r) yout[16 * w + 4 * g + r][c16] = o[r] + p.bias[3 * DH + c16];
+  for (int ot = 0; ot < kOutTiles; ++ot) {
+    const int rt = w + ot * kFwdWaves;
+    f32x4 o = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+    for (int kc = 0; kc < DH; kc += 32) {
+      const bf16x8 b = *(const bf16x8*)(p.w4t + (size_t)c16 * DH + kc + 8 * g);
+      const bf16x8 a = *(const bf16x8*)(act + (16 * rt + c16) * ACT_LD + kc + 8 * g);
+      o = mfma(a, b, o);
+    }
+    if (c16 < 3) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) yout[16 * rt + 4 * g + r][c16] = o[r] + p.bias[3 * DH + c16];
+    }
   }
   __syncthreads();
   if (t < FWD_ROWS && row0 + t < n) {
