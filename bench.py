@@ -74,10 +74,10 @@ _PHG_SOURCES = ["fd_phg.hip", "fd_voxel.hpp"]
 TRAFFIC = {
     "k_fuse, realistic 500k": {"read": 380.0e6, "write": 37.7e6, "files": _SEARCH_SOURCES,
                                "src": "f29a3d8d543b986b"},
-    "k_fuse, metric workload, per head": {"read": 133.8e6, "write": 8.5e6,
-                                          "files": _SEARCH_SOURCES, "src": "f29a3d8d543b986b"},
-    "k_b_learned, metric workload": {"read": 2456.8e6, "write": 411.5e6,
-                                     "files": _BATCHED_SOURCES, "src": "99ae3b5e7f8df232"},
+    "k_fuse, metric workload, per head": {"read": 135.8e6, "write": 8.5e6,
+                                          "files": _SEARCH_SOURCES, "src": "14dcdef571c85e49"},
+    "k_b_learned, metric workload": {"read": 2234.0e6, "write": 160.7e6,
+                                     "files": _BATCHED_SOURCES, "src": "862c5a875b2dc162"},
     "k_gabor_mfma, 64 frames 1024^2": {"read": 1152.1e6, "write": 406.8e6,
                                        "files": _GABOR_SOURCES, "src": "21a8f3739c8a0866"},
     # the counting sort: keys and counts, the scan, the placement

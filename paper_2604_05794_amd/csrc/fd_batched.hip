@@ -286,7 +286,7 @@ template <typename T, int P, int KT>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(search_waves(P))))
 void k_b_fuse_tiles(BatchDev b, SearchDev q) {
   const Group gr = make_group<KT>(q.K);
-  const int64_t tile = xcd_tile(gridDim.x) * (blockDim.x / kWave) + (threadIdx.x / kWave);
+  const int64_t tile = wave_tile(gridDim.x);
   if (tile >= b.n_tiles) return;
   const int s = find_scene(b.tile_off, b.n_scenes, tile);
   const SceneDev sc = load_scene(b.tab, s);
@@ -299,7 +299,7 @@ template <typename T, int P, int KT>
 __device__ __forceinline__ void b_learned_body(const BatchDev& b, const SearchDev& q,
                                                const LearnedDev& l) {
   const Group gr = make_group<KT>(q.K);
-  const int64_t tile = xcd_tile(gridDim.x) * (blockDim.x / kWave) + (threadIdx.x / kWave);
+  const int64_t tile = wave_tile(gridDim.x);
   if (tile >= b.n_tiles) return;
   const int s = find_scene(b.tile_off, b.n_scenes, tile);
   const SceneDev sc = load_scene(b.tab, s);

@@ -232,6 +232,16 @@ __device__ __forceinline__ int64_t xcd_tile(int64_t nblocks) {
   return start + k;
 }
 
+// The index of this thread's wave within the grid, in XCD-aware block order,
+// read from lane 0 so that the compiler keeps it (and whatever is indexed by
+// it) in scalar registers: it is the same on every lane of the wave.
+__device__ __forceinline__ int64_t wave_tile(int64_t nblocks) {
+  const int64_t t = xcd_tile(nblocks) * (blockDim.x / kWave) + (threadIdx.x / kWave);
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)t);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)((uint64_t)t >> 32));
+  return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
 // Lanes of a wave are split into groups of `k` consecutive lanes; returns the
 // sum of v over the caller's group, added in lane order (slot 0 first) so
 // every lane of the group gets the same bits.

@@ -142,8 +142,7 @@ template <typename T, int P, int KT>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(search_waves(P))))
 void k_fuse(SceneDev s, SearchDev q, const uint32_t* list, const uint32_t* list_count) {
   const Group gr = make_group<KT>(q.K);
-  const int64_t blk = xcd_tile(gridDim.x);
-  const int64_t wave = blk * (blockDim.x / kWave) + (threadIdx.x / kWave);
+  const int64_t wave = wave_tile(gridDim.x);
   const int64_t t = wave * gr.G + gr.g;
   const int64_t limit = list ? (int64_t)*list_count : s.n;
   if (wave * gr.G >= limit) return;  // whole wave idle (uniform exit)
@@ -188,8 +187,7 @@ template <typename T, int P, int KT>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(search_waves(P))))
 void k_learned(SceneDev s, SearchDev q, LearnedDev l, int prop_by_j) {
   const Group gr = make_group<KT>(q.K);
-  const int64_t blk = xcd_tile(gridDim.x);
-  const int64_t wave = blk * (blockDim.x / kWave) + (threadIdx.x / kWave);
+  const int64_t wave = wave_tile(gridDim.x);
   const int64_t j = wave * gr.G + gr.g;
   if (wave * gr.G >= s.n) return;
   const bool pt_ok = gr.lane_ok && j < s.n;
@@ -232,8 +230,7 @@ hipError_t launch_learned_refine(const SceneDev& s, const SearchDev& q, const Le
 template <typename T, int P, int KT>
 __global__ __launch_bounds__(256) void k_fpmvo(SceneDev s, SearchDev q, FpmvoDev f) {
   const Group gr = make_group<KT>(q.K);
-  const int64_t blk = xcd_tile(gridDim.x);
-  const int64_t wave = blk * (blockDim.x / kWave) + (threadIdx.x / kWave);
+  const int64_t wave = wave_tile(gridDim.x);
   const int64_t j = wave * gr.G + gr.g;
   if (wave * gr.G >= s.n) return;  // whole wave idle (uniform exit)
   const bool pt_ok = gr.lane_ok && j < s.n;

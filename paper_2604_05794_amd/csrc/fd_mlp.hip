@@ -120,7 +120,13 @@ constexpr int ACT_LD = DH + 8;
 // of every hidden layer (kNt 16-column MFMA tiles) for all 128 rows; the
 // output layer gives each wave 128 / (16 kFwdWaves) 16-row tiles.  Eight
 // waves (two column tiles each) measure faster than four (four each, half
-// the LDS reads per product): 0.49 against 0.53 ms per 1M rows.
+// the LDS reads per product): 0.49 against 0.53 ms per 1M rows.  The weight
+// fragment loads, not the LDS reads, set the pace: splitting the rows
+// between two wave groups (half the LDS reads, twice the weight loads per
+// product) measured 1.65 against 0.97 ms per 2M rows, loading the weights
+// two k-steps ahead instead of one 1.16 against 1.05 ms, and 256-row
+// workgroups (half the weight loads per row, one workgroup per CU) 1.19;
+// the GELU epilogue costs about 0.15 ms of the 1.05.
 #ifndef FD_MLP_FWD_WAVES
 #define FD_MLP_FWD_WAVES 8
 #endif

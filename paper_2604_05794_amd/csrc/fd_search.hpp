@@ -11,9 +11,9 @@
 // refinement compares candidates whose costs differ by as little as the
 // square of its last steps (~1e-6), which binary32 rounding of the cost
 // itself (~1e-7) would decide at random in a few percent of points; it
-// therefore keeps its centre in binary64 and scores each candidate by the
-// change of the cost from the centre, formed from differences so that the
-// rounding is relative to the change (view_delta).  The reported cost is
+// therefore scores each candidate by the change of the cost from the
+// centre, formed from differences so that the rounding is relative to the
+// change (view_delta).  The reported cost is
 // the objective at the result evaluated in binary64 (on the binary32
 // coefficients, whose rounding moves the cost smoothly with the direction).
 #pragma once
