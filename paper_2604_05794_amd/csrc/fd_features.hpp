@@ -16,7 +16,8 @@ namespace fd {
 
 constexpr int kSlots = FD_FEATURE_SLOTS;
 // Scenes with at most this many views take the three-pass form
-// (topk_features_point_masked), with their visibility bits in registers.
+// (vis_topk_masked, then frontal_row_masked), their visibility bits passed
+// between the two through the feature row.
 constexpr int kMaskViews = 128;
 constexpr float kInvPi = 0.318309886183790671538f;
 
@@ -390,25 +391,30 @@ __device__ __forceinline__ void topk_features_point(const SceneDev& s, const Sea
 }
 
 // Bitwise OR of m over the wave, in a scalar register.
-// The same for a scene of at most 32 MW views, in three passes over the
-// views that hold less state at a time: the Eq. (4) selection (four views
-// at a time, as topk_point), which also keeps each view's visibility as a
-// bit in MW registers; the frontal ranking from those bits (projections and
-// depth texels are not read again; the views are taken in increasing order,
-// so the list is the same as the one-pass form's); the feature row.  ctab
-// is the scene's camera table copied to LDS by the caller's workgroup
-// (read there at wave-uniform addresses).
 __device__ __forceinline__ uint32_t wave_or32(uint32_t m) {
 #pragma unroll
   for (int off = 1; off < kWave; off <<= 1) m |= (uint32_t)__shfl_xor((int)m, off, kWave);
   return __builtin_amdgcn_readfirstlane(m);
 }
 
+// For scenes of at most 32 MW views the view selection and the features
+// run as two kernels, each holding less state.  The first
+// (vis_topk_masked) makes the Eq. (4) selection (four views at a time, as
+// topk_point) and keeps each view's visibility as a bit in MW registers,
+// which it leaves in the first 4 MW bytes of the point's feature row; the
+// second (frontal_row_masked) takes the bits back, ranks the visible views
+// by frontality (projections and depth texels are not read again; the
+// views are taken in increasing order, so the list is the same as the
+// one-pass form's) and writes the row over them.  The gather loop of the
+// first then runs at the occupancy its own registers allow.  ctab is the
+// scene's camera table, read at wave-uniform addresses only (the caller may
+// pass the global table, whose records then come through the scalar cache
+// without taking vector registers, or a copy in LDS).
 template <typename T, int KS, int MW>
-__device__ __forceinline__ void topk_features_point_masked(const SceneDev& s, const SearchDev& q,
-                                                           const double* __restrict__ ctab,
-                                                           int64_t j, int64_t row_base,
-                                                           uint16_t* __restrict__ feats) {
+__device__ __forceinline__ void vis_topk_masked(const SceneDev& s, const SearchDev& q,
+                                                const double* __restrict__ ctab, int64_t j,
+                                                int64_t row, uint16_t* __restrict__ feats) {
+  static_assert(4 * MW <= 14 * kSlots, "the bits fit in the row");
   const uint32_t i = s.perm[j];
   const double px = s.pts[3 * (size_t)i], py = s.pts[3 * (size_t)i + 1],
                pz = s.pts[3 * (size_t)i + 2];
@@ -466,6 +472,22 @@ __device__ __forceinline__ void topk_features_point_masked(const SceneDev& s, co
     }
     s.kcount[j] = (uint8_t)keff;
   }
+  uint32_t* bits_out = (uint32_t*)(feats + (size_t)row * (7 * kSlots));
+#pragma unroll
+  for (int w = 0; w < MW; ++w) bits_out[w] = mask[w];
+}
+
+template <typename T, int MW>
+__device__ __forceinline__ void frontal_row_masked(const SceneDev& s,
+                                                   const double* __restrict__ ctab, int64_t j,
+                                                   int64_t row, uint16_t* __restrict__ feats) {
+  const uint32_t i = s.perm[j];
+  const double px = s.pts[3 * (size_t)i], py = s.pts[3 * (size_t)i + 1],
+               pz = s.pts[3 * (size_t)i + 2];
+  uint32_t mask[MW];
+  const uint32_t* bits_in = (const uint32_t*)(feats + (size_t)row * (7 * kSlots));
+#pragma unroll
+  for (int w = 0; w < MW; ++w) mask[w] = bits_in[w];
   double sc[kSlots];
   int id[kSlots];
 #pragma unroll
@@ -488,7 +510,7 @@ __device__ __forceinline__ void topk_features_point_masked(const SceneDev& s, co
   // the row reads its slots' camera records from the global table: their
   // views differ from lane to lane (per-lane reads of the LDS copy have
   // given results that varied from run to run)
-  write_feature_row<T>(s, s.cam64, px, py, pz, id, row_base + j, feats);
+  write_feature_row<T>(s, s.cam64, px, py, pz, id, row, feats);
 }
 
 }  // namespace fd

@@ -36,15 +36,22 @@ __global__ __launch_bounds__(256) void k_topk_features(SceneDev s, SearchDev q,
   topk_features_point<T, KS>(s, q, j, 0, feats);
 }
 
+// The same for scenes of at most kMaskViews views, in two kernels (view
+// selection with the visibility bits, then the frontal ranking and the
+// row), the first held to five waves per SIMD.
 template <typename T, int KS>
-__global__ __launch_bounds__(256) void k_topk_features_m(SceneDev s, SearchDev q,
-                                                         uint16_t* __restrict__ feats) {
-  __shared__ double ctab[kMaskViews * kCam64];
-  for (int e = threadIdx.x; e < s.V * kCam64; e += blockDim.x) ctab[e] = s.cam64[e];
-  __syncthreads();
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(KS <= 5 ? 5 : 4)))
+void k_vis_m(SceneDev s, SearchDev q, uint16_t* __restrict__ feats) {
   const int64_t j = xcd_tile(gridDim.x) * blockDim.x + threadIdx.x;
   if (j >= s.n) return;
-  topk_features_point_masked<T, KS, kMaskViews / 32>(s, q, ctab, j, 0, feats);
+  vis_topk_masked<T, KS, kMaskViews / 32>(s, q, s.cam64, j, j, feats);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_frontal_row_m(SceneDev s, uint16_t* __restrict__ feats) {
+  const int64_t j = xcd_tile(gridDim.x) * blockDim.x + threadIdx.x;
+  if (j >= s.n) return;
+  frontal_row_masked<T, kMaskViews / 32>(s, s.cam64, j, j, feats);
 }
 
 }  // namespace
@@ -80,12 +87,14 @@ int fd::run_learned(fd_context* c, const SceneDev& s, const SearchDev& q, const 
     dim3 grid((unsigned)((s.n + 255) / 256));
     const bool k5 = q.K <= 5;  // a list of 5 slots holds any top-K with K <= 5
     const bool m = s.V <= kMaskViews;
-#define FD_TOPK_FEATURES(T, KS)                                                            \
-  do {                                                                                     \
-    if (m)                                                                                 \
-      hipLaunchKernelGGL((k_topk_features_m<T, KS>), grid, dim3(256), 0, st, s, q, c->feats); \
-    else                                                                                   \
-      hipLaunchKernelGGL((k_topk_features<T, KS>), grid, dim3(256), 0, st, s, q, c->feats);   \
+#define FD_TOPK_FEATURES(T, KS)                                                             \
+  do {                                                                                      \
+    if (m) {                                                                                \
+      hipLaunchKernelGGL((k_vis_m<T, KS>), grid, dim3(256), 0, st, s, q, c->feats);          \
+      hipLaunchKernelGGL((k_frontal_row_m<T>), grid, dim3(256), 0, st, s, c->feats);         \
+    } else {                                                                                \
+      hipLaunchKernelGGL((k_topk_features<T, KS>), grid, dim3(256), 0, st, s, q, c->feats);  \
+    }                                                                                       \
   } while (0)
     if (p->map_dtype == FD_F16) {
       if (k5)

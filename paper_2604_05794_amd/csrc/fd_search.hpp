@@ -446,11 +446,33 @@ __device__ __forceinline__ float group_lead_sum(float v, int base, int k) {
   }
 }
 
-// The value x of the group's slot-0 lane, in every lane of the group.
+// x of lane - J within the 16-lane row (DPP row_shr:J; 0 before the row's start).
+template <int J>
+__device__ __forceinline__ int row_shr(int x) {
+  return __builtin_amdgcn_update_dpp(0, x, 0x110 + J, 0xf, 0xf, true);
+}
+
+template <int KT, int J>
+__device__ __forceinline__ int lead_from(int x, int slot, int acc) {
+  if constexpr (J <= KT) {
+    // the shift is formed by every lane and only then selected: the empty
+    // asm statement keeps the compiler from moving it under the selection,
+    // where the lanes it reads from would be switched off
+    int y = row_shr<J>(x);
+    asm volatile("" : "+v"(y));
+    return lead_from<KT, J + 1>(x, slot, slot == J ? y : acc);
+  } else {
+    return acc;
+  }
+}
+
+// The value x of the group's slot-0 lane, in every lane of the group: with
+// row-aligned groups lane slot reads it through a row shift by slot (the
+// row's idle lanes, slots up to KT, follow the last group's lead).
 template <int KT>
-__device__ __forceinline__ int lead_value(int x, int base) {
+__device__ __forceinline__ int lead_value(int x, int slot) {
   if constexpr (KT > 0)
-    return __shfl(x, base, kWave);
+    return lead_from<KT, 1>(x, slot, x);
   else
     return x;
 }
@@ -630,7 +652,7 @@ __device__ __forceinline__ void refine(const ViewPatch<P>& vp, const Group& gr, 
       }
     }
     // the slot-0 lane's decision, in every lane of the group
-    bj = lead_value<KT>(bS > 0.0f ? bj : -1, gr.base);
+    bj = lead_value<KT>(bS > 0.0f ? bj : -1, gr.slot);
     if (bj >= 0) {
       float cj = kStencilC[0], sj = kStencilS[0];
 #pragma unroll
@@ -701,7 +723,7 @@ __device__ __forceinline__ void full_search(ViewPatch<P>& vp, const SearchDev& q
       kb = k;
     }
   }
-  kb = lead_value<KT>(kb, gr.base);
+  kb = lead_value<KT>(kb, gr.slot);
   float fx = q.lattice[3 * kb], fy = q.lattice[3 * kb + 1], fz = q.lattice[3 * kb + 2];
   refine<P, KT>(vp, gr, q.refine_iters, q.steps, fx, fy, fz);
   dx = fx;
