@@ -256,7 +256,13 @@ __device__ __forceinline__ void build_patch64(const SceneDev& s, const SearchDev
   const double x0 = floor(pr.u), y0 = floor(pr.v);
   const double fx = pr.u - x0, fy = pr.v - y0;
   const int ix = (int)x0 - HP, iy = (int)y0 - HP;
+  // One patch row per pass (the loop is not unrolled: each sample takes
+  // four sine/cosine evaluations), appended at the end of the arrays after
+  // the earlier rows move up by one row, so that every array index is a
+  // constant and the patch stays in registers (indexing by the row made it
+  // a private array in memory).
   for (int b = 0; b < P; ++b) {
+    double ra[P], rb[P], rc[P];
 #pragma unroll
     for (int a = 0; a < P; ++a) {
       double cb = 0.0, mx = 0.0, my = 0.0;
@@ -275,10 +281,21 @@ __device__ __forceinline__ void build_patch64(const SceneDev& s, const SearchDev
         }
       const double n = sqrt(mx * mx + my * my);
       const double al = 0.5 * cb * cb;
-      const int k = b * P + a;
-      vp.a[k] = n > 0.0 ? al : 0.0;
-      vp.b[k] = n > 0.0 ? al * mx / n : 0.0;
-      vp.c[k] = n > 0.0 ? 2.0 * al * my / n : 0.0;
+      ra[a] = n > 0.0 ? al : 0.0;
+      rb[a] = n > 0.0 ? al * mx / n : 0.0;
+      rc[a] = n > 0.0 ? 2.0 * al * my / n : 0.0;
+    }
+#pragma unroll
+    for (int k = 0; k < P2 - P; ++k) {
+      vp.a[k] = vp.a[k + P];
+      vp.b[k] = vp.b[k + P];
+      vp.c[k] = vp.c[k + P];
+    }
+#pragma unroll
+    for (int a = 0; a < P; ++a) {
+      vp.a[P2 - P + a] = ra[a];
+      vp.b[P2 - P + a] = rb[a];
+      vp.c[P2 - P + a] = rc[a];
     }
   }
 }
