@@ -279,44 +279,47 @@ struct GemmArgs {
 // the products of the whole stage run from LDS.
 constexpr int kGemmT = 64, kGemmK = 32, kGemmKS = 256, kGemmLd = kGemmKS + 8;
 
+// Operand staging registers as a native vector type (the uint4 struct
+// copied between an array and LDS made the compiler keep the array in
+// private memory).
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
 template <bool AK, bool BK>
 __device__ __forceinline__ void gemm_load_step(const GemmArgs& g, int m0, int n0, int k0, int t,
-                                               uint4& va, uint4& vb) {
+                                               u32x4& va, u32x4& vb) {
   if (AK) {  // thread t: row t / 4, k 8 (t % 4) .. + 7
     const int r = t >> 2, kq = (t & 3) * 8;
-    va = m0 + r < g.M ? *(const uint4*)(g.a + (int64_t)(m0 + r) * g.sam + k0 + kq)
-                      : make_uint4(0, 0, 0, 0);
+    va = m0 + r < g.M ? *(const u32x4*)(g.a + (int64_t)(m0 + r) * g.sam + k0 + kq)
+                      : u32x4{0u, 0u, 0u, 0u};
   } else {   // thread t: k t / 8, rows 8 (t % 8) .. + 7 (M is a multiple of 64 here)
     const int k = t >> 3, mq = (t & 7) * 8;
-    va = *(const uint4*)(g.a + (int64_t)(k0 + k) * g.sak + m0 + mq);
+    va = *(const u32x4*)(g.a + (int64_t)(k0 + k) * g.sak + m0 + mq);
   }
   if (BK) {
     const int r = t >> 2, kq = (t & 3) * 8;
-    vb = *(const uint4*)(g.b + (int64_t)(n0 + r) * g.sbn + k0 + kq);
+    vb = *(const u32x4*)(g.b + (int64_t)(n0 + r) * g.sbn + k0 + kq);
   } else {
     const int k = t >> 3, nq = (t & 7) * 8;
-    vb = *(const uint4*)(g.b + (int64_t)(k0 + k) * g.sbk + n0 + nq);
+    vb = *(const u32x4*)(g.b + (int64_t)(k0 + k) * g.sbk + n0 + nq);
   }
 }
 
 template <bool AK, bool BK>
 __device__ __forceinline__ void gemm_store_step(uint16_t (*As)[kGemmLd], uint16_t (*Bs)[kGemmLd],
-                                                int kk, int t, const uint4& va, const uint4& vb) {
+                                                int kk, int t, const u32x4& va, const u32x4& vb) {
   if (AK) {
-    *(uint4*)&As[t >> 2][kk + (t & 3) * 8] = va;
+    *(u32x4*)&As[t >> 2][kk + (t & 3) * 8] = va;
   } else {
     const int k = t >> 3, mq = (t & 7) * 8;
-    const uint32_t w[4] = {va.x, va.y, va.z, va.w};
 #pragma unroll
-    for (int j = 0; j < 8; ++j) As[mq + j][kk + k] = (uint16_t)(w[j >> 1] >> (16 * (j & 1)));
+    for (int j = 0; j < 8; ++j) As[mq + j][kk + k] = (uint16_t)(va[j >> 1] >> (16 * (j & 1)));
   }
   if (BK) {
-    *(uint4*)&Bs[t >> 2][kk + (t & 3) * 8] = vb;
+    *(u32x4*)&Bs[t >> 2][kk + (t & 3) * 8] = vb;
   } else {
     const int k = t >> 3, nq = (t & 7) * 8;
-    const uint32_t w[4] = {vb.x, vb.y, vb.z, vb.w};
 #pragma unroll
-    for (int j = 0; j < 8; ++j) Bs[nq + j][kk + k] = (uint16_t)(w[j >> 1] >> (16 * (j & 1)));
+    for (int j = 0; j < 8; ++j) Bs[nq + j][kk + k] = (uint16_t)(vb[j >> 1] >> (16 * (j & 1)));
   }
 }
 
@@ -348,7 +351,7 @@ __global__ __launch_bounds__(256) void k_gemm_bf16(GemmArgs g) {
   const int kz0 = blockIdx.z * kslice, kz1 = kz0 + kslice;
   for (int ks = kz0; ks < kz1; ks += kGemmKS) {
     const int kn = min(kGemmKS, kz1 - ks);  // a multiple of 32
-    uint4 va[kGemmKS / kGemmK], vb[kGemmKS / kGemmK];
+    u32x4 va[kGemmKS / kGemmK], vb[kGemmKS / kGemmK];
 #pragma unroll
     for (int q = 0; q < kGemmKS / kGemmK; ++q)
       if (q * kGemmK < kn) gemm_load_step<AK, BK>(g, m0, n0, ks + q * kGemmK, t, va[q], vb[q]);
