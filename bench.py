@@ -72,12 +72,12 @@ _GABOR_SOURCES = ["fd_gabor.hip"]
 _VOLUME_SOURCES = ["fd_volume.hip", "fd_voxel.hpp"]
 _PHG_SOURCES = ["fd_phg.hip", "fd_voxel.hpp"]
 TRAFFIC = {
-    "k_fuse, realistic 500k": {"read": 379.7e6, "write": 37.7e6, "files": _SEARCH_SOURCES,
-                               "src": "69471fb013ca6e6b"},
-    "k_fuse, metric workload, per head": {"read": 133.4e6, "write": 8.5e6,
-                                          "files": _SEARCH_SOURCES, "src": "69471fb013ca6e6b"},
-    "k_b_learned, metric workload": {"read": 2227.9e6, "write": 160.7e6,
-                                     "files": _BATCHED_SOURCES, "src": "3244fdc8a0af2879"},
+    "k_fuse, realistic 500k": {"read": 409.9e6, "write": 37.6e6, "files": _SEARCH_SOURCES,
+                               "src": "f1cf612e32964315"},
+    "k_fuse, metric workload, per head": {"read": 135.8e6, "write": 8.5e6,
+                                          "files": _SEARCH_SOURCES, "src": "f1cf612e32964315"},
+    "k_b_learned, metric workload": {"read": 2258.3e6, "write": 160.7e6,
+                                     "files": _BATCHED_SOURCES, "src": "b9fe1b77b1dd8781"},
     "k_gabor_mfma, 64 frames 1024^2": {"read": 1152.1e6, "write": 406.8e6,
                                        "files": _GABOR_SOURCES, "src": "21a8f3739c8a0866"},
     # the counting sort: keys and counts, the scan, the placement
