@@ -390,3 +390,46 @@ def test_network_against_a_fibonacci_proposal_at_equal_budget():
     assert err_net <= 2.0 and err_fib <= 2.0
     assert kept_net > 0.02 and kept_fib > 0.02
     assert abs(kept_net - kept_fib) <= 0.05
+
+
+@pytest.mark.parametrize("views", [64, 136])
+def test_features_inside_the_learned_search_equal_the_features_entry_point(views):
+    """With the network, the learned form makes the feature rows inside its
+    view selection (two kernels for scenes of at most 128 views, one pass
+    above that) and in processing order.  Handed instead the network's
+    proposals for the rows of the standalone features entry point (one
+    pass, point order), it must give the same bits, per scene and
+    batched: the rows are the same whichever kernels make them."""
+    nat = _native()
+    rec = dict(scenegen.RECIPES["realistic"])
+    rec.update(n_points=8000, n_strands=800, n_views=views, res=256)
+    sc = scenegen.make_scene(rec, 21)
+    net = nat.MLP(path=os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))),
+                                    "paper_2604_05794_amd", "weights", "proposal_mlp.fdmlp"))
+    step0, tau = net.calibration()
+    pts, cams, th, cf = _dev_scene(sc)
+    dm = torch.from_numpy(sc.depth).to(DEV)
+    kw = dict(patch=5, n_candidates=64, refine_iters=8, top_k=5)
+    lk = dict(mode=nat.FD_MODE_LEARNED, learned_iters=2, learned_step0=step0,
+              fallback_cost=tau)
+    ctx = nat.Context(max_points=sc.n_points)
+    d1, c1 = nat.fuse_directions(pts, cams, th, cf, ctx=ctx, depth_maps=dm,
+                                 head_centre=sc.head_centre, mlp=net, **lk, **kw)
+    prop = net.forward(nat.features(pts, cams, th, cf, head_centre=sc.head_centre,
+                                    depth_maps=dm))
+    d2, c2 = nat.fuse_directions(pts, cams, th, cf, ctx=ctx, depth_maps=dm,
+                                 head_centre=sc.head_centre, proposal=nat.FD_PROPOSAL_GIVEN,
+                                 proposal_dirs=prop, **lk, **kw)
+    torch.cuda.synchronize()
+    kept = int((~(torch.all(d1 == nat.fuse_directions(
+        pts, cams, th, cf, ctx=ctx, depth_maps=dm, **kw)[0], dim=1))).sum())
+    print(f"{views} views: {sc.n_points} points, {kept} not equal to the plain result",
+          flush=True)
+    assert torch.equal(d1, d2) and torch.equal(c1, c2)
+    scene = dict(points=pts, cams=cams, orient_maps=th, conf_maps=cf, depth_maps=dm,
+                 head_centre=sc.head_centre, dirs=torch.empty_like(d1),
+                 costs=torch.empty_like(c1))
+    bctx = nat.Context(max_points=sc.n_points, max_views=sc.n_views, max_scenes=1)
+    nat.fuse_batched([scene], bctx, mlp=net, **lk, **kw)
+    torch.cuda.synchronize()
+    assert torch.equal(scene["dirs"], d1) and torch.equal(scene["costs"], c1)
