@@ -78,6 +78,10 @@ TRAFFIC = {
                                           "files": _SEARCH_SOURCES, "src": "f1cf612e32964315"},
     "k_b_learned, metric workload": {"read": 2258.3e6, "write": 160.7e6,
                                      "files": _BATCHED_SOURCES, "src": "b9fe1b77b1dd8781"},
+    # the autotuned one-wave-per-tile form (the persistent form's traffic
+    # depends on its queue shape)
+    "k_b_fuse_tiles, 16 hairstyles": {"read": 3812.9e6, "write": 348.6e6,
+                                      "files": _BATCHED_SOURCES, "src": "b9fe1b77b1dd8781"},
     "k_gabor_mfma, 64 frames 1024^2": {"read": 1152.1e6, "write": 406.8e6,
                                        "files": _GABOR_SOURCES, "src": "21a8f3739c8a0866"},
     # the counting sort: keys and counts, the scan, the placement
@@ -555,8 +559,9 @@ def run_batched(args):
         f"bitwise equal {same}")
     flop = plain_flop_per_point(kw["patch"], kw["n_candidates"], kw["refine_iters"], 5)
     achieved = flop * n / (st_b["fuse"] * 1e-3) / 1e12
-    kern = "k_b_fuse_tiles (persistent tile queue)" if tuned[1] > 0 else \
-        "k_b_fuse (one wave per tile)"
+    kern = "k_b_fuse (persistent tile queue)" if tuned[1] > 0 else \
+        "k_b_fuse_tiles (one wave per tile)"
+    traffic_key = ("k_b_fuse" if tuned[1] > 0 else "k_b_fuse_tiles") + ", 16 hairstyles"
     out = {
         "metric": METRIC, "value": v_b, "unit": "points/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": el_b * 1e3 / args.steps,
@@ -576,8 +581,9 @@ def run_batched(args):
         "stages_ms_per_launch": st_b, "stages_ms_per_launch_per_scene": st_p,
         "roofline": {"bound": "alu", "kernel": kern, "achieved": achieved,
                      "peak": PEAK_FP32, "unit": "TFLOP/s", "frac": achieved / PEAK_FP32,
-                     "traffic": None, "avg_launch_ms": st_b["fuse"], "points_per_launch": n,
-                     "flop_per_point": flop, "flop_per_sim_eval": FLOP_PER_SIM_EVAL},
+                     "traffic": traffic_of(traffic_key), "avg_launch_ms": st_b["fuse"],
+                     "points_per_launch": n, "flop_per_point": flop,
+                     "flop_per_sim_eval": FLOP_PER_SIM_EVAL},
     }
     if not args.no_cpu_baseline:
         sc = scenes[len(scenes) // 2][0]
