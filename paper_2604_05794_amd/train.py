@@ -161,6 +161,11 @@ def main():
     ap.add_argument("--budget-deg", type=float, default=1.5)
     ap.add_argument("--learned-iters", type=int, default=2)
     ap.add_argument("--quick", action="store_true", help="small data, for a smoke run")
+    ap.add_argument("--train-data", choices=["workloads", "config1"], default="workloads",
+                    help="pairs from the workloads the network runs on (the committed "
+                         "checkpoint), or from the small helical recipe and its own plain "
+                         "search (P=3, 48 candidates): the two readings of the training "
+                         "data; calibration uses the same held-out workload scenes")
     ap.add_argument("--recalibrate", metavar="CKPT",
                     help="only calibrate an existing checkpoint and write it to --out")
     args = ap.parse_args()
@@ -179,7 +184,11 @@ def main():
     # 2M training pairs: two 500k-point scenes of the realistic recipe and
     # four 250k-point heads of tight curls (seeds 1000+), labels from the
     # plain search with each recipe's own parameters
-    if args.quick:
+    if args.train_data == "config1":
+        # 2M pairs: eight 250k-point scenes of the small helical recipe
+        train_set = [("tiny", 1000 + k, 25_000 if args.quick else 250_000)
+                     for k in range(2 if args.quick else 8)]
+    elif args.quick:
         train_set = [("realistic", 1000, 50_000), ("curls", 1000, 50_000)]
     else:
         train_set = [("realistic", 1000, None), ("realistic", 1001, None),
